@@ -1,0 +1,355 @@
+"""FP64 oracle of the expected counts and the binned Poisson NLL.
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's CPU
+baseline import this.  Everything is materialised and evaluated densely in
+float64 with library primitives (scipy.special, numpy matmul / convolve,
+math.fsum); there is no tiling, fusion or reordering.
+
+Notation: T true-energy bins with centres E_i, N reco bins with edges x_j,
+S species with deposited spectra F[s, i] (unit row sums), rates r_s,
+response parameters rho, cells R[j, i] = probability that an event deposited
+in true bin i is reconstructed in reco bin j (Eq. 1 discretised).
+"""
+from __future__ import annotations
+
+import math
+from types import SimpleNamespace
+
+import numpy as np
+from scipy import special
+
+GAUSS = "gauss"
+GG = "gg"
+
+
+class DomainError(ValueError):
+    """Parameters outside the model's domain (the NLL is +inf there)."""
+
+
+# ---------------------------------------------------------------------------
+# Column parameters of the response (Eq. 1: R_x(N_x, E; p0, p1, ...)).
+# ---------------------------------------------------------------------------
+def true_centres(desc):
+    te = np.asarray(desc.true_edges, np.float64)
+    return 0.5 * (te[:-1] + te[1:])
+
+
+def gg_log_cv2(k, p):
+    """ln(1 + Var/Mean^2) of the generalized gamma with shape k, exponent p:
+    ln[Gamma(k) Gamma(k + 2/p) / Gamma(k + 1/p)^2]."""
+    return special.gammaln(k) + special.gammaln(k + 2.0 / p) - 2.0 * special.gammaln(k + 1.0 / p)
+
+
+def gg_solve_shape(tau, p):
+    """Shape k with gg_log_cv2(k, p) = tau, by bisection on ln k (the left
+    side decreases monotonically in k)."""
+    tau = np.asarray(tau, np.float64)
+    lo = np.full(tau.shape, -40.0)
+    hi = np.full(tau.shape, 25.0)
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        too_small_k = gg_log_cv2(np.exp(mid), p) > tau
+        lo = np.where(too_small_k, mid, lo)
+        hi = np.where(too_small_k, hi, mid)
+    return np.exp(0.5 * (lo + hi))
+
+
+def column_params(desc, resp):
+    """Per true-bin column parameters.
+
+    Gaussian: mean m_i = E_i, sigma_i = sqrt(a E_i + b E_i^2).
+    Generalized gamma (Stacy) with fixed exponent p: mean m_i = L Q_i E_i,
+    variance s_i^2 = v0 + v1 m_i + v2 m_i^2, and (k_i, a_i) such that
+    GG(a, k, p) has that mean and variance:
+        Var/Mean^2 = Gamma(k)Gamma(k+2/p)/Gamma(k+1/p)^2 - 1,
+        a = m Gamma(k) / Gamma(k + 1/p).
+    """
+    E = true_centres(desc)
+    resp = np.asarray(resp, np.float64)
+    if not np.all(np.isfinite(resp)):
+        raise DomainError("non-finite response parameter")
+    if desc.kind == GAUSS:
+        a, b = resp
+        var = a * E + b * E * E
+        if np.any(var < 0):
+            raise DomainError("sigma^2 < 0")
+        return SimpleNamespace(kind=GAUSS, E=E, m=E.copy(), sigma=np.sqrt(var))
+    L, v0, v1, v2 = resp
+    p = float(desc.gg_p)
+    m = L * np.asarray(desc.quench, np.float64) * E
+    s2 = v0 + v1 * m + v2 * m * m
+    if np.any(m <= 0) or np.any(s2 <= 0):
+        raise DomainError("GG mean or variance not positive")
+    tau = np.log1p(s2 / (m * m))
+    k = gg_solve_shape(tau, p)
+    a = m * np.exp(special.gammaln(k) - special.gammaln(k + 1.0 / p))
+    return SimpleNamespace(kind=GG, E=E, m=m, s2=s2, tau=tau, k=k, a=a, p=p)
+
+
+# ---------------------------------------------------------------------------
+# CDF at the reco edges and the cells (Eq. 1 integrated over each reco bin).
+# ---------------------------------------------------------------------------
+def edge_tails(desc, cp):
+    """For every column i and reco edge x_j: the smaller tail of the CDF and
+    which side it is on.  lower[i, j] = True means tail = F(x_j) (<= 1/2),
+    else tail = 1 - F(x_j).  F(x) = P(X < x); a zero-width Gaussian puts all
+    of its mass in the reco bin [x_j, x_j+1) holding the mean."""
+    x = np.asarray(desc.reco_edges, np.float64)[None, :]
+    if cp.kind == GAUSS:
+        m = cp.m[:, None]
+        s = cp.sigma[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            z = (x - m) / s
+        pos = s > 0
+        lower = np.where(pos, z <= 0, x <= m)
+        tail = np.where(pos, special.ndtr(np.where(lower, z, -z)), 0.0)
+        return tail, lower
+    k = cp.k[:, None]
+    a = cp.a[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        y = np.where(x > 0, (np.maximum(x, 0.0) / a) ** cp.p, 0.0)
+    P = special.gammainc(k, y)
+    Q = special.gammaincc(k, y)
+    lower = P <= 0.5
+    return np.where(lower, P, Q), lower
+
+
+def cells_from_tails(tail, lower):
+    """R[j, i] from the edge tails: the difference is taken on the side where
+    both edge values are small; a cell straddling the median is
+    1 - F(x_j) - (1 - F(x_j+1))."""
+    tl, th = tail[:, :-1], tail[:, 1:]
+    ll, lh = lower[:, :-1], lower[:, 1:]
+    cells = np.where(ll & lh, th - tl, np.where(~ll & ~lh, tl - th, 1.0 - tl - th))
+    return cells.T.copy()
+
+
+def response_matrix(desc, cp):
+    """Dense response matrix R [N, T] (Eq. 1 on the true x reco grid)."""
+    tail, lower = edge_tails(desc, cp)
+    return cells_from_tails(tail, lower)
+
+
+def _gg_dF_dk(desc, cp):
+    """dF(x_j)/dk_i at fixed scale a_i, by Richardson-extrapolated central
+    differences of the regularized incomplete gamma in its first argument."""
+    lower = edge_tails(desc, cp)[1]
+    sign = np.where(lower, 1.0, -1.0)
+
+    def side_tail(kk):
+        x = np.asarray(desc.reco_edges, np.float64)[None, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            y = np.where(x > 0, (np.maximum(x, 0.0) / cp.a[:, None]) ** cp.p, 0.0)
+        kk = kk[:, None]
+        return np.where(lower, special.gammainc(kk, y), special.gammaincc(kk, y))
+
+    h = 1e-3 * cp.k
+    d1 = (side_tail(cp.k + h) - side_tail(cp.k - h)) / (2 * h)[:, None]
+    d2 = (side_tail(cp.k + h / 2) - side_tail(cp.k - h / 2)) / h[:, None]
+    return sign * (4.0 * d2 - d1) / 3.0
+
+
+def response_derivs(desc, cp):
+    """dR/d(rho_q) [N, T] for every response parameter rho_q.
+
+    Gaussian: dR/dsigma = -[z phi(z)]_{x_j}^{x_j+1} / sigma, with
+    dsigma/da = E/(2 sigma), dsigma/db = E^2/(2 sigma).
+    Generalized gamma: dR/da = -(p/a)[g(y)]_{x_j}^{x_j+1} with
+    g(y) = y^k e^-y / Gamma(k); dR/dk by Richardson differences; chained
+    through k(tau), tau = ln(1 + s^2/m^2), a = m Gamma(k)/Gamma(k+1/p).
+    """
+    x = np.asarray(desc.reco_edges, np.float64)[None, :]
+    if cp.kind == GAUSS:
+        s = cp.sigma[:, None]
+        if np.any(cp.sigma == 0):
+            raise DomainError("sigma = 0: response derivative undefined")
+        z = (x - cp.m[:, None]) / s
+        zphi = z * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+        dR_dsig = (-(zphi[:, 1:] - zphi[:, :-1]) / s).T      # [N, T]
+        E = cp.E
+        return [dR_dsig * (E / (2 * cp.sigma))[None, :],
+                dR_dsig * (E * E / (2 * cp.sigma))[None, :]]
+    p, k, a, m, s2 = cp.p, cp.k, cp.a, cp.m, cp.s2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        y = np.where(x > 0, (np.maximum(x, 0.0) / a[:, None]) ** p, 0.0)
+        g = np.where(y > 0, np.exp(k[:, None] * np.log(y) - y - special.gammaln(k)[:, None]), 0.0)
+    dF_da = -(p / a)[:, None] * g
+    dR_da = (dF_da[:, 1:] - dF_da[:, :-1]).T
+    dF_dk = _gg_dF_dk(desc, cp)
+    dR_dk = (dF_dk[:, 1:] - dF_dk[:, :-1]).T
+    dG = special.digamma(k) + special.digamma(k + 2 / p) - 2 * special.digamma(k + 1 / p)
+    dlnA_dk = special.digamma(k) - special.digamma(k + 1 / p)
+    return SimpleNamespace(dR_dk=dR_dk, dR_da=dR_da, dG=dG, dlnA_dk=dlnA_dk)
+
+
+def _gg_chain(cp, resp, parts):
+    """Combine dR/dk and dR/da into dR/d(L, v0, v1, v2)."""
+    L, v0, v1, v2 = resp
+    m, s2, k, a = cp.m, cp.s2, cp.k, cp.a
+    out = []
+    for q in range(4):
+        dm = m / L if q == 0 else np.zeros_like(m)
+        ds2 = [np.zeros_like(m), np.ones_like(m), m, m * m][q] + (v1 + 2 * v2 * m) * dm
+        dtau = (ds2 / (m * m) - 2 * s2 * dm / (m ** 3)) / (1 + s2 / (m * m))
+        dk = dtau / parts.dG
+        da = a * (dm / m + parts.dlnA_dk * dk)
+        out.append(parts.dR_dk * dk[None, :] + parts.dR_da * da[None, :])
+    return out
+
+
+def response_param_derivs(desc, cp, resp):
+    d = response_derivs(desc, cp)
+    if cp.kind == GAUSS:
+        return d
+    return _gg_chain(cp, np.asarray(resp, np.float64), d)
+
+
+# ---------------------------------------------------------------------------
+# Species contraction (Eq. 1), pile-up (Eq. 2) and the expected counts of the
+# likelihood terms (Eqs. 3-4).
+# ---------------------------------------------------------------------------
+def normalised_spectra(desc):
+    F = np.asarray(desc.spectra, np.float64)
+    return np.array([row / math.fsum(row) for row in F])
+
+
+def contraction(desc, R):
+    """M[j, s] = exposure * sum_i R[j, i] F[s, i]."""
+    return float(desc.exposure) * (R @ normalised_spectra(desc).T)
+
+
+def pileup(desc, M):
+    """M'[:, s] = (1 - p) M[:, s] + p (g_hat * M[:, s]), g_hat = g / sum g,
+    a causal convolution truncated at the top of the reco range."""
+    p = float(desc.pu_frac)
+    if p == 0.0 or desc.pu_g is None:
+        return M.copy()
+    g = np.asarray(desc.pu_g, np.float64)
+    ghat = g / math.fsum(g)
+    N = M.shape[0]
+    conv = np.stack([np.convolve(M[:, s], ghat)[:N] for s in range(M.shape[1])], axis=1)
+    return (1.0 - p) * M + p * conv
+
+
+def expected(desc, Mp, r):
+    """Expected counts per likelihood term, linear in both M' and r.
+
+    Single histogram: mu = M' r.
+    Multivariate (Eq. 4): with c_sub = (1 - t) r, c_tag = t r:
+      vetoed mu_sub = M' c_sub, tagged mu_tag = M' c_tag (Eq. 3);
+      radial nu_k = sum_s c_sub,s (sum_{j in radial window} M'_js) rho_sk;
+      pulse shape lambda_jk = sum_s M'_js c_sub,s T_sk (rows of the fit
+      window), all built from the TFC-vetoed expectation."""
+    r = np.asarray(r, np.float64)
+    j0, j1 = desc.win
+    if not desc.multivariate:
+        return {"energy": (Mp @ r)[j0:j1]}
+    t = np.asarray(desc.tag_frac, np.float64)
+    c_sub = (1.0 - t) * r
+    c_tag = t * r
+    out = {"energy": (Mp @ c_sub)[j0:j1], "tagged": (Mp @ c_tag)[j0:j1]}
+    if desc.rad_tmpl is not None:
+        rw0, rw1 = desc.rad_win
+        A = c_sub * Mp[rw0:rw1].sum(axis=0)
+        out["radial"] = A @ np.asarray(desc.rad_tmpl, np.float64)
+    if desc.ps_tmpl is not None:
+        out["ps"] = ((Mp * c_sub[None, :]) @ np.asarray(desc.ps_tmpl, np.float64))[j0:j1]
+    return out
+
+
+def observed(desc, data):
+    j0, j1 = desc.win
+    out = {"energy": np.asarray(data.energy, np.float64)[j0:j1]}
+    if desc.multivariate:
+        out["tagged"] = np.asarray(data.tagged, np.float64)[j0:j1]
+        if desc.rad_tmpl is not None:
+            out["radial"] = np.asarray(data.radial, np.float64)
+        if desc.ps_tmpl is not None:
+            out["ps"] = np.asarray(data.ps, np.float64)[j0:j1]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Binned Poisson NLL without the data-only constant: sum (mu - n ln mu).
+# ---------------------------------------------------------------------------
+def nll_terms(mu, n):
+    mu = np.asarray(mu, np.float64).ravel()
+    n = np.asarray(n, np.float64).ravel()
+    if not np.all(np.isfinite(mu)) or np.any(mu < 0) or np.any((mu == 0) & (n > 0)):
+        raise DomainError("expected count negative, or zero where counts > 0")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(n > 0, mu - n * np.log(mu), mu)
+
+
+def split_theta(desc, theta):
+    theta = np.asarray(theta, np.float64)
+    if theta.shape != (desc.P,):
+        raise ValueError(f"theta must have {desc.P} entries")
+    if not np.all(np.isfinite(theta)):
+        raise DomainError("non-finite theta")
+    return theta[: desc.S], theta[desc.S:]
+
+
+def forward(desc, theta):
+    r, resp = split_theta(desc, theta)
+    cp = column_params(desc, resp)
+    R = response_matrix(desc, cp)
+    Mp = pileup(desc, contraction(desc, R))
+    return SimpleNamespace(cp=cp, R=R, Mp=Mp, r=r, resp=resp, mu=expected(desc, Mp, r))
+
+
+def nll(desc, data, theta):
+    """Extended binned Poisson NLL (all terms of Eq. 3 / Eq. 4)."""
+    f = forward(desc, theta)
+    obs = observed(desc, data)
+    return math.fsum(math.fsum(nll_terms(f.mu[key], obs[key])) for key in f.mu)
+
+
+def lnfact(desc, data):
+    """Sum of ln Gamma(n + 1) over all bins entering the NLL."""
+    obs = observed(desc, data)
+    return math.fsum(math.fsum(special.gammaln(v.ravel() + 1.0)) for v in obs.values())
+
+
+def grad(desc, data, theta):
+    """Gradient of the NLL, forward mode: for every parameter q the
+    derivatives of the expected counts dmu/dq are formed explicitly and
+    contracted with w = 1 - n/mu."""
+    return nll_grad(desc, data, theta)[1]
+
+
+def nll_grad(desc, data, theta):
+    f = forward(desc, theta)
+    obs = observed(desc, data)
+    val = math.fsum(math.fsum(nll_terms(f.mu[key], obs[key])) for key in f.mu)
+    w = {}
+    for key in f.mu:
+        mu = f.mu[key]
+        n = obs[key]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w[key] = np.where(n > 0, 1.0 - n / mu, 1.0)
+
+    def contract(dmu):
+        return math.fsum(math.fsum((w[key] * dmu[key]).ravel()) for key in w)
+
+    g = np.zeros(desc.P)
+    for s in range(desc.S):
+        e = np.zeros(desc.S)
+        e[s] = 1.0
+        g[s] = contract(expected(desc, f.Mp, e))
+    for q, dR in enumerate(response_param_derivs(desc, f.cp, f.resp)):
+        dMp = pileup(desc, contraction(desc, dR))
+        g[desc.S + q] = contract(expected(desc, dMp, f.r))
+    return val, g
+
+
+def per_species_expected(desc, theta):
+    """M' [N, S]: expected counts per unit rate of every species, after the
+    response and pile-up, at the response parameters of theta."""
+    return forward(desc, theta).Mp
+
+
+def support_cells(desc, theta, eps=1e-30):
+    """Number of cells with R[j, i] > eps (the work the method must do)."""
+    f = forward(desc, theta)
+    return int(np.count_nonzero(f.R > eps))

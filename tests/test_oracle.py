@@ -1,0 +1,474 @@
+"""Pins of the FP64 oracle against things other than itself: brute-force
+quadrature, closed forms, invariants and special cases that reduce to
+library routines (the paper prints no worked example with values)."""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle
+import synth
+from oracle import model as om
+
+
+# ---------------------------------------------------------------------------
+# small models
+# ---------------------------------------------------------------------------
+def tiny_gauss(T=6, N=8, S=2, seed=0):
+    rng = np.random.default_rng(seed)
+    te = np.linspace(0.1, 1.3, T + 1)
+    re = np.linspace(0.0, 1.6, N + 1)
+    F = rng.random((S, T)) + 0.1
+    F /= F.sum(1, keepdims=True)
+    th = np.concatenate([rng.uniform(50, 200, S), [0.05, 0.01]])
+    return synth.ModelDesc(kind="gauss", true_edges=te, reco_edges=re, spectra=F,
+                           species=[f"s{i}" for i in range(S)], win=(0, N), theta_true=th)
+
+
+def tiny_gg(T=5, N=7, S=2, p=1.25, seed=0):
+    rng = np.random.default_rng(seed)
+    te = np.linspace(0.002, 0.08, T + 1)
+    re = np.linspace(0.0, 40.0, N + 1)
+    F = rng.random((S, T)) + 0.1
+    F /= F.sum(1, keepdims=True)
+    Q = 1 - 0.25 * np.exp(-0.5 * (te[:-1] + te[1:]) / 0.2)
+    th = np.concatenate([rng.uniform(50, 200, S), [500.0, 4.0, 1.1, 4e-4]])
+    return synth.ModelDesc(kind="gg", true_edges=te, reco_edges=re, spectra=F, gg_p=p,
+                           quench=Q, species=[f"s{i}" for i in range(S)], win=(0, N),
+                           theta_true=th)
+
+
+def poisson_data(desc, theta, seed=1):
+    mu = om.forward(desc, theta).mu["energy"]
+    return synth.Data(energy=np.random.default_rng(seed).poisson(mu).astype(float))
+
+
+# ---------------------------------------------------------------------------
+# brute force in mpmath (30 digits): density integrated over every reco bin
+# ---------------------------------------------------------------------------
+def mp_gauss_cells(E, sig, x):
+    out = np.zeros((len(x) - 1, len(E)))
+    for i, (m, s) in enumerate(zip(E, sig)):
+        dens = lambda u: mp.exp(-(u - m) ** 2 / (2 * s * s)) / (s * mp.sqrt(2 * mp.pi))  # noqa
+        for j in range(len(x) - 1):
+            out[j, i] = float(mp.quad(dens, [x[j], m, x[j + 1]] if x[j] < m < x[j + 1]
+                                      else [x[j], x[j + 1]]))
+    return out
+
+
+def mp_gg_cells(k, a, p, x):
+    out = np.zeros((len(x) - 1, len(k)))
+    for i, (kk, aa) in enumerate(zip(k, a)):
+        kk, aa = mp.mpf(kk), mp.mpf(aa)
+        lg = mp.loggamma(kk)
+
+        def dens(u):
+            if u <= 0:
+                return mp.mpf(0)
+            return p * mp.exp((p * kk - 1) * mp.log(u) - (u / aa) ** p - p * kk * mp.log(aa) - lg)
+        for j in range(len(x) - 1):
+            out[j, i] = float(mp.quad(dens, [max(x[j], 0), x[j + 1]])) if x[j + 1] > 0 else 0.0
+    return out
+
+
+def test_gauss_cells_vs_quadrature():
+    mp.mp.dps = 40
+    d = tiny_gauss()
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    ref = mp_gauss_cells(cp.m, cp.sigma, d.reco_edges)
+    assert np.all(np.abs(R - ref) <= 1e-16 + 1e-13 * np.abs(ref))
+
+
+@pytest.mark.parametrize("p", [1.25, 0.8, 2.0])
+def test_gg_cells_vs_quadrature(p):
+    mp.mp.dps = 30
+    d = tiny_gg(p=p)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    assert cp.k.min() < 3 and cp.k.max() > 5      # spans small and large shapes
+    R = om.response_matrix(d, cp)
+    ref = mp_gg_cells(cp.k, cp.a, p, d.reco_edges)
+    assert np.all(np.abs(R - ref) <= 1e-15 + 1e-11 * np.abs(ref))
+
+
+def test_gg_cdf_vs_mpmath_gammainc():
+    mp.mp.dps = 30
+    d = tiny_gg(T=3, N=5)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    tail, lower = om.edge_tails(d, cp)
+    for i in range(d.T):
+        for j, x in enumerate(d.reco_edges):
+            y = (mp.mpf(x) / cp.a[i]) ** cp.p if x > 0 else mp.mpf(0)
+            P = mp.gammainc(cp.k[i], 0, y, regularized=True)
+            ref = P if lower[i, j] else 1 - P
+            assert abs(tail[i, j] - float(ref)) <= 1e-15 + 1e-12 * float(ref)
+
+
+def test_gg_p1_is_gamma_closed_form():
+    """p = 1: moment matching has the closed form k = m^2/s^2, a = s^2/m and
+    the CDF is the gamma distribution's."""
+    d = tiny_gg(p=1.0)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    np.testing.assert_allclose(cp.k, cp.m ** 2 / cp.s2, rtol=1e-9)
+    np.testing.assert_allclose(cp.a, cp.s2 / cp.m, rtol=1e-9)
+    R = om.response_matrix(d, cp)
+    cdf = stats.gamma.cdf(d.reco_edges[None, :], cp.k[:, None], scale=cp.a[:, None])
+    np.testing.assert_allclose(R, np.diff(cdf, axis=1).T, rtol=1e-10, atol=1e-15)
+
+
+def test_gg_moment_matching_mpmath():
+    mp.mp.dps = 30
+    d = synth.config2()
+    cp = om.column_params(d, d.theta_true[d.S:])
+    for i in [0, 3, 20, 150, 900, 2999]:
+        k, a, p = mp.mpf(cp.k[i]), mp.mpf(cp.a[i]), mp.mpf(cp.p)
+        g0 = mp.gamma(k)
+        mean = a * mp.gamma(k + 1 / p) / g0
+        var = a * a * mp.gamma(k + 2 / p) / g0 - mean ** 2
+        assert abs(float(mean) / cp.m[i] - 1) < 1e-12
+        assert abs(float(var) / cp.s2[i] - 1) < 1e-7
+
+
+@pytest.mark.parametrize("kind", ["gauss", "gg"])
+def test_column_normalisation_with_under_overflow(kind):
+    d = synth.config1() if kind == "gauss" else synth.config2()
+    d.reco_edges = np.concatenate([[-np.inf], d.reco_edges, [np.inf]])
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    np.testing.assert_allclose(R.sum(axis=0), 1.0, rtol=0, atol=1e-14)
+
+
+def test_delta_spectrum_gives_kernel_column():
+    d = synth.config1()
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    for i in [0, 57, 160, 399]:
+        e = d.copy()
+        e.spectra = np.zeros((1, d.T))
+        e.spectra[0, i] = 1.0
+        e.species = ["delta"]
+        mu = om.forward(e, np.concatenate([[1.0], d.theta_true[d.S:]])).mu["energy"]
+        np.testing.assert_array_equal(mu, R[:, i])
+
+
+def test_delta_kernel_rebins_spectrum():
+    d = synth.config1()
+    th = d.theta_true.copy()
+    th[d.S:] = 0.0                      # sigma = 0 everywhere
+    mu = om.forward(d, th).mu["energy"]
+    E = om.true_centres(d)
+    ref = np.zeros(d.N)
+    vals = (th[: d.S, None] * d.spectra).sum(0)
+    for i, e in enumerate(E):
+        j = np.searchsorted(d.reco_edges, e, side="right") - 1
+        if 0 <= j < d.N:
+            ref[j] += vals[i]
+    np.testing.assert_allclose(mu, ref, rtol=1e-13, atol=1e-9)
+
+
+def test_delta_kernel_on_edge_goes_to_upper_bin():
+    d = tiny_gauss(T=2, N=4)
+    d.true_edges = np.array([0.3, 0.5, 0.7])       # centres 0.4 (on an edge) and 0.6
+    d.reco_edges = np.array([0.0, 0.2, 0.4, 0.6, 0.8])
+    th = np.concatenate([[1.0, 1.0], [0.0, 0.0]])
+    d.spectra = np.array([[1.0, 0.0], [0.0, 1.0]])
+    mu = om.forward(d, th).mu["energy"]
+    np.testing.assert_array_equal(mu, [0.0, 0.0, 1.0, 1.0])
+
+
+# ---------------------------------------------------------------------------
+# pile-up (Eq. 2)
+# ---------------------------------------------------------------------------
+def _pu_desc(N, g, p):
+    d = tiny_gauss(N=N)
+    d.pu_g, d.pu_frac = np.asarray(g, float), p
+    return d
+
+
+def test_pileup_zero_fraction_is_identity():
+    M = np.random.default_rng(0).random((30, 3))
+    d = _pu_desc(30, np.ones(5), 0.0)
+    assert np.array_equal(om.pileup(d, M), M)
+
+
+def test_pileup_delta_is_identity():
+    M = np.random.default_rng(0).random((30, 3))
+    d = _pu_desc(30, [2.0, 0.0, 0.0], 0.3)
+    np.testing.assert_allclose(om.pileup(d, M), M, rtol=3e-16, atol=0)
+
+
+def test_pileup_brute_force_loop():
+    rng = np.random.default_rng(3)
+    N, K, p = 12, 5, 0.17
+    M = rng.random((N, 2))
+    g = rng.random(K)
+    gh = g / g.sum()
+    ref = np.zeros_like(M)
+    for s in range(2):
+        for j in range(N):
+            acc = 0.0
+            for k in range(K):
+                if j - k >= 0:
+                    acc += gh[k] * M[j - k, s]
+            ref[j, s] = (1 - p) * M[j, s] + p * acc
+    np.testing.assert_allclose(om.pileup(_pu_desc(N, g, p), M), ref, rtol=1e-14)
+
+
+def test_pileup_conserves_mass_on_padded_window():
+    rng = np.random.default_rng(4)
+    N, K = 40, 8
+    M = np.zeros((N, 2))
+    M[: N - K] = rng.random((N - K, 2))
+    out = om.pileup(_pu_desc(N, rng.random(K), 0.4), M)
+    np.testing.assert_allclose(out.sum(0), M.sum(0), rtol=1e-14)
+
+
+def test_pileup_composition():
+    rng = np.random.default_rng(5)
+    N = 50
+    M = rng.random((N, 1))
+    g1, g2 = rng.random(6), rng.random(4)
+    g1, g2 = g1 / g1.sum(), g2 / g2.sum()
+    twice = om.pileup(_pu_desc(N, g2, 1.0), om.pileup(_pu_desc(N, g1, 1.0), M))
+    once = om.pileup(_pu_desc(N, np.convolve(g1, g2), 1.0), M)
+    np.testing.assert_allclose(twice, once, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# expected counts and the NLL
+# ---------------------------------------------------------------------------
+def test_rate_linearity():
+    d = synth.config1()
+    resp = d.theta_true[d.S:]
+    r1, r2 = np.array([1.0, 2, 3, 4]), np.array([5.0, -1, 0.5, 2])
+    mu = lambda r: om.forward(d, np.concatenate([r, resp])).mu["energy"]  # noqa
+    np.testing.assert_allclose(mu(2 * r1 + 3 * r2), 2 * mu(r1) + 3 * mu(r2), rtol=1e-12, atol=1e-12)
+
+
+def test_nll_matches_poisson_logpmf():
+    d, data = synth.load("c1")
+    mu = om.forward(d, d.theta_true).mu["energy"]
+    ref = -np.sum(stats.poisson.logpmf(data.energy, mu)) - np.sum(special.gammaln(data.energy + 1))
+    assert abs(oracle.nll(d, data, d.theta_true) - ref) < 1e-9 * abs(ref)
+    lnf = oracle.lnfact(d, data)
+    assert abs(oracle.nll(d, data, d.theta_true) + lnf + np.sum(stats.poisson.logpmf(data.energy, mu))) < 1e-6
+
+
+def test_nll_constant_mu_closed_form():
+    n = np.array([0.0, 3, 7, 1, 0, 12])
+    c = 2.5
+    t = om.nll_terms(np.full(6, c), n)
+    assert math.isclose(math.fsum(t), 6 * c - math.log(c) * n.sum(), rel_tol=1e-15)
+
+
+def test_nll_conventions():
+    assert list(om.nll_terms([0.0, 2.0], [0.0, 0.0])) == [0.0, 2.0]
+    with pytest.raises(om.DomainError):
+        om.nll_terms([0.0], [1.0])
+    with pytest.raises(om.DomainError):
+        om.nll_terms([-1e-3], [0.0])
+    with pytest.raises(om.DomainError):
+        om.nll_terms([np.nan], [0.0])
+
+
+@pytest.mark.parametrize("name", ["c1", "c3a"])
+def test_euler_identity_rates(name):
+    d, data = synth.load(name)
+    th = d.theta_true * 1.01
+    g = oracle.grad(d, data, th)
+    f = om.forward(d, th)
+    obs = om.observed(d, data)
+    lhs = float(th[: d.S] @ g[: d.S])
+    rhs = math.fsum(math.fsum((f.mu[k] - obs[k]).ravel()) for k in f.mu)
+    assert abs(lhs - rhs) < 1e-9 * math.fsum(math.fsum(np.abs(f.mu[k]).ravel()) for k in f.mu)
+
+
+def _richardson(fun, x, h):
+    D = lambda hh: (fun(x + hh) - fun(x - hh)) / (2 * hh)  # noqa
+    return (4 * D(h / 2) - D(h)) / 3
+
+
+@pytest.mark.parametrize("maker", ["gauss", "gg", "mv"])
+def test_gradient_vs_richardson(maker):
+    if maker == "gauss":
+        d = synth.config1()
+    elif maker == "gg":
+        d = tiny_gg(T=60, N=45)
+        d.pu_g, d.pu_frac = np.exp(-np.arange(6) / 2.0), 0.05
+    else:
+        d = synth.config3a()
+    th0 = d.theta_true * (1 + 0.02 * np.random.default_rng(7).standard_normal(d.P))
+    if d.multivariate:
+        data = synth.load("c3a")[1]
+    else:
+        data = poisson_data(d, d.theta_true)
+    g = oracle.grad(d, data, th0)
+    for q in range(d.P):
+        def f(v):
+            t = th0.copy()
+            t[q] = v
+            return oracle.nll(d, data, t)
+        fd = _richardson(f, th0[q], 1e-3 * abs(th0[q]))
+        assert abs(g[q] - fd) <= 1e-6 * max(abs(fd), 1e-3) + 1e-7, (q, g[q], fd)
+
+
+def test_gg_dF_dk_vs_mpmath_diff():
+    mp.mp.dps = 30
+    d = tiny_gg(T=3, N=6)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    dk = om._gg_dF_dk(d, cp)
+    for i in range(d.T):
+        for j, x in enumerate(d.reco_edges):
+            if x <= 0:
+                continue
+            y = (mp.mpf(x) / cp.a[i]) ** cp.p
+            ref = mp.diff(lambda kk: mp.gammainc(kk, 0, y, regularized=True), cp.k[i])
+            assert abs(dk[i, j] - float(ref)) < 1e-9 * max(1e-6, abs(float(ref)))
+
+
+def mp_tiny_nll(d, data, theta):
+    """The whole NLL of a tiny single-histogram model in 30-digit mpmath:
+    moment matching by findroot, cells by quadrature of the density,
+    contraction, pile-up and NLL as explicit sums."""
+    S, T, N = d.S, d.T, d.N
+    r = theta[:S]
+    resp = theta[S:]
+    E = [(mp.mpf(d.true_edges[i]) + mp.mpf(d.true_edges[i + 1])) / 2 for i in range(T)]
+    x = [mp.mpf(v) for v in d.reco_edges]
+    R = [[mp.mpf(0)] * T for _ in range(N)]
+    for i in range(T):
+        if d.kind == "gauss":
+            m, s = E[i], mp.sqrt(resp[0] * E[i] + resp[1] * E[i] ** 2)
+            dens = lambda u, m=m, s=s: mp.exp(-(u - m) ** 2 / (2 * s * s)) / (s * mp.sqrt(2 * mp.pi))  # noqa
+        else:
+            p = mp.mpf(d.gg_p)
+            m = resp[0] * mp.mpf(d.quench[i]) * E[i]
+            s2 = resp[1] + resp[2] * m + resp[3] * m * m
+            tau = mp.log(1 + s2 / m ** 2)
+            G = lambda k: mp.loggamma(k) + mp.loggamma(k + 2 / p) - 2 * mp.loggamma(k + 1 / p) - tau  # noqa
+            k = mp.findroot(G, mp.mpf(1) / (p * p * tau))
+            a = m * mp.exp(mp.loggamma(k) - mp.loggamma(k + 1 / p))
+
+            def dens(u, k=k, a=a, p=p):
+                if u <= 0:
+                    return mp.mpf(0)
+                return p * mp.exp((p * k - 1) * mp.log(u) - (u / a) ** p - p * k * mp.log(a) - mp.loggamma(k))
+        for j in range(N):
+            R[j][i] = mp.quad(dens, [max(x[j], 0) if d.kind != "gauss" else x[j], x[j + 1]])
+    F = [[mp.mpf(v) for v in row] for row in d.spectra]
+    F = [[v / mp.fsum(row) for v in row] for row in F]
+    mu0 = [mp.fsum(R[j][i] * mp.fsum(r[s] * F[s][i] for s in range(S)) for i in range(T))
+           for j in range(N)]
+    if d.pu_frac and d.pu_g is not None:
+        g = [mp.mpf(v) for v in d.pu_g]
+        gs = mp.fsum(g)
+        pf = mp.mpf(d.pu_frac)
+        mu = [(1 - pf) * mu0[j] + pf * mp.fsum(g[k] / gs * mu0[j - k] for k in range(len(g)) if j - k >= 0)
+              for j in range(N)]
+    else:
+        mu = mu0
+    n = [mp.mpf(v) for v in data.energy]
+    return mp.fsum(mu[j] - n[j] * mp.log(mu[j]) if n[j] > 0 else mu[j] for j in range(N))
+
+
+@pytest.mark.parametrize("kind", ["gauss", "gg"])
+def test_full_nll_and_gradient_vs_mpmath(kind):
+    mp.mp.dps = 30
+    if kind == "gauss":
+        d = tiny_gauss(T=4, N=5)
+    else:
+        d = tiny_gg(T=3, N=5)
+        d.pu_g, d.pu_frac = np.array([1.0, 0.5, 0.25]), 0.1
+    data = poisson_data(d, d.theta_true)
+    th = d.theta_true * 1.03
+    v, g = oracle.nll_grad(d, data, th)
+    thm = [mp.mpf(t) for t in th]
+    ref = mp_tiny_nll(d, data, thm)
+    assert abs(v - float(ref)) < 1e-12 * abs(float(ref))
+    for q in range(d.S, d.P):       # response parameters (the rates are linear)
+        def f(u, q=q):
+            t = list(thm)
+            t[q] = u
+            return mp_tiny_nll(d, data, t)
+        dref = float(mp.diff(f, thm[q], h=mp.mpf(th[q]) * mp.mpf("1e-8")))
+        assert abs(g[q] - dref) < 1e-8 * max(abs(dref), 1e-6), (q, g[q], dref)
+
+
+# ---------------------------------------------------------------------------
+# fits (workflow steps 5-7)
+# ---------------------------------------------------------------------------
+def test_single_species_fit_closed_form():
+    d = tiny_gauss(S=1, T=20, N=15)
+    data = poisson_data(d, d.theta_true)
+    mask = np.array([True, False, False])
+    res = oracle.fit(d, data, d.theta_true * np.array([1.3, 1, 1]), float_mask=mask)
+    Mp = oracle.per_species_expected(d, d.theta_true)[:, 0]
+    assert abs(res.theta[0] - data.energy.sum() / Mp.sum()) < 1e-9 * res.theta[0]
+
+
+@pytest.mark.slow
+def test_asimov_fit_recovers_truth_and_interior_sum():
+    d = synth.config1()
+    mu = om.forward(d, d.theta_true).mu["energy"]
+    asimov = synth.Data(energy=mu)
+    th0 = d.theta_true * np.array([1.1, 0.9, 1.05, 0.95, 1.2, 0.8])
+    res = oracle.fit(d, asimov, th0)
+    np.testing.assert_allclose(res.theta, d.theta_true, rtol=1e-8)
+    # Poisson data: at an interior optimum sum(mu) = sum(n)
+    d, data = synth.load("c1")
+    res = oracle.fit(d, data, th0)
+    muh = om.forward(d, res.theta).mu["energy"]
+    assert abs(muh.sum() - data.energy.sum()) < 1e-6 * data.energy.sum()
+    assert res.edm < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# multivariate terms (Eqs. 3-4)
+# ---------------------------------------------------------------------------
+def test_mv_zero_tagging_reduces_to_plain():
+    d, data = synth.load("c1")
+    m = d.copy()
+    m.tag_frac = np.zeros(d.S)
+    mdata = synth.Data(energy=data.energy, tagged=np.zeros(d.N))
+    assert oracle.nll(m, mdata, d.theta_true) == oracle.nll(d, data, d.theta_true)
+
+
+def test_mv_half_tagging_splits_evenly():
+    d = synth.config3a()
+    d.tag_frac = np.full(d.S, 0.5)
+    mu = om.forward(d, d.theta_true).mu
+    plain = om.forward(synth.config1(), d.theta_true).mu["energy"]
+    np.testing.assert_allclose(mu["energy"], plain / 2, rtol=1e-14)
+    np.testing.assert_allclose(mu["tagged"], plain / 2, rtol=1e-14)
+
+
+def test_mv_single_ps_bin_equals_vetoed_term():
+    d, data = synth.load("c3a")
+    d.ps_tmpl = np.ones((d.S, 1))
+    d.rad_tmpl = None
+    data.ps = data.energy[:, None].copy()
+    f = om.forward(d, d.theta_true)
+    np.testing.assert_allclose(f.mu["ps"][:, 0], f.mu["energy"], rtol=1e-14)
+
+
+def test_mv_brute_force_radial_and_ps():
+    d = synth.config3a()
+    d.rad_win = (20, 150)
+    rng = np.random.default_rng(11)
+    r = rng.uniform(1e3, 1e4, d.S)
+    Mp = rng.random((d.N, d.S))
+    mu = om.expected(d, Mp, r)
+    t, rho, Tps = d.tag_frac, d.rad_tmpl, d.ps_tmpl
+    for k in [0, 37, 99]:
+        acc = 0.0
+        for s in range(d.S):
+            acc += (1 - t[s]) * r[s] * sum(Mp[j, s] for j in range(20, 150)) * rho[s, k]
+        assert abs(mu["radial"][k] - acc) < 1e-12 * acc
+    for j in [0, 77, 199]:
+        for k in [0, 20, 49]:
+            acc = sum(Mp[j, s] * (1 - t[s]) * r[s] * Tps[s, k] for s in range(d.S))
+            assert abs(mu["ps"][j, k] - acc) < 1e-12 * acc
+    for j in [3, 150]:
+        assert abs(mu["tagged"][j] - sum(Mp[j, s] * t[s] * r[s] for s in range(d.S))) < 1e-9
