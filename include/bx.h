@@ -1,0 +1,207 @@
+/*
+ * bx.h -- C ABI of the MI355X spectral-fit likelihood library (libbx.so).
+ *
+ * The library evaluates, on one gfx950 GPU, the model that every step of a
+ * binned spectral fit repeats (Ding et al., arXiv:1805.11125):
+ *
+ *   - the deposited spectrum of every species folded with an analytic detector
+ *     response on the true x reco energy grid (Sec. 3, Eq. 1);
+ *   - the pile-up convolution with a random-trigger spectrum (Sec. 3, Eq. 2);
+ *   - the binned Poisson negative log-likelihood over the TFC-vetoed and
+ *     TFC-tagged energy histograms (Sec. 3, Eq. 3), plus the radial and
+ *     pulse-shape terms of the multivariate likelihood (Sec. 3, Eq. 4);
+ *   - its analytic gradient, and a quasi-Newton minimiser that varies the
+ *     parameters until the likelihood is optimal (Sec. 4, workflow steps 5-7).
+ *
+ * Conventions used by every call
+ *   - NLL = sum over all terms and bins of (mu - n ln mu).  The data-only
+ *     constant sum ln Gamma(n+1) is left out (see bx_model_lnfact).  A bin with
+ *     n = 0 contributes mu.  mu < 0, or mu = 0 with n > 0, is a domain error.
+ *   - Parameters theta = [r_0 .. r_{S-1} | response parameters]; r_s is the
+ *     expected number of events of species s over its whole deposited spectrum
+ *     (times the exposure).  Gaussian response: (a, b) with
+ *     sigma(E)^2 = a E + b E^2, mean E.  Generalized-gamma response with fixed
+ *     exponent p: (L, v0, v1, v2) with mean m = L Q(E) E and variance
+ *     s^2 = v0 + v1 m + v2 m^2, shape and scale moment-matched.
+ *   - The cell R[j][i] is the probability that an event deposited in true bin i
+ *     (at its centre) is reconstructed in reco bin [x_j, x_j+1).  Counts falling
+ *     outside [x_0, x_N) are lost.  A zero-width Gaussian puts all of its mass
+ *     in the reco bin holding its mean.
+ *   - Arrays are row-major and host memory unless a name says "dev".
+ *   - No C++ exception crosses this interface.  Every call returns a bx_status;
+ *     bx_last_error() gives a message for the calling thread.
+ *   - A bx_model is not thread-safe; a bx_server is (submit and poll).
+ */
+#ifndef BX_H
+#define BX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BX_OK = 0,
+  BX_PENDING = 1,        /* bx_fit_poll: the fit is still queued or running */
+  BX_E_INVAL = -1,       /* invalid argument (sizes, ordering, null pointers) */
+  BX_E_NOMEM = -2,       /* device memory could not be allocated */
+  BX_E_DEVICE = -3,      /* HIP runtime error or no usable GPU */
+  BX_E_DOMAIN = -4,      /* parameters outside the model's domain */
+  BX_E_BUSY = -5,        /* object in use, or request larger than the budget */
+  BX_E_NOTFOUND = -6     /* unknown ticket */
+} bx_status;
+
+typedef enum { BX_RESP_GAUSS = 0, BX_RESP_GG = 1 } bx_response;
+typedef enum { BX_PREC_F32 = 0, BX_PREC_F64 = 1 } bx_precision;
+
+/* Model description (Sec. 4, workflow step 2: spectra, response, dataset and
+ * likelihood terms).  All arrays are copied by bx_model_build. */
+typedef struct {
+  int32_t T;                  /* true-energy bins (>= 1) */
+  int32_t N;                  /* reco bins (>= 1) */
+  int32_t S;                  /* species (1..16) */
+  const double* true_edges;   /* [T+1] strictly increasing */
+  const double* reco_edges;   /* [N+1] strictly increasing */
+  const double* spectra;      /* [S][T] deposited spectra, >= 0, each row > 0
+                                 (normalised to unit sum in FP64 at build) */
+  int32_t response;           /* bx_response */
+  double gg_p;                /* GG exponent p > 0 (GG only) */
+  const double* quench;       /* [T] quenching factor at bin centres (GG only) */
+  double exposure;            /* > 0 */
+  int32_t pu_K;               /* random-trigger spectrum length, 0 = no pile-up */
+  const double* pu_g;         /* [pu_K] >= 0 with positive sum (normalised at build) */
+  double pu_frac;             /* pile-up fraction p in [0, 1]; needs uniform reco bins */
+  int32_t win_lo, win_hi;     /* fit window [win_lo, win_hi) over reco bins */
+  int32_t precision;          /* bx_precision of the response cells; sums are FP64 */
+  /* multivariate terms (Eqs. 3-4); multivariate = 0 ignores the rest */
+  int32_t multivariate;
+  const double* tag_frac;     /* [S] TFC tag fraction of each species, in [0, 1] */
+  int32_t n_rad;              /* radial bins (0..128; 0 = no radial term) */
+  const double* rad_tmpl;     /* [S][n_rad] radial template per species */
+  int32_t rad_lo, rad_hi;     /* reco window whose vetoed counts feed the radial term */
+  int32_t n_ps;               /* pulse-shape bins (0..64; 0 = no PS term) */
+  const double* ps_tmpl;      /* [S][n_ps] pulse-shape template per species */
+} bx_model_desc;
+
+/* Observed histograms (FP64 counts; integers or Asimov values >= 0). */
+typedef struct {
+  const double* energy;       /* [N] energy histogram (TFC-vetoed if multivariate) */
+  const double* tagged;       /* [N] TFC-tagged histogram (multivariate) */
+  const double* radial;       /* [n_rad] */
+  const double* ps;           /* [N][n_ps] energy x pulse-shape histogram */
+} bx_data;
+
+typedef struct bx_model bx_model;
+typedef struct bx_server bx_server;
+
+/* Build a model: validate, copy every array to device memory, allocate the
+ * evaluation workspace.  hip_stream: a hipStream_t the model uses for all of
+ * its work (borrowed), or NULL for a stream the model owns.
+ * Errors: BX_E_INVAL for bad sizes, non-increasing edges, negative spectra or
+ * all-zero rows, non-uniform reco bins with pile-up on, a window out of range;
+ * BX_E_NOMEM; BX_E_DEVICE.  On error *out is NULL. */
+bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* hip_stream,
+                         bx_model** out);
+
+/* Replace the observed histograms (same shapes).  Stream-ordered copy. */
+bx_status bx_model_set_data(bx_model* m, const bx_data* data);
+
+/* Release the model and its device memory.  BX_E_BUSY while a server fit uses it. */
+bx_status bx_model_free(bx_model* m);
+
+/* Number of parameters P = S + (2 Gaussian | 4 GG). */
+int32_t bx_model_nparams(const bx_model* m);
+
+/* Sum of ln Gamma(n+1) over every bin in the NLL (FP64, computed at build and
+ * on bx_model_set_data).  NLL + lnfact is the full negative log-likelihood. */
+bx_status bx_model_lnfact(const bx_model* m, double* out);
+
+/* NLL at theta[P] (host).  Synchronous.  Domain errors return BX_E_DOMAIN and
+ * *nll = +INFINITY (non-finite theta, sigma^2 < 0, GG mean or variance <= 0,
+ * mu < 0 or mu = 0 < n). */
+bx_status bx_nll_eval(bx_model* m, const double* theta, double* nll);
+
+/* NLL and its gradient grad[P] (host).  Synchronous.  Domain errors as for
+ * bx_nll_eval; the gradient is undefined (BX_E_DOMAIN) when some Gaussian
+ * width is exactly zero.  On BX_E_DOMAIN grad is left untouched. */
+bx_status bx_nll_grad(bx_model* m, const double* theta, double* nll, double* grad);
+
+/* Device-pointer variant for stream-ordered use (autograd): reads
+ * d_theta[P], writes d_out[0] = NLL (+INFINITY on a domain error) and
+ * d_out[1..P] = gradient.  stream: hipStream_t to run on (NULL = the model's).
+ * Asynchronous; the status describes the enqueue only. */
+bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, void* stream);
+
+/* Expected counts of every likelihood term at theta, for the full reco range:
+ * out = [mu_energy[N] | mu_tagged[N] | nu_radial[n_rad] | lambda_ps[N][n_ps]]
+ * (single histogram: mu[N] only).  bx_model_expected_size gives the length. */
+int64_t bx_model_expected_size(const bx_model* m);
+bx_status bx_model_expected(bx_model* m, const double* theta, double* out);
+
+/* Diagnostics: average duration (milliseconds) of each stage of one NLL +
+ * gradient evaluation at theta, over `reps` back-to-back evaluations launched
+ * one kernel at a time (no graph) on the model's stream and timed with HIP
+ * events there.  ms[9] = {column parameters, forward cell sweep + species
+ * contraction, partial-sum reduction, pile-up + likelihood terms, radial term,
+ * pile-up adjoint, backward cell sweep, final sums, whole evaluation}. */
+bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms);
+
+/* ---- fitting (Sec. 4, steps 5-7) ---- */
+typedef enum { BX_FIT = 0, BX_EVAL_GRAD = 1 } bx_request_kind;
+typedef enum { BX_CONVERGED = 0, BX_MAXITER = 1, BX_FAILED = 2 } bx_fit_status;
+
+typedef struct {
+  int32_t kind;            /* bx_request_kind */
+  const double* x0;        /* [P] start (FIT) or evaluation point (EVAL_GRAD) */
+  const uint8_t* float_mask; /* [P] 1 = varied, 0 = fixed; NULL = all varied */
+  const double* lo;        /* [P] lower bounds or NULL (rates default to 0) */
+  const double* hi;        /* [P] upper bounds or NULL (none) */
+  double edm_tol;          /* stop when EDM = g^T H^-1 g / 2 < edm_tol (<= 0: 1e-9) */
+  int32_t max_iter;        /* quasi-Newton iterations (<= 0: 500) */
+} bx_fit_opts;
+
+typedef struct {
+  int32_t status;          /* bx_fit_status */
+  double nll;
+  double x[32];            /* parameters at the end (first P used) */
+  double grad[32];         /* gradient at x */
+  double edm;
+  int32_t n_iter, n_eval;
+  int64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady-clock timestamps */
+} bx_fit_result;
+
+/* Plain path: fit one model on the calling thread (host BFGS, one device
+ * evaluation per step). */
+bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r);
+
+/* Fit server: admits requests while their device memory fits hbm_budget_bytes
+ * (0 = the device's free memory) and max_slots (<= 0: 4096), keeps each admitted
+ * fit's parameters, optimiser state and histograms resident, and advances
+ * every active fit by one quasi-Newton step per batched evaluation
+ * (continuous batching: fits join and leave at step boundaries).  The server
+ * owns a worker thread and its own stream (hip_stream NULL) or borrows one. */
+bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip_stream,
+                           bx_server** out);
+bx_status bx_server_destroy(bx_server* s);
+
+/* Queue a request on model m (borrowed until the ticket reaches a terminal
+ * state; the model's current data are copied at submission).  o is copied.
+ * BX_E_BUSY if the request can never fit the budget. */
+bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_t* ticket);
+
+/* Result of a ticket: BX_PENDING while running; BX_OK with *r filled once
+ * terminal (the ticket is then retired); BX_E_NOTFOUND otherwise. */
+bx_status bx_fit_poll(bx_server* s, uint64_t ticket, bx_fit_result* r);
+
+/* Block until every submitted ticket is terminal. */
+bx_status bx_server_drain(bx_server* s);
+
+/* Message of the last error on the calling thread (static storage). */
+const char* bx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BX_H */

@@ -353,3 +353,29 @@ def support_cells(desc, theta, eps=1e-30):
     """Number of cells with R[j, i] > eps (the work the method must do)."""
     f = forward(desc, theta)
     return int(np.count_nonzero(f.R > eps))
+
+
+def grad_scale(desc, data, theta):
+    """Magnitude scale of each gradient component: sum over bins of
+    |dmu_b/dq| (1 + n_b/mu_b), the size of the two terms that cancel in
+    dNLL/dq = sum (1 - n/mu) dmu/dq.  Gradient tolerances are relative to it
+    (the gradient itself goes to zero at the minimum)."""
+    f = forward(desc, theta)
+    obs = observed(desc, data)
+    a = {}
+    for key in f.mu:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a[key] = np.where(obs[key] > 0, 1.0 + obs[key] / f.mu[key], 1.0)
+
+    def contract(dmu):
+        return math.fsum(math.fsum((a[key] * np.abs(dmu[key])).ravel()) for key in a)
+
+    sc = np.zeros(desc.P)
+    for s in range(desc.S):
+        e = np.zeros(desc.S)
+        e[s] = 1.0
+        sc[s] = contract(expected(desc, f.Mp, e))
+    for q, dR in enumerate(response_param_derivs(desc, f.cp, f.resp)):
+        dMp = pileup(desc, contraction(desc, dR))
+        sc[desc.S + q] = contract(expected(desc, dMp, f.r))
+    return sc

@@ -1,0 +1,91 @@
+// Device-side data layout of one fit (model + data + per-evaluation
+// workspace).  All pointers are device pointers; a batch of fits is an array
+// of these in device memory, and every kernel takes (fits, active list) with
+// blockIdx.y selecting the fit, so one fit and a batch of thousands run the
+// same code with the same per-fit arithmetic.
+#pragma once
+#include <stdint.h>
+
+#include "bx_math.h"
+
+namespace bx {
+
+constexpr int kSP = 16;        // species padded to the MFMA width
+constexpr int kRowTile = 16;   // reco edges per tile (15 cells)
+constexpr int kRowStep = 15;   // cells per row tile
+constexpr int kColTile = 16;   // true bins per tile
+constexpr int kMaxResp = 4;    // response parameters (Gauss 2, GG 4)
+constexpr int kBlock = 256;    // threads per block (4 waves)
+
+enum : int { kGauss = 0, kGG = 1 };
+enum : int { kF32 = 0, kF64 = 1 };
+enum : int {                   // domain flags
+  kBadSigma = 1,               // Gaussian sigma^2 < 0
+  kBadGG = 2,                  // GG mean or variance <= 0, or shape out of range
+  kBadMu = 4,                  // an expected count < 0, or 0 with counts > 0
+  kBadTheta = 8,               // non-finite parameter
+  kZeroWidth = 16              // sigma = 0 somewhere: response derivative undefined
+};
+
+struct ColPar {
+  double c0;        // Gauss: m;        GG: ct = p ln a + ln k
+  double c1;        // Gauss: 1/sigma;  GG: k
+  double v;         // sum_s r_s F^_si  (expected deposited counts in true bin i)
+  float f32[8];     // GG edge constants (k, 1/k, sqrt(k/2), cR, ce, dlnG*, ln k - psi, p)
+  double f64[8];    // the same in FP64
+  double J[2][kMaxResp];  // d(c1, c2)/d(response parameter q)
+  int jlo, jhi;     // cells that may be non-zero (support)
+  int bad;          // domain flags
+  int pad;
+};
+
+struct FitDev {
+  // shape
+  int T, N, S, P, nresp, kind, prec, mv;
+  int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
+  int n_rt, n_ct, CG, n_cg, RG, n_rg, n_rowblk;
+  int pad0;
+  double pu_frac;
+  GGConst gg;
+  // inputs (device)
+  const double* xraw;   // [N+1] reco edges
+  const double* xe;     // [N+1] Gauss: edges; GG: ln edges (-inf at x <= 0)
+  const double* Ec;     // [T] true-bin centres
+  const double* Qt;     // [T] quenching (GG)
+  const float* F32;     // [T][16] exposure * normalised spectra
+  const double* F64;    // [T][16]
+  const double* ghat;   // [K] normalised random-trigger spectrum
+  const double* tag;    // [16] tag fractions
+  const double* rad;    // [16][n_rad]
+  const double* pst;    // [16][n_ps]
+  const double* n_e;    // [N] energy (vetoed) histogram
+  const double* n_t;    // [N] tagged
+  const double* n_r;    // [n_rad]
+  const double* n_p;    // [N][n_ps]
+  // per-evaluation state
+  const double* theta;  // [P]
+  ColPar* cp;           // [T]
+  int2* tb;             // [n_ct] support of each column tile (cells)
+  void* Mpart;          // [n_cg][N][16] R
+  double* M;            // [N][16]
+  double* Mp;           // [N][16] after pile-up
+  double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part
+  double* Ht;           // [N][16] pile-up adjoint of H
+  double* nllpart;      // [n_rowblk]
+  int* flagpart;        // [n_rowblk]
+  double* gpart;        // [n_rowblk][16] rate-gradient partials
+  double* rad_out;      // [2 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16]
+  double* abpart;       // [n_rg][T][2]
+  double* out;          // [2 + P]: nll, grad[P], flags
+};
+
+// Grid sizes of one batched launch (maxima over the fits in it).
+struct LaunchShape {
+  int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks;
+  int kind, prec, any_mv, any_rad;
+};
+void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
+                 bool with_grad, hipStream_t st, hipEvent_t* ev = nullptr);
+void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
+
+}  // namespace bx

@@ -1,0 +1,616 @@
+// Host runtime: validation, model placement in device memory, the C ABI of
+// the plain path (build / eval / grad / expected counts) and the plain
+// quasi-Newton fitter (Sec. 4, workflow steps 1-7 of the paper's package).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bx_model.hpp"
+#include "bx_fitcore.hpp"
+
+namespace bx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+bx_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return BX_E_DEVICE;
+}
+#define BX_HIP(call, what)                  \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+static bx_status inval(const std::string& m) {
+  set_error(m);
+  return BX_E_INVAL;
+}
+
+// ---------------------------------------------------------------------------
+// Stirling-series constants of the generalized gamma with exponent p:
+// ln Gamma(x + a) ~ (x + a - 1/2) ln x - x + ln sqrt(2 pi)
+//                   + sum_n (-1)^(n+1) B_{n+1}(a) / (n (n+1) x^n).
+// ---------------------------------------------------------------------------
+static void make_gg_const(double p, GGConst* c) {
+  long double bern[kSeriesTerms + 3];
+  bern[0] = 1.0L;
+  for (int n = 1; n < kSeriesTerms + 3; ++n) {  // sum_{k<=n} C(n+1, k) B_k = 0
+    long double s = 0.0L, binom = 1.0L;
+    for (int k = 0; k < n; ++k) {
+      s += binom * bern[k];
+      binom = binom * (n + 1 - k) / (k + 1);
+    }
+    bern[n] = -s / (n + 1);
+  }
+  auto bpoly = [&](int n, long double a) {  // Bernoulli polynomial B_n(a)
+    long double s = 0.0L, binom = 1.0L;
+    for (int k = 0; k <= n; ++k) {
+      s += binom * bern[k] * powl(a, n - k);
+      binom = binom * (n - k) / (k + 1);
+    }
+    return s;
+  };
+  c->p = p;
+  c->ip = 1.0 / p;
+  const long double a1 = 1.0L / p, a2 = 2.0L / p;
+  c->cG[0] = c->cD[0] = 0.0;
+  for (int n = 1; n <= kSeriesTerms; ++n) {
+    const long double sg = (n % 2 == 1) ? 1.0L : -1.0L, den = (long double)n * (n + 1);
+    c->cG[n] = (double)(sg * (bpoly(n + 1, 0) + bpoly(n + 1, a2) - 2 * bpoly(n + 1, a1)) / den);
+    c->cD[n] = (double)(sg * (bpoly(n + 1, a1) - bpoly(n + 1, 0)) / den);
+  }
+}
+
+Tiles choose_tiles(int T, int N, int kind, int prec) {
+  // Column tiles per forward wave and row tiles per backward wave.  The
+  // choice depends only on this fit's shape; an on-disk table written by the
+  // tuner (BX_TUNE_CACHE) overrides the defaults.
+  Tiles t{4, 4};
+  const char* path = getenv("BX_TUNE_CACHE");
+  if (path && *path) {
+    FILE* fp = fopen(path, "r");
+    if (fp) {
+      char line[256];
+      while (fgets(line, sizeof line, fp)) {
+        int k, pr, tmin, tmax, nmin, nmax, cg, rg;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d", &k, &pr, &tmin, &tmax, &nmin, &nmax, &cg, &rg) == 8 &&
+            k == kind && pr == prec && T >= tmin && T <= tmax && N >= nmin && N <= nmax && cg > 0 && rg > 0) {
+          t.CG = cg;
+          t.RG = rg;
+          break;
+        }
+      }
+      fclose(fp);
+    }
+  }
+  const char* ov = getenv("BX_TILES");  // "CG,RG" for sweeps
+  if (ov && *ov) {
+    int cg = 0, rg = 0;
+    if (sscanf(ov, "%d,%d", &cg, &rg) == 2 && cg > 0 && rg > 0) t = Tiles{cg, rg};
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+static bool finite_nonneg(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i]) || v[i] < 0.0) return false;
+  return true;
+}
+static bool increasing(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i]) || (i > 0 && !(v[i] > v[i - 1]))) return false;
+  return true;
+}
+
+bx_status set_host_data(HostModel* h, const bx_data* x) {
+  if (!x || !x->energy) return inval("data: energy histogram is NULL");
+  if (!finite_nonneg(x->energy, h->N)) return inval("data: energy counts must be finite and >= 0");
+  h->n_e.assign(x->energy, x->energy + h->N);
+  if (h->mv) {
+    if (!x->tagged || !finite_nonneg(x->tagged, h->N)) return inval("data: tagged histogram missing or invalid");
+    h->n_t.assign(x->tagged, x->tagged + h->N);
+    if (h->n_rad > 0) {
+      if (!x->radial || !finite_nonneg(x->radial, h->n_rad)) return inval("data: radial histogram missing or invalid");
+      h->n_r.assign(x->radial, x->radial + h->n_rad);
+    }
+    if (h->n_ps > 0) {
+      if (!x->ps || !finite_nonneg(x->ps, (size_t)h->N * h->n_ps)) return inval("data: PS histogram missing or invalid");
+      h->n_p.assign(x->ps, x->ps + (size_t)h->N * h->n_ps);
+    }
+  }
+  return BX_OK;
+}
+
+bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h) {
+  if (!d) return inval("desc is NULL");
+  if (d->T < 1 || d->N < 1 || d->S < 1 || d->S > kSP) return inval("need T >= 1, N >= 1, 1 <= S <= 16");
+  if ((int64_t)d->T * d->N > (int64_t)1 << 31) return inval("T x N too large");
+  if (!d->true_edges || !increasing(d->true_edges, d->T + 1)) return inval("true_edges must be finite and strictly increasing");
+  if (!d->reco_edges || !increasing(d->reco_edges, d->N + 1)) return inval("reco_edges must be finite and strictly increasing");
+  if (!d->spectra || !finite_nonneg(d->spectra, (size_t)d->S * d->T)) return inval("spectra must be finite and >= 0");
+  if (d->response != BX_RESP_GAUSS && d->response != BX_RESP_GG) return inval("unknown response kind");
+  if (d->precision != BX_PREC_F32 && d->precision != BX_PREC_F64) return inval("unknown precision");
+  if (!std::isfinite(d->exposure) || !(d->exposure > 0)) return inval("exposure must be > 0");
+  if (d->response == BX_RESP_GG) {
+    if (!std::isfinite(d->gg_p) || !(d->gg_p > 0.05) || d->gg_p > 20) return inval("gg_p must be in (0.05, 20]");
+    if (!d->quench) return inval("GG response needs the quenching table");
+    for (int i = 0; i < d->T; ++i)
+      if (!std::isfinite(d->quench[i]) || !(d->quench[i] > 0)) return inval("quench must be finite and > 0");
+  }
+  if (d->win_lo < 0 || d->win_hi > d->N || d->win_lo >= d->win_hi) return inval("fit window out of range");
+  if (d->pu_K < 0) return inval("pu_K < 0");
+  HostModel& m = *h;
+  m.T = d->T; m.N = d->N; m.S = d->S;
+  m.kind = d->response == BX_RESP_GAUSS ? kGauss : kGG;
+  m.nresp = m.kind == kGauss ? 2 : 4;
+  m.P = m.S + m.nresp;
+  m.prec = d->precision == BX_PREC_F32 ? kF32 : kF64;
+  m.win_lo = d->win_lo; m.win_hi = d->win_hi;
+  m.exposure = d->exposure;
+  m.p = m.kind == kGG ? d->gg_p : 1.0;
+  m.K = 0; m.pu_frac = 0.0;
+  if (d->pu_K > 0 && d->pu_frac != 0.0) {
+    if (!d->pu_g || !finite_nonneg(d->pu_g, d->pu_K)) return inval("pu_g must be finite and >= 0");
+    if (!std::isfinite(d->pu_frac) || d->pu_frac < 0 || d->pu_frac > 1) return inval("pu_frac must be in [0, 1]");
+    long double sg = 0.0L;
+    for (int k = 0; k < d->pu_K; ++k) sg += d->pu_g[k];
+    if (!(sg > 0)) return inval("pu_g has zero sum");
+    const double w0 = d->reco_edges[1] - d->reco_edges[0];
+    for (int j = 1; j < d->N; ++j) {
+      const double w = d->reco_edges[j + 1] - d->reco_edges[j];
+      if (std::fabs(w - w0) > 1e-9 * std::fabs(w0)) return inval("pile-up needs uniform reco bins");
+    }
+    m.K = d->pu_K;
+    m.pu_frac = d->pu_frac;
+    m.ghat.resize(m.K);
+    for (int k = 0; k < m.K; ++k) m.ghat[k] = (double)(d->pu_g[k] / sg);
+  }
+  m.mv = d->multivariate ? 1 : 0;
+  m.n_rad = m.n_ps = 0;
+  m.rad_lo = m.rad_hi = 0;
+  m.tag.assign(kSP, 0.0);
+  if (m.mv) {
+    if (!d->tag_frac) return inval("multivariate model needs tag_frac");
+    for (int s = 0; s < m.S; ++s) {
+      if (!std::isfinite(d->tag_frac[s]) || d->tag_frac[s] < 0 || d->tag_frac[s] > 1) return inval("tag_frac must be in [0, 1]");
+      m.tag[s] = d->tag_frac[s];
+    }
+    if (d->n_rad < 0 || d->n_rad > 128) return inval("n_rad must be in [0, 128]");
+    if (d->n_ps < 0 || d->n_ps > 64) return inval("n_ps must be in [0, 64]");
+    m.n_rad = d->n_rad;
+    m.n_ps = d->n_ps;
+    if (m.n_rad > 0) {
+      if (!d->rad_tmpl || !finite_nonneg(d->rad_tmpl, (size_t)m.S * m.n_rad)) return inval("rad_tmpl invalid");
+      if (d->rad_lo < 0 || d->rad_hi > m.N || d->rad_lo >= d->rad_hi) return inval("radial window out of range");
+      m.rad_lo = d->rad_lo; m.rad_hi = d->rad_hi;
+      m.rad.assign((size_t)kSP * m.n_rad, 0.0);
+      for (int s = 0; s < m.S; ++s)
+        for (int k = 0; k < m.n_rad; ++k) m.rad[s * m.n_rad + k] = d->rad_tmpl[s * m.n_rad + k];
+    }
+    if (m.n_ps > 0) {
+      if (!d->ps_tmpl || !finite_nonneg(d->ps_tmpl, (size_t)m.S * m.n_ps)) return inval("ps_tmpl invalid");
+      m.pst.assign((size_t)kSP * m.n_ps, 0.0);
+      for (int s = 0; s < m.S; ++s)
+        for (int k = 0; k < m.n_ps; ++k) m.pst[s * m.n_ps + k] = d->ps_tmpl[s * m.n_ps + k];
+    }
+  }
+  // grids
+  m.xraw.assign(d->reco_edges, d->reco_edges + m.N + 1);
+  m.xe.resize(m.N + 1);
+  for (int j = 0; j <= m.N; ++j)
+    m.xe[j] = m.kind == kGauss ? m.xraw[j] : (m.xraw[j] > 0 ? std::log(m.xraw[j]) : -INFINITY);
+  m.Ec.resize(m.T);
+  for (int i = 0; i < m.T; ++i) m.Ec[i] = 0.5 * (d->true_edges[i] + d->true_edges[i + 1]);
+  m.Qt.assign(m.T, 1.0);
+  if (m.kind == kGG) m.Qt.assign(d->quench, d->quench + m.T);
+  // spectra: unit rows (FP64), times exposure, species padded to 16
+  m.F64.assign((size_t)m.T * kSP, 0.0);
+  m.F32.assign((size_t)m.T * kSP, 0.f);
+  for (int s = 0; s < m.S; ++s) {
+    long double sum = 0.0L;
+    for (int i = 0; i < m.T; ++i) sum += d->spectra[(size_t)s * m.T + i];
+    if (!(sum > 0)) return inval("a spectrum row sums to zero");
+    for (int i = 0; i < m.T; ++i) {
+      const double v = m.exposure * (double)(d->spectra[(size_t)s * m.T + i] / sum);
+      m.F64[(size_t)i * kSP + s] = v;
+      m.F32[(size_t)i * kSP + s] = (float)v;
+    }
+  }
+  if (m.kind == kGG) make_gg_const(m.p, &m.gg);
+  else memset(&m.gg, 0, sizeof m.gg);
+  m.tiles = choose_tiles(m.T, m.N, m.kind, m.prec);
+  return set_host_data(h, x);
+}
+
+double host_lnfact(const HostModel& h) {
+  long double s = 0.0L;
+  for (int j = h.win_lo; j < h.win_hi; ++j) {
+    s += std::lgamma(h.n_e[j] + 1.0);
+    if (h.mv) s += std::lgamma(h.n_t[j] + 1.0);
+    if (h.mv && h.n_ps > 0)
+      for (int k = 0; k < h.n_ps; ++k) s += std::lgamma(h.n_p[(size_t)j * h.n_ps + k] + 1.0);
+  }
+  if (h.mv)
+    for (int k = 0; k < h.n_rad; ++k) s += std::lgamma(h.n_r[k] + 1.0);
+  return (double)s;
+}
+
+// ---------------------------------------------------------------------------
+// Device placement.
+// ---------------------------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+static void derive_tiles(const HostModel& h, FitDev* f) {
+  f->n_rt = (h.N + kRowStep - 1) / kRowStep;
+  f->n_ct = (h.T + kColTile - 1) / kColTile;
+  f->CG = h.tiles.CG;
+  f->RG = h.tiles.RG;
+  f->n_cg = (f->n_ct + f->CG - 1) / f->CG;
+  f->n_rg = (f->n_rt + f->RG - 1) / f->RG;
+  f->n_rowblk = (h.N + 15) / 16;
+}
+
+static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, double** out) {
+  Carver c{base};
+  derive_tiles(h, f);
+  const size_t rsz = h.prec == kF32 ? 4 : 8;
+  f->xraw = c.take<double>(h.N + 1);
+  f->xe = c.take<double>(h.N + 1);
+  f->Ec = c.take<double>(h.T);
+  f->Qt = c.take<double>(h.T);
+  f->F32 = c.take<float>((size_t)h.T * kSP);
+  f->F64 = c.take<double>((size_t)h.T * kSP);
+  f->ghat = c.take<double>(h.K);
+  f->tag = c.take<double>(kSP);
+  f->rad = c.take<double>((size_t)kSP * h.n_rad);
+  f->pst = c.take<double>((size_t)kSP * h.n_ps);
+  f->n_e = c.take<double>(h.N);
+  f->n_t = c.take<double>(h.N);
+  f->n_r = c.take<double>(h.n_rad);
+  f->n_p = c.take<double>((size_t)h.N * h.n_ps);
+  *theta = c.take<double>(h.P);
+  f->theta = *theta;
+  f->cp = c.take<ColPar>(h.T);
+  f->tb = c.take<int2>(f->n_ct);
+  f->Mpart = (void*)c.take<char>((size_t)f->n_cg * h.N * kSP * rsz);
+  f->M = c.take<double>((size_t)h.N * kSP);
+  f->Mp = c.take<double>((size_t)h.N * kSP);
+  f->H = c.take<double>((size_t)h.N * kSP);
+  f->Ht = c.take<double>((size_t)h.N * kSP);
+  f->nllpart = c.take<double>(f->n_rowblk);
+  f->flagpart = c.take<int>(f->n_rowblk);
+  f->gpart = c.take<double>((size_t)f->n_rowblk * kSP);
+  f->rad_out = c.take<double>(2 + 2 * kSP);
+  f->abpart = c.take<double>((size_t)f->n_rg * h.T * 2);
+  *out = c.take<double>(2 + h.P);
+  f->out = *out;
+  return (c.off + 255) & ~(size_t)255;
+}
+
+size_t device_fit_bytes(const HostModel& h) {
+  FitDev f{};
+  double *t, *o;
+  return carve(h, nullptr, &f, &t, &o);
+}
+
+LaunchShape shape_of(const FitDev& f) {
+  LaunchShape L;
+  L.max_T = f.T;
+  L.max_fwd_blocks = (f.n_rt * f.n_cg + 3) / 4;
+  L.max_NS = f.N * kSP;
+  L.max_rowblk = f.n_rowblk;
+  L.max_bwd_blocks = (f.n_ct * f.n_rg + 3) / 4;
+  L.kind = f.kind;
+  L.prec = f.prec;
+  L.any_mv = f.mv;
+  L.any_rad = f.mv && f.n_rad > 0;
+  return L;
+}
+
+template <class T>
+static hipError_t up(const T* dst, const std::vector<T>& v, hipStream_t st) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync((void*)dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st) {
+  BX_HIP(up(df.dev.n_e, h.n_e, st), "upload data");
+  BX_HIP(up(df.dev.n_t, h.n_t, st), "upload data");
+  BX_HIP(up(df.dev.n_r, h.n_r, st), "upload data");
+  BX_HIP(up(df.dev.n_p, h.n_p, st), "upload data");
+  return BX_OK;
+}
+
+bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st) {
+  FitDev& f = df->dev;
+  memset(&f, 0, sizeof f);
+  df->base = base;
+  df->bytes = carve(h, (char*)base, &f, &df->d_theta, &df->d_out);
+  f.T = h.T; f.N = h.N; f.S = h.S; f.P = h.P; f.nresp = h.nresp; f.kind = h.kind; f.prec = h.prec; f.mv = h.mv;
+  f.win_lo = h.win_lo; f.win_hi = h.win_hi; f.K = h.K; f.n_rad = h.n_rad; f.rad_lo = h.rad_lo;
+  f.rad_hi = h.rad_hi; f.n_ps = h.n_ps;
+  f.pu_frac = h.pu_frac;
+  f.gg = h.gg;
+  BX_HIP(up(f.xraw, h.xraw, st), "upload");
+  BX_HIP(up(f.xe, h.xe, st), "upload");
+  BX_HIP(up(f.Ec, h.Ec, st), "upload");
+  BX_HIP(up(f.Qt, h.Qt, st), "upload");
+  BX_HIP(up(f.F32, h.F32, st), "upload");
+  BX_HIP(up(f.F64, h.F64, st), "upload");
+  BX_HIP(up(f.ghat, h.ghat, st), "upload");
+  BX_HIP(up(f.tag, h.tag, st), "upload");
+  BX_HIP(up(f.rad, h.rad, st), "upload");
+  BX_HIP(up(f.pst, h.pst, st), "upload");
+  return upload_data(h, *df, st);
+}
+
+}  // namespace bx
+
+using namespace bx;
+
+// ---------------------------------------------------------------------------
+// Plain-path evaluation.
+// ---------------------------------------------------------------------------
+static bx_status capture(bx_model* m, bool grad, hipGraphExec_t* exec) {
+  hipGraph_t g;
+  BX_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
+  launch_eval(m->d_fit, m->d_active, 1, shape_of(m->df.dev), grad, m->cap_stream);
+  BX_HIP(hipStreamEndCapture(m->cap_stream, &g), "graph capture");
+  hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  return BX_OK;
+}
+
+static bx_status enqueue_eval(bx_model* m, bool grad, hipStream_t st) {
+  hipGraphExec_t* ex = grad ? &m->g_grad : &m->g_eval;
+  if (!*ex) {
+    bx_status s = capture(m, grad, ex);
+    if (s != BX_OK) return s;
+  }
+  BX_HIP(hipGraphLaunch(*ex, st), "graph launch");
+  return BX_OK;
+}
+
+namespace bx {
+// Evaluate at host theta; fills nll (and grad).  Shared with the plain fitter.
+bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad) {
+  const int P = m->h.P;
+  for (int q = 0; q < P; ++q)
+    if (!std::isfinite(theta[q])) {
+      *nll = INFINITY;
+      set_error("non-finite parameter");
+      return BX_E_DOMAIN;
+    }
+  double* hp = m->h_pin;
+  memcpy(hp, theta, P * sizeof(double));
+  BX_HIP(hipMemcpyAsync(m->df.d_theta, hp, P * sizeof(double), hipMemcpyHostToDevice, m->stream), "theta upload");
+  bx_status s = enqueue_eval(m, grad != nullptr, m->stream);
+  if (s != BX_OK) return s;
+  BX_HIP(hipMemcpyAsync(hp + P, m->df.d_out, (2 + P) * sizeof(double), hipMemcpyDeviceToHost, m->stream), "result download");
+  BX_HIP(hipStreamSynchronize(m->stream), "evaluation");
+  const double* o = hp + P;
+  const int fl = (int)o[1 + P];
+  const int hard = fl & (kBadSigma | kBadGG | kBadMu | kBadTheta);
+  if (hard || (grad && (fl & kZeroWidth))) {
+    *nll = hard ? INFINITY : o[0];
+    set_error(hard & kBadMu ? "expected count < 0, or 0 where counts > 0"
+              : hard ? "response parameters outside their domain"
+                     : "zero-width response: gradient undefined");
+    return BX_E_DOMAIN;
+  }
+  *nll = o[0];
+  if (grad) memcpy(grad, o + 1, P * sizeof(double));
+  return BX_OK;
+}
+}  // namespace bx
+
+extern "C" {
+
+const char* bx_last_error(void) { return bx::g_err.c_str(); }
+
+bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* hip_stream, bx_model** out) {
+  if (!out) return inval("out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    set_error("no HIP device");
+    return BX_E_DEVICE;
+  }
+  bx_model* m = new (std::nothrow) bx_model();
+  if (!m) return BX_E_NOMEM;
+  bx_status s = make_host_model(desc, data, &m->h);
+  if (s != BX_OK) {
+    delete m;
+    return s;
+  }
+  auto fail = [&](bx_status st) {
+    bx_model_free(m);
+    return st;
+  };
+  if (hipGetDevice(&m->device) != hipSuccess) return fail(hip_fail(hipErrorNoDevice, "hipGetDevice"));
+  if (hip_stream) {
+    m->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) return fail(BX_E_DEVICE);
+    m->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(BX_E_DEVICE);
+  const size_t bytes = device_fit_bytes(m->h);
+  void* base = nullptr;
+  if (hipMalloc(&base, bytes) != hipSuccess) {
+    set_error("hipMalloc of the model workspace failed");
+    return fail(BX_E_NOMEM);
+  }
+  s = place_fit(m->h, base, &m->df, m->stream);
+  if (s != BX_OK) return fail(s);
+  if (hipMalloc(&m->d_fit, sizeof(FitDev)) != hipSuccess || hipMalloc(&m->d_active, sizeof(int)) != hipSuccess)
+    return fail(BX_E_NOMEM);
+  const int zero = 0;
+  if (hipMemcpyAsync(m->d_fit, &m->df.dev, sizeof(FitDev), hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+      hipMemcpyAsync(m->d_active, &zero, sizeof(int), hipMemcpyHostToDevice, m->stream) != hipSuccess)
+    return fail(BX_E_DEVICE);
+  if (hipHostMalloc((void**)&m->h_pin, (2 * m->h.P + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(BX_E_NOMEM);
+  if (hipStreamSynchronize(m->stream) != hipSuccess) return fail(hip_fail(hipErrorUnknown, "model upload"));
+  m->lnfact = host_lnfact(m->h);
+  *out = m;
+  return BX_OK;
+}
+
+bx_status bx_model_set_data(bx_model* m, const bx_data* data) {
+  if (!m) return inval("model is NULL");
+  if (m->users.load() > 0) {
+    set_error("model in use by a server fit");
+    return BX_E_BUSY;
+  }
+  bx_status s = set_host_data(&m->h, data);
+  if (s != BX_OK) return s;
+  s = upload_data(m->h, m->df, m->stream);
+  if (s != BX_OK) return s;
+  BX_HIP(hipStreamSynchronize(m->stream), "data upload");
+  m->lnfact = host_lnfact(m->h);
+  return BX_OK;
+}
+
+bx_status bx_model_free(bx_model* m) {
+  if (!m) return BX_OK;
+  if (m->users.load() > 0) {
+    set_error("model in use by a server fit");
+    return BX_E_BUSY;
+  }
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  if (m->g_eval) (void)hipGraphExecDestroy(m->g_eval);
+  if (m->g_grad) (void)hipGraphExecDestroy(m->g_grad);
+  if (m->df.base) (void)hipFree(m->df.base);
+  if (m->d_fit) (void)hipFree(m->d_fit);
+  if (m->d_active) (void)hipFree(m->d_active);
+  if (m->h_pin) (void)hipHostFree(m->h_pin);
+  if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+  return BX_OK;
+}
+
+int32_t bx_model_nparams(const bx_model* m) { return m ? m->h.P : -1; }
+
+bx_status bx_model_lnfact(const bx_model* m, double* out) {
+  if (!m || !out) return inval("NULL argument");
+  *out = m->lnfact;
+  return BX_OK;
+}
+
+bx_status bx_nll_eval(bx_model* m, const double* theta, double* nll) {
+  if (!m || !theta || !nll) return inval("NULL argument");
+  return model_eval(m, theta, nll, nullptr);
+}
+
+bx_status bx_nll_grad(bx_model* m, const double* theta, double* nll, double* grad) {
+  if (!m || !theta || !nll || !grad) return inval("NULL argument");
+  return model_eval(m, theta, nll, grad);
+}
+
+bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, void* stream) {
+  if (!m || !d_theta || !d_out) return inval("NULL argument");
+  hipStream_t st = stream ? (hipStream_t)stream : m->stream;
+  const int P = m->h.P;
+  BX_HIP(hipMemcpyAsync(m->df.d_theta, d_theta, P * sizeof(double), hipMemcpyDeviceToDevice, st), "theta copy");
+  bx_status s = enqueue_eval(m, true, st);
+  if (s != BX_OK) return s;
+  BX_HIP(hipMemcpyAsync(d_out, m->df.d_out, (1 + P) * sizeof(double), hipMemcpyDeviceToDevice, st), "result copy");
+  return BX_OK;
+}
+
+int64_t bx_model_expected_size(const bx_model* m) {
+  if (!m) return -1;
+  const HostModel& h = m->h;
+  return h.mv ? 2 * (int64_t)h.N + h.n_rad + (int64_t)h.N * h.n_ps : h.N;
+}
+
+bx_status bx_model_expected(bx_model* m, const double* theta, double* out) {
+  if (!m || !theta || !out) return inval("NULL argument");
+  double nll;
+  bx_status s = model_eval(m, theta, &nll, nullptr);
+  if (s != BX_OK && s != BX_E_DOMAIN) return s;
+  const int64_t n = bx_model_expected_size(m);
+  double* d = nullptr;
+  BX_HIP(hipMallocAsync((void**)&d, n * sizeof(double), m->stream), "hipMallocAsync");
+  launch_expected(m->d_fit, d, m->h.N, m->h.mv ? m->h.n_rad : 0, m->h.mv ? m->h.n_ps : 0, m->stream);
+  BX_HIP(hipMemcpyAsync(out, d, n * sizeof(double), hipMemcpyDeviceToHost, m->stream), "download");
+  BX_HIP(hipFreeAsync(d, m->stream), "hipFreeAsync");
+  BX_HIP(hipStreamSynchronize(m->stream), "expected");
+  return s;
+}
+
+bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms) {
+  if (!m || !theta || !ms || reps < 1) return inval("bad argument");
+  double nll;
+  bx_status s = model_eval(m, theta, &nll, nullptr);  // uploads theta, warms up
+  if (s != BX_OK) return s;
+  hipEvent_t ev[9];
+  for (int k = 0; k < 9; ++k)
+    if (hipEventCreate(&ev[k]) != hipSuccess) return hip_fail(hipErrorUnknown, "hipEventCreate");
+  double acc[9] = {0};
+  const LaunchShape L = shape_of(m->df.dev);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    launch_eval(m->d_fit, m->d_active, 1, L, true, m->stream, ev);
+    e = hipEventSynchronize(ev[8]);
+    for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      acc[k] += t;
+    }
+    float tt = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&tt, ev[0], ev[8]);
+    acc[8] += tt;
+  }
+  for (int k = 0; k < 9; ++k) (void)hipEventDestroy(ev[k]);
+  if (e != hipSuccess) return hip_fail(e, "stage timing");
+  for (int k = 0; k < 9; ++k) ms[k] = acc[k] / reps;
+  return BX_OK;
+}
+
+bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r) {
+  if (!m || !o || !r || !o->x0) return inval("NULL argument");
+  const int P = m->h.P;
+  if (P > 32) return inval("too many parameters");
+  FitProblem pb;
+  bx_status s = fit_problem(P, m->h.S, o, &pb);
+  if (s != BX_OK) return s;
+  memset(r, 0, sizeof *r);
+  const auto t0 = std::chrono::steady_clock::now().time_since_epoch();
+  r->t_submit_ns = r->t_admit_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t0).count();
+  Bfgs opt(pb);
+  double x[32], f = 0.0, g[32];
+  while (opt.next(x)) {
+    const bx_status e = model_eval(m, x, &f, g);
+    if (e != BX_OK && e != BX_E_DOMAIN) return e;
+    opt.feed(e == BX_OK ? f : INFINITY, g);
+  }
+  opt.result(r);
+  const auto t1 = std::chrono::steady_clock::now().time_since_epoch();
+  r->t_done_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t1).count();
+  return BX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+// HIP kernels of one likelihood evaluation (gfx950, wave64).
+//
+//   k_colparams   per true bin: response column parameters, support, chain
+//                 factors to the response parameters (Eq. 1's R_x(N_x, E; p)).
+//   k_cells_fwd   per (reco tile, group of true tiles): CDF at 16 shared reco
+//                 edges x 16 true bins, cells by differencing neighbour lanes,
+//                 fed straight into MFMA 16x16x4 as A with the species
+//                 spectra as B: M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).
+//                 Cells never touch HBM.
+//   k_reduce_M    FP64 sum of the per-group partials in a fixed order.
+//   k_rowterms    pile-up M' = (1-p) M + p g^*M (Eq. 2), expected counts of
+//                 every likelihood term per reco row (Eqs. 3-4), Poisson NLL
+//                 terms, the adjoint weights H and per-block partials.
+//   k_radial      radial term (Eq. 4) -- one block per fit.
+//   k_adjoint     H~ = P^T H (the pile-up adjoint).
+//   k_cells_bwd   per (true tile, group of reco tiles): the same CDF sweep
+//                 with d/d(column parameters); accumulates
+//                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
+//                 W_ji = sum_s H~_js r_s F^_si.
+//   k_final       fixed-order sums: NLL, rate gradient, response gradient.
+//
+// No reduction uses atomics: every sum has a fixed order, so a fit's result
+// does not depend on what else runs in the same launch.
+#include <hip/hip_runtime.h>
+
+#include "bx_dev.h"
+
+namespace bx {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float dpp_from_next(float x) {
+  // lane l receives lane l+1 of its 16-lane row (row_shl:1); lane 15 keeps x
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x101, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dpp_from_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x101, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x101, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
+}
+
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <class R> struct Acc4;
+template <> struct Acc4<float> { typedef v4f T; };
+template <> struct Acc4<double> { typedef v4d T; };
+
+// Conservative cell range [jlo, jhi] holding every cell that can exceed
+// exp(-B) of the column's mass, from the x-interval [xlo, xhi].
+__device__ int2 cell_range(const double* x, int N, double xlo, double xhi) {
+  // first j with x[j+1] > xlo
+  int lo = 0, hi = N;  // search over edges 1..N
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid + 1] > xlo) hi = mid; else lo = mid + 1;
+  }
+  const int jlo = lo;
+  lo = 0; hi = N;      // number of edges x[j] < xhi among 0..N-1
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] < xhi) lo = mid + 1; else hi = mid;
+  }
+  const int jhi = lo - 1;
+  return make_int2(max(jlo - 1, 0), min(jhi + 1, N - 1));
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_colparams(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  int jlo = 1 << 30, jhi = -1;
+  if (i < f.T) {
+    ColPar c;
+    c.bad = 0;
+    const double* th = f.theta;
+    double v = 0.0;
+    for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
+    c.v = v;
+    for (int q = 0; q < kMaxResp; ++q) c.J[0][q] = c.J[1][q] = 0.0;
+    const double E = f.Ec[i];
+    bool okth = true;
+    for (int q = 0; q < f.P; ++q) okth = okth && isfinite(th[q]);
+    if (!okth) c.bad |= kBadTheta;
+    if (f.kind == kGauss) {
+      const double a = th[f.S], b = th[f.S + 1];
+      const double var = a * E + b * E * E;
+      if (!(var >= 0.0)) c.bad |= kBadSigma;
+      const double sig = sqrt(fmax(var, 0.0));
+      c.c0 = E;
+      c.c1 = sig > 0.0 ? 1.0 / sig : 0.0;
+      if (sig > 0.0) {
+        c.J[1][0] = E / (2.0 * sig);
+        c.J[1][1] = E * E / (2.0 * sig);
+      } else {
+        c.bad |= kZeroWidth;
+      }
+      const double zb = sqrt(2.0 * kSupportB);
+      const int2 r = cell_range(f.xraw, f.N, E - zb * sig, E + zb * sig);
+      jlo = r.x; jhi = r.y;
+    } else {
+      const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
+      const double m = L * f.Qt[i] * E;
+      const double s2 = v0 + v1 * m + v2 * m * m;
+      if (!(m > 0.0) || !(s2 > 0.0)) {
+        c.bad |= kBadGG;
+        c.c0 = 0.0; c.c1 = 1.0;
+        for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
+      } else {
+        const double tau = log1p(s2 / (m * m));
+        const double k = gg_solve_k(f.gg, tau, nullptr);
+        if (!(k > 1e-300) || !(k < 1e12)) c.bad |= kBadGG;
+        const GGShape sh = gg_shape(f.gg, k, true);
+        const double p = f.gg.p;
+        const double lna = log(m) - sh.D1;
+        const double lnk = log(k);
+        c.c0 = p * lna + lnk;
+        c.c1 = k;
+        const double cR = exp(-sh.lngs) / sqrt(kTwoPi * k);
+        const double cst[8] = {k, 1.0 / k, sqrt(0.5 * k), cR, 0.5 / sqrt(kTwoPi * k), sh.dlngs, lnk - sh.psi, p};
+        for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
+        // chain factors d(k, ln a)/d(L, v0, v1, v2)
+        for (int q = 0; q < 4; ++q) {
+          const double dm = (q == 0) ? m / L : 0.0;
+          const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + (v1 + 2.0 * v2 * m) * dm;
+          const double dtau = (ds2 / (m * m) - 2.0 * s2 * dm / (m * m * m)) / (1.0 + s2 / (m * m));
+          const double dk = dtau / sh.dG;
+          c.J[0][q] = dk;
+          c.J[1][q] = dm / m - sh.dD1 * dk;
+        }
+        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p)
+        const double cb = kSupportB / k;
+        double th_ = cb > 2.0 ? log1p(cb) + log1p(log1p(cb)) : sqrt(2.0 * cb);
+        for (int it = 0; it < 40; ++it) {
+          const double e = expm1(th_);
+          const double d = (e - th_ - cb) / e;
+          th_ -= d;
+          if (fabs(d) < 1e-12 * fmax(1.0, th_)) break;
+        }
+        double tl = -(1.0 + cb);
+        for (int it = 0; it < 40; ++it) {
+          const double e = expm1(tl);
+          const double d = (e - tl - cb) / e;
+          tl -= d;
+          if (fabs(d) < 1e-12 * fmax(1.0, -tl)) break;
+        }
+        const double xlo = exp((c.c0 + tl) / p), xhi = exp((c.c0 + th_) / p);
+        const int2 r = cell_range(f.xraw, f.N, xlo, xhi);
+        jlo = r.x; jhi = r.y;
+      }
+    }
+    if (c.bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
+    c.jlo = jlo; c.jhi = jhi; c.pad = 0;
+    f.cp[i] = c;
+  }
+  // support of each 16-column tile
+  for (int m = 8; m >= 1; m >>= 1) {
+    jlo = min(jlo, __shfl_xor(jlo, m, 16));
+    jhi = max(jhi, __shfl_xor(jhi, m, 16));
+  }
+  if ((threadIdx.x & 15) == 0 && i < f.T) f.tb[i >> 4] = make_int2(jlo, jhi);
+}
+
+// Edge evaluation for one lane.
+template <class R, int KIND, bool D>
+__device__ __forceinline__ EdgeVal<R> edge_at(const FitDev& f, const ColPar& c, double xe) {
+  if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
+  GGCol<R> g;
+  const float* s = c.f32;
+  const double* d = c.f64;
+  g.ct = c.c0;
+  if (sizeof(R) == 4) {
+    g.k = (R)s[0]; g.ik = (R)s[1]; g.skh = (R)s[2]; g.cR = (R)s[3]; g.ce = (R)s[4];
+    g.dlngs = (R)s[5]; g.lnk_psi = (R)s[6]; g.p = (R)s[7];
+  } else {
+    g.k = (R)d[0]; g.ik = (R)d[1]; g.skh = (R)d[2]; g.cR = (R)d[3]; g.ce = (R)d[4];
+    g.dlngs = (R)d[5]; g.lnk_psi = (R)d[6]; g.p = (R)d[7];
+  }
+  return gg_edge<R, D>(xe, g);
+}
+
+// ---------------------------------------------------------------------------
+template <class R, int KIND>
+__global__ void __launch_bounds__(kBlock) k_cells_fwd(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int rt = wave / f.n_cg, cg = wave % f.n_cg;
+  if (rt >= f.n_rt) return;
+  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int j0 = rt * kRowStep;
+  const int je = min(j0 + jr, f.N);
+  const double xe = f.xe[je];
+  const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
+  const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
+  typename Acc4<R>::T acc = {0, 0, 0, 0};
+  const int ct_end = min((cg + 1) * f.CG, f.n_ct);
+  for (int ct = cg * f.CG; ct < ct_end; ++ct) {
+    const int2 b = f.tb[ct];
+    if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ct * kColTile + 4 * q + g;
+      const bool iok = i < f.T;
+      const ColPar& c = f.cp[iok ? i : f.T - 1];
+      const EdgeVal<R> ev = edge_at<R, KIND, false>(f, c, xe);
+      const R hi = dpp_from_next(ev.v);
+      const R a = (row_ok && iok) ? cell_from(ev.v, hi) : (R)0;
+      const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
+      acc = mfma16(a, bb, acc);
+    }
+  }
+  R* out = (R*)f.Mpart + (size_t)cg * f.N * kSP;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    // result layout of MFMA 16x16x4: lane l, register r holds row 4(l/16) + r
+    // (f32) or row l/16 + 4r (f64), column l%16
+    const int row = sizeof(R) == 4 ? 4 * g + r : g + 4 * r;
+    if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= f.N * kSP) return;
+  const R* p = (const R*)f.Mpart + t;
+  const size_t stride = (size_t)f.N * kSP;
+  double s = 0.0;
+  for (int cg = 0; cg < f.n_cg; ++cg) s += (double)p[cg * stride];
+  f.M[t] = s;
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sum16(double x) {  // fixed-order sum over a 16-lane row
+  x += __shfl_xor(x, 8, 16);
+  x += __shfl_xor(x, 4, 16);
+  x += __shfl_xor(x, 2, 16);
+  x += __shfl_xor(x, 1, 16);
+  return x;
+}
+
+__device__ __forceinline__ double nll_term(double mu, double n, double* w, int* bad) {
+  if (!(mu >= 0.0) || (mu == 0.0 && n > 0.0) || !isfinite(mu)) {
+    *bad |= kBadMu;
+    *w = 0.0;
+    return 0.0;
+  }
+  if (n > 0.0) {
+    *w = 1.0 - n / mu;
+    return mu - n * log(mu);
+  }
+  *w = 1.0;
+  return mu;
+}
+
+// 16 rows x 16 species per block.
+__global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  if ((int)blockIdx.x >= f.n_rowblk) return;
+  __shared__ double mp[16][kSP];
+  __shared__ double red[kBlock];
+  __shared__ int redf[kBlock];
+  __shared__ double wps[16][64];
+  const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
+  const int j = blockIdx.x * 16 + rl;
+  const bool jok = j < f.N;
+  double m = 0.0;
+  if (jok) {
+    m = f.M[j * kSP + s];
+    if (f.K > 0 && f.pu_frac != 0.0) {
+      double acc = 0.0;
+      const int kmax = min(j, f.K - 1);
+      for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * f.M[(j - k) * kSP + s];
+      m = (1.0 - f.pu_frac) * m + f.pu_frac * acc;
+    }
+    f.Mp[j * kSP + s] = m;
+  }
+  mp[rl][s] = m;
+  __syncthreads();
+  const double* th = f.theta;
+  const double r_s = s < f.S ? th[s] : 0.0;
+  const bool inwin = jok && j >= f.win_lo && j < f.win_hi;
+  double term = 0.0, h = 0.0;
+  int bad = 0;
+  if (!f.mv) {
+    const double mu = sum16(m * r_s);
+    double w = 0.0;
+    if (inwin) {
+      const double t = nll_term(mu, f.n_e[j], &w, &bad);
+      if (s == 0) term = t;
+    }
+    h = w;
+  } else {
+    const double t_s = s < f.S ? f.tag[s] : 0.0;
+    const double musub = sum16(m * (1.0 - t_s) * r_s);
+    const double mutag = sum16(m * t_s * r_s);
+    double wsub = 0.0, wtag = 0.0;
+    if (inwin) {
+      const double t1 = nll_term(musub, f.n_e[j], &wsub, &bad);
+      const double t2 = nll_term(mutag, f.n_t[j], &wtag, &bad);
+      if (s == 0) term = t1 + t2;
+    }
+    // pulse-shape row j: lambda_jk = sum_s M'_js (1 - t_s) r_s T_sk
+    for (int k = s; k < f.n_ps; k += 16) {
+      double w = 0.0;
+      if (inwin) {
+        double lam = 0.0;
+        for (int u = 0; u < f.S; ++u) lam += mp[rl][u] * (1.0 - f.tag[u]) * th[u] * f.pst[u * f.n_ps + k];
+        term += nll_term(lam, f.n_p[(size_t)j * f.n_ps + k], &w, &bad);
+      }
+      wps[rl][k] = w;
+    }
+    __syncthreads();
+    double hps = 0.0;
+    if (s < f.S)
+      for (int k = 0; k < f.n_ps; ++k) hps += wps[rl][k] * f.pst[s * f.n_ps + k];
+    // H_js = w_sub (1 - t_s) + w_tag t_s + (1 - t_s) sum_k w_ps,jk T_sk
+    h = wsub * (1.0 - t_s) + wtag * t_s + (1.0 - t_s) * hps;
+  }
+  if (jok) f.H[j * kSP + s] = (s < f.S) ? h : 0.0;
+  // block partials: NLL (fixed tree), flags, rate gradient sum_j H_js M'_js
+  __syncthreads();
+  red[threadIdx.x] = term;
+  redf[threadIdx.x] = bad;
+  __syncthreads();
+  for (int st = kBlock / 2; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[threadIdx.x] += red[threadIdx.x + st];
+      redf[threadIdx.x] |= redf[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    f.nllpart[blockIdx.x] = red[0];
+    f.flagpart[blockIdx.x] = redf[0];
+  }
+  __syncthreads();
+  red[threadIdx.x] = (jok && s < f.S) ? h * m : 0.0;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double a = 0.0;
+    for (int r = 0; r < 16; ++r) a += red[r * 16 + threadIdx.x];
+    f.gpart[blockIdx.x * kSP + threadIdx.x] = a;
+  }
+}
+
+// Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
+__global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  __shared__ double part[16][kSP];
+  __shared__ double SW[kSP], A[kSP], wr[128], red[kBlock];
+  __shared__ int redf[kBlock];
+  const int s = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  double acc = 0.0;
+  for (int j = f.rad_lo + grp; j < f.rad_hi; j += 16) acc += f.Mp[j * kSP + s];
+  part[grp][s] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double t = 0.0;
+    for (int g = 0; g < 16; ++g) t += part[g][threadIdx.x];
+    SW[threadIdx.x] = t;
+    A[threadIdx.x] = threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * t : 0.0;
+  }
+  __syncthreads();
+  double term = 0.0;
+  int bad = 0;
+  for (int k = threadIdx.x; k < f.n_rad; k += kBlock) {
+    double nu = 0.0;
+    for (int u = 0; u < f.S; ++u) nu += A[u] * f.rad[u * f.n_rad + k];
+    double w;
+    term += nll_term(nu, f.n_r[k], &w, &bad);
+    if (k < 128) wr[k] = w;
+  }
+  red[threadIdx.x] = term;
+  redf[threadIdx.x] = bad;
+  __syncthreads();
+  for (int st = kBlock / 2; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[threadIdx.x] += red[threadIdx.x + st];
+      redf[threadIdx.x] |= redf[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 16) {
+    double rw = 0.0;
+    if ((int)threadIdx.x < f.S)
+      for (int k = 0; k < f.n_rad; ++k) rw += wr[k] * f.rad[threadIdx.x * f.n_rad + k];
+    f.rad_out[2 + threadIdx.x] = rw;
+    f.rad_out[2 + 16 + threadIdx.x] = (threadIdx.x < (unsigned)f.S) ? (1.0 - f.tag[threadIdx.x]) * SW[threadIdx.x] * rw : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    f.rad_out[0] = red[0];
+    f.rad_out[1] = (double)redf[0];
+  }
+}
+
+// H~ = P^T H_tot, H_tot = H + [j in W](1 - t_s) rho.w_s.
+__global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= f.N * kSP) return;
+  const int j = t >> 4, s = t & 15;
+  const bool rad = f.mv && f.n_rad > 0 && s < f.S;
+  const double radw = rad ? (1.0 - f.tag[s]) * f.rad_out[2 + s] : 0.0;
+  auto htot = [&](int jj) {
+    return f.H[jj * kSP + s] + ((rad && jj >= f.rad_lo && jj < f.rad_hi) ? radw : 0.0);
+  };
+  double h = htot(j);
+  if (f.K > 0 && f.pu_frac != 0.0) {
+    double acc = 0.0;
+    const int kmax = min(f.K - 1, f.N - 1 - j);
+    for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * htot(j + k);
+    h = (1.0 - f.pu_frac) * h + f.pu_frac * acc;
+  }
+  f.Ht[t] = h;
+}
+
+// ---------------------------------------------------------------------------
+template <class R, int KIND>
+__global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int ct = wave / f.n_rg, rg = wave % f.n_rg;
+  if (ct >= f.n_ct) return;
+  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int2 b = f.tb[ct];
+  double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
+  const int rt_end = min((rg + 1) * f.RG, f.n_rt);
+  for (int rt = rg * f.RG; rt < rt_end; ++rt) {
+    const int j0 = rt * kRowStep;
+    if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
+    const int je = min(j0 + jr, f.N);
+    const double xe = f.xe[je];
+    const int j = j0 + jr;
+    const bool row_ok = (jr < kRowStep) && (j < f.N);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ct * kColTile + 4 * q + g;
+      const bool iok = i < f.T;
+      const ColPar& c = f.cp[iok ? i : f.T - 1];
+      const EdgeVal<R> ev = edge_at<R, KIND, true>(f, c, xe);
+      const R d1h = dpp_from_next(ev.d1);
+      const R d2h = dpp_from_next(ev.d2);
+      if (row_ok && iok) {
+        double W;
+        if (!f.mv) {
+          W = f.Ht[j * kSP] * c.v;
+        } else {
+          W = 0.0;
+          for (int s = 0; s < f.S; ++s) W += f.Ht[j * kSP + s] * f.theta[s] * f.F64[i * kSP + s];
+        }
+        aA[q] += W * (double)(d1h - ev.d1);
+        aB[q] += W * (double)(d2h - ev.d2);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double A = sum16(aA[q]), B = sum16(aB[q]);
+    const int i = ct * kColTile + 4 * q + g;
+    if (jr == 0 && i < f.T) {
+      f.abpart[((size_t)rg * f.T + i) * 2 + 0] = A;
+      f.abpart[((size_t)rg * f.T + i) * 2 + 1] = B;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  __shared__ double red[kMaxResp][1024];
+  __shared__ int redf[1024];
+  double g[kMaxResp] = {0, 0, 0, 0};
+  int bad = 0;
+  for (int i = threadIdx.x; i < f.T; i += 1024) {
+    const ColPar& c = f.cp[i];
+    bad |= c.bad;
+    if (with_grad) {
+      double A = 0.0, B = 0.0;
+      for (int rg = 0; rg < f.n_rg; ++rg) {
+        A += f.abpart[((size_t)rg * f.T + i) * 2 + 0];
+        B += f.abpart[((size_t)rg * f.T + i) * 2 + 1];
+      }
+      for (int q = 0; q < f.nresp; ++q) g[q] += A * c.J[0][q] + B * c.J[1][q];
+    }
+  }
+  for (int q = 0; q < kMaxResp; ++q) red[q][threadIdx.x] = g[q];
+  redf[threadIdx.x] = bad;
+  __syncthreads();
+  for (int st = 512; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      for (int q = 0; q < kMaxResp; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+      redf[threadIdx.x] |= redf[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double nll = 0.0;
+    int fl = redf[0];
+    for (int b = 0; b < f.n_rowblk; ++b) {
+      nll += f.nllpart[b];
+      fl |= f.flagpart[b];
+    }
+    if (f.mv && f.n_rad > 0) {
+      nll += f.rad_out[0];
+      fl |= (int)f.rad_out[1];
+    }
+    if (!with_grad) fl &= ~kZeroWidth;
+    f.out[0] = (fl & ~kZeroWidth) ? INFINITY : nll;
+    f.out[1 + f.P] = (double)fl;
+    for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = red[q][0];
+  }
+  if (threadIdx.x < 16 && (int)threadIdx.x < f.S) {
+    double a = 0.0;
+    for (int b = 0; b < f.n_rowblk; ++b) a += f.gpart[b * kSP + threadIdx.x];
+    if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + threadIdx.x];
+    f.out[1 + threadIdx.x] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequence of one evaluation for the fits in `active` (n of them);
+// `shape` holds the per-launch grid sizes (maxima over the batch).
+
+
+void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
+                 bool with_grad, hipStream_t st, hipEvent_t* ev) {
+  const dim3 blk(kBlock);
+  // ev (optional): events recorded before each stage; stages are
+  // 0 colparams, 1 cells_fwd, 2 reduce_M, 3 rowterms, 4 radial, 5 adjoint,
+  // 6 cells_bwd, 7 final, 8 end
+  auto mark = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  };
+  mark(0);
+  hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kBlock - 1) / kBlock, n), blk, 0, st, d_fits, d_active);
+  const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), gr((L.max_NS + kBlock - 1) / kBlock, n);
+  mark(1);
+  if (L.prec == kF32) {
+    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, blk, 0, st, d_fits, d_active);
+    else hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, blk, 0, st, d_fits, d_active);
+    mark(2);
+    hipLaunchKernelGGL(k_reduce_M<float>, gr, blk, 0, st, d_fits, d_active);
+  } else {
+    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, blk, 0, st, d_fits, d_active);
+    else hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, blk, 0, st, d_fits, d_active);
+    mark(2);
+    hipLaunchKernelGGL(k_reduce_M<double>, gr, blk, 0, st, d_fits, d_active);
+  }
+  mark(3);
+  hipLaunchKernelGGL(k_rowterms, dim3(L.max_rowblk, n), blk, 0, st, d_fits, d_active);
+  mark(4);
+  if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
+  mark(5);
+  if (with_grad) {
+    hipLaunchKernelGGL(k_adjoint, gr, blk, 0, st, d_fits, d_active);
+  }
+  mark(6);
+  if (with_grad) {
+    if (L.prec == kF32) {
+      if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_bwd<float, kGauss>), gb, blk, 0, st, d_fits, d_active);
+      else hipLaunchKernelGGL((k_cells_bwd<float, kGG>), gb, blk, 0, st, d_fits, d_active);
+    } else {
+      if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_bwd<double, kGauss>), gb, blk, 0, st, d_fits, d_active);
+      else hipLaunchKernelGGL((k_cells_bwd<double, kGG>), gb, blk, 0, st, d_fits, d_active);
+    }
+  }
+  mark(7);
+  hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+  mark(8);
+}
+
+
+// Expected counts of every term over the full reco range (diagnostics):
+// out = [mu_energy[N] | mu_tagged[N] | nu[n_rad] | lambda[N][n_ps]].
+__global__ void __launch_bounds__(kBlock) k_expected(const FitDev* fits, double* out) {
+  const FitDev& f = fits[0];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const double* th = f.theta;
+  if (!f.mv) {
+    if (t < f.N) {
+      double mu = 0.0;
+      for (int s = 0; s < f.S; ++s) mu += f.Mp[t * kSP + s] * th[s];
+      out[t] = mu;
+    }
+    return;
+  }
+  if (t < f.N) {
+    double a = 0.0, b = 0.0;
+    for (int s = 0; s < f.S; ++s) {
+      a += f.Mp[t * kSP + s] * (1.0 - f.tag[s]) * th[s];
+      b += f.Mp[t * kSP + s] * f.tag[s] * th[s];
+    }
+    out[t] = a;
+    out[f.N + t] = b;
+  }
+  if (t < f.n_rad) {
+    double nu = 0.0;
+    for (int s = 0; s < f.S; ++s) {
+      double sw = 0.0;
+      for (int j = f.rad_lo; j < f.rad_hi; ++j) sw += f.Mp[j * kSP + s];
+      nu += (1.0 - f.tag[s]) * th[s] * sw * f.rad[s * f.n_rad + t];
+    }
+    out[2 * f.N + t] = nu;
+  }
+  if (t < f.N * f.n_ps) {
+    const int j = t / f.n_ps, k = t % f.n_ps;
+    double lam = 0.0;
+    for (int s = 0; s < f.S; ++s) lam += f.Mp[j * kSP + s] * (1.0 - f.tag[s]) * th[s] * f.pst[s * f.n_ps + k];
+    out[2 * f.N + f.n_rad + t] = lam;
+  }
+}
+
+void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st) {
+  const int n = max(max(N, n_rad), N * n_ps);
+  hipLaunchKernelGGL(k_expected, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d_fit, d_out);
+}
+
+}  // namespace bx

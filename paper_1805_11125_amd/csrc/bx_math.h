@@ -1,0 +1,343 @@
+// Special functions of the detector response, for gfx950 (and the host, for
+// unit tests of the arithmetic).  Everything here is per column (FP64) or per
+// reco edge (FP32 or FP64).
+//
+//  * Gaussian response: the bin-integrated normal law, written with the
+//    smaller tail (erfc) at every reco edge.
+//  * Generalized-gamma (Stacy) response with exponent p: F(x) = P(k, (x/a)^p)
+//    with P, Q the regularized incomplete gamma ratios.  Large k: Temme's
+//    uniform asymptotic expansion in eta, eta^2/2 = lambda - 1 - ln(lambda),
+//    lambda = y/k (coefficients from gen_temme.py).  Small k: the power series
+//    of P and the Legendre continued fraction of Q (modified Lentz), carried
+//    with a forward-mode derivative in k.
+//  * Column constants (FP64): ln Gamma differences by the Stirling series with
+//    Bernoulli-polynomial coefficients after an upward shift, digamma, and
+//    Gamma*(k) = Gamma(k) / (sqrt(2 pi / k) k^k e^-k).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "temme_coef.h"
+
+#define BX_HD __host__ __device__ __forceinline__
+
+namespace bx {
+
+// ---------------------------------------------------------------------------
+// Constants shared by host set-up and kernels.
+// ---------------------------------------------------------------------------
+constexpr int kSeriesTerms = 16;   // Stirling-type series length
+constexpr double kShift = 10.0;    // argument shift before the series
+constexpr double kSupportB = 75.0; // tails beyond k*phi = B (or z^2/2 = B) are < 1e-32
+constexpr float kTemmeMinK = 12.f; // FP32: uniform expansion from this shape on
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kLnSqrtTwoPi = 0.91893853320467274178032973640562;
+
+// Per-model constants of the generalized gamma with exponent p.
+struct GGConst {
+  double p, ip;                 // p, 1/p
+  double cG[kSeriesTerms + 1];  // G(x) = ln Gamma(x) + ln Gamma(x+2/p) - 2 ln Gamma(x+1/p) = sum cG[n] x^-n
+  double cD[kSeriesTerms + 1];  // D(x) = ln Gamma(x+1/p) - ln Gamma(x) - ln(x)/p = sum cD[n] x^-n
+};
+
+// ---------------------------------------------------------------------------
+// FP64 column helpers.
+// ---------------------------------------------------------------------------
+BX_HD double series_inv(const double* c, int n, double x) {  // sum_{i=1..n} c[i] x^-i
+  const double ix = 1.0 / x;
+  double s = 0.0;
+  for (int i = n; i >= 1; --i) s = (s + c[i]) * ix;
+  return s;
+}
+BX_HD double dseries_inv(const double* c, int n, double x) {  // d/dx of the above
+  const double ix = 1.0 / x;
+  double s = 0.0;
+  for (int i = n; i >= 1; --i) s = s * ix - i * c[i];
+  return s * ix * ix;
+}
+
+// Stirling remainder ln Gamma*(x) for x >= kShift: sum B_2n / (2n (2n-1) x^(2n-1)).
+BX_HD double lngamstar_big(double x) {
+  const double ix = 1.0 / x, ix2 = ix * ix;
+  // B2/2, B4/12, B6/30, B8/56, B10/90, B12/132, B14/182, B16/240
+  const double c[8] = {1.0 / 12, -1.0 / 360, 1.0 / 1260, -1.0 / 1680, 1.0 / 1188,
+                       -691.0 / 360360, 1.0 / 156, -3617.0 / 122400};
+  double s = 0.0;
+  for (int i = 7; i >= 0; --i) s = s * ix2 + c[i];
+  return s * ix;
+}
+// digamma for x >= kShift: ln x - 1/(2x) - sum B_2n / (2n x^2n)
+BX_HD double digamma_big(double x) {
+  const double ix = 1.0 / x, ix2 = ix * ix;
+  const double c[8] = {1.0 / 12, -1.0 / 120, 1.0 / 252, -1.0 / 240, 1.0 / 132,
+                       -691.0 / 32760, 1.0 / 12, -3617.0 / 8160};
+  double s = 0.0;
+  for (int i = 7; i >= 0; --i) s = s * ix2 + c[i];
+  return log(x) - 0.5 * ix - s * ix2;
+}
+
+// Column quantities of the GG shape k (all FP64).
+struct GGShape {
+  double G, dG;      // G(k), G'(k)
+  double D1, dD1;    // ln Gamma(k+1/p) - ln Gamma(k), derivative
+  double lngs;       // ln Gamma*(k)
+  double dlngs;      // d ln Gamma*(k)/dk = psi(k) - ln k + 1/(2k)
+  double psi;        // psi(k)
+};
+
+BX_HD GGShape gg_shape(const GGConst& c, double k, bool full) {
+  GGShape o;
+  const double a1 = c.ip, a2 = 2.0 * c.ip;
+  double x = k, lnprod = 0.0, dsum = 0.0, lnprodD = 0.0, dsumD = 0.0, lnprodG = 0.0, psum = 0.0;
+  if (k < kShift) {
+    double prG = 1.0, prD = 1.0, prGam = 1.0;
+    for (int m = 0; m < (int)kShift; ++m) {
+      const double km = k + m;
+      prG *= (km + a2) * km / ((km + a1) * (km + a1));
+      prD *= (km + a1) / km;
+      prGam *= km;
+      dsum += 1.0 / (km + a2) + 1.0 / km - 2.0 / (km + a1);
+      dsumD += 1.0 / (km + a1) - 1.0 / km;
+      psum += 1.0 / km;
+    }
+    lnprod = log(prG);
+    lnprodD = log(prD);
+    lnprodG = log(prGam);
+    x = k + kShift;
+  }
+  o.G = series_inv(c.cG, kSeriesTerms, x) - lnprod;
+  o.dG = dseries_inv(c.cG, kSeriesTerms, x) - dsum;
+  o.D1 = c.ip * log(x) + series_inv(c.cD, kSeriesTerms, x) - lnprodD;
+  o.dD1 = c.ip / x + dseries_inv(c.cD, kSeriesTerms, x) - dsumD;
+  if (full) {
+    // ln Gamma(k) = ln Gamma(x) - ln prod, ln Gamma(x) = (x - 1/2) ln x - x + ln sqrt(2 pi) + lngs(x)
+    if (k < kShift) {
+      const double lgx = (x - 0.5) * log(x) - x + kLnSqrtTwoPi + lngamstar_big(x);
+      const double lgk = lgx - lnprodG;
+      o.lngs = lgk - ((k - 0.5) * log(k) - k + kLnSqrtTwoPi);
+      o.psi = digamma_big(x) - psum;
+    } else {
+      o.lngs = lngamstar_big(k);
+      o.psi = digamma_big(k);
+    }
+    o.dlngs = o.psi - log(k) + 0.5 / k;
+  }
+  return o;
+}
+
+// Shape k of the GG with ln(1 + Var/Mean^2) = tau: Newton in u = ln k.
+BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters) {
+  double u = -log(c.p * c.p * tau);   // large-k limit G ~ 1/(p^2 k)
+  if (tau > 1.0) u = -tau;            // small-k limit G ~ -ln k
+  int it = 0;
+  for (; it < 60; ++it) {
+    const double k = exp(u);
+    const GGShape s = gg_shape(c, k, false);
+    double du = (s.G - tau) / (k * s.dG);
+    du = fmax(-2.0, fmin(2.0, du));
+    u -= du;
+    if (fabs(du) < 4e-16 * fmax(1.0, fabs(u))) break;
+  }
+  if (iters) *iters = it;
+  return exp(u);
+}
+
+// phi(t) = e^t - 1 - t (accurate for small t); also returns e^t - 1.
+template <class R>
+BX_HD R phi_t(R t, R* um1) {
+  if (fabs(t) < (R)0.5) {
+    // t^2 (1/2! + t/3! + ... ) up to t^12
+    R s = (R)(1.0 / 479001600.0);
+    const R c[10] = {(R)(1.0 / 39916800.0), (R)(1.0 / 3628800.0), (R)(1.0 / 362880.0),
+                     (R)(1.0 / 40320.0),    (R)(1.0 / 5040.0),    (R)(1.0 / 720.0),
+                     (R)(1.0 / 120.0),      (R)(1.0 / 24.0),      (R)(1.0 / 6.0),
+                     (R)(0.5)};
+    for (int i = 0; i < 10; ++i) s = s * t + c[i];
+    const R ph = s * t * t;
+    *um1 = ph + t;
+    return ph;
+  }
+  const R u = expm1(t);
+  *um1 = u;
+  return u - t;
+}
+
+// ---------------------------------------------------------------------------
+// Per-edge evaluation.  Result: v = signed smaller tail (v >= 0: F(x) = v on
+// the lower side; v <= 0 with the sign bit set: 1 - F(x) = -v on the upper
+// side), and dF/dc1, dF/dc2 for the column parameters (Gauss: m, sigma; GG:
+// k, ln a).
+// ---------------------------------------------------------------------------
+template <class R>
+struct EdgeVal {
+  R v, d1, d2;
+};
+
+// Gaussian.  zd = (x - m)/sigma formed in FP64 by the caller.
+template <class R, bool D>
+BX_HD EdgeVal<R> gauss_edge(double x, double m, double inv_sigma) {
+  EdgeVal<R> o;
+  if (inv_sigma > 0.0) {
+    const R z = (R)((x - m) * inv_sigma);
+    const R tail = (R)0.5 * erfc(fabs(z) * (R)0.70710678118654752440);
+    o.v = z > (R)0 ? -tail : tail;
+    if (D) {
+      const R ph = exp((R)-0.5 * z * z) * (R)0.39894228040143267794;
+      o.d1 = -ph * (R)inv_sigma;
+      o.d2 = -z * ph * (R)inv_sigma;
+    }
+  } else {  // zero width: all mass in the bin [x_j, x_j+1) holding m
+    o.v = x > m ? -(R)0 : (R)0;
+    o.d1 = o.d2 = (R)0;
+  }
+  return o;
+}
+
+// Column constants of the GG edge routine (FP32 or FP64 copies).
+template <class R>
+struct GGCol {
+  double ct;     // p ln a + ln k   (t = p ln x - ct)
+  R k, ik;       // k, 1/k
+  R skh;         // sqrt(k/2)
+  R cR;          // 1 / (sqrt(2 pi k) Gamma*(k))
+  R ce;          // 1 / (2 sqrt(2 pi k))
+  R dlngs;       // d ln Gamma*/dk
+  R lnk_psi;     // ln k - psi(k)
+  R p;           // exponent
+};
+
+// Uniform expansion (large k): functions h_n(eta).
+template <class R>
+BX_HD R horner(const double* c, int deg, R x) {
+  R s = (R)c[deg];
+  for (int i = deg - 1; i >= 0; --i) s = s * x + (R)c[i];
+  return s;
+}
+
+template <class R, bool D>
+BX_HD EdgeVal<R> gg_edge_temme(R t, const GGCol<R>& c) {
+  R u;
+  const R ph = phi_t(t, &u);
+  const bool up = t > (R)0;
+  const R eta = up ? sqrt((R)2 * ph) : -sqrt((R)2 * ph);
+  const R E = exp(-c.k * ph);
+  const R w = fabs(eta) * c.skh;
+  R h0, h1, h2, h3;
+  if (fabs(eta) < (R)1) {
+    constexpr bool f32 = sizeof(R) == 4;
+    h0 = horner<R>(bx_temme_h0, f32 ? 13 : BX_TEMME_H0_DEG, eta);
+    h1 = horner<R>(bx_temme_h1, f32 ? 12 : BX_TEMME_H1_DEG, eta);
+    h2 = horner<R>(bx_temme_h2, f32 ? 10 : BX_TEMME_H2_DEG, eta);
+    h3 = horner<R>(bx_temme_h3, f32 ? 8 : BX_TEMME_H3_DEG, eta);
+  } else {
+    const R ie = (R)1 / eta, ie2 = ie * ie, iu = (R)1 / u, iu2 = iu * iu;
+    const R mu = (R)1 + u;
+    h0 = iu - ie;
+    h1 = ie2 * ie - mu * iu2 * iu - (R)(1.0 / 12) * ie;
+    h2 = (R)-3 * ie2 * ie2 * ie + mu * ((R)2 * mu + (R)1) * iu2 * iu2 * iu +
+         (R)(1.0 / 12) * ie2 * ie - (R)bx_temme_dh1_0 * ie;
+    h3 = (R)15 * ie2 * ie2 * ie2 * ie - mu * ((R)6 * mu * mu + (R)8 * mu + (R)1) * iu2 * iu2 * iu2 * iu -
+         (R)0.25 * ie2 * ie2 * ie + (R)bx_temme_dh1_0 * ie2 * ie - (R)bx_temme_dh2_0 * ie;
+  }
+  const R ik = c.ik;
+  const R Hs = h0 + ik * (h1 + ik * (h2 + ik * h3));
+  const R Rt = E * c.cR * Hs;
+  const R T = (R)0.5 * erfc(w) + (up ? Rt : -Rt);
+  EdgeVal<R> o;
+  o.v = up ? -T : T;
+  if (D) {
+    const R g = c.k * c.cR * E;  // y^k e^-y / Gamma(k)
+    const R dH = ik * ik * (h1 + ik * ((R)2 * h2 + (R)3 * ik * h3));
+    const R dQk_eta = E * (-eta * c.ce + c.cR * Hs * ((R)-0.5 * eta * eta - (R)0.5 * ik - c.dlngs) -
+                           c.cR * dH);
+    o.d1 = -(dQk_eta + g * ik);  // dF/dk at fixed y
+    o.d2 = -c.p * g;             // dF/d ln a at fixed k
+  }
+  return o;
+}
+
+// Small k: power series of P (y < k + 1) or continued fraction of Q, each
+// with d/dk carried alongside (forward mode).
+template <class R, bool D>
+BX_HD EdgeVal<R> gg_edge_small(R t, const GGCol<R>& c) {
+  constexpr bool f32 = sizeof(R) == 4;
+  const R eps = f32 ? (R)3e-8 : (R)1e-17;
+  const int itmax = f32 ? 200 : 4000;
+  R u;
+  const R ph = phi_t(t, &u);
+  const R k = c.k;
+  const R y = k * ((R)1 + u);
+  const R g = k * c.cR * exp(-k * ph);  // y^k e^-y / Gamma(k)
+  const R lny_psi = t + c.lnk_psi;      // ln y - psi(k)
+  EdgeVal<R> o;
+  if (y < k + (R)1) {
+    R a = (R)1, da = (R)0, S = (R)1, dS = (R)0;
+    for (int n = 1; n < itmax; ++n) {
+      const R inv = (R)1 / (k + (R)n);
+      const R an = a * y * inv;
+      da = (da * y - an) * inv;
+      a = an;
+      S += a;
+      dS += da;
+      if (a < eps * S) break;
+    }
+    const R P = g * c.ik * S;
+    const R dP = g * c.ik * (S * (lny_psi - c.ik) + dS);  // psi(k+1) = psi(k) + 1/k
+    o.v = P <= (R)0.5 ? P : -((R)1 - P);
+    o.d1 = dP;
+  } else {
+    // Q = g * 1/(y+1-k- 1(1-k)/(y+3-k- 2(2-k)/(y+5-k- ...))), modified Lentz
+    const R tiny = f32 ? (R)1e-30 : (R)1e-300;
+    R b = y + (R)1 - k, db = (R)-1;
+    R cc = (R)1 / tiny, dcc = (R)0;
+    R d = (R)1 / b, dd = -db * d * d;
+    R h = d, dh = dd;
+    for (int i = 1; i < itmax; ++i) {
+      const R an = -(R)i * ((R)i - k), dan = (R)i;
+      b += (R)2;
+      R dn = an * d + b;
+      R ddn = dan * d + an * dd + db;
+      if (fabs(dn) < tiny) dn = tiny;
+      R cn = b + an / cc;
+      R dcn = db + (dan * cc - an * dcc) / (cc * cc);
+      if (fabs(cn) < tiny) cn = tiny;
+      d = (R)1 / dn;
+      dd = -ddn * d * d;
+      cc = cn;
+      dcc = dcn;
+      const R del = d * cc, ddel = dd * cc + d * dcc;
+      dh = dh * del + h * ddel;
+      h *= del;
+      if (fabs(del - (R)1) < eps) break;
+    }
+    const R Q = g * h;
+    o.v = -Q;
+    o.d1 = -(g * lny_psi * h + g * dh);
+  }
+  if (D) o.d2 = -c.p * g;
+  return o;
+}
+
+template <class R, bool D>
+BX_HD EdgeVal<R> gg_edge(double lnx, const GGCol<R>& c) {
+  if (!(lnx > -1e300)) {  // x <= 0: F = 0
+    EdgeVal<R> o;
+    o.v = (R)0;
+    o.d1 = o.d2 = (R)0;
+    return o;
+  }
+  const R t = (R)((double)c.p * lnx - c.ct);
+  constexpr bool f32 = sizeof(R) == 4;
+  if (f32 && c.k >= (R)kTemmeMinK) return gg_edge_temme<R, D>(t, c);
+  return gg_edge_small<R, D>(t, c);
+}
+
+// Cell from two neighbouring encoded edge values (lower edge lo, upper hi).
+template <class R>
+BX_HD R cell_from(R lo, R hi) {
+  const bool straddle = signbit(hi) && !signbit(lo);
+  return (hi - lo) + (straddle ? (R)1 : (R)0);
+}
+
+}  // namespace bx

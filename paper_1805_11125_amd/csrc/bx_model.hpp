@@ -1,0 +1,71 @@
+// Host-side model object and helpers shared by the C ABI, the plain fitter
+// and the fit server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <string>
+#include <vector>
+
+#include "../../include/bx.h"
+#include "bx_dev.h"
+
+namespace bx {
+
+
+
+void set_error(const std::string& msg);
+bx_status hip_fail(hipError_t e, const char* what);
+
+// Tile choice for a fit of this shape (depends only on the fit's own shape).
+struct Tiles {
+  int CG, RG;
+};
+Tiles choose_tiles(int T, int N, int kind, int prec);
+
+// Host copy of everything a fit needs, independent of device placement.
+struct HostModel {
+  int T, N, S, P, nresp, kind, prec, mv;
+  int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
+  double p, pu_frac, exposure;
+  std::vector<double> xraw, xe, Ec, Qt, F64, ghat, tag, rad, pst;
+  std::vector<float> F32;
+  std::vector<double> n_e, n_t, n_r, n_p;
+  GGConst gg;
+  Tiles tiles;
+};
+
+bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h);
+bx_status set_host_data(HostModel* h, const bx_data* x);
+double host_lnfact(const HostModel& h);
+
+// Device placement of one fit: one allocation holding inputs and workspace.
+struct DeviceFit {
+  void* base = nullptr;
+  size_t bytes = 0;
+  FitDev dev{};          // host copy with device pointers
+  double* d_theta = nullptr;
+  double* d_out = nullptr;
+};
+size_t device_fit_bytes(const HostModel& h);
+// Carve `base` (device memory of device_fit_bytes(h)) and upload h; stream-ordered.
+bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st);
+bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st);
+LaunchShape shape_of(const FitDev& f);
+
+}  // namespace bx
+
+struct bx_model {
+  bx::HostModel h;
+  bx::DeviceFit df;
+  bx::FitDev* d_fit = nullptr;   // device copy of df.dev
+  int* d_active = nullptr;       // {0}
+  hipStream_t stream = nullptr;  // launches
+  bool own_stream = false;
+  hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  hipGraphExec_t g_eval = nullptr, g_grad = nullptr;
+  double* h_pin = nullptr;       // pinned: theta[P] | out[2 + P]
+  double lnfact = 0.0;
+  std::atomic<int> users{0};     // server fits referencing this model
+  int device = 0;
+};

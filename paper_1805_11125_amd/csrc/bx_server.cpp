@@ -1,0 +1,330 @@
+// Fit server: HBM-budget admission, resident per-fit state, and continuous
+// batching -- every scheduler step evaluates the NLL and gradient of all
+// active fits in one batched launch (per response kind and precision), then
+// advances each fit's own minimiser by one step.  Fits join when memory and a
+// slot free up and leave when they finish.  A fit's arithmetic depends only
+// on its own shape and parameters (tile shapes from its own T and N, fixed
+// reduction orders), so its result does not depend on the rest of the batch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "bx_fitcore.hpp"
+#include "bx_model.hpp"
+
+namespace bx {
+
+static int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+constexpr int kThetaStride = 32;
+constexpr int kOutStride = 34;
+
+struct Req {
+  uint64_t ticket = 0;
+  bx_model* model = nullptr;
+  HostModel h;             // model arrays with this request's data
+  FitProblem pb;
+  std::unique_ptr<Bfgs> opt;
+  size_t bytes = 0;
+  int slot = -1;
+  void* mem = nullptr;
+  DeviceFit df;            // host copy of the slot's FitDev (source of its upload)
+  bx_fit_result res{};
+  bool done = false;
+};
+
+}  // namespace bx
+
+using namespace bx;
+
+struct bx_server {
+  size_t budget = 0, used = 0;
+  int max_slots = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  FitDev* d_fits = nullptr;       // [max_slots]
+  int* d_active = nullptr;        // [max_slots]
+  double* d_theta = nullptr;      // [max_slots][32]
+  double* d_out = nullptr;        // [max_slots][34]
+  double* h_theta = nullptr;      // pinned
+  double* h_out = nullptr;        // pinned
+  int* h_active = nullptr;        // pinned
+  std::vector<int> free_slots;
+  std::deque<std::shared_ptr<Req>> queue;
+  std::vector<std::shared_ptr<Req>> active;
+  std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets;
+  uint64_t next_ticket = 1;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::thread worker;
+  bool stop = false;
+  int pending = 0;
+  int device = 0;
+};
+
+static void retire(bx_server* s, const std::shared_ptr<Req>& r);
+
+// Admit queued requests while slots and budget allow (called with mu held).
+static void admit(bx_server* s) {
+  while (!s->queue.empty() && !s->free_slots.empty()) {
+    auto r = s->queue.front();
+    if (s->used + r->bytes > s->budget) break;
+    void* mem = nullptr;
+    const bool got = hipMallocAsync(&mem, r->bytes, s->stream) == hipSuccess;
+    if (!got && !s->active.empty()) break;  // retry when a fit leaves
+    s->queue.pop_front();
+    r->mem = mem;
+    r->slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    s->used += r->bytes;
+    DeviceFit& df = r->df;
+    if (!got || place_fit(r->h, mem, &df, s->stream) != BX_OK) {
+      r->res.status = BX_FAILED;
+      retire(s, r);
+      continue;
+    }
+    df.dev.theta = s->d_theta + (size_t)r->slot * kThetaStride;
+    df.dev.out = s->d_out + (size_t)r->slot * kOutStride;
+    (void)hipMemcpyAsync(s->d_fits + r->slot, &df.dev, sizeof(FitDev), hipMemcpyHostToDevice, s->stream);
+    r->res.t_admit_ns = now_ns();
+    s->active.push_back(r);
+  }
+}
+
+static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
+  if (r->mem) (void)hipFreeAsync(r->mem, s->stream);
+  r->mem = nullptr;
+  s->used -= r->bytes;
+  s->free_slots.push_back(r->slot);
+  r->res.t_done_ns = now_ns();
+  r->done = true;
+  r->model->users.fetch_sub(1);
+  --s->pending;
+}
+
+static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
+  // stage every active fit's next point
+  for (auto& r : act) {
+    double x[32];
+    r->opt->next(x);
+    memcpy(s->h_theta + (size_t)r->slot * kThetaStride, x, sizeof(double) * r->h.P);
+  }
+  // contiguous ranges are small; copy the whole staged array once
+  int max_slot = 0;
+  for (auto& r : act) max_slot = std::max(max_slot, r->slot + 1);
+  (void)hipMemcpyAsync(s->d_theta, s->h_theta, sizeof(double) * kThetaStride * max_slot, hipMemcpyHostToDevice,
+                       s->stream);
+  // one batched launch per (kind, precision) group
+  for (int kind = 0; kind < 2; ++kind)
+    for (int prec = 0; prec < 2; ++prec) {
+      int n = 0;
+      LaunchShape L{};
+      L.kind = kind;
+      L.prec = prec;
+      const int grp = kind * 2 + prec;  // each group stages its list separately
+      int* act_list = s->h_active + (size_t)grp * s->max_slots;
+      int* d_list = s->d_active + (size_t)grp * s->max_slots;
+      for (auto& r : act) {
+        if (r->h.kind != kind || r->h.prec != prec) continue;
+        FitDev f{};
+        f.T = r->h.T; f.N = r->h.N; f.mv = r->h.mv; f.n_rad = r->h.n_rad;
+        f.kind = kind; f.prec = prec;
+        f.n_rt = (f.N + kRowStep - 1) / kRowStep;
+        f.n_ct = (f.T + kColTile - 1) / kColTile;
+        f.n_cg = (f.n_ct + r->h.tiles.CG - 1) / r->h.tiles.CG;
+        f.n_rg = (f.n_rt + r->h.tiles.RG - 1) / r->h.tiles.RG;
+        f.n_rowblk = (f.N + 15) / 16;
+        const LaunchShape l = shape_of(f);
+        L.max_T = std::max(L.max_T, l.max_T);
+        L.max_fwd_blocks = std::max(L.max_fwd_blocks, l.max_fwd_blocks);
+        L.max_NS = std::max(L.max_NS, l.max_NS);
+        L.max_rowblk = std::max(L.max_rowblk, l.max_rowblk);
+        L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
+        L.any_mv |= l.any_mv;
+        L.any_rad |= l.any_rad;
+        act_list[n++] = r->slot;
+      }
+      if (!n) continue;
+      (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
+      launch_eval(s->d_fits, d_list, n, L, true, s->stream);
+    }
+  (void)hipMemcpyAsync(s->h_out, s->d_out, sizeof(double) * kOutStride * max_slot, hipMemcpyDeviceToHost, s->stream);
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& r : act) {
+    const double* o = s->h_out + (size_t)r->slot * kOutStride;
+    const int P = r->h.P;
+    const int fl = (int)o[1 + P];
+    const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
+    r->opt->feed(bad ? INFINITY : o[0], o + 1);
+  }
+}
+
+static void worker_loop(bx_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    admit(s);
+    if (s->active.empty()) {
+      if (s->stop) break;
+      s->cv.wait(lk);
+      continue;
+    }
+    std::vector<std::shared_ptr<Req>> act = s->active;
+    lk.unlock();
+    step(s, act);
+    lk.lock();
+    std::vector<std::shared_ptr<Req>> keep;
+    for (auto& r : s->active) {
+      if (r->opt->done()) {
+        r->opt->result(&r->res);
+        retire(s, r);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    s->active.swap(keep);
+    s->cv_done.notify_all();
+  }
+}
+
+extern "C" {
+
+bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip_stream, bx_server** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return BX_E_INVAL;
+  }
+  *out = nullptr;
+  bx_server* s = new (std::nothrow) bx_server();
+  if (!s) return BX_E_NOMEM;
+  s->max_slots = max_slots > 0 ? max_slots : 4096;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    set_error("no HIP device");
+    return BX_E_DEVICE;
+  }
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    delete s;
+    set_error("hipMemGetInfo failed");
+    return BX_E_DEVICE;
+  }
+  s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return BX_E_DEVICE;
+    }
+    s->own_stream = true;
+  }
+  const size_t M = s->max_slots;
+  if (hipMalloc(&s->d_fits, sizeof(FitDev) * M) != hipSuccess || hipMalloc(&s->d_active, sizeof(int) * 4 * M) != hipSuccess ||
+      hipMalloc(&s->d_theta, sizeof(double) * kThetaStride * M) != hipSuccess ||
+      hipMalloc(&s->d_out, sizeof(double) * kOutStride * M) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_theta, sizeof(double) * kThetaStride * M, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutStride * M, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_active, sizeof(int) * 4 * M, hipHostMallocDefault) != hipSuccess) {
+    bx_server_destroy(s);
+    set_error("server allocation failed");
+    return BX_E_NOMEM;
+  }
+  memset(s->h_theta, 0, sizeof(double) * kThetaStride * M);
+  for (int i = (int)M - 1; i >= 0; --i) s->free_slots.push_back(i);
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return BX_OK;
+}
+
+bx_status bx_server_destroy(bx_server* s) {
+  if (!s) return BX_OK;
+  if (s->worker.joinable()) {
+    bx_server_drain(s);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv.notify_all();
+    s->worker.join();
+  }
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->d_fits) (void)hipFree(s->d_fits);
+  if (s->d_active) (void)hipFree(s->d_active);
+  if (s->d_theta) (void)hipFree(s->d_theta);
+  if (s->d_out) (void)hipFree(s->d_out);
+  if (s->h_theta) (void)hipHostFree(s->h_theta);
+  if (s->h_out) (void)hipHostFree(s->h_out);
+  if (s->h_active) (void)hipHostFree(s->h_active);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return BX_OK;
+}
+
+bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_t* ticket) {
+  if (!s || !m || !o || !o->x0 || !ticket) {
+    set_error("NULL argument");
+    return BX_E_INVAL;
+  }
+  auto r = std::make_shared<Req>();
+  r->res.t_submit_ns = now_ns();
+  bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb);
+  if (st != BX_OK) return st;
+  r->h = m->h;
+  r->bytes = (device_fit_bytes(r->h) + 4095) & ~(size_t)4095;
+  if (r->bytes > s->budget) {
+    set_error("request larger than the server's memory budget");
+    return BX_E_BUSY;
+  }
+  r->opt.reset(new Bfgs(r->pb));
+  r->model = m;
+  m->users.fetch_add(1);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    s->tickets[r->ticket] = r;
+    s->queue.push_back(r);
+    ++s->pending;
+    *ticket = r->ticket;
+  }
+  s->cv.notify_all();
+  return BX_OK;
+}
+
+bx_status bx_fit_poll(bx_server* s, uint64_t ticket, bx_fit_result* res) {
+  if (!s || !res) {
+    set_error("NULL argument");
+    return BX_E_INVAL;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) {
+    set_error("unknown ticket");
+    return BX_E_NOTFOUND;
+  }
+  if (!it->second->done) return BX_PENDING;
+  *res = it->second->res;
+  s->tickets.erase(it);
+  return BX_OK;
+}
+
+bx_status bx_server_drain(bx_server* s) {
+  if (!s) return BX_E_INVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->pending == 0; });
+  return BX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances: NLL within 1e-9 relative; every gradient component within 1e-6
+of its magnitude scale sum_b |dmu_b/dq| (1 + n_b/mu_b) (the two cancelling
+terms of dNLL/dq); expected counts per bin within 1e-11 relative (FP64 cells)
+or 3e-5 relative to the term's largest bin (FP32 cells).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import model as om
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 0, 1
+
+
+@pytest.fixture(scope="module")
+def bx():
+    import paper_1805_11125_amd as bx
+    return bx
+
+
+def perturbed(d, seed=3, eps=0.01):
+    z = np.random.default_rng(seed).standard_normal(d.P)
+    th = d.theta_true * (1 + eps * z)
+    return th
+
+
+def check_point(bx, d, x, th, prec, label):
+    m = bx.Model(d, x, precision=prec)
+    v, g = m.nll_grad(th)
+    v0, g0 = oracle.nll_grad(d, x, th)
+    sc = oracle.grad_scale(d, x, th)
+    rel = abs(v - v0) / abs(v0)
+    gerr = np.abs(g - g0) / sc
+    print(f"{label}: NLL {v:.10g} oracle {v0:.10g} |d|={abs(v - v0):.3g} rel={rel:.2e}; "
+          f"grad max err/scale={gerr.max():.2e}")
+    assert rel <= 1e-9, (v, v0)
+    assert np.all(gerr <= 1e-6), gerr
+    ve = m.nll(th)
+    assert ve == v
+    return m, v, g
+
+
+@pytest.mark.parametrize("name,prec", [("c1", F64), ("c1", F32), ("c2", F32), ("c2", F64),
+                                       ("c3a", F64), ("c3a", F32), ("c3b", F32)])
+def test_nll_grad_parity(bx, name, prec):
+    d, x = synth.load(name)
+    check_point(bx, d, x, perturbed(d), prec, f"{name}/prec{prec}")
+
+
+@pytest.mark.parametrize("name,prec", [("c1", F64), ("c2", F32), ("c3a", F64)])
+def test_expected_counts_parity(bx, name, prec):
+    d, x = synth.load(name)
+    th = perturbed(d, seed=5)
+    m = bx.Model(d, x, precision=prec)
+    mu = m.expected(th)
+    f = om.forward(d, th)
+    full = d.copy()
+    full.win = (0, d.N)
+    ref = om.expected(full, f.Mp, f.r)
+    for key, arr in ref.items():
+        got = np.asarray(mu[key]).reshape(arr.shape)
+        if prec == F64:
+            np.testing.assert_allclose(got, arr, rtol=1e-11, atol=1e-12 * np.abs(arr).max())
+        else:
+            assert np.max(np.abs(got - arr)) <= 3e-5 * np.abs(arr).max(), key
+
+
+def test_lnfact_matches_oracle(bx):
+    for name in ["c1", "c3a"]:
+        d, x = synth.load(name)
+        m = bx.Model(d, x, precision=F64)
+        assert abs(m.lnfact() - oracle.lnfact(d, x)) <= 1e-12 * oracle.lnfact(d, x)
+
+
+def ragged_gauss(T, N, S, seed, win=None):
+    rng = np.random.default_rng(seed)
+    te = np.sort(rng.uniform(0.0, 2.0, T + 1))
+    te[0], te[-1] = 0.0, 2.0
+    re = np.linspace(0.0, 2.1, N + 1)
+    F = rng.random((S, T)) + 0.05
+    th = np.concatenate([rng.uniform(1e3, 1e4, S), [0.03, 0.002]])
+    d = synth.ModelDesc(kind="gauss", true_edges=te, reco_edges=re, spectra=F,
+                        species=[f"s{i}" for i in range(S)], win=win or (0, N), theta_true=th)
+    mu = om.forward(d, th).mu["energy"]
+    x = synth.Data(energy=np.zeros(N))
+    x.energy[d.win[0]:d.win[1]] = rng.poisson(mu)
+    return d, x
+
+
+@pytest.mark.parametrize("T,N,S", [(1, 1, 1), (17, 16, 3), (33, 31, 16), (250, 151, 5), (16, 15, 2)])
+def test_ragged_shapes(bx, T, N, S):
+    d, x = ragged_gauss(T, N, S, seed=T + N)
+    for prec in (F64, F32):
+        check_point(bx, d, x, perturbed(d, eps=0.05), prec, f"ragged T{T} N{N} S{S} p{prec}")
+
+
+def test_window_subset(bx):
+    d, x = ragged_gauss(120, 90, 3, seed=9, win=(17, 71))
+    check_point(bx, d, x, perturbed(d), F64, "window")
+
+
+def test_gg_ragged_with_pileup(bx):
+    d = synth.config2(pu_g=synth.pileup_spectrum())
+    keep = [0, 1, 5, 9]
+    d.true_edges = d.true_edges[:701]
+    d.spectra = d.spectra[keep][:, :700]
+    d.quench = d.quench[:700]
+    d.species = [d.species[i] for i in keep]
+    d.reco_edges = d.reco_edges[:334]
+    d.win = (3, 333)
+    d.theta_true = np.concatenate([d.theta_true[keep], d.theta_true[-4:]])
+    mu = om.forward(d, d.theta_true).mu["energy"]
+    e = np.zeros(d.N)
+    e[3:333] = np.random.default_rng(2).poisson(mu)
+    x = synth.Data(energy=e)
+    for prec in (F32, F64):
+        check_point(bx, d, x, perturbed(d), prec, f"gg ragged p{prec}")
+
+
+def test_zero_width_gauss_eval_and_grad_domain(bx):
+    d, x = synth.load("c1")
+    th = d.theta_true.copy()
+    th[d.S:] = 0.0
+    m = bx.Model(d, x, precision=F64)
+    v = m.nll(th)
+    v0 = oracle.nll(d, x, th) if np.all(np.isfinite(om.forward(d, th).mu["energy"])) else None
+    if v0 is not None and math.isfinite(v0):
+        assert abs(v - v0) <= 1e-9 * abs(v0)
+    with pytest.raises(bx.DomainError):
+        m.nll_grad(th)
+
+
+def test_domain_errors(bx):
+    d, x = synth.load("c1")
+    m = bx.Model(d, x, precision=F64)
+    th = d.theta_true.copy()
+    th[d.S] = -1.0                       # sigma^2 < 0
+    with pytest.raises(bx.DomainError):
+        m.nll(th)
+    th = d.theta_true.copy()
+    th[0] = np.nan
+    with pytest.raises(bx.DomainError):
+        m.nll(th)
+    th = d.theta_true.copy()
+    th[: d.S] = 0.0                      # mu = 0 where counts > 0
+    with pytest.raises(bx.DomainError):
+        m.nll(th)
+    # the model still works after domain errors
+    assert math.isfinite(m.nll(d.theta_true))
+
+
+def test_repeatable_bitwise(bx):
+    d, x = synth.load("c2")
+    m = bx.Model(d, x, precision=F32)
+    th = perturbed(d)
+    a = m.nll_grad(th)
+    for _ in range(3):
+        b = m.nll_grad(th)
+        assert a[0] == b[0] and np.array_equal(a[1], b[1])
