@@ -16,6 +16,9 @@ constexpr int kRowStep = 15;   // cells per row tile
 constexpr int kColTile = 16;   // true bins per tile
 constexpr int kMaxResp = 4;    // response parameters (Gauss 2, GG 4)
 constexpr int kBlock = 256;    // threads per block (4 waves)
+constexpr int kCpBlock = 64;   // threads per block of the column-parameter kernel
+constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG true tiles)
+constexpr int kMaxK = 256;     // longest random-trigger spectrum
 
 enum : int { kGauss = 0, kGG = 1 };
 enum : int { kF32 = 0, kF64 = 1 };
@@ -44,7 +47,10 @@ struct FitDev {
   int T, N, S, P, nresp, kind, prec, mv;
   int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
   int n_rt, n_ct, CG, n_cg, RG, n_rg, n_rowblk;
+  int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
+  int uniform;            // reco bins of equal width
   int pad0;
+  double x0, inv_w;       // first reco edge, 1 / bin width (uniform bins)
   double pu_frac;
   GGConst gg;
   // inputs (device)
@@ -66,8 +72,8 @@ struct FitDev {
   const double* theta;  // [P]
   ColPar* cp;           // [T]
   int2* tb;             // [n_ct] support of each column tile (cells)
-  void* Mpart;          // [n_cg][N][16] R
-  double* M;            // [N][16]
+  void* Mpart;          // [n_cg][N][16] R: one partial per forward block
+  double* M;            // [N][16] sum of the partials (FP64)
   double* Mp;           // [N][16] after pile-up
   double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part
   double* Ht;           // [N][16] pile-up adjoint of H
@@ -75,7 +81,8 @@ struct FitDev {
   int* flagpart;        // [n_rowblk]
   double* gpart;        // [n_rowblk][16] rate-gradient partials
   double* rad_out;      // [2 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16]
-  double* abpart;       // [n_rg][T][2]
+  int* cpflag;          // [n_cpblk] domain flags of the column parameters
+  double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags
 };
 

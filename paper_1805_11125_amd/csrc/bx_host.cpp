@@ -73,7 +73,7 @@ Tiles choose_tiles(int T, int N, int kind, int prec) {
   // Column tiles per forward wave and row tiles per backward wave.  The
   // choice depends only on this fit's shape; an on-disk table written by the
   // tuner (BX_TUNE_CACHE) overrides the defaults.
-  Tiles t{4, 4};
+  Tiles t{1, 1};
   const char* path = getenv("BX_TUNE_CACHE");
   if (path && *path) {
     FILE* fp = fopen(path, "r");
@@ -147,7 +147,7 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
       if (!std::isfinite(d->quench[i]) || !(d->quench[i] > 0)) return inval("quench must be finite and > 0");
   }
   if (d->win_lo < 0 || d->win_hi > d->N || d->win_lo >= d->win_hi) return inval("fit window out of range");
-  if (d->pu_K < 0) return inval("pu_K < 0");
+  if (d->pu_K < 0 || d->pu_K > kMaxK) return inval("pu_K must be in [0, 256]");
   HostModel& m = *h;
   m.T = d->T; m.N = d->N; m.S = d->S;
   m.kind = d->response == BX_RESP_GAUSS ? kGauss : kGG;
@@ -259,14 +259,24 @@ struct Carver {
   }
 };
 
-static void derive_tiles(const HostModel& h, FitDev* f) {
+void derive_tiles(const HostModel& h, FitDev* f) {
+  f->T = h.T;
+  f->N = h.N;
   f->n_rt = (h.N + kRowStep - 1) / kRowStep;
   f->n_ct = (h.T + kColTile - 1) / kColTile;
   f->CG = h.tiles.CG;
   f->RG = h.tiles.RG;
-  f->n_cg = (f->n_ct + f->CG - 1) / f->CG;
-  f->n_rg = (f->n_rt + f->RG - 1) / f->RG;
+  // a forward block holds 4 waves of CG true tiles; a backward block 4 waves
+  // of RG reco tiles
+  f->n_cg = (f->n_ct + kFwdWaves * f->CG - 1) / (kFwdWaves * f->CG);
+  f->n_rg = (f->n_rt + 4 * f->RG - 1) / (4 * f->RG);
   f->n_rowblk = (h.N + 15) / 16;
+  f->n_cpblk = (h.T + kCpBlock - 1) / kCpBlock;
+  f->n_bwdblk = f->n_ct * f->n_rg;
+  f->kind = h.kind;
+  f->prec = h.prec;
+  f->mv = h.mv;
+  f->n_rad = h.n_rad;
 }
 
 static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, double** out) {
@@ -300,7 +310,8 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->flagpart = c.take<int>(f->n_rowblk);
   f->gpart = c.take<double>((size_t)f->n_rowblk * kSP);
   f->rad_out = c.take<double>(2 + 2 * kSP);
-  f->abpart = c.take<double>((size_t)f->n_rg * h.T * 2);
+  f->cpflag = c.take<int>(f->n_cpblk);
+  f->bwdpart = c.take<double>((size_t)f->n_bwdblk * 4);
   *out = c.take<double>(2 + h.P);
   f->out = *out;
   return (c.off + 255) & ~(size_t)255;
@@ -315,10 +326,10 @@ size_t device_fit_bytes(const HostModel& h) {
 LaunchShape shape_of(const FitDev& f) {
   LaunchShape L;
   L.max_T = f.T;
-  L.max_fwd_blocks = (f.n_rt * f.n_cg + 3) / 4;
+  L.max_fwd_blocks = f.n_rt * f.n_cg;
   L.max_NS = f.N * kSP;
   L.max_rowblk = f.n_rowblk;
-  L.max_bwd_blocks = (f.n_ct * f.n_rg + 3) / 4;
+  L.max_bwd_blocks = f.n_ct * f.n_rg;
   L.kind = f.kind;
   L.prec = f.prec;
   L.any_mv = f.mv;
@@ -350,6 +361,13 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   f.rad_hi = h.rad_hi; f.n_ps = h.n_ps;
   f.pu_frac = h.pu_frac;
   f.gg = h.gg;
+  // equal reco bins allow a direct edge index in the support search
+  const double w0 = h.xraw[1] - h.xraw[0];
+  bool uni = true;
+  for (int j = 1; j < h.N && uni; ++j) uni = std::fabs((h.xraw[j + 1] - h.xraw[j]) - w0) <= 1e-12 * std::fabs(w0);
+  f.uniform = uni ? 1 : 0;
+  f.x0 = h.xraw[0];
+  f.inv_w = 1.0 / w0;
   BX_HIP(up(f.xraw, h.xraw, st), "upload");
   BX_HIP(up(f.xe, h.xe, st), "upload");
   BX_HIP(up(f.Ec, h.Ec, st), "upload");

@@ -2,21 +2,23 @@
 //
 //   k_colparams   per true bin: response column parameters, support, chain
 //                 factors to the response parameters (Eq. 1's R_x(N_x, E; p)).
-//   k_cells_fwd   per (reco tile, group of true tiles): CDF at 16 shared reco
-//                 edges x 16 true bins, cells by differencing neighbour lanes,
-//                 fed straight into MFMA 16x16x4 as A with the species
-//                 spectra as B: M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).
-//                 Cells never touch HBM.
-//   k_reduce_M    FP64 sum of the per-group partials in a fixed order.
-//   k_rowterms    pile-up M' = (1-p) M + p g^*M (Eq. 2), expected counts of
+//   k_cells_fwd   per (reco tile, 4 true tiles): each wave evaluates the CDF
+//                 at 16 shared reco edges x 16 true bins, forms the cells by
+//                 differencing neighbour lanes and feeds them straight into
+//                 MFMA 16x16x4 as A with the species spectra as B:
+//                 M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).  The 4 waves'
+//                 tiles are added in LDS; cells never touch HBM.
+//   k_rowterms    FP64 sum of the forward partials (fixed order), pile-up
+//                 M' = (1-p) M + p g^*M (Eq. 2) from LDS, expected counts of
 //                 every likelihood term per reco row (Eqs. 3-4), Poisson NLL
 //                 terms, the adjoint weights H and per-block partials.
 //   k_radial      radial term (Eq. 4) -- one block per fit.
-//   k_adjoint     H~ = P^T H (the pile-up adjoint).
-//   k_cells_bwd   per (true tile, group of reco tiles): the same CDF sweep
-//                 with d/d(column parameters); accumulates
+//   k_adjoint     H~ = P^T H (the pile-up adjoint), from LDS.
+//   k_cells_bwd   per (true tile, 4 reco tiles): the same CDF sweep with the
+//                 derivatives in the two column parameters; accumulates
 //                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
-//                 W_ji = sum_s H~_js r_s F^_si.
+//                 W_ji = sum_s H~_js r_s F^_si, and contracts them with the
+//                 column chain factors into a per-block gradient partial.
 //   k_final       fixed-order sums: NLL, rate gradient, response gradient.
 //
 // No reduction uses atomics: every sum has a fixed order, so a fit's result
@@ -52,11 +54,26 @@ template <class R> struct Acc4;
 template <> struct Acc4<float> { typedef v4f T; };
 template <> struct Acc4<double> { typedef v4d T; };
 
+__device__ __forceinline__ double sum16(double x) {  // fixed-order sum over a 16-lane row
+  x += __shfl_xor(x, 8, 16);
+  x += __shfl_xor(x, 4, 16);
+  x += __shfl_xor(x, 2, 16);
+  x += __shfl_xor(x, 1, 16);
+  return x;
+}
+
 // Conservative cell range [jlo, jhi] holding every cell that can exceed
 // exp(-B) of the column's mass, from the x-interval [xlo, xhi].
-__device__ int2 cell_range(const double* x, int N, double xlo, double xhi) {
-  // first j with x[j+1] > xlo
-  int lo = 0, hi = N;  // search over edges 1..N
+__device__ int2 cell_range(const FitDev& f, double xlo, double xhi) {
+  const int N = f.N;
+  if (f.uniform) {  // equal bins: direct index, widened by one bin each side
+    const double a = fmin(fmax((xlo - f.x0) * f.inv_w, -2.0), (double)N + 2.0);
+    const double b = fmin(fmax((xhi - f.x0) * f.inv_w, -2.0), (double)N + 2.0);
+    if (!(a == a) || !(b == b)) return make_int2(0, N - 1);
+    return make_int2(max((int)floor(a) - 1, 0), min((int)ceil(b) + 1, N - 1));
+  }
+  const double* x = f.xraw;
+  int lo = 0, hi = N;  // first j with x[j+1] > xlo
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (x[mid + 1] > xlo) hi = mid; else lo = mid + 1;
@@ -67,31 +84,31 @@ __device__ int2 cell_range(const double* x, int N, double xlo, double xhi) {
     const int mid = (lo + hi) >> 1;
     if (x[mid] < xhi) lo = mid + 1; else hi = mid;
   }
-  const int jhi = lo - 1;
-  return make_int2(max(jlo - 1, 0), min(jhi + 1, N - 1));
+  return make_int2(max(jlo - 1, 0), min(lo, N - 1));
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_colparams(const FitDev* fits, const int* active) {
+__global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  int jlo = 1 << 30, jhi = -1;
+  if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
+  const int i = blockIdx.x * kCpBlock + threadIdx.x;
+  int jlo = 1 << 30, jhi = -1, bad = 0;
   if (i < f.T) {
     ColPar c;
-    c.bad = 0;
     const double* th = f.theta;
     double v = 0.0;
     for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
     c.v = v;
     for (int q = 0; q < kMaxResp; ++q) c.J[0][q] = c.J[1][q] = 0.0;
+    for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
     const double E = f.Ec[i];
     bool okth = true;
     for (int q = 0; q < f.P; ++q) okth = okth && isfinite(th[q]);
-    if (!okth) c.bad |= kBadTheta;
+    if (!okth) bad |= kBadTheta;
     if (f.kind == kGauss) {
       const double a = th[f.S], b = th[f.S + 1];
       const double var = a * E + b * E * E;
-      if (!(var >= 0.0)) c.bad |= kBadSigma;
+      if (!(var >= 0.0)) bad |= kBadSigma;
       const double sig = sqrt(fmax(var, 0.0));
       c.c0 = E;
       c.c1 = sig > 0.0 ? 1.0 / sig : 0.0;
@@ -99,23 +116,22 @@ __global__ void __launch_bounds__(kBlock) k_colparams(const FitDev* fits, const 
         c.J[1][0] = E / (2.0 * sig);
         c.J[1][1] = E * E / (2.0 * sig);
       } else {
-        c.bad |= kZeroWidth;
+        bad |= kZeroWidth;
       }
       const double zb = sqrt(2.0 * kSupportB);
-      const int2 r = cell_range(f.xraw, f.N, E - zb * sig, E + zb * sig);
+      const int2 r = cell_range(f, E - zb * sig, E + zb * sig);
       jlo = r.x; jhi = r.y;
     } else {
       const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
       const double m = L * f.Qt[i] * E;
       const double s2 = v0 + v1 * m + v2 * m * m;
       if (!(m > 0.0) || !(s2 > 0.0)) {
-        c.bad |= kBadGG;
+        bad |= kBadGG;
         c.c0 = 0.0; c.c1 = 1.0;
-        for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
       } else {
         const double tau = log1p(s2 / (m * m));
         const double k = gg_solve_k(f.gg, tau, nullptr);
-        if (!(k > 1e-300) || !(k < 1e12)) c.bad |= kBadGG;
+        if (!(k > 1e-300) || !(k < 1e12)) bad |= kBadGG;
         const GGShape sh = gg_shape(f.gg, k, true);
         const double p = f.gg.p;
         const double lna = log(m) - sh.D1;
@@ -134,51 +150,54 @@ __global__ void __launch_bounds__(kBlock) k_colparams(const FitDev* fits, const 
           c.J[0][q] = dk;
           c.J[1][q] = dm / m - sh.dD1 * dk;
         }
-        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p)
+        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p);
+        // Newton from outside each root stays outside it (conservative)
         const double cb = kSupportB / k;
         double th_ = cb > 2.0 ? log1p(cb) + log1p(log1p(cb)) : sqrt(2.0 * cb);
-        for (int it = 0; it < 40; ++it) {
+        for (int it = 0; it < 30; ++it) {
           const double e = expm1(th_);
           const double d = (e - th_ - cb) / e;
           th_ -= d;
-          if (fabs(d) < 1e-12 * fmax(1.0, th_)) break;
+          if (fabs(d) < 1e-6 * fmax(1.0, th_)) break;
         }
         double tl = -(1.0 + cb);
-        for (int it = 0; it < 40; ++it) {
+        for (int it = 0; it < 30; ++it) {
           const double e = expm1(tl);
           const double d = (e - tl - cb) / e;
           tl -= d;
-          if (fabs(d) < 1e-12 * fmax(1.0, -tl)) break;
+          if (fabs(d) < 1e-6 * fmax(1.0, -tl)) break;
         }
         const double xlo = exp((c.c0 + tl) / p), xhi = exp((c.c0 + th_) / p);
-        const int2 r = cell_range(f.xraw, f.N, xlo, xhi);
+        const int2 r = cell_range(f, xlo, xhi);
         jlo = r.x; jhi = r.y;
       }
     }
-    if (c.bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
-    c.jlo = jlo; c.jhi = jhi; c.pad = 0;
+    if (bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
+    c.jlo = jlo; c.jhi = jhi; c.bad = bad; c.pad = 0;
     f.cp[i] = c;
   }
-  // support of each 16-column tile
+  // support of each 16-column tile, domain flags of the block
   for (int m = 8; m >= 1; m >>= 1) {
     jlo = min(jlo, __shfl_xor(jlo, m, 16));
     jhi = max(jhi, __shfl_xor(jhi, m, 16));
   }
   if ((threadIdx.x & 15) == 0 && i < f.T) f.tb[i >> 4] = make_int2(jlo, jhi);
+  for (int m = 32; m >= 1; m >>= 1) bad |= __shfl_xor(bad, m, 64);
+  if (threadIdx.x == 0) f.cpflag[blockIdx.x] = bad;
 }
 
 // Edge evaluation for one lane.
 template <class R, int KIND, bool D>
-__device__ __forceinline__ EdgeVal<R> edge_at(const FitDev& f, const ColPar& c, double xe) {
+__device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
   if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
   GGCol<R> g;
-  const float* s = c.f32;
-  const double* d = c.f64;
   g.ct = c.c0;
   if (sizeof(R) == 4) {
+    const float* s = c.f32;
     g.k = (R)s[0]; g.ik = (R)s[1]; g.skh = (R)s[2]; g.cR = (R)s[3]; g.ce = (R)s[4];
     g.dlngs = (R)s[5]; g.lnk_psi = (R)s[6]; g.p = (R)s[7];
   } else {
+    const double* d = c.f64;
     g.k = (R)d[0]; g.ik = (R)d[1]; g.skh = (R)d[2]; g.cR = (R)d[3]; g.ce = (R)d[4];
     g.dlngs = (R)d[5]; g.lnk_psi = (R)d[6]; g.p = (R)d[7];
   }
@@ -186,21 +205,24 @@ __device__ __forceinline__ EdgeVal<R> edge_at(const FitDev& f, const ColPar& c, 
 }
 
 // ---------------------------------------------------------------------------
+// Block (rt, cg): reco rows [15 rt, 15 rt + 15); wave w takes true tiles
+// ct = (kFwdWaves cg + w) CG + c, c < CG.
 template <class R, int KIND>
-__global__ void __launch_bounds__(kBlock) k_cells_fwd(const FitDev* fits, const int* active) {
+__global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
-  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int rt = wave / f.n_cg, cg = wave % f.n_cg;
-  if (rt >= f.n_rt) return;
-  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int rt = blockIdx.x / f.n_cg, cg = blockIdx.x % f.n_cg;
+  if (rt >= f.n_rt) return;  // block-uniform
+  __shared__ R part[kFwdWaves][4][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int j0 = rt * kRowStep;
   const int je = min(j0 + jr, f.N);
   const double xe = f.xe[je];
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
   typename Acc4<R>::T acc = {0, 0, 0, 0};
-  const int ct_end = min((cg + 1) * f.CG, f.n_ct);
-  for (int ct = cg * f.CG; ct < ct_end; ++ct) {
+  const int ct0 = (kFwdWaves * cg + wv) * f.CG;
+  const int ct_end = min(ct0 + f.CG, f.n_ct);
+  for (int ct = ct0; ct < ct_end; ++ct) {
     const int2 b = f.tb[ct];
     if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
 #pragma unroll
@@ -208,45 +230,31 @@ __global__ void __launch_bounds__(kBlock) k_cells_fwd(const FitDev* fits, const 
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < f.T;
       const ColPar& c = f.cp[iok ? i : f.T - 1];
-      const EdgeVal<R> ev = edge_at<R, KIND, false>(f, c, xe);
+      const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
+      const EdgeVal<R> ev = edge_at<R, KIND, false>(c, xe);
       const R hi = dpp_from_next(ev.v);
       const R a = (row_ok && iok) ? cell_from(ev.v, hi) : (R)0;
-      const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
       acc = mfma16(a, bb, acc);
     }
   }
-  R* out = (R*)f.Mpart + (size_t)cg * f.N * kSP;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    // result layout of MFMA 16x16x4: lane l, register r holds row 4(l/16) + r
-    // (f32) or row l/16 + 4r (f64), column l%16
-    const int row = sizeof(R) == 4 ? 4 * g + r : g + 4 * r;
-    if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = acc[r];
+  for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
+  __syncthreads();
+  if (wv == 0) {
+    R* out = (R*)f.Mpart + (size_t)cg * f.N * kSP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      R v = part[0][r][lane];
+      for (int w = 1; w < kFwdWaves; ++w) v += part[w][r][lane];
+      // result layout of MFMA 16x16x4: lane l, register r holds row 4(l/16) + r
+      // (f32) or row l/16 + 4r (f64), column l%16
+      const int row = sizeof(R) == 4 ? 4 * g + r : g + 4 * r;
+      if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = v;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= f.N * kSP) return;
-  const R* p = (const R*)f.Mpart + t;
-  const size_t stride = (size_t)f.N * kSP;
-  double s = 0.0;
-  for (int cg = 0; cg < f.n_cg; ++cg) s += (double)p[cg * stride];
-  f.M[t] = s;
-}
-
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double sum16(double x) {  // fixed-order sum over a 16-lane row
-  x += __shfl_xor(x, 8, 16);
-  x += __shfl_xor(x, 4, 16);
-  x += __shfl_xor(x, 2, 16);
-  x += __shfl_xor(x, 1, 16);
-  return x;
-}
-
 __device__ __forceinline__ double nll_term(double mu, double n, double* w, int* bad) {
   if (!(mu >= 0.0) || (mu == 0.0 && n > 0.0) || !isfinite(mu)) {
     *bad |= kBadMu;
@@ -261,24 +269,57 @@ __device__ __forceinline__ double nll_term(double mu, double n, double* w, int* 
   return mu;
 }
 
+__device__ __forceinline__ int pu_len(const FitDev& f) {
+  return (f.K > 0 && f.pu_frac != 0.0) ? f.K : 1;
+}
+
+// M[j, s] = sum over forward blocks of the partials, FP64, fixed order.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active[blockIdx.y]];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= f.N * kSP) return;
+  const R* p = (const R*)f.Mpart + t;
+  const size_t stride = (size_t)f.N * kSP;
+  const int n = f.n_cg;
+  double s = 0.0;
+  int c = 0;
+  for (; c + 4 <= n; c += 4) {  // four independent loads in flight
+    const R a0 = p[c * stride], a1 = p[(c + 1) * stride], a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
+    s += (double)a0;
+    s += (double)a1;
+    s += (double)a2;
+    s += (double)a3;
+  }
+  for (; c < n; ++c) s += (double)p[c * stride];
+  f.M[t] = s;
+}
+
 // 16 rows x 16 species per block.
 __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
-  if ((int)blockIdx.x >= f.n_rowblk) return;
+  if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
+  __shared__ double Ml[16 + kMaxK - 1][kSP];
   __shared__ double mp[16][kSP];
   __shared__ double red[kBlock];
   __shared__ int redf[kBlock];
   __shared__ double wps[16][64];
   const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
-  const int j = blockIdx.x * 16 + rl;
+  const int j0 = blockIdx.x * 16;
+  const int K = pu_len(f);
+  const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, f.N);
+  // M rows [r0, r1) staged in LDS for the pile-up sums
+  for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = f.M[(size_t)r0 * kSP + e];
+  __syncthreads();
+  const int j = j0 + rl;
   const bool jok = j < f.N;
   double m = 0.0;
   if (jok) {
-    m = f.M[j * kSP + s];
-    if (f.K > 0 && f.pu_frac != 0.0) {
+    m = Ml[j - r0][s];
+    if (K > 1) {
       double acc = 0.0;
-      const int kmax = min(j, f.K - 1);
-      for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * f.M[(j - k) * kSP + s];
+      const int kmax = min(j, K - 1);
+      for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Ml[j - k - r0][s];
       m = (1.0 - f.pu_frac) * m + f.pu_frac * acc;
     }
     f.Mp[j * kSP + s] = m;
@@ -327,7 +368,6 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   }
   if (jok) f.H[j * kSP + s] = (s < f.S) ? h : 0.0;
   // block partials: NLL (fixed tree), flags, rate gradient sum_j H_js M'_js
-  __syncthreads();
   red[threadIdx.x] = term;
   redf[threadIdx.x] = bad;
   __syncthreads();
@@ -355,6 +395,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
+  if (!f.mv || f.n_rad <= 0) return;  // block-uniform
   __shared__ double part[16][kSP];
   __shared__ double SW[kSP], A[kSP], wr[128], red[kBlock];
   __shared__ int redf[kBlock];
@@ -367,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
     double t = 0.0;
     for (int g = 0; g < 16; ++g) t += part[g][threadIdx.x];
     SW[threadIdx.x] = t;
-    A[threadIdx.x] = threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * t : 0.0;
+    A[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * t : 0.0;
   }
   __syncthreads();
   double term = 0.0;
@@ -377,7 +418,7 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
     for (int u = 0; u < f.S; ++u) nu += A[u] * f.rad[u * f.n_rad + k];
     double w;
     term += nll_term(nu, f.n_r[k], &w, &bad);
-    if (k < 128) wr[k] = w;
+    wr[k] = w;
   }
   red[threadIdx.x] = term;
   redf[threadIdx.x] = bad;
@@ -394,7 +435,8 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
     if ((int)threadIdx.x < f.S)
       for (int k = 0; k < f.n_rad; ++k) rw += wr[k] * f.rad[threadIdx.x * f.n_rad + k];
     f.rad_out[2 + threadIdx.x] = rw;
-    f.rad_out[2 + 16 + threadIdx.x] = (threadIdx.x < (unsigned)f.S) ? (1.0 - f.tag[threadIdx.x]) * SW[threadIdx.x] * rw : 0.0;
+    f.rad_out[2 + 16 + threadIdx.x] =
+        (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * SW[threadIdx.x] * rw : 0.0;
   }
   if (threadIdx.x == 0) {
     f.rad_out[0] = red[0];
@@ -402,57 +444,68 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
   }
 }
 
-// H~ = P^T H_tot, H_tot = H + [j in W](1 - t_s) rho.w_s.
+// H~ = P^T H_tot, H_tot = H + [j in W](1 - t_s) rho.w_s; 16 rows per block.
 __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= f.N * kSP) return;
-  const int j = t >> 4, s = t & 15;
-  const bool rad = f.mv && f.n_rad > 0 && s < f.S;
-  const double radw = rad ? (1.0 - f.tag[s]) * f.rad_out[2 + s] : 0.0;
-  auto htot = [&](int jj) {
-    return f.H[jj * kSP + s] + ((rad && jj >= f.rad_lo && jj < f.rad_hi) ? radw : 0.0);
-  };
-  double h = htot(j);
-  if (f.K > 0 && f.pu_frac != 0.0) {
+  if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
+  __shared__ double Hl[16 + kMaxK - 1][kSP];
+  const int j0 = blockIdx.x * 16;
+  const int K = pu_len(f);
+  const int r1 = min(j0 + 16 + K - 1, f.N);
+  const bool rad = f.mv && f.n_rad > 0;
+  for (int e = threadIdx.x; e < (r1 - j0) * kSP; e += kBlock) {
+    const int jj = j0 + (e >> 4), s = e & 15;
+    double h = f.H[jj * kSP + s];
+    if (rad && s < f.S && jj >= f.rad_lo && jj < f.rad_hi) h += (1.0 - f.tag[s]) * f.rad_out[2 + s];
+    Hl[e >> 4][s] = h;
+  }
+  __syncthreads();
+  const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
+  const int j = j0 + rl;
+  if (j >= f.N) return;
+  double h = Hl[rl][s];
+  if (K > 1) {
     double acc = 0.0;
-    const int kmax = min(f.K - 1, f.N - 1 - j);
-    for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * htot(j + k);
+    const int kmax = min(K - 1, f.N - 1 - j);
+    for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Hl[rl + k][s];
     h = (1.0 - f.pu_frac) * h + f.pu_frac * acc;
   }
-  f.Ht[t] = h;
+  f.Ht[j * kSP + s] = h;
 }
 
 // ---------------------------------------------------------------------------
+// Block (ct, rg): true tile ct; wave w takes reco tiles rt = (4 rg + w) RG + c.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active[blockIdx.y]];
-  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int ct = wave / f.n_rg, rg = wave % f.n_rg;
-  if (ct >= f.n_ct) return;
-  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int ct = blockIdx.x / f.n_rg, rg = blockIdx.x % f.n_rg;
+  if (ct >= f.n_ct) return;  // block-uniform
+  __shared__ double colA[4][16], colB[4][16];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int2 b = f.tb[ct];
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
-  const int rt_end = min((rg + 1) * f.RG, f.n_rt);
-  for (int rt = rg * f.RG; rt < rt_end; ++rt) {
+  const int rt0 = (4 * rg + wv) * f.RG;
+  const int rt_end = min(rt0 + f.RG, f.n_rt);
+  for (int rt = rt0; rt < rt_end; ++rt) {
     const int j0 = rt * kRowStep;
     if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
     const int je = min(j0 + jr, f.N);
     const double xe = f.xe[je];
     const int j = j0 + jr;
     const bool row_ok = (jr < kRowStep) && (j < f.N);
+    const double w1 = row_ok ? f.Ht[j * kSP] : 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < f.T;
       const ColPar& c = f.cp[iok ? i : f.T - 1];
-      const EdgeVal<R> ev = edge_at<R, KIND, true>(f, c, xe);
+      const EdgeVal<R> ev = edge_at<R, KIND, true>(c, xe);
       const R d1h = dpp_from_next(ev.d1);
       const R d2h = dpp_from_next(ev.d2);
       if (row_ok && iok) {
         double W;
         if (!f.mv) {
-          W = f.Ht[j * kSP] * c.v;
+          W = w1 * c.v;
         } else {
           W = 0.0;
           for (int s = 0; s < f.S; ++s) W += f.Ht[j * kSP + s] * f.theta[s] * f.F64[i * kSP + s];
@@ -465,72 +518,87 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double A = sum16(aA[q]), B = sum16(aB[q]);
-    const int i = ct * kColTile + 4 * q + g;
-    if (jr == 0 && i < f.T) {
-      f.abpart[((size_t)rg * f.T + i) * 2 + 0] = A;
-      f.abpart[((size_t)rg * f.T + i) * 2 + 1] = B;
+    if (jr == 0) {
+      colA[wv][4 * q + g] = A;
+      colB[wv][4 * q + g] = B;
     }
+  }
+  __syncthreads();
+  // column totals (fixed order over the 4 waves), times the chain factors
+  if (threadIdx.x < 64) {
+    const int c16 = threadIdx.x & 15, q = threadIdx.x >> 4;  // q: response parameter
+    const int i = ct * kColTile + c16;
+    double v = 0.0;
+    if (i < f.T && q < f.nresp) {
+      const double A = ((colA[0][c16] + colA[1][c16]) + colA[2][c16]) + colA[3][c16];
+      const double B = ((colB[0][c16] + colB[1][c16]) + colB[2][c16]) + colB[3][c16];
+      const ColPar& c = f.cp[i];
+      v = A * c.J[0][q] + B * c.J[1][q];
+    }
+    v = sum16(v);
+    if (c16 == 0) f.bwdpart[(size_t)blockIdx.x * 4 + q] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
   const FitDev& f = fits[active[blockIdx.y]];
-  __shared__ double red[kMaxResp][1024];
+  __shared__ double red[5][1024];
   __shared__ int redf[1024];
-  double g[kMaxResp] = {0, 0, 0, 0};
-  int bad = 0;
-  for (int i = threadIdx.x; i < f.T; i += 1024) {
-    const ColPar& c = f.cp[i];
-    bad |= c.bad;
-    if (with_grad) {
-      double A = 0.0, B = 0.0;
-      for (int rg = 0; rg < f.n_rg; ++rg) {
-        A += f.abpart[((size_t)rg * f.T + i) * 2 + 0];
-        B += f.abpart[((size_t)rg * f.T + i) * 2 + 1];
-      }
-      for (int q = 0; q < f.nresp; ++q) g[q] += A * c.J[0][q] + B * c.J[1][q];
-    }
+  const int t = threadIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  int fl = 0;
+  for (int b = t; b < f.n_rowblk; b += 1024) {
+    acc[0] += f.nllpart[b];
+    fl |= f.flagpart[b];
   }
-  for (int q = 0; q < kMaxResp; ++q) red[q][threadIdx.x] = g[q];
-  redf[threadIdx.x] = bad;
+  for (int b = t; b < f.n_cpblk; b += 1024) fl |= f.cpflag[b];
+  if (with_grad)
+    for (int b = t; b < f.n_bwdblk; b += 1024)
+      for (int q = 0; q < 4; ++q) acc[1 + q] += f.bwdpart[(size_t)b * 4 + q];
+  for (int q = 0; q < 5; ++q) red[q][t] = acc[q];
+  redf[t] = fl;
   __syncthreads();
   for (int st = 512; st >= 1; st >>= 1) {
-    if ((int)threadIdx.x < st) {
-      for (int q = 0; q < kMaxResp; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
-      redf[threadIdx.x] |= redf[threadIdx.x + st];
+    if (t < st) {
+      for (int q = 0; q < 5; ++q) red[q][t] += red[q][t + st];
+      redf[t] |= redf[t + st];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double nll = 0.0;
-    int fl = redf[0];
-    for (int b = 0; b < f.n_rowblk; ++b) {
-      nll += f.nllpart[b];
-      fl |= f.flagpart[b];
-    }
+  double tot[5];
+  for (int q = 0; q < 5; ++q) tot[q] = red[q][0];
+  const int flags0 = redf[0];
+  __syncthreads();
+  // rate gradient: species s = t % 16, row blocks b = t / 16 + 64 n
+  double gr = 0.0;
+  for (int b = t >> 4; b < f.n_rowblk; b += 64) gr += f.gpart[b * kSP + (t & 15)];
+  red[0][t] = gr;
+  __syncthreads();
+  for (int st = 512; st >= 16; st >>= 1) {
+    if (t < st) red[0][t] += red[0][t + st];
+    __syncthreads();
+  }
+  if (t < f.S) {
+    double a = red[0][t];
+    if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + t];
+    f.out[1 + t] = a;
+  }
+  if (t == 0) {
+    int flags = flags0;
+    double nll = tot[0];
     if (f.mv && f.n_rad > 0) {
       nll += f.rad_out[0];
-      fl |= (int)f.rad_out[1];
+      flags |= (int)f.rad_out[1];
     }
-    if (!with_grad) fl &= ~kZeroWidth;
-    f.out[0] = (fl & ~kZeroWidth) ? INFINITY : nll;
-    f.out[1 + f.P] = (double)fl;
-    for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = red[q][0];
-  }
-  if (threadIdx.x < 16 && (int)threadIdx.x < f.S) {
-    double a = 0.0;
-    for (int b = 0; b < f.n_rowblk; ++b) a += f.gpart[b * kSP + threadIdx.x];
-    if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + threadIdx.x];
-    f.out[1 + threadIdx.x] = a;
+    if (!with_grad) flags &= ~kZeroWidth;
+    f.out[0] = (flags & ~kZeroWidth) ? INFINITY : nll;
+    f.out[1 + f.P] = (double)flags;
+    for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Launch sequence of one evaluation for the fits in `active` (n of them);
-// `shape` holds the per-launch grid sizes (maxima over the batch).
-
-
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
                  bool with_grad, hipStream_t st, hipEvent_t* ev) {
   const dim3 blk(kBlock);
@@ -541,28 +609,28 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
     if (ev) (void)hipEventRecord(ev[k], st);
   };
   mark(0);
-  hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kBlock - 1) / kBlock, n), blk, 0, st, d_fits, d_active);
-  const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), gr((L.max_NS + kBlock - 1) / kBlock, n);
+  hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st, d_fits,
+                     d_active);
+  const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), grow(L.max_rowblk, n);
+  const dim3 gred((L.max_NS + kBlock - 1) / kBlock, n), bf(kFwdWaves * 64);
   mark(1);
   if (L.prec == kF32) {
-    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, blk, 0, st, d_fits, d_active);
-    else hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, blk, 0, st, d_fits, d_active);
+    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, bf, 0, st, d_fits, d_active);
+    else hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, bf, 0, st, d_fits, d_active);
     mark(2);
-    hipLaunchKernelGGL(k_reduce_M<float>, gr, blk, 0, st, d_fits, d_active);
+    hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);
   } else {
-    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, blk, 0, st, d_fits, d_active);
-    else hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, blk, 0, st, d_fits, d_active);
+    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, bf, 0, st, d_fits, d_active);
+    else hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, bf, 0, st, d_fits, d_active);
     mark(2);
-    hipLaunchKernelGGL(k_reduce_M<double>, gr, blk, 0, st, d_fits, d_active);
+    hipLaunchKernelGGL(k_reduce_M<double>, gred, blk, 0, st, d_fits, d_active);
   }
   mark(3);
-  hipLaunchKernelGGL(k_rowterms, dim3(L.max_rowblk, n), blk, 0, st, d_fits, d_active);
+  hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
   mark(4);
   if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
   mark(5);
-  if (with_grad) {
-    hipLaunchKernelGGL(k_adjoint, gr, blk, 0, st, d_fits, d_active);
-  }
+  if (with_grad) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
   mark(6);
   if (with_grad) {
     if (L.prec == kF32) {
@@ -577,7 +645,6 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
   hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
   mark(8);
 }
-
 
 // Expected counts of every term over the full reco range (diagnostics):
 // out = [mu_energy[N] | mu_tagged[N] | nu[n_rad] | lambda[N][n_ps]].

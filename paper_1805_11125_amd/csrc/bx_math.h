@@ -91,19 +91,27 @@ BX_HD GGShape gg_shape(const GGConst& c, double k, bool full) {
   const double a1 = c.ip, a2 = 2.0 * c.ip;
   double x = k, lnprod = 0.0, dsum = 0.0, lnprodD = 0.0, dsumD = 0.0, lnprodG = 0.0, psum = 0.0;
   if (k < kShift) {
-    double prG = 1.0, prD = 1.0, prGam = 1.0;
+    // products over m < shift of (k+m), (k+m+1/p), (k+m+2/p) and their k
+    // derivatives (product rule), so the logarithmic derivatives need one
+    // division each: ln Gamma(k + a) = ln Gamma(k + shift + a) - sum_m ln(k + m + a)
+    double P0 = 1.0, P1 = 1.0, P2 = 1.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
     for (int m = 0; m < (int)kShift; ++m) {
       const double km = k + m;
-      prG *= (km + a2) * km / ((km + a1) * (km + a1));
-      prD *= (km + a1) / km;
-      prGam *= km;
-      dsum += 1.0 / (km + a2) + 1.0 / km - 2.0 / (km + a1);
-      dsumD += 1.0 / (km + a1) - 1.0 / km;
-      psum += 1.0 / km;
+      d0 = d0 * km + P0;
+      P0 *= km;
+      d1 = d1 * (km + a1) + P1;
+      P1 *= km + a1;
+      d2 = d2 * (km + a2) + P2;
+      P2 *= km + a2;
     }
-    lnprod = log(prG);
-    lnprodD = log(prD);
-    lnprodG = log(prGam);
+    const double l0 = log(P0), l1 = log(P1), l2 = log(P2);
+    const double q0 = d0 / P0, q1 = d1 / P1, q2 = d2 / P2;
+    lnprod = l2 + l0 - 2.0 * l1;
+    dsum = q2 + q0 - 2.0 * q1;
+    lnprodD = l1 - l0;
+    dsumD = q1 - q0;
+    lnprodG = l0;
+    psum = q0;
     x = k + kShift;
   }
   o.G = series_inv(c.cG, kSeriesTerms, x) - lnprod;
@@ -128,20 +136,39 @@ BX_HD GGShape gg_shape(const GGConst& c, double k, bool full) {
 
 // Shape k of the GG with ln(1 + Var/Mean^2) = tau: Newton in u = ln k.
 BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters) {
-  double u = -log(c.p * c.p * tau);   // large-k limit G ~ 1/(p^2 k)
-  if (tau > 1.0) u = -tau;            // small-k limit G ~ -ln k
+  // start: G ~ cG1/k + cG2/k^2 for large k (solve the quadratic), G ~ -ln k
+  // for small k
+  double u;
+  if (tau < 0.1) {
+    const double a1 = c.cG[1], a2 = c.cG[2];
+    u = log((a1 + sqrt(fmax(a1 * a1 + 4.0 * tau * a2, 0.0))) / (2.0 * tau));
+  } else {
+    u = tau > 1.0 ? -tau : -log(c.p * c.p * tau);
+  }
   int it = 0;
-  for (; it < 60; ++it) {
+  for (; it < 40; ++it) {
     const double k = exp(u);
     const GGShape s = gg_shape(c, k, false);
     double du = (s.G - tau) / (k * s.dG);
     du = fmax(-2.0, fmin(2.0, du));
     u -= du;
-    if (fabs(du) < 4e-16 * fmax(1.0, fabs(u))) break;
+    // quadratic convergence: after a step below 1e-9 the error is ~1e-18
+    if (fabs(du) < 1e-9) break;
   }
   if (iters) *iters = it;
   return exp(u);
 }
+
+// Reciprocal: the FP32 hardware reciprocal (1 ulp) on the GPU, exact division
+// otherwise.
+BX_HD float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+BX_HD double rcp(double x) { return 1.0 / x; }
 
 // phi(t) = e^t - 1 - t (accurate for small t); also returns e^t - 1.
 template <class R>
@@ -274,7 +301,7 @@ BX_HD EdgeVal<R> gg_edge_small(R t, const GGCol<R>& c) {
   if (y < k + (R)1) {
     R a = (R)1, da = (R)0, S = (R)1, dS = (R)0;
     for (int n = 1; n < itmax; ++n) {
-      const R inv = (R)1 / (k + (R)n);
+      const R inv = rcp(k + (R)n);
       const R an = a * y * inv;
       da = (da * y - an) * inv;
       a = an;
@@ -291,7 +318,7 @@ BX_HD EdgeVal<R> gg_edge_small(R t, const GGCol<R>& c) {
     const R tiny = f32 ? (R)1e-30 : (R)1e-300;
     R b = y + (R)1 - k, db = (R)-1;
     R cc = (R)1 / tiny, dcc = (R)0;
-    R d = (R)1 / b, dd = -db * d * d;
+    R d = rcp(b), dd = -db * d * d;
     R h = d, dh = dd;
     for (int i = 1; i < itmax; ++i) {
       const R an = -(R)i * ((R)i - k), dan = (R)i;
@@ -299,10 +326,11 @@ BX_HD EdgeVal<R> gg_edge_small(R t, const GGCol<R>& c) {
       R dn = an * d + b;
       R ddn = dan * d + an * dd + db;
       if (fabs(dn) < tiny) dn = tiny;
-      R cn = b + an / cc;
-      R dcn = db + (dan * cc - an * dcc) / (cc * cc);
+      const R icc = rcp(cc);
+      R cn = b + an * icc;
+      R dcn = db + (dan * cc - an * dcc) * icc * icc;
       if (fabs(cn) < tiny) cn = tiny;
-      d = (R)1 / dn;
+      d = rcp(dn);
       dd = -ddn * d * d;
       cc = cn;
       dcc = dcn;

@@ -48,6 +48,7 @@ struct DeviceFit {
   double* d_out = nullptr;
 };
 size_t device_fit_bytes(const HostModel& h);
+void derive_tiles(const HostModel& h, FitDev* f);
 // Carve `base` (device memory of device_fit_bytes(h)) and upload h; stream-ordered.
 bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st);
 bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st);

@@ -139,13 +139,7 @@ static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
       for (auto& r : act) {
         if (r->h.kind != kind || r->h.prec != prec) continue;
         FitDev f{};
-        f.T = r->h.T; f.N = r->h.N; f.mv = r->h.mv; f.n_rad = r->h.n_rad;
-        f.kind = kind; f.prec = prec;
-        f.n_rt = (f.N + kRowStep - 1) / kRowStep;
-        f.n_ct = (f.T + kColTile - 1) / kColTile;
-        f.n_cg = (f.n_ct + r->h.tiles.CG - 1) / r->h.tiles.CG;
-        f.n_rg = (f.n_rt + r->h.tiles.RG - 1) / r->h.tiles.RG;
-        f.n_rowblk = (f.N + 15) / 16;
+        derive_tiles(r->h, &f);
         const LaunchShape l = shape_of(f);
         L.max_T = std::max(L.max_T, l.max_T);
         L.max_fwd_blocks = std::max(L.max_fwd_blocks, l.max_fwd_blocks);
