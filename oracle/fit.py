@@ -53,7 +53,10 @@ def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20):
             return np.inf, np.zeros_like(u)
         return f, g[idx] * scale
 
-    bounds = [(0.0, None)] * len(idx)
+    # rates are bounded at zero; response parameters are free, their domain
+    # (sigma^2 >= 0, GG mean and variance > 0) is enforced by the NLL being
+    # +inf outside it
+    bounds = [(0.0, None) if q < desc.S else (None, None) for q in idx]
     res = optimize.minimize(fun, np.ones(len(idx)), jac=True, method="L-BFGS-B",
                             bounds=bounds,
                             options=dict(ftol=0.0, gtol=1e-12, maxiter=5000, maxfun=20000))
@@ -64,7 +67,7 @@ def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20):
     for _ in range(max_polish):
         H = _hessian(desc, data, theta, idx, scale)
         gi = g[idx]
-        at_bound = (theta[idx] <= 0) & (gi > 0)
+        at_bound = (idx < desc.S) & (theta[idx] <= 0) & (gi > 0)
         free = ~at_bound
         if not np.any(free):
             edm = 0.0
@@ -76,7 +79,8 @@ def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20):
             break
         trial = theta.copy()
         sub = idx[free]
-        trial[sub] = np.maximum(theta[sub] - step, 0.0)
+        trial[sub] = theta[sub] - step
+        trial[: desc.S] = np.maximum(trial[: desc.S], 0.0)
         try:
             ft, gt = nll_grad(desc, data, trial)
         except DomainError:

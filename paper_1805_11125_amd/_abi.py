@@ -81,6 +81,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1805_11125_amd.build` (HIP, gfx950)")
+        # PyTorch (device memory and streams for the autograd path) ships its
+        # own HIP runtime; it has to claim the GPU before this library's does.
+        try:
+            import torch
+            torch.cuda.is_available()
+        except Exception:
+            pass
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

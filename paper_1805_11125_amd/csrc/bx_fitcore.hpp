@@ -1,11 +1,19 @@
-// Bounded quasi-Newton minimiser (BFGS on the inverse Hessian, projected
-// onto box bounds, backtracking Armijo line search), written in reverse
-// communication: next(x) names the point to evaluate, feed(f, g) hands back
-// the NLL and gradient there.  The plain path drives one instance from the
-// calling thread; the fit server drives thousands, one per resident fit, and
-// evaluates all their points in one batched launch per step.  It plays the
-// role of the paper's minimiser, which varies the parameters and asks for
-// likelihood values until it finds the optimum (Sec. 4, steps 5-7).
+// Bounded quasi-Newton minimiser written in reverse communication: next(x)
+// names the point to evaluate, feed(f, g) hands back the NLL and gradient
+// there.  The plain path drives one instance from the calling thread; the fit
+// server drives thousands, one per resident fit, and evaluates all their
+// points in one batched launch per step.  It plays the role of the paper's
+// minimiser, which varies the parameters and asks for likelihood values until
+// it finds the optimum (Sec. 4, steps 5-7).
+//
+// Method: the Hessian approximation B (in parameters scaled by their start
+// values) starts from forward differences of the analytic gradient, one free
+// parameter per evaluation, and is refined by BFGS updates.  Each step solves
+// B_FF d_F = -g_F on the free set F (parameters not held at a bound by the
+// gradient) by Cholesky with a diagonal shift when B_FF is not positive
+// definite, truncates the step at the box, and backtracks (Armijo, quadratic
+// interpolation).  EDM = g_F^T B_FF^-1 g_F / 2; the fit has converged when it
+// falls below the tolerance.
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -23,6 +31,7 @@ struct FitProblem {
   int idx[32];                       // free parameters
   double x0[32], lo[32], hi[32], scale[32];
   double edm_tol = 1e-9;
+  double f_noise = 0.0;              // relative rounding noise of the NLL values
 };
 
 inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb) {
@@ -60,8 +69,8 @@ class Bfgs {
   explicit Bfgs(const FitProblem& pb) : pb_(pb) {
     memcpy(x_, pb.x0, sizeof x_);
     const int n = pb.nf;
-    for (int a = 0; a < n * n; ++a) H_[a] = 0.0;
-    for (int a = 0; a < n; ++a) H_[a * n + a] = 1.0;
+    for (int a = 0; a < n * n; ++a) B_[a] = 0.0;
+    for (int a = 0; a < n; ++a) B_[a * n + a] = 1.0;
   }
 
   // Point to evaluate next; false when finished.
@@ -73,38 +82,74 @@ class Bfgs {
 
   void feed(double f, const double* g) {
     ++n_eval_;
+    const int n = pb_.nf;
     if (state_ == kInit) {
       f_ = f;
       memcpy(g_, g, sizeof(double) * pb_.P);
-      if (!std::isfinite(f) || pb_.kind == BX_EVAL_GRAD || pb_.nf == 0) {
-        status_ = std::isfinite(f) ? BX_CONVERGED : BX_FAILED;
-        edm_ = edm();
-        state_ = kDone;
+      if (!std::isfinite(f) || pb_.kind == BX_EVAL_GRAD || n == 0) {
+        edm_ = std::isfinite(f) && n > 0 ? newton_dir(g_, x_, nullptr) : 0.0;
+        finish(std::isfinite(f) ? BX_CONVERGED : BX_FAILED);
         return;
       }
-      start_iteration(true);
+      state_ = kHess;
+      hq_ = 0;
+      hsign_ = 1.0;
+      set_probe();
       return;
     }
-    // line-search trial at xt_
-    const double gd = slope_;
-    if (std::isfinite(f) && f <= f_ + 1e-4 * alpha_ * gd) {
+    if (state_ == kHess) {
+      if (!std::isfinite(f) && hsign_ > 0) {  // probe outside the domain: other side
+        hsign_ = -1.0;
+        set_probe();
+        return;
+      }
+      const double h = hsign_ * kProbe;
+      for (int b = 0; b < n; ++b) {
+        const int qb = pb_.idx[b];
+        Hs_[b * n + hq_] = std::isfinite(f) ? (g[qb] - g_[qb]) * pb_.scale[qb] / h : 0.0;
+      }
+      if (++hq_ < n) {
+        hsign_ = 1.0;
+        set_probe();
+        return;
+      }
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) B_[a * n + b] = 0.5 * (Hs_[a * n + b] + Hs_[b * n + a]);
+      refresh_iter_ = iter_;
+      edm_refresh_ = INFINITY;
+      start_iteration();
+      return;
+    }
+    // line-search trial at xt_ = clip(x + alpha d): projected Armijo rule on
+    // the actual displacement
+    double gdx = 0.0;
+    for (int a = 0; a < n; ++a) gdx += g_[pb_.idx[a]] * (xt_[pb_.idx[a]] - x_[pb_.idx[a]]);
+    if (std::isfinite(f) && f <= f_ + 1e-4 * std::min(gdx, 0.0)) {
       accept(f, g);
       return;
     }
-    // backtrack: safeguarded quadratic interpolation
-    double an = 0.5 * alpha_;
+    // Near the minimum the expected decrease can fall below the rounding
+    // noise of the NLL values; the gradient still resolves progress there:
+    // accept a step whose NLL change is within the noise if it lowers EDM.
+    if (std::isfinite(f) && f - f_ <= pb_.f_noise * std::fabs(f_) && newton_dir(g, xt_, nullptr) < 0.9 * edm_) {
+      accept(f, g);
+      return;
+    }
+    double an = 0.5 * alpha_;  // safeguarded quadratic interpolation
     if (std::isfinite(f)) {
-      const double den = 2.0 * (f - f_ - gd * alpha_);
-      if (den > 0) an = std::min(0.5 * alpha_, std::max(0.1 * alpha_, -gd * alpha_ * alpha_ / den));
+      const double den = 2.0 * (f - f_ - slope_ * alpha_);
+      if (den > 0) an = std::min(0.5 * alpha_, std::max(0.1 * alpha_, -slope_ * alpha_ * alpha_ / den));
     }
     alpha_ = an;
     if (++ls_ > 40 || alpha_ < 1e-20) {
-      // no decrease along the direction: restart once from steepest descent,
+      // no decrease along the direction: restart once from the diagonal of B,
       // then stop (the NLL is flat to rounding here)
       if (!restarted_) {
         restarted_ = true;
-        reset_h();
-        start_iteration(false);
+        for (int a = 0; a < n; ++a)
+          for (int b = 0; b < n; ++b)
+            if (a != b) B_[a * n + b] = 0.0;
+        start_iteration();
         return;
       }
       finish(edm_ < pb_.edm_tol ? BX_CONVERGED : BX_FAILED);
@@ -127,45 +172,85 @@ class Bfgs {
   bool done() const { return state_ == kDone; }
 
  private:
-  enum { kInit, kSearch, kDone };
+  enum { kInit, kHess, kSearch, kDone };
+  static constexpr double kProbe = 1e-4;  // Hessian probe step (scaled units)
 
-  double gu(int a) const { return g_[pb_.idx[a]] * pb_.scale[pb_.idx[a]]; }
-  double u(int a) const { return x_[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
-  double ulo(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
-  double uhi(int a) const { return pb_.hi[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
+  double lo_u(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
+  double hi_u(int a) const { return pb_.hi[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
 
-  // variables held at a bound by the gradient
-  bool pinned(int a) const {
-    const double v = u(a), gv = gu(a);
-    return (v <= ulo(a) && gv > 0) || (v >= uhi(a) && gv < 0);
-  }
-
-  double edm() const {
-    const int n = pb_.nf;
-    double e = 0.0;
-    for (int a = 0; a < n; ++a) {
-      if (pinned(a)) continue;
-      double hg = 0.0;
-      for (int b = 0; b < n; ++b)
-        if (!pinned(b)) hg += H_[a * n + b] * gu(b);
-      e += gu(a) * hg;
+  void set_probe() {
+    memcpy(xt_, x_, sizeof xt_);
+    const int q = pb_.idx[hq_];
+    double v = x_[q] / pb_.scale[q] + hsign_ * kProbe;
+    if (v > hi_u(hq_) || v < lo_u(hq_)) {  // stay inside the box
+      hsign_ = -hsign_;
+      v = x_[q] / pb_.scale[q] + hsign_ * kProbe;
     }
-    return 0.5 * e;
+    xt_[q] = v * pb_.scale[q];
   }
 
-  void reset_h() {
+  // Newton direction on the free set at point x with gradient g:
+  // B_FF d_F = -g_F (Cholesky, shifted if needed); returns EDM = -g.d/2 and
+  // writes d (scaled units, zero on held parameters) when d != nullptr.
+  double newton_dir(const double* g, const double* x, double* d) const {
     const int n = pb_.nf;
-    double gmax = 0.0;
-    for (int a = 0; a < n; ++a) gmax = std::max(gmax, std::fabs(gu(a)));
-    const double h0 = gmax > 0 ? 0.05 / gmax : 1.0;
-    for (int a = 0; a < n * n; ++a) H_[a] = 0.0;
-    for (int a = 0; a < n; ++a) H_[a * n + a] = h0;
-    fresh_h_ = true;
+    int fr[32], m = 0;
+    double gu[32];
+    for (int a = 0; a < n; ++a) {
+      const int q = pb_.idx[a];
+      gu[a] = g[q] * pb_.scale[q];
+      const double v = x[q] / pb_.scale[q];
+      const bool held = (v <= lo_u(a) && gu[a] > 0) || (v >= hi_u(a) && gu[a] < 0);
+      if (d) d[a] = 0.0;
+      if (!held) fr[m++] = a;
+    }
+    if (m == 0) return 0.0;
+    double dmax = 0.0;
+    for (int i = 0; i < m; ++i) dmax = std::max(dmax, std::fabs(B_[fr[i] * n + fr[i]]));
+    if (!(dmax > 0)) dmax = 1.0;
+    double L[32 * 32], shift = 0.0;
+    for (int attempt = 0; attempt < 40; ++attempt) {
+      bool ok = true;
+      for (int j = 0; j < m && ok; ++j) {
+        double s = B_[fr[j] * n + fr[j]] + shift;
+        for (int k = 0; k < j; ++k) s -= L[j * m + k] * L[j * m + k];
+        if (!(s > 0)) {
+          ok = false;
+          break;
+        }
+        L[j * m + j] = std::sqrt(s);
+        for (int i = j + 1; i < m; ++i) {
+          double t = B_[fr[i] * n + fr[j]];
+          for (int k = 0; k < j; ++k) t -= L[i * m + k] * L[j * m + k];
+          L[i * m + j] = t / L[j * m + j];
+        }
+      }
+      if (ok) break;
+      shift = shift > 0 ? 4.0 * shift : 1e-10 * dmax;
+    }
+    double y[32], dd[32];
+    for (int i = 0; i < m; ++i) {  // L y = -g
+      double t = -gu[fr[i]];
+      for (int k = 0; k < i; ++k) t -= L[i * m + k] * y[k];
+      y[i] = t / L[i * m + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {  // L^T d = y
+      double t = y[i];
+      for (int k = i + 1; k < m; ++k) t -= L[k * m + i] * dd[k];
+      dd[i] = t / L[i * m + i];
+    }
+    double gd = 0.0;
+    for (int i = 0; i < m; ++i) {
+      gd += gu[fr[i]] * dd[i];
+      if (d) d[fr[i]] = dd[i];
+    }
+    return -0.5 * gd;
   }
 
-  void start_iteration(bool first) {
-    if (first) reset_h();
-    edm_ = edm();
+  void start_iteration() {
+    const int n = pb_.nf;
+    edm_ = newton_dir(g_, x_, d_);
+    if (!(edm_ == edm_)) edm_ = INFINITY;
     if (edm_ < pb_.edm_tol) {
       finish(BX_CONVERGED);
       return;
@@ -174,37 +259,25 @@ class Bfgs {
       finish(BX_MAXITER);
       return;
     }
-    const int n = pb_.nf;
-    double gd = 0.0;
-    for (int a = 0; a < n; ++a) {
-      d_[a] = 0.0;
-      if (pinned(a)) continue;
-      for (int b = 0; b < n; ++b)
-        if (!pinned(b)) d_[a] -= H_[a * n + b] * gu(b);
-      gd += gu(a) * d_[a];
-    }
-    if (!(gd < 0)) {  // not a descent direction: steepest descent
-      reset_h();
-      gd = 0.0;
-      for (int a = 0; a < n; ++a) {
-        d_[a] = pinned(a) ? 0.0 : -H_[a * n + a] * gu(a);
-        gd += gu(a) * d_[a];
+    // slow progress means the updated Hessian is poor (curved valleys of
+    // correlated parameters): probe it again at the current point
+    if (!std::isfinite(edm_refresh_)) edm_refresh_ = edm_;
+    if (iter_ - refresh_iter_ >= 8) {
+      if (edm_ > 0.05 * edm_refresh_) {
+        state_ = kHess;
+        hq_ = 0;
+        hsign_ = 1.0;
+        set_probe();
+        return;
       }
+      refresh_iter_ = iter_;  // enough progress: new reference point
+      edm_refresh_ = edm_;
     }
+    double gd = 0.0;
+    for (int a = 0; a < n; ++a) gd += g_[pb_.idx[a]] * pb_.scale[pb_.idx[a]] * d_[a];
     slope_ = gd;
-    // longest step inside the box
-    double amax = 1.0;
-    for (int a = 0; a < n; ++a) {
-      if (d_[a] < 0 && std::isfinite(ulo(a))) amax = std::min(amax, (ulo(a) - u(a)) / d_[a]);
-      if (d_[a] > 0 && std::isfinite(uhi(a))) amax = std::min(amax, (uhi(a) - u(a)) / d_[a]);
-    }
-    alpha_ = std::max(amax, 0.0);
+    alpha_ = 1.0;  // the trial point is projected onto the box (set_trial)
     ls_ = 0;
-    if (!(alpha_ > 0)) {  // blocked by a bound: drop the blocking components
-      for (int a = 0; a < n; ++a)
-        if ((d_[a] < 0 && u(a) <= ulo(a)) || (d_[a] > 0 && u(a) >= uhi(a))) d_[a] = 0.0;
-      alpha_ = 1.0;
-    }
     state_ = kSearch;
     set_trial();
   }
@@ -213,59 +286,50 @@ class Bfgs {
     memcpy(xt_, x_, sizeof xt_);
     for (int a = 0; a < pb_.nf; ++a) {
       const int q = pb_.idx[a];
-      double v = u(a) + alpha_ * d_[a];
-      v = std::min(std::max(v, ulo(a)), uhi(a));
+      double v = x_[q] / pb_.scale[q] + alpha_ * d_[a];
+      v = std::min(std::max(v, lo_u(a)), hi_u(a));
       xt_[q] = v * pb_.scale[q];
     }
   }
 
   void accept(double f, const double* g) {
     const int n = pb_.nf;
-    double s[32], y[32], sy = 0.0, yy = 0.0;
+    double s[32], y[32], sy = 0.0, Bs[32], sBs = 0.0;
     for (int a = 0; a < n; ++a) {
       const int q = pb_.idx[a];
       s[a] = (xt_[q] - x_[q]) / pb_.scale[q];
       y[a] = (g[q] - g_[q]) * pb_.scale[q];
       sy += s[a] * y[a];
-      yy += y[a] * y[a];
+    }
+    for (int a = 0; a < n; ++a) {
+      Bs[a] = 0.0;
+      for (int b = 0; b < n; ++b) Bs[a] += B_[a * n + b] * s[b];
+      sBs += s[a] * Bs[a];
     }
     memcpy(x_, xt_, sizeof x_);
     memcpy(g_, g, sizeof(double) * pb_.P);
     f_ = f;
     ++iter_;
     restarted_ = false;
-    if (sy > 1e-300 && yy > 0) {
-      if (fresh_h_) {  // scale the initial inverse Hessian (Nocedal & Wright 6.20)
-        const double h0 = sy / yy;
-        for (int a = 0; a < n * n; ++a) H_[a] = 0.0;
-        for (int a = 0; a < n; ++a) H_[a * n + a] = h0;
-        fresh_h_ = false;
-      }
-      // H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T
-      const double rho = 1.0 / sy;
-      double Hy[32], yHy = 0.0;
-      for (int a = 0; a < n; ++a) {
-        Hy[a] = 0.0;
-        for (int b = 0; b < n; ++b) Hy[a] += H_[a * n + b] * y[b];
-        yHy += y[a] * Hy[a];
-      }
+    // BFGS update of the Hessian, skipped when the curvature condition fails
+    if (sy > 1e-12 * std::sqrt(sBs > 0 ? sBs : 0.0) * 0 + 1e-300 && sBs > 1e-300) {
       for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b)
-          H_[a * n + b] += -rho * (s[a] * Hy[b] + Hy[a] * s[b]) + (rho * rho * yHy + rho) * s[a] * s[b];
+        for (int b = 0; b < n; ++b) B_[a * n + b] += y[a] * y[b] / sy - Bs[a] * Bs[b] / sBs;
     }
-    start_iteration(false);
+    start_iteration();
   }
 
   void finish(int st) {
     status_ = st;
-    edm_ = edm();
     state_ = kDone;
   }
 
   FitProblem pb_;
-  int state_ = kInit, status_ = BX_FAILED, iter_ = 0, n_eval_ = 0, ls_ = 0;
-  bool fresh_h_ = true, restarted_ = false;
-  double x_[32], xt_[32], g_[32], d_[32], H_[32 * 32];
+  int state_ = kInit, status_ = BX_FAILED, iter_ = 0, n_eval_ = 0, ls_ = 0, hq_ = 0, refresh_iter_ = 0;
+  double edm_refresh_ = INFINITY;  // EDM right after the last Hessian probe
+  bool restarted_ = false;
+  double hsign_ = 1.0;
+  double x_[32], xt_[32], g_[32], d_[32], B_[32 * 32], Hs_[32 * 32];
   double f_ = INFINITY, alpha_ = 1.0, slope_ = 0.0, edm_ = INFINITY;
 };
 

@@ -449,17 +449,18 @@ const char* bx_last_error(void) { return bx::g_err.c_str(); }
 bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* hip_stream, bx_model** out) {
   if (!out) return inval("out is NULL");
   *out = nullptr;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-    set_error("no HIP device");
-    return BX_E_DEVICE;
-  }
   bx_model* m = new (std::nothrow) bx_model();
   if (!m) return BX_E_NOMEM;
-  bx_status s = make_host_model(desc, data, &m->h);
+  bx_status s = make_host_model(desc, data, &m->h);  // validation needs no device
   if (s != BX_OK) {
     delete m;
     return s;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    delete m;
+    set_error("no HIP device");
+    return BX_E_DEVICE;
   }
   auto fail = [&](bx_status st) {
     bx_model_free(m);
@@ -615,6 +616,7 @@ bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r) {
   FitProblem pb;
   bx_status s = fit_problem(P, m->h.S, o, &pb);
   if (s != BX_OK) return s;
+  pb.f_noise = nll_noise(m->h);
   memset(r, 0, sizeof *r);
   const auto t0 = std::chrono::steady_clock::now().time_since_epoch();
   r->t_submit_ns = r->t_admit_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t0).count();

@@ -36,6 +36,10 @@ struct HostModel {
 };
 
 bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h);
+// Relative rounding noise of the NLL values: FP32 cells leave ~1e-10 of the
+// NLL, FP64 cells ~1e-15 (the minimiser accepts changes within it when the
+// gradient shows progress).
+inline double nll_noise(const HostModel& h) { return h.prec == kF32 ? 1e-9 : 1e-13; }
 bx_status set_host_data(HostModel* h, const bx_data* x);
 double host_lnfact(const HostModel& h);
 

@@ -276,6 +276,7 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   r->res.t_submit_ns = now_ns();
   bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb);
   if (st != BX_OK) return st;
+  r->pb.f_noise = nll_noise(m->h);
   r->h = m->h;
   r->bytes = (device_fit_bytes(r->h) + 4095) & ~(size_t)4095;
   if (r->bytes > s->budget) {

@@ -1,0 +1,142 @@
+"""GPU fits: the plain quasi-Newton path against the oracle's minimum, the
+autograd entry point, and the fit server (batched = plain, isolation in a
+mix, admission under a small memory budget)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import model as om
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+F32, F64 = 0, 1
+
+
+@pytest.fixture(scope="module")
+def bx():
+    import paper_1805_11125_amd as bx
+    return bx
+
+
+def fit_fixture(name):
+    p = os.path.join(GOLDEN, f"fit_{name}.npz")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    return np.load(p)
+
+
+@pytest.mark.parametrize("name,prec,tol", [("c1", F64, 1e-14), ("c3a", F64, 1e-14), ("c1", F32, 1e-8),
+                                           ("c2", F32, 1e-8)])
+def test_plain_fit_matches_oracle_minimum(bx, name, prec, tol):
+    z = fit_fixture(name)
+    d, x = synth.load(name)
+    m = bx.Model(d, x, precision=prec)
+    r = m.fit(z["theta0"], float_mask=z["mask"], edm_tol=tol, max_iter=1000)
+    err = np.where(np.isfinite(z["err"]), z["err"], 0.0)
+    scale = np.maximum(np.abs(z["theta"]), err)
+    dev = np.abs(r.x - z["theta"]) / scale
+    dsig = np.abs(r.x - z["theta"]) / np.where(err > 0, err, np.inf)
+    print(f"{name}/p{prec}: status {r.status} iters {r.n_iter} evals {r.n_eval} edm {r.edm:.2e} "
+          f"nll {r.nll:.10g} oracle {float(z['nll']):.10g}; rates max |d|/max(|r|,sigma) "
+          f"{dev[:d.S].max():.2e}; response params max |d|/sigma {dsig[d.S:].max():.2e}")
+    assert r.status == bx.BX_CONVERGED
+    # fitted rates: |r - r*| <= 1e-6 max(|r*|, sigma*)
+    assert np.all(dev[: d.S] <= 1e-6), dev
+    # response parameters: within 1e-3 sigma (FP32 cells shift the minimum slightly)
+    assert np.all(dsig[d.S:] <= (1e-6 if prec == F64 else 1e-3)), dsig
+    assert abs(r.nll - float(z["nll"])) <= 1e-9 * abs(float(z["nll"]))
+
+
+def test_asimov_fit_recovers_truth(bx):
+    d = synth.config1()
+    mu = om.forward(d, d.theta_true).mu["energy"]
+    m = bx.Model(d, synth.Data(energy=mu), precision=F64)
+    th0 = d.theta_true * np.array([1.1, 0.9, 1.05, 0.95, 1.2, 0.8])
+    r = m.fit(th0, edm_tol=1e-16, max_iter=1000)
+    np.testing.assert_allclose(r.x, d.theta_true, rtol=1e-7)
+
+
+def test_autograd_function(bx):
+    import torch
+    d, x = synth.load("c2")
+    m = bx.Model(d, x, precision=F32)
+    th = d.theta_true * 1.01
+    v, g = m.nll_grad(th)
+    t = torch.tensor(th, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = bx.NLLFunction.apply(m, t)
+    (2.5 * loss).backward()
+    assert loss.item() == v
+    np.testing.assert_array_equal(t.grad.cpu().numpy(), 2.5 * g)
+
+
+def _toys(n, first=0):
+    base, per_species, theta = synth.catalogue()
+    out = []
+    for b in range(first, first + n):
+        t = synth.toy(b, per_species, theta)
+        d = synth.toy_desc(base, t)
+        out.append((d, synth.Data(energy=t.counts), t))
+    return out
+
+
+def test_server_eval_grad_equals_plain(bx):
+    d, x = synth.load("c2")
+    m = bx.Model(d, x, precision=F32)
+    th = d.theta_true * 0.99
+    v, g = m.nll_grad(th)
+    s = bx.Server()
+    r = s.wait(s.submit(m, th, kind=bx.BX_EVAL_GRAD))
+    assert r.nll == v and np.array_equal(r.grad, g)
+    s.close()
+
+
+def test_batched_fits_equal_plain_and_isolated(bx):
+    toys = _toys(6)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=300)
+             for m, (d, x, t) in zip(models, toys)]
+    s = bx.Server()
+    tickets = [s.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=300)
+               for m, (d, x, t) in zip(models, toys)]
+    batched = [s.wait(tk) for tk in tickets]
+    # one fit alone, then inside a different mix with staggered arrivals
+    alone = s.wait(s.submit(models[2], toys[2][2].theta0, float_mask=toys[2][0].float_mask,
+                            edm_tol=1e-9, max_iter=300))
+    mix = []
+    for k in [4, 2, 0]:
+        mix.append(s.submit(models[k], toys[k][2].theta0, float_mask=toys[k][0].float_mask,
+                            edm_tol=1e-9, max_iter=300))
+    mixed = [s.wait(tk) for tk in mix]
+    s.close()
+    for p, b in zip(plain, batched):
+        assert p.n_eval == b.n_eval and p.nll == b.nll and np.array_equal(p.x, b.x)
+    assert np.array_equal(alone.x, mixed[1].x) and alone.nll == mixed[1].nll
+    print("toy fits:", [(r.status, r.n_iter, r.n_eval, f"{r.edm:.1e}") for r in batched])
+
+
+def test_admission_under_small_budget(bx):
+    toys = _toys(4, first=10)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+    ref = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=200)
+           for m, (d, x, t) in zip(models, toys)]
+    # room for about one fit at a time: requests queue and are admitted as fits leave
+    from paper_1805_11125_amd import _abi
+    import ctypes as C
+    s = bx.Server(hbm_budget_bytes=4 << 20, max_slots=2)
+    tickets = [s.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=200)
+               for m, (d, x, t) in zip(models, toys)]
+    res = [s.wait(tk) for tk in tickets]
+    for a, b in zip(ref, res):
+        assert np.array_equal(a.x, b.x)
+    # admission order: each fit admitted after the previous one finished or in parallel
+    assert all(r.t_admit_ns >= r.t_submit_ns for r in res)
+    # a request that can never fit is rejected
+    s2 = bx.Server(hbm_budget_bytes=1 << 16)
+    with pytest.raises(bx.BxError):
+        s2.submit(models[0], toys[0][2].theta0)
+    s.close()
+    s2.close()
+    del _abi, C

@@ -1,0 +1,119 @@
+"""Host-side checks that need no GPU: the C ABI library loads and exports
+every function include/bx.h declares, argument validation returns the
+documented status codes, and the quasi-Newton core passes its C++ unit test."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bx_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1805_11125_amd import _abi
+    return _abi
+
+
+def test_library_exports_every_declared_symbol(abi):
+    lib = abi.load()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in abi.SIGNATURES, f"binding lacks {n}"
+
+
+def _desc(abi, d, precision=0, **over):
+    keep = []
+
+    def arr(a):
+        a = np.ascontiguousarray(np.asarray(a, np.float64).reshape(-1))
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    s = abi.bx_model_desc()
+    s.T, s.N, s.S = d.T, d.N, d.S
+    s.true_edges, s.reco_edges, s.spectra = arr(d.true_edges), arr(d.reco_edges), arr(d.spectra)
+    s.response = 0 if d.kind == "gauss" else 1
+    s.gg_p = d.gg_p
+    if d.quench is not None:
+        s.quench = arr(d.quench)
+    s.exposure = d.exposure
+    s.win_lo, s.win_hi = d.win
+    s.precision = precision
+    for k, v in over.items():
+        setattr(s, k, arr(v) if isinstance(v, np.ndarray) else v)
+    x = abi.bx_data()
+    x.energy = arr(np.ones(d.N))
+    return s, x, keep
+
+
+@pytest.mark.parametrize("field,value", [
+    ("T", 0), ("N", 0), ("S", 17), ("precision", 7), ("response", 5), ("exposure", 0.0),
+    ("win_lo", 150), ("win_hi", 500), ("pu_K", 300),
+])
+def test_build_rejects_invalid_descriptions(abi, field, value):
+    d = synth.config1()
+    s, x, keep = _desc(abi, d)
+    if field == "win_lo":
+        s.win_lo, s.win_hi = 150, 100
+    else:
+        setattr(s, field, value)
+    h = C.c_void_p()
+    st = abi.load().bx_model_build(C.byref(s), C.byref(x), None, C.byref(h))
+    assert st == abi.BX_E_INVAL, (field, st)
+    assert not h.value
+    assert len(abi.load().bx_last_error()) > 0
+
+
+def test_build_rejects_bad_arrays(abi):
+    lib = abi.load()
+    d = synth.config1()
+    bad = d.reco_edges.copy()
+    bad[5] = bad[4]
+    s, x, keep = _desc(abi, d, reco_edges=bad)
+    h = C.c_void_p()
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+    sp = d.spectra.copy()
+    sp[1] = 0.0
+    s, x, keep = _desc(abi, d, spectra=sp)
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+    s, x, keep = _desc(abi, d)
+    x.energy = None
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+    # pile-up on non-uniform reco bins
+    d2 = synth.config1()
+    d2.reco_edges = np.concatenate([d2.reco_edges[:-1], [d2.reco_edges[-1] + 0.5]])
+    s, x, keep = _desc(abi, d2, pu_K=3, pu_g=np.ones(3), pu_frac=0.1)
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+
+
+def test_null_arguments(abi):
+    lib = abi.load()
+    v = C.c_double()
+    assert lib.bx_nll_eval(None, None, C.byref(v)) == abi.BX_E_INVAL
+    assert lib.bx_model_nparams(None) == -1
+    assert lib.bx_model_free(None) == abi.BX_OK
+    assert lib.bx_model_build(None, None, None, None) == abi.BX_E_INVAL
+
+
+def test_fitcore_unit(tmp_path):
+    exe = tmp_path / "test_fitcore"
+    src = os.path.join(ROOT, "tests", "host", "test_fitcore.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-o", str(exe), src], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "OK" in out.stdout
