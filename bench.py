@@ -41,8 +41,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--toys", type=int, default=0, help="batched toy fits to time (0 = skip)")
+    ap.add_argument("--toys", type=int, default=1024, help="batched toy fits to time (0 = skip)")
+    ap.add_argument("--plain-toys", type=int, default=64, help="toys fitted on the plain path")
+    ap.add_argument("--qps", type=str, default="30,300", help="serving arrival rates ('' = skip)")
+    ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -66,6 +71,102 @@ def cpu_baseline(d, x, th, budget_s=12.0):
                       f"(dense scipy incomplete-gamma cells, Richardson dR/dk), one thread"}
 
 
+def toy_study(bx, synth, n_toys, n_plain):
+    """Batched toy fits through the fit server vs the same toys fitted one
+    at a time through the plain path (histograms resident before timing)."""
+    base, per_species, theta = synth.catalogue()
+    toys = []
+    for b in range(n_toys):
+        t = synth.toy(b, per_species, theta)
+        d = synth.toy_desc(base, t)
+        toys.append((bx.Model(d, synth.Data(energy=t.counts), precision=bx.BX_PREC_F32), d, t))
+    srv = bx.Server()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+               for m, d, t in toys]
+    res = [srv.wait(k, sleep=2e-4) for k in tickets]
+    el = time.perf_counter() - t0
+    srv.close()
+    n_plain = min(n_plain, n_toys)
+    t1 = time.perf_counter()
+    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+             for m, d, t in toys[:n_plain]]
+    el_p = time.perf_counter() - t1
+    same = all(np.array_equal(p.x, r.x) for p, r in zip(plain, res))
+    for m, _, _ in toys:
+        m.close()
+    st = np.array([r.status for r in res])
+    return {"toys": n_toys, "batched_fits_per_s": n_toys / el, "plain_fits_per_s": n_plain / el_p,
+            "plain_sample": n_plain, "speedup": (n_toys / el) / (n_plain / el_p),
+            "converged": int((st == bx.BX_CONVERGED).sum()),
+            "median_iters": float(np.median([r.n_iter for r in res])),
+            "median_evals": float(np.median([r.n_eval for r in res])),
+            "batched_equals_plain_bitwise": bool(same), "edm_tol": 1e-8}
+
+
+def serving(bx, synth, qps_list, n_req):
+    """Poisson arrivals mixing config-1 fits (Gaussian, FP64), config-2 fits
+    (generalized gamma, FP32) with fresh Poisson data, and NLL+gradient
+    requests; latency = done - submit.  The plain baseline serves the same
+    stream first-in first-out through the plain path on one thread."""
+    d1, d2 = synth.config1(), synth.config2(pu_g=synth.pileup_spectrum())
+    tab1, tab2 = synth.species_table("c1"), synth.species_table("c2")
+    out = {}
+    for qps in qps_list:
+        reqs, rng = synth.request_stream(qps, n_req)
+        jobs = []
+        for r in reqs:
+            d, tab, prec = (d1, tab1, bx.BX_PREC_F64) if r.kind == "fit1" else (d2, tab2, bx.BX_PREC_F32)
+            n = synth.draw_species_sum(rng, tab, d.theta_true[: d.S])
+            m = bx.Model(d, synth.Data(energy=n), precision=prec)
+            z = rng.standard_normal(d.P)
+            x0 = d.theta_true * (1 + (0.01 if r.kind == "evalgrad" else 0.05) * z)
+            x0[~d.float_mask] = d.theta_true[~d.float_mask]
+            jobs.append((r, m, x0, d.float_mask))
+        srv = bx.Server()
+        t0 = time.perf_counter()
+        tickets = []
+        for r, m, x0, mask in jobs:
+            dt = t0 + r.t_arrival - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            kind = bx.BX_EVAL_GRAD if r.kind == "evalgrad" else bx.BX_FIT
+            tickets.append(srv.submit(m, x0, float_mask=mask, edm_tol=1e-8, max_iter=500, kind=kind))
+        res = [srv.wait(k, sleep=2e-4) for k in tickets]
+        span = (max(x.t_done_ns for x in res) - min(x.t_submit_ns for x in res)) * 1e-9
+        srv.close()
+        lat = np.array([x.latency_s for x in res])
+        kinds = np.array([r.kind for r, *_ in jobs])
+        # plain FIFO baseline on the same stream
+        t_free, plat = 0.0, []
+        for r, m, x0, mask in jobs:
+            s0 = time.perf_counter()
+            if r.kind == "evalgrad":
+                m.nll_grad(x0)
+            else:
+                m.fit(x0, float_mask=mask, edm_tol=1e-8, max_iter=500)
+            dur = time.perf_counter() - s0
+            start = max(r.t_arrival, t_free)
+            t_free = start + dur
+            plat.append(t_free - r.t_arrival)
+        plat = np.array(plat)
+        n_fit = int((kinds != "evalgrad").sum())
+        rec = {"requests": n_req, "fits_per_s": n_fit / (span + 1e-12) if span > 0 else None,
+               "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+               "plain_p50_s": float(np.percentile(plat, 50)), "plain_p99_s": float(np.percentile(plat, 99)),
+               "plain_fits_per_s": n_fit / max(t_free, 1e-12),
+               "converged": int(sum(x.status == bx.BX_CONVERGED for x in res))}
+        for k in ("fit1", "fit2", "evalgrad"):
+            sel = lat[kinds == k]
+            if len(sel):
+                rec[f"{k}_p50_s"] = float(np.percentile(sel, 50))
+                rec[f"{k}_p99_s"] = float(np.percentile(sel, 99))
+        out[str(qps)] = rec
+        for _, m, _, _ in jobs:
+            m.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -77,6 +178,15 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if a.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 5}))
+        return
     d, x = synth.load("c2")
     th = d.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d.P))
     m = bx.Model(d, x, precision=bx.BX_PREC_F32)
@@ -126,6 +236,13 @@ def main():
                      "frac": achieved / PEAK_FP32, "traffic": None,
                      "cells_per_launch": cells, "kernel_ms": kms},
     }
+    m.close()
+    if a.toys > 0:
+        res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)
+        print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)
+    if a.qps:
+        res["serving"] = serving(bx, synth, [float(q) for q in a.qps.split(",")], a.requests)
+        print(f"serving: {res['serving']}", file=sys.stderr, flush=True)
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d, x, th)
     print(json.dumps(res))
