@@ -29,11 +29,33 @@ WORKLOAD = ("single fit, 3000 true x 900 reco bins (1 keV x 1 p.e.), 12 species,
             "generalized-gamma response (light yield, 3 resolution params, quenching), "
             "2% pile-up (K=128), 3e6 events")
 PEAK_FP32 = 157.3e12   # MI355X published dense FP32 vector FLOP/s
-# algorithmic FP32 operations per response cell (see the design notes):
-# forward = CDF at the cell's upper edge (uniform expansion, 149) + species
-# contraction (2 S = 24); backward = CDF with both parameter derivatives (185)
-FLOP_FWD_PER_CELL = 149 + 24
-FLOP_BWD_PER_CELL = 185
+# Algorithmic operations per response cell on the dominant code path (the
+# uniform expansion of the incomplete gamma, |eta| < 1), counted from the
+# formula: add/mul/transcendental = 1, FMA = 2.  Forward: one edge CDF (130)
+# plus the species contraction 2 S; backward: the edge CDF with the two
+# column-parameter derivatives and the adjoint weight (162).
+FLOP_FWD_EDGE = 130
+FLOP_BWD_PER_CELL = 162
+
+
+def kernel_traffic(name):
+    """HBM bytes per dispatch measured with rocprofv3 counters (profiles/),
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1805_11125_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("bx_kernels.hip", "bx_math.h", "bx_dev.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    try:
+        text = open(os.path.join(ROOT, "profiles", "config2_hbm_counters.md")).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes"):
+            kv = dict(t.split("=") for t in line.split()[1:])
+            if kv.get("src_sha") == h.hexdigest()[:16] and name in kv:
+                return float(kv[name])
+    return None
 
 
 def parse():
@@ -220,8 +242,9 @@ def main():
     if bwd_ms >= fwd_ms:
         kname, kms, flops = "k_cells_bwd", bwd_ms, cells * FLOP_BWD_PER_CELL
     else:
-        kname, kms, flops = "k_cells_fwd", fwd_ms, cells * FLOP_FWD_PER_CELL
+        kname, kms, flops = "k_cells_fwd", fwd_ms, cells * (FLOP_FWD_EDGE + 2 * d.S)
     achieved = flops / (kms * 1e-3)
+    traffic = kernel_traffic(kname)
     res = {
         "metric": METRIC, "value": evals, "unit": "evals/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 / evals,
@@ -233,8 +256,9 @@ def main():
         "stage_ms": {k: round(v, 5) for k, v in st.items()},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None,
-                     "cells_per_launch": cells, "kernel_ms": kms},
+                     "frac": achieved / PEAK_FP32, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "cells_per_launch": cells,
+                     "kernel_ms": kms},
     }
     m.close()
     if a.toys > 0:
