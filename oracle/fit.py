@@ -33,7 +33,7 @@ def _hessian(desc, data, theta, idx, scale):
     return 0.5 * (H + H.T)
 
 
-def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20):
+def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20, lbfgs_maxiter=5000):
     theta0 = np.asarray(theta0, np.float64).copy()
     mask = np.ones(desc.P, bool) if float_mask is None else np.asarray(float_mask, bool)
     idx = np.flatnonzero(mask)
@@ -59,7 +59,8 @@ def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20):
     bounds = [(0.0, None) if q < desc.S else (None, None) for q in idx]
     res = optimize.minimize(fun, np.ones(len(idx)), jac=True, method="L-BFGS-B",
                             bounds=bounds,
-                            options=dict(ftol=0.0, gtol=1e-12, maxiter=5000, maxfun=20000))
+                            options=dict(ftol=0.0, gtol=1e-12, maxiter=lbfgs_maxiter,
+                                         maxfun=4 * lbfgs_maxiter))
     theta = full(res.x)
     f, g = nll_grad(desc, data, theta)
     edm = np.inf
