@@ -19,6 +19,7 @@ constexpr int kBlock = 256;    // threads per block (4 waves)
 constexpr int kCpBlock = 64;   // threads per block of the column-parameter kernel
 constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG true tiles)
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
+constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
 
 enum : int { kGauss = 0, kGG = 1 };
 enum : int { kF32 = 0, kF64 = 1 };
@@ -84,6 +85,8 @@ struct FitDev {
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags
+  const double* theta_src;  // pinned host copy of theta to read first, or null
+  double* out_host;         // pinned host result buffer to fill as well, or null
 };
 
 // Grid sizes of one batched launch (maxima over the fits in it).

@@ -67,6 +67,13 @@ static void make_gg_const(double p, GGConst* c) {
     c->cG[n] = (double)(sg * (bpoly(n + 1, 0) + bpoly(n + 1, a2) - 2 * bpoly(n + 1, a1)) / den);
     c->cD[n] = (double)(sg * (bpoly(n + 1, a1) - bpoly(n + 1, 0)) / den);
   }
+  // start table of the device shape solve: ln k on a grid of ln tau
+  c->has_tab = 0;
+  for (int i = 0; i < kKTab; ++i) {
+    const double lt = kKTabLo + i * (kKTabHi - kKTabLo) / (kKTab - 1);
+    c->lnk_tab[i] = (float)std::log(gg_solve_k(*c, std::exp(lt), nullptr));
+  }
+  c->has_tab = 1;
 }
 
 Tiles choose_tiles(int T, int N, int kind, int prec) {
@@ -96,6 +103,7 @@ Tiles choose_tiles(int T, int N, int kind, int prec) {
     int cg = 0, rg = 0;
     if (sscanf(ov, "%d,%d", &cg, &rg) == 2 && cg > 0 && rg > 0) t = Tiles{cg, rg};
   }
+  t.RG = std::min(t.RG, kMaxRG);
   return t;
 }
 
@@ -314,6 +322,8 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->bwdpart = c.take<double>((size_t)f->n_bwdblk * 4);
   *out = c.take<double>(2 + h.P);
   f->out = *out;
+  f->theta_src = nullptr;
+  f->out_host = nullptr;
   return (c.off + 255) & ~(size_t)255;
 }
 
@@ -388,10 +398,10 @@ using namespace bx;
 // ---------------------------------------------------------------------------
 // Plain-path evaluation.
 // ---------------------------------------------------------------------------
-static bx_status capture(bx_model* m, bool grad, hipGraphExec_t* exec) {
+static bx_status capture(bx_model* m, const FitDev* d_fit, bool grad, hipGraphExec_t* exec) {
   hipGraph_t g;
   BX_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
-  launch_eval(m->d_fit, m->d_active, 1, shape_of(m->df.dev), grad, m->cap_stream);
+  launch_eval(d_fit, nullptr, 1, shape_of(m->df.dev), grad, m->cap_stream);  // fit = blockIdx.y = 0
   BX_HIP(hipStreamEndCapture(m->cap_stream, &g), "graph capture");
   hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
@@ -399,10 +409,12 @@ static bx_status capture(bx_model* m, bool grad, hipGraphExec_t* exec) {
   return BX_OK;
 }
 
-static bx_status enqueue_eval(bx_model* m, bool grad, hipStream_t st) {
-  hipGraphExec_t* ex = grad ? &m->g_grad : &m->g_eval;
+// host: theta is read from, and the results written to, the pinned buffer
+// h_pin by the kernels themselves (no copy nodes); otherwise device buffers.
+static bx_status enqueue_eval(bx_model* m, bool grad, bool host, hipStream_t st) {
+  hipGraphExec_t* ex = !host ? &m->g_grad_dev : grad ? &m->g_grad : &m->g_eval;
   if (!*ex) {
-    bx_status s = capture(m, grad, ex);
+    bx_status s = capture(m, host ? m->d_fit_h : m->d_fit, grad, ex);
     if (s != BX_OK) return s;
   }
   BX_HIP(hipGraphLaunch(*ex, st), "graph launch");
@@ -421,10 +433,8 @@ bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad
     }
   double* hp = m->h_pin;
   memcpy(hp, theta, P * sizeof(double));
-  BX_HIP(hipMemcpyAsync(m->df.d_theta, hp, P * sizeof(double), hipMemcpyHostToDevice, m->stream), "theta upload");
-  bx_status s = enqueue_eval(m, grad != nullptr, m->stream);
+  bx_status s = enqueue_eval(m, grad != nullptr, true, m->stream);
   if (s != BX_OK) return s;
-  BX_HIP(hipMemcpyAsync(hp + P, m->df.d_out, (2 + P) * sizeof(double), hipMemcpyDeviceToHost, m->stream), "result download");
   BX_HIP(hipStreamSynchronize(m->stream), "evaluation");
   const double* o = hp + P;
   const int fl = (int)o[1 + P];
@@ -482,14 +492,25 @@ bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* h
   }
   s = place_fit(m->h, base, &m->df, m->stream);
   if (s != BX_OK) return fail(s);
-  if (hipMalloc(&m->d_fit, sizeof(FitDev)) != hipSuccess || hipMalloc(&m->d_active, sizeof(int)) != hipSuccess)
+  if (hipMalloc(&m->d_fit, 2 * sizeof(FitDev)) != hipSuccess || hipMalloc(&m->d_active, sizeof(int)) != hipSuccess)
     return fail(BX_E_NOMEM);
+  m->d_fit_h = m->d_fit + 1;
+  // coherent pinned memory: the kernels read theta from it and write the
+  // results into it, visible to the host once the stream has synchronised
+  if (hipHostMalloc((void**)&m->h_pin, (2 * m->h.P + 2) * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return fail(BX_E_NOMEM);
+  void* d_pin = nullptr;
+  if (hipHostGetDevicePointer(&d_pin, m->h_pin, 0) != hipSuccess)
+    return fail(hip_fail(hipErrorUnknown, "hipHostGetDevicePointer"));
+  FitDev fh = m->df.dev;
+  fh.theta_src = (const double*)d_pin;
+  fh.out_host = (double*)d_pin + m->h.P;
   const int zero = 0;
   if (hipMemcpyAsync(m->d_fit, &m->df.dev, sizeof(FitDev), hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+      hipMemcpyAsync(m->d_fit_h, &fh, sizeof(FitDev), hipMemcpyHostToDevice, m->stream) != hipSuccess ||
       hipMemcpyAsync(m->d_active, &zero, sizeof(int), hipMemcpyHostToDevice, m->stream) != hipSuccess)
     return fail(BX_E_DEVICE);
-  if (hipHostMalloc((void**)&m->h_pin, (2 * m->h.P + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return fail(BX_E_NOMEM);
   if (hipStreamSynchronize(m->stream) != hipSuccess) return fail(hip_fail(hipErrorUnknown, "model upload"));
   m->lnfact = host_lnfact(m->h);
   *out = m;
@@ -520,6 +541,7 @@ bx_status bx_model_free(bx_model* m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   if (m->g_eval) (void)hipGraphExecDestroy(m->g_eval);
   if (m->g_grad) (void)hipGraphExecDestroy(m->g_grad);
+  if (m->g_grad_dev) (void)hipGraphExecDestroy(m->g_grad_dev);
   if (m->df.base) (void)hipFree(m->df.base);
   if (m->d_fit) (void)hipFree(m->d_fit);
   if (m->d_active) (void)hipFree(m->d_active);
@@ -553,7 +575,7 @@ bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, voi
   hipStream_t st = stream ? (hipStream_t)stream : m->stream;
   const int P = m->h.P;
   BX_HIP(hipMemcpyAsync(m->df.d_theta, d_theta, P * sizeof(double), hipMemcpyDeviceToDevice, st), "theta copy");
-  bx_status s = enqueue_eval(m, true, st);
+  bx_status s = enqueue_eval(m, true, false, st);
   if (s != BX_OK) return s;
   BX_HIP(hipMemcpyAsync(d_out, m->df.d_out, (1 + P) * sizeof(double), hipMemcpyDeviceToDevice, st), "result copy");
   return BX_OK;
@@ -592,7 +614,7 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   const LaunchShape L = shape_of(m->df.dev);
   hipError_t e = hipSuccess;
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    launch_eval(m->d_fit, m->d_active, 1, L, true, m->stream, ev);
+    launch_eval(m->d_fit, nullptr, 1, L, true, m->stream, ev);
     e = hipEventSynchronize(ev[8]);
     for (int k = 0; k < 8 && e == hipSuccess; ++k) {
       float t = 0.f;

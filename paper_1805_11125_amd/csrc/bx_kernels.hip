@@ -8,7 +8,8 @@
 //                 MFMA 16x16x4 as A with the species spectra as B:
 //                 M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).  The 4 waves'
 //                 tiles are added in LDS; cells never touch HBM.
-//   k_rowterms    FP64 sum of the forward partials (fixed order), pile-up
+//   k_reduce_M    FP64 sum of the forward partials (fixed order).
+//   k_rowterms    pile-up
 //                 M' = (1-p) M + p g^*M (Eq. 2) from LDS, expected counts of
 //                 every likelihood term per reco row (Eqs. 3-4), Poisson NLL
 //                 terms, the adjoint weights H and per-block partials.
@@ -19,10 +20,14 @@
 //                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
 //                 W_ji = sum_s H~_js r_s F^_si, and contracts them with the
 //                 column chain factors into a per-block gradient partial.
-//   k_final       fixed-order sums: NLL, rate gradient, response gradient.
+//   k_final       fixed-order totals: NLL, rate gradient, response gradient;
+//                 also written to the caller's pinned host buffer when set.
 //
 // No reduction uses atomics: every sum has a fixed order, so a fit's result
-// does not depend on what else runs in the same launch.
+// does not depend on what else runs in the same launch.  Cross-block sums are
+// separate launches rather than last-block elections: an agent-scope fence
+// per block writes back the XCD's L2 on gfx950 and costs far more than a
+// kernel boundary inside a graph.
 #include <hip/hip_runtime.h>
 
 #include "bx_dev.h"
@@ -89,13 +94,17 @@ __device__ int2 cell_range(const FitDev& f, double xlo, double xhi) {
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
   const int i = blockIdx.x * kCpBlock + threadIdx.x;
   int jlo = 1 << 30, jhi = -1, bad = 0;
+  // theta straight from pinned host memory when the caller passed it there;
+  // block 0 leaves a device copy for the later kernels
+  const double* th = f.theta_src ? f.theta_src : f.theta;
+  if (f.theta_src && blockIdx.x == 0 && (int)threadIdx.x < f.P)
+    const_cast<double*>(f.theta)[threadIdx.x] = f.theta_src[threadIdx.x];
   if (i < f.T) {
     ColPar c;
-    const double* th = f.theta;
     double v = 0.0;
     for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
     c.v = v;
@@ -142,32 +151,35 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
         const double cst[8] = {k, 1.0 / k, sqrt(0.5 * k), cR, 0.5 / sqrt(kTwoPi * k), sh.dlngs, lnk - sh.psi, p};
         for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
         // chain factors d(k, ln a)/d(L, v0, v1, v2)
+        const double im = 1.0 / m, im2 = im * im;
+        const double itau = 1.0 / ((1.0 + s2 * im2) * sh.dG);  // dk = dtau' * itau
+        const double dsdm = v1 + 2.0 * v2 * m;
         for (int q = 0; q < 4; ++q) {
           const double dm = (q == 0) ? m / L : 0.0;
-          const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + (v1 + 2.0 * v2 * m) * dm;
-          const double dtau = (ds2 / (m * m) - 2.0 * s2 * dm / (m * m * m)) / (1.0 + s2 / (m * m));
-          const double dk = dtau / sh.dG;
+          const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + dsdm * dm;
+          const double dk = (ds2 * im2 - 2.0 * s2 * dm * im2 * im) * itau;
           c.J[0][q] = dk;
-          c.J[1][q] = dm / m - sh.dD1 * dk;
+          c.J[1][q] = dm * im - sh.dD1 * dk;
         }
-        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p);
-        // Newton from outside each root stays outside it (conservative)
-        const double cb = kSupportB / k;
-        double th_ = cb > 2.0 ? log1p(cb) + log1p(log1p(cb)) : sqrt(2.0 * cb);
-        for (int it = 0; it < 30; ++it) {
-          const double e = expm1(th_);
-          const double d = (e - th_ - cb) / e;
+        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p).
+        // FP32 Newton from outside each root stays outside it; B is raised by
+        // 5 % to cover the FP32 rounding (the bounds only need to be conservative)
+        const float cb = (float)(1.05 * kSupportB / k);
+        float th_ = cb > 2.f ? log1pf(cb) + log1pf(log1pf(cb)) : sqrtf(2.f * cb);
+        for (int it = 0; it < 12; ++it) {
+          const float e = expm1f(th_);
+          const float d = (e - th_ - cb) * rcp(e);
           th_ -= d;
-          if (fabs(d) < 1e-6 * fmax(1.0, th_)) break;
+          if (fabsf(d) < 1e-4f * fmaxf(1.f, th_)) break;
         }
-        double tl = -(1.0 + cb);
-        for (int it = 0; it < 30; ++it) {
-          const double e = expm1(tl);
-          const double d = (e - tl - cb) / e;
+        float tl = -(1.f + cb);
+        for (int it = 0; it < 12; ++it) {
+          const float e = expm1f(tl);
+          const float d = (e - tl - cb) * rcp(e);
           tl -= d;
-          if (fabs(d) < 1e-6 * fmax(1.0, -tl)) break;
+          if (fabsf(d) < 1e-4f * fmaxf(1.f, -tl)) break;
         }
-        const double xlo = exp((c.c0 + tl) / p), xhi = exp((c.c0 + th_) / p);
+        const double xlo = exp((c.c0 + (double)tl) / p), xhi = exp((c.c0 + (double)th_) / p);
         const int2 r = cell_range(f, xlo, xhi);
         jlo = r.x; jhi = r.y;
       }
@@ -209,7 +221,7 @@ __device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
 // ct = (kFwdWaves cg + w) CG + c, c < CG.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int rt = blockIdx.x / f.n_cg, cg = blockIdx.x % f.n_cg;
   if (rt >= f.n_rt) return;  // block-uniform
   __shared__ R part[kFwdWaves][4][64];
@@ -276,7 +288,7 @@ __device__ __forceinline__ int pu_len(const FitDev& f) {
 // M[j, s] = sum over forward blocks of the partials, FP64, fixed order.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= f.N * kSP) return;
   const R* p = (const R*)f.Mpart + t;
@@ -297,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
 
 // 16 rows x 16 species per block.
 __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
   __shared__ double Ml[16 + kMaxK - 1][kSP];
   __shared__ double mp[16][kSP];
@@ -394,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
 
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if (!f.mv || f.n_rad <= 0) return;  // block-uniform
   __shared__ double part[16][kSP];
   __shared__ double SW[kSP], A[kSP], wr[128], red[kBlock];
@@ -446,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
 
 // H~ = P^T H_tot, H_tot = H + [j in W](1 - t_s) rho.w_s; 16 rows per block.
 __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
   __shared__ double Hl[16 + kMaxK - 1][kSP];
   const int j0 = blockIdx.x * 16;
@@ -477,12 +489,43 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 // Block (ct, rg): true tile ct; wave w takes reco tiles rt = (4 rg + w) RG + c.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active[blockIdx.y]];
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int ct = blockIdx.x / f.n_rg, rg = blockIdx.x % f.n_rg;
   if (ct >= f.n_ct) return;  // block-uniform
   __shared__ double colA[4][16], colB[4][16];
+  __shared__ double hst[4 * kMaxRG * kRowStep + kMaxK], htl[4 * kMaxRG * kRowStep], gl[kMaxK];
+  __shared__ double pq[4 * kMaxRG * kRowStep][4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int2 b = f.tb[ct];
+  // single histogram: the pile-up adjoint w~ = P^T w of this block's reco
+  // rows, from the rows it needs staged in LDS (multivariate fits read the
+  // full adjoint H~ written by k_adjoint)
+  const int r0 = 4 * rg * f.RG * kRowStep;
+  const int nr = max(min(4 * f.RG * kRowStep, f.N - r0), 0);
+  if (!f.mv) {
+    const int K = pu_len(f);
+    const int ns = min(nr + K - 1, f.N - r0);
+    for (int e = threadIdx.x; e < ns; e += kBlock) hst[e] = f.H[(r0 + e) * kSP];
+    for (int e = threadIdx.x; e < K; e += kBlock) gl[e] = K > 1 ? f.ghat[e] : 0.0;
+    __syncthreads();
+    if (K > 1) {
+      // four threads per row, taps k = part (mod 4); partials added in a fixed order
+      for (int e4 = threadIdx.x; e4 < 4 * nr; e4 += kBlock) {
+        const int e = e4 >> 2, part = e4 & 3;
+        const int kmax = min(K - 1, f.N - 1 - (r0 + e));
+        double acc = 0.0;
+        for (int k = part; k <= kmax; k += 4) acc += gl[k] * hst[e + k];
+        pq[e][part] = acc;
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nr; e += kBlock) {
+      double h = hst[e];
+      if (K > 1) h = (1.0 - f.pu_frac) * h + f.pu_frac * ((pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]));
+      htl[e] = h;
+    }
+    __syncthreads();
+  }
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
   const int rt0 = (4 * rg + wv) * f.RG;
   const int rt_end = min(rt0 + f.RG, f.n_rt);
@@ -493,7 +536,7 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
     const double xe = f.xe[je];
     const int j = j0 + jr;
     const bool row_ok = (jr < kRowStep) && (j < f.N);
-    const double w1 = row_ok ? f.Ht[j * kSP] : 0.0;
+    const double w1 = (row_ok && !f.mv) ? htl[j - r0] : 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
@@ -541,61 +584,86 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
-  const FitDev& f = fits[active[blockIdx.y]];
-  __shared__ double red[5][1024];
-  __shared__ int redf[1024];
-  const int t = threadIdx.x;
+// Fixed-order sums of the per-block partials into out[] (NT threads).  The
+// order depends only on NT and the partial counts, so the eval-only launch and
+// the backward kernel's last block give identical bits.
+__device__ __forceinline__ double sum64(double x) {
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ int or64(int x) {
+  for (int o = 32; o >= 1; o >>= 1) x |= __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int NT>
+__device__ void final_sums(const FitDev& f, int with_grad) {
+  constexpr int NW = NT / 64;
+  __shared__ double wred[NW][5 + kSP];
+  __shared__ int wflag[NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   double acc[5] = {0, 0, 0, 0, 0};
   int fl = 0;
-  for (int b = t; b < f.n_rowblk; b += 1024) {
+  for (int b = t; b < f.n_rowblk; b += NT) {
     acc[0] += f.nllpart[b];
     fl |= f.flagpart[b];
   }
-  for (int b = t; b < f.n_cpblk; b += 1024) fl |= f.cpflag[b];
+  for (int b = t; b < f.n_cpblk; b += NT) fl |= f.cpflag[b];
   if (with_grad)
-    for (int b = t; b < f.n_bwdblk; b += 1024)
+    for (int b = t; b < f.n_bwdblk; b += NT)
       for (int q = 0; q < 4; ++q) acc[1 + q] += f.bwdpart[(size_t)b * 4 + q];
-  for (int q = 0; q < 5; ++q) red[q][t] = acc[q];
-  redf[t] = fl;
-  __syncthreads();
-  for (int st = 512; st >= 1; st >>= 1) {
-    if (t < st) {
-      for (int q = 0; q < 5; ++q) red[q][t] += red[q][t + st];
-      redf[t] |= redf[t + st];
-    }
-    __syncthreads();
-  }
-  double tot[5];
-  for (int q = 0; q < 5; ++q) tot[q] = red[q][0];
-  const int flags0 = redf[0];
-  __syncthreads();
-  // rate gradient: species s = t % 16, row blocks b = t / 16 + 64 n
+  // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
   double gr = 0.0;
-  for (int b = t >> 4; b < f.n_rowblk; b += 64) gr += f.gpart[b * kSP + (t & 15)];
-  red[0][t] = gr;
-  __syncthreads();
-  for (int st = 512; st >= 16; st >>= 1) {
-    if (t < st) red[0][t] += red[0][t + st];
-    __syncthreads();
+  for (int b = t >> 4; b < f.n_rowblk; b += NT / 16) gr += f.gpart[b * kSP + (t & 15)];
+  gr += __shfl_xor(gr, 16, 64);
+  gr += __shfl_xor(gr, 32, 64);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc[q] = sum64(acc[q]);
+  fl = or64(fl);
+  if (lane == 0) {
+    for (int q = 0; q < 5; ++q) wred[w][q] = acc[q];
+    wflag[w] = fl;
   }
+  if (lane < kSP) wred[w][5 + lane] = gr;
+  __syncthreads();
+  // results go to f.out and, when set, straight into the caller's pinned
+  // host buffer as well (no separate copy node)
   if (t < f.S) {
-    double a = red[0][t];
+    double a = wred[0][5 + t];
+    for (int v = 1; v < NW; ++v) a += wred[v][5 + t];
     if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + t];
     f.out[1 + t] = a;
+    if (f.out_host) f.out_host[1 + t] = a;
   }
   if (t == 0) {
-    int flags = flags0;
+    double tot[5];
+    int flags = wflag[0];
+    for (int q = 0; q < 5; ++q) tot[q] = wred[0][q];
+    for (int v = 1; v < NW; ++v) {
+      for (int q = 0; q < 5; ++q) tot[q] += wred[v][q];
+      flags |= wflag[v];
+    }
     double nll = tot[0];
     if (f.mv && f.n_rad > 0) {
       nll += f.rad_out[0];
       flags |= (int)f.rad_out[1];
     }
     if (!with_grad) flags &= ~kZeroWidth;
-    f.out[0] = (flags & ~kZeroWidth) ? INFINITY : nll;
+    const double v0 = (flags & ~kZeroWidth) ? INFINITY : nll;
+    f.out[0] = v0;
     f.out[1 + f.P] = (double)flags;
     for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+    if (f.out_host) {
+      f.out_host[0] = v0;
+      f.out_host[1 + f.P] = (double)flags;
+      for (int q = 0; q < f.nresp; ++q) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+    }
   }
+  if (f.out_host) __threadfence_system();
+}
+
+__global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
+  final_sums<1024>(fits[active ? active[blockIdx.y] : blockIdx.y], with_grad);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +698,8 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
   mark(4);
   if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
   mark(5);
-  if (with_grad) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
+  // the single-histogram adjoint is formed inside k_cells_bwd
+  if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
   mark(6);
   if (with_grad) {
     if (L.prec == kF32) {

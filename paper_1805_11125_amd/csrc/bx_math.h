@@ -35,10 +35,15 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kLnSqrtTwoPi = 0.91893853320467274178032973640562;
 
 // Per-model constants of the generalized gamma with exponent p.
+constexpr int kKTab = 512;             // start table of the shape solve
+constexpr double kKTabLo = -14.0;      // ln tau range of the table
+constexpr double kKTabHi = 4.0;
 struct GGConst {
   double p, ip;                 // p, 1/p
   double cG[kSeriesTerms + 1];  // G(x) = ln Gamma(x) + ln Gamma(x+2/p) - 2 ln Gamma(x+1/p) = sum cG[n] x^-n
   double cD[kSeriesTerms + 1];  // D(x) = ln Gamma(x+1/p) - ln Gamma(x) - ln(x)/p = sum cD[n] x^-n
+  float lnk_tab[kKTab];         // ln k at ln tau = kKTabLo + i (kKTabHi - kKTabLo)/(kKTab - 1)
+  int has_tab;
 };
 
 // ---------------------------------------------------------------------------
@@ -139,7 +144,13 @@ BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters) {
   // start: G ~ cG1/k + cG2/k^2 for large k (solve the quadratic), G ~ -ln k
   // for small k
   double u;
-  if (tau < 0.1) {
+  const double lt = log(tau);
+  if (c.has_tab && lt > kKTabLo && lt < kKTabHi) {  // table start: ~1e-4 relative
+    const double pos = (lt - kKTabLo) * ((kKTab - 1) / (kKTabHi - kKTabLo));
+    const int i0 = (int)pos;
+    const double w = pos - i0;
+    u = (1.0 - w) * (double)c.lnk_tab[i0] + w * (double)c.lnk_tab[i0 + 1];
+  } else if (tau < 0.1) {
     const double a1 = c.cG[1], a2 = c.cG[2];
     u = log((a1 + sqrt(fmax(a1 * a1 + 4.0 * tau * a2, 0.0))) / (2.0 * tau));
   } else {

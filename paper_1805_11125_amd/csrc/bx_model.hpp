@@ -63,13 +63,15 @@ LaunchShape shape_of(const FitDev& f);
 struct bx_model {
   bx::HostModel h;
   bx::DeviceFit df;
-  bx::FitDev* d_fit = nullptr;   // device copy of df.dev
+  bx::FitDev* d_fit = nullptr;   // device copy of df.dev (theta and results in device memory)
+  bx::FitDev* d_fit_h = nullptr; // the same, reading theta from and writing results to h_pin
   int* d_active = nullptr;       // {0}
   hipStream_t stream = nullptr;  // launches
   bool own_stream = false;
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
-  hipGraphExec_t g_eval = nullptr, g_grad = nullptr;
-  double* h_pin = nullptr;       // pinned: theta[P] | out[2 + P]
+  hipGraphExec_t g_eval = nullptr, g_grad = nullptr;  // host-buffer path (d_fit_h)
+  hipGraphExec_t g_grad_dev = nullptr;                // device-buffer path (d_fit)
+  double* h_pin = nullptr;       // pinned, coherent: theta[P] | out[2 + P]
   double lnfact = 0.0;
   std::atomic<int> users{0};     // server fits referencing this model
   int device = 0;
