@@ -160,6 +160,9 @@ typedef struct {
   const double* hi;        /* [P] upper bounds or NULL (none) */
   double edm_tol;          /* stop when EDM = g^T H^-1 g / 2 < edm_tol (<= 0: 1e-9) */
   int32_t max_iter;        /* quasi-Newton iterations (<= 0: 500) */
+  int32_t max_eval;        /* NLL + gradient evaluations (<= 0: 200 + 100 n + 5 n^2,
+                              n = varied parameters); reaching it ends the fit with
+                              BX_MAXITER at the best point accepted so far */
 } bx_fit_opts;
 
 typedef struct {

@@ -43,7 +43,8 @@ class FitResult:
         return (self.t_done_ns - self.t_submit_ns) * 1e-9
 
 
-def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, kind=BX_FIT):
+def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, kind=BX_FIT,
+              max_eval=0):
     keep = []
     x0 = _f64(x0)
     keep.append(x0)
@@ -64,6 +65,7 @@ def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0,
         o.hi = dptr(hi)
     o.edm_tol = float(edm_tol)
     o.max_iter = int(max_iter)
+    o.max_eval = int(max_eval)
     return o, keep
 
 
@@ -193,8 +195,8 @@ class Model:
         check(self._lib.bx_nll_grad_dev(self._h, C.c_void_p(theta_dev), C.c_void_p(out_dev),
                                         C.c_void_p(stream) if stream else None))
 
-    def fit(self, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0):
-        o, keep = _fit_opts(self.P, x0, float_mask, lo, hi, edm_tol, max_iter)
+    def fit(self, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, max_eval=0):
+        o, keep = _fit_opts(self.P, x0, float_mask, lo, hi, edm_tol, max_iter, max_eval=max_eval)
         r = _abi.bx_fit_result()
         check(self._lib.bx_fit(self._h, C.byref(o), C.byref(r)))
         del keep
@@ -224,8 +226,8 @@ class Server:
         self._P = {}
 
     def submit(self, model: Model, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0,
-               max_iter=0, kind=BX_FIT):
-        o, keep = _fit_opts(model.P, x0, float_mask, lo, hi, edm_tol, max_iter, kind)
+               max_iter=0, kind=BX_FIT, max_eval=0):
+        o, keep = _fit_opts(model.P, x0, float_mask, lo, hi, edm_tol, max_iter, kind, max_eval)
         t = C.c_uint64()
         check(self._lib.bx_fit_submit(self._h, model.handle, C.byref(o), C.byref(t)))
         self._P[t.value] = model.P

@@ -27,7 +27,7 @@ namespace bx {
 void set_error(const std::string& msg);
 
 struct FitProblem {
-  int P = 0, S = 0, nf = 0, kind = BX_FIT, max_iter = 500;
+  int P = 0, S = 0, nf = 0, kind = BX_FIT, max_iter = 500, max_eval = 0;
   int idx[32];                       // free parameters
   double x0[32], lo[32], hi[32], scale[32];
   double edm_tol = 1e-9;
@@ -61,6 +61,8 @@ inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb)
     pb->scale[q] = std::fabs(pb->x0[q]) > 0 ? std::fabs(pb->x0[q]) : 1.0;
     if (!o->float_mask || o->float_mask[q]) pb->idx[pb->nf++] = q;
   }
+  const int n = pb->nf;
+  pb->max_eval = o->max_eval > 0 ? o->max_eval : 200 + 100 * n + 5 * n * n;
   return BX_OK;
 }
 
@@ -83,6 +85,10 @@ class Bfgs {
   void feed(double f, const double* g) {
     ++n_eval_;
     const int n = pb_.nf;
+    if (state_ != kInit && n_eval_ >= pb_.max_eval) {  // budget spent: keep the accepted point
+      finish(BX_MAXITER);
+      return;
+    }
     if (state_ == kInit) {
       f_ = f;
       memcpy(g_, g, sizeof(double) * pb_.P);

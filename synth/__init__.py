@@ -311,6 +311,14 @@ class Toy:
     theta_true: np.ndarray
     theta0: np.ndarray
     counts: np.ndarray
+    species: np.ndarray   # catalogue indices of the floated species
+
+
+# A species is floated in a toy only if its expectation inside the toy's reco
+# window is at least this many events: a species with (numerically) nothing in
+# the window leaves its rate unconstrained, and the fit of such a toy is not
+# well posed.
+TOY_MIN_EVENTS = 1000.0
 
 
 def toy_shape(b):
@@ -320,26 +328,37 @@ def toy_shape(b):
     return rng, n_reco, n_species
 
 
+def toy_species(n_reco, n_species, per_species_catalogue, theta_cat):
+    """The first n_species catalogue species (in catalogue order) with at
+    least TOY_MIN_EVENTS expected events in reco bins [0, n_reco)."""
+    n_cat = per_species_catalogue.shape[1]
+    inside = per_species_catalogue[:n_reco].sum(0) * theta_cat[:n_cat]
+    ok = np.flatnonzero(inside >= TOY_MIN_EVENTS)
+    return ok[:n_species]
+
+
 def toy(b, per_species_catalogue, theta_cat) -> Toy:
     """Toy b of the batched study.  per_species_catalogue: stored expected
     counts per unit rate, [900, 14], of the catalogue model at the truth."""
     rng, n_reco, n_species = toy_shape(b)
-    rates = theta_cat[:n_species].copy()
+    sp = toy_species(n_reco, n_species, per_species_catalogue, theta_cat)
+    n_species = len(sp)
+    rates = theta_cat[sp].copy()
     resp = theta_cat[-4:].copy()
-    counts = draw_species_sum(rng, per_species_catalogue[:n_reco, :n_species], rates)
+    counts = draw_species_sum(rng, per_species_catalogue[:n_reco, sp], rates)
     theta_true = np.concatenate([rates, resp])
     z = rng.standard_normal(len(theta_true))
     theta0 = theta_true * (1 + 0.05 * z)
     theta0[:n_species] = np.maximum(theta0[:n_species], 1.0)
     theta0[n_species + 1] = theta_true[n_species + 1]  # v0 is fixed
-    return Toy(b, n_reco, n_species, theta_true, theta0, counts)
+    return Toy(b, n_reco, n_species, theta_true, theta0, counts, sp)
 
 
 def toy_desc(base_catalogue: ModelDesc, t: Toy) -> ModelDesc:
     d = base_catalogue.copy()
     d.reco_edges = d.reco_edges[: t.n_reco + 1].copy()
-    d.spectra = d.spectra[: t.n_species].copy()
-    d.species = d.species[: t.n_species]
+    d.spectra = d.spectra[t.species].copy()
+    d.species = [d.species[i] for i in t.species]
     d.win = (0, t.n_reco)
     d.theta_true = t.theta_true.copy()
     mask = np.ones(t.n_species + 4, dtype=bool)

@@ -24,7 +24,7 @@ static int fails = 0;
 template <class F>
 static bx_fit_result run(int P, int S, const double* x0, F fg, const uint8_t* mask = nullptr,
                          const double* lo = nullptr, const double* hi = nullptr, int kind = BX_FIT,
-                         double tol = 1e-14) {
+                         double tol = 1e-14, int max_eval = 0) {
   bx_fit_opts o{};
   o.kind = kind;
   o.x0 = x0;
@@ -33,6 +33,7 @@ static bx_fit_result run(int P, int S, const double* x0, F fg, const uint8_t* ma
   o.hi = hi;
   o.edm_tol = tol;
   o.max_iter = 2000;
+  o.max_eval = max_eval;
   FitProblem pb;
   fit_problem(P, S, &o, &pb);
   Bfgs opt(pb);
@@ -85,6 +86,11 @@ int main() {
     double lo[2] = {-INFINITY, -INFINITY};
     bx_fit_result r = run(2, 0, x0, fg, nullptr, lo, nullptr, BX_FIT, 1e-20);
     CHECK(std::fabs(r.x[0] - 1) < 1e-6 && std::fabs(r.x[1] - 1) < 1e-6, "rosenbrock minimum");
+    // an evaluation budget ends the fit at the last accepted point
+    bx_fit_result rb = run(2, 0, x0, fg, nullptr, lo, nullptr, BX_FIT, 1e-20, 12);
+    double gb[2];
+    CHECK(rb.status == BX_MAXITER && rb.n_eval == 12, "evaluation budget");
+    CHECK(rb.nll == fg(rb.x, gb) && rb.nll < fg(x0, gb), "budget keeps an accepted, lower point");
   }
   // minimum outside the box: rate held at its lower bound 0
   {

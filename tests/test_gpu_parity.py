@@ -55,6 +55,19 @@ def test_nll_grad_parity(bx, name, prec):
     check_point(bx, d, x, perturbed(d), prec, f"{name}/prec{prec}")
 
 
+# Toy start points (5 % perturbed truth) with short reco windows: narrow
+# generalized-gamma columns share tiles with wide ones, so their edges are
+# evaluated deep in the tail (k phi ~ 100 for toy 143's column 81).
+@pytest.mark.parametrize("b", [143, 3, 13])
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_toy_start_parity(bx, b, prec):
+    base, per_species, theta = synth.catalogue()
+    t = synth.toy(b, per_species, theta)
+    d = synth.toy_desc(base, t)
+    x = synth.Data(energy=t.counts)
+    check_point(bx, d, x, t.theta0, prec, f"toy{b}/prec{prec}")
+
+
 @pytest.mark.parametrize("name,prec", [("c1", F64), ("c2", F32), ("c3a", F64)])
 def test_expected_counts_parity(bx, name, prec):
     d, x = synth.load(name)
