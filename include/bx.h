@@ -141,11 +141,14 @@ int64_t bx_model_expected_size(const bx_model* m);
 bx_status bx_model_expected(bx_model* m, const double* theta, double* out);
 
 /* Diagnostics: average duration (milliseconds) of each stage of one NLL +
- * gradient evaluation at theta, over `reps` back-to-back evaluations launched
- * one kernel at a time (no graph) on the model's stream and timed with HIP
- * events there.  ms[9] = {column parameters, forward cell sweep + species
- * contraction, partial-sum reduction, pile-up + likelihood terms, radial term,
- * pile-up adjoint, backward cell sweep, final sums, whole evaluation}. */
+ * gradient evaluation at theta.  After one evaluation at theta, each stage's
+ * kernel is launched `reps` times back to back on the model's stream between
+ * two HIP events (each launch recomputes that stage's output from the
+ * previous stages' results); ms[8] times `reps` whole evaluations launched
+ * kernel by kernel (no graph) the same way.  ms[9] = {column parameters,
+ * forward cell sweep + species contraction, partial-sum reduction, pile-up +
+ * likelihood terms, radial term, pile-up adjoint, backward cell sweep, final
+ * sums, whole evaluation}; a stage the model does not have reads ~0. */
 bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms);
 
 /* ---- fitting (Sec. 4, steps 5-7) ---- */

@@ -350,9 +350,25 @@ def per_species_expected(desc, theta):
 
 
 def support_cells(desc, theta, eps=1e-30):
-    """Number of cells with R[j, i] > eps (the work the method must do)."""
+    """Number of cells with R[j, i] > eps."""
     f = forward(desc, theta)
     return int(np.count_nonzero(f.R > eps))
+
+
+def support_edges(desc, theta, q=1e-12):
+    """CDF evaluations one response sweep needs (Eq. 1 integrated over the
+    reco bins): for every column, the reco edges whose CDF lies in [q, 1 - q]
+    plus the edge just outside on each side, which closes the first and last
+    cell of the column's support."""
+    _, resp = split_theta(desc, theta)
+    tail, _ = edge_tails(desc, column_params(desc, resp))
+    n_edges = tail.shape[1]
+    total = 0
+    for row in tail >= q:
+        idx = np.flatnonzero(row)
+        if idx.size:
+            total += int(min(idx[-1] + 1, n_edges - 1) - max(idx[0] - 1, 0) + 1)
+    return total
 
 
 def grad_scale(desc, data, theta):

@@ -20,6 +20,7 @@ constexpr int kCpBlock = 64;   // threads per block of the column-parameter kern
 constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG true tiles)
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
 constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
+constexpr int kMaxCG = 8;      // true tiles per forward wave
 
 enum : int { kGauss = 0, kGG = 1 };
 enum : int { kF32 = 0, kF64 = 1 };
@@ -94,8 +95,11 @@ struct LaunchShape {
   int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks;
   int kind, prec, any_mv, any_rad;
 };
+constexpr int kStages = 8;  // colparams, cells_fwd, reduce_M, rowterms, radial, adjoint, cells_bwd, final
+void launch_stage(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
+                  int stage, hipStream_t st);
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
-                 bool with_grad, hipStream_t st, hipEvent_t* ev = nullptr);
+                 bool with_grad, hipStream_t st);
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
 
 }  // namespace bx

@@ -104,6 +104,7 @@ Tiles choose_tiles(int T, int N, int kind, int prec) {
     if (sscanf(ov, "%d,%d", &cg, &rg) == 2 && cg > 0 && rg > 0) t = Tiles{cg, rg};
   }
   t.RG = std::min(t.RG, kMaxRG);
+  t.CG = std::min(t.CG, kMaxCG);
   return t;
 }
 
@@ -607,27 +608,30 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   double nll;
   bx_status s = model_eval(m, theta, &nll, nullptr);  // uploads theta, warms up
   if (s != BX_OK) return s;
-  hipEvent_t ev[9];
-  for (int k = 0; k < 9; ++k)
-    if (hipEventCreate(&ev[k]) != hipSuccess) return hip_fail(hipErrorUnknown, "hipEventCreate");
-  double acc[9] = {0};
+  // Each stage is timed on its own: `reps` back-to-back launches of its
+  // kernel between two events (every stage only rewrites what it produces
+  // from the previous stages' results, which the evaluation above left in
+  // place).  ms[8] times `reps` whole evaluations the same way.
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return hip_fail(hipErrorUnknown, "hipEventCreate");
   const LaunchShape L = shape_of(m->df.dev);
   hipError_t e = hipSuccess;
-  for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    launch_eval(m->d_fit, nullptr, 1, L, true, m->stream, ev);
-    e = hipEventSynchronize(ev[8]);
-    for (int k = 0; k < 8 && e == hipSuccess; ++k) {
-      float t = 0.f;
-      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-      acc[k] += t;
+  for (int k = 0; k <= kStages && e == hipSuccess; ++k) {
+    e = hipEventRecord(e0, m->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      if (k < kStages) launch_stage(m->d_fit, nullptr, 1, L, true, k, m->stream);
+      else launch_eval(m->d_fit, nullptr, 1, L, true, m->stream);
     }
-    float tt = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&tt, ev[0], ev[8]);
-    acc[8] += tt;
+    if (e == hipSuccess) e = hipEventRecord(e1, m->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    ms[k] = (double)t / reps;
   }
-  for (int k = 0; k < 9; ++k) (void)hipEventDestroy(ev[k]);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "stage timing");
-  for (int k = 0; k < 9; ++k) ms[k] = acc[k] / reps;
   return BX_OK;
 }
 

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
       } else {
         bad |= kZeroWidth;
       }
-      const double zb = sqrt(2.0 * kSupportB);
+      const double zb = sqrt(2.0 * (f.prec == kF32 ? kSupportB32 : kSupportB));
       const int2 r = cell_range(f, E - zb * sig, E + zb * sig);
       jlo = r.x; jhi = r.y;
     } else {
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
         // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p).
         // FP32 Newton from outside each root stays outside it; B is raised by
         // 5 % to cover the FP32 rounding (the bounds only need to be conservative)
-        const float cb = (float)(1.05 * kSupportB / k);
+        const float cb = (float)(1.05 * (f.prec == kF32 ? kSupportB32 : kSupportB) / k);
         float th_ = cb > 2.f ? log1pf(cb) + log1pf(log1pf(cb)) : sqrtf(2.f * cb);
         for (int it = 0; it < 12; ++it) {
           const float e = expm1f(th_);
@@ -217,26 +217,54 @@ __device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
 }
 
 // ---------------------------------------------------------------------------
-// Block (rt, cg): reco rows [15 rt, 15 rt + 15); wave w takes true tiles
-// ct = (kFwdWaves cg + w) CG + c, c < CG.
+// Block (rt, cg): reco rows [15 rt, 15 rt + 15).  The true tiles whose
+// support meets these rows (a contiguous band for a smooth response, about a
+// third of them on the 3000 x 900 grid) are listed in ascending order, and
+// wave w of chunk cg takes list entries (kFwdWaves cg + w) CG + c, c < CG: the
+// working waves fill the first blocks of each reco tile, and the rest find
+// their chunk empty and only write zero partials.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int rt = blockIdx.x / f.n_cg, cg = blockIdx.x % f.n_cg;
   if (rt >= f.n_rt) return;  // block-uniform
   __shared__ R part[kFwdWaves][4][64];
+  __shared__ int wcount[kFwdWaves];
+  __shared__ int mylist[kFwdWaves * kMaxCG];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int j0 = rt * kRowStep;
+  // this block's window [lo, lo + kFwdWaves CG) of the list of active tiles
+  const int lo = kFwdWaves * f.CG * cg, win = kFwdWaves * f.CG;
+  int n_act = 0;
+  for (int c0 = 0; c0 < f.n_ct; c0 += kFwdWaves * 64) {
+    const int ct = c0 + (int)threadIdx.x;
+    bool act = false;
+    if (ct < f.n_ct) {
+      const int2 b = f.tb[ct];
+      act = !(b.y < j0 || b.x > j0 + kRowStep - 1);
+    }
+    const unsigned long long m = __ballot(act);
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int off = n_act, tot = n_act;
+    for (int w = 0; w < kFwdWaves; ++w) {
+      off += w < wv ? wcount[w] : 0;
+      tot += wcount[w];
+    }
+    const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+    if (act && pos >= lo && pos < lo + win) mylist[pos - lo] = ct;
+    n_act = tot;
+    __syncthreads();
+  }
   const int je = min(j0 + jr, f.N);
   const double xe = f.xe[je];
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
   typename Acc4<R>::T acc = {0, 0, 0, 0};
-  const int ct0 = (kFwdWaves * cg + wv) * f.CG;
-  const int ct_end = min(ct0 + f.CG, f.n_ct);
-  for (int ct = ct0; ct < ct_end; ++ct) {
-    const int2 b = f.tb[ct];
-    if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
+  const int e0 = wv * f.CG;
+  const int e_end = min(e0 + f.CG, n_act - lo);
+  for (int e = e0; e < e_end; ++e) {
+    const int ct = mylist[e];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
@@ -486,7 +514,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 }
 
 // ---------------------------------------------------------------------------
-// Block (ct, rg): true tile ct; wave w takes reco tiles rt = (4 rg + w) RG + c.
+// Block (ct, rg): true tile ct; its support covers the contiguous reco tiles
+// [rt_a, rt_b], and wave w takes rt = rt_a + (4 rg + w) RG + c, c < RG.  The
+// working blocks of a true tile are thus its first ones; the others write a
+// zero partial and leave.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
@@ -497,10 +528,17 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
   __shared__ double pq[4 * kMaxRG * kRowStep][4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int2 b = f.tb[ct];
+  const int rt_a = b.y >= b.x ? max(b.x, 0) / kRowStep : 0;
+  const int rt_b = b.y >= b.x ? min(b.y / kRowStep, f.n_rt - 1) : -1;
+  const int rt_blk = rt_a + 4 * rg * f.RG;  // first reco tile of this block
+  if (rt_blk > rt_b) {                      // block-uniform: nothing in range
+    if (threadIdx.x < 4) f.bwdpart[(size_t)blockIdx.x * 4 + threadIdx.x] = 0.0;
+    return;
+  }
   // single histogram: the pile-up adjoint w~ = P^T w of this block's reco
   // rows, from the rows it needs staged in LDS (multivariate fits read the
   // full adjoint H~ written by k_adjoint)
-  const int r0 = 4 * rg * f.RG * kRowStep;
+  const int r0 = rt_blk * kRowStep;
   const int nr = max(min(4 * f.RG * kRowStep, f.N - r0), 0);
   if (!f.mv) {
     const int K = pu_len(f);
@@ -527,8 +565,8 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
     __syncthreads();
   }
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
-  const int rt0 = (4 * rg + wv) * f.RG;
-  const int rt_end = min(rt0 + f.RG, f.n_rt);
+  const int rt0 = rt_blk + wv * f.RG;
+  const int rt_end = min(rt0 + f.RG, rt_b + 1);
   for (int rt = rt0; rt < rt_end; ++rt) {
     const int j0 = rt * kRowStep;
     if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
@@ -667,52 +705,56 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 }
 
 // ---------------------------------------------------------------------------
-void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
-                 bool with_grad, hipStream_t st, hipEvent_t* ev) {
+// One stage of an evaluation: 0 colparams, 1 cells_fwd, 2 reduce_M,
+// 3 rowterms, 4 radial, 5 adjoint, 6 cells_bwd, 7 final.  Stages that do not
+// apply (radial/adjoint without multivariate terms, the backward stages
+// without the gradient) launch nothing.
+void launch_stage(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
+                  int stage, hipStream_t st) {
   const dim3 blk(kBlock);
-  // ev (optional): events recorded before each stage; stages are
-  // 0 colparams, 1 cells_fwd, 2 reduce_M, 3 rowterms, 4 radial, 5 adjoint,
-  // 6 cells_bwd, 7 final, 8 end
-  auto mark = [&](int k) {
-    if (ev) (void)hipEventRecord(ev[k], st);
-  };
-  mark(0);
-  hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st, d_fits,
-                     d_active);
   const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), grow(L.max_rowblk, n);
   const dim3 gred((L.max_NS + kBlock - 1) / kBlock, n), bf(kFwdWaves * 64);
-  mark(1);
-  if (L.prec == kF32) {
-    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, bf, 0, st, d_fits, d_active);
-    else hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, bf, 0, st, d_fits, d_active);
-    mark(2);
-    hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);
-  } else {
-    if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, bf, 0, st, d_fits, d_active);
-    else hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, bf, 0, st, d_fits, d_active);
-    mark(2);
-    hipLaunchKernelGGL(k_reduce_M<double>, gred, blk, 0, st, d_fits, d_active);
+  const bool f32 = L.prec == kF32, gauss = L.kind == kGauss;
+  switch (stage) {
+    case 0:
+      hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st,
+                         d_fits, d_active);
+      break;
+    case 1:
+      if (f32 && gauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, bf, 0, st, d_fits, d_active);
+      if (f32 && !gauss) hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, bf, 0, st, d_fits, d_active);
+      if (!f32 && gauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, bf, 0, st, d_fits, d_active);
+      if (!f32 && !gauss) hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, bf, 0, st, d_fits, d_active);
+      break;
+    case 2:
+      if (f32) hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);
+      else hipLaunchKernelGGL(k_reduce_M<double>, gred, blk, 0, st, d_fits, d_active);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
+      break;
+    case 4:
+      if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
+      break;
+    case 5:  // the single-histogram adjoint is formed inside k_cells_bwd
+      if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
+      break;
+    case 6:
+      if (!with_grad) break;
+      if (f32 && gauss) hipLaunchKernelGGL((k_cells_bwd<float, kGauss>), gb, blk, 0, st, d_fits, d_active);
+      if (f32 && !gauss) hipLaunchKernelGGL((k_cells_bwd<float, kGG>), gb, blk, 0, st, d_fits, d_active);
+      if (!f32 && gauss) hipLaunchKernelGGL((k_cells_bwd<double, kGauss>), gb, blk, 0, st, d_fits, d_active);
+      if (!f32 && !gauss) hipLaunchKernelGGL((k_cells_bwd<double, kGG>), gb, blk, 0, st, d_fits, d_active);
+      break;
+    case 7:
+      hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+      break;
   }
-  mark(3);
-  hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
-  mark(4);
-  if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
-  mark(5);
-  // the single-histogram adjoint is formed inside k_cells_bwd
-  if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
-  mark(6);
-  if (with_grad) {
-    if (L.prec == kF32) {
-      if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_bwd<float, kGauss>), gb, blk, 0, st, d_fits, d_active);
-      else hipLaunchKernelGGL((k_cells_bwd<float, kGG>), gb, blk, 0, st, d_fits, d_active);
-    } else {
-      if (L.kind == kGauss) hipLaunchKernelGGL((k_cells_bwd<double, kGauss>), gb, blk, 0, st, d_fits, d_active);
-      else hipLaunchKernelGGL((k_cells_bwd<double, kGG>), gb, blk, 0, st, d_fits, d_active);
-    }
-  }
-  mark(7);
-  hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
-  mark(8);
+}
+
+void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
+                 hipStream_t st) {
+  for (int k = 0; k < kStages; ++k) launch_stage(d_fits, d_active, n, L, with_grad, k, st);
 }
 
 // Expected counts of every term over the full reco range (diagnostics):

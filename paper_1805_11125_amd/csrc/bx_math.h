@@ -29,9 +29,10 @@ namespace bx {
 // ---------------------------------------------------------------------------
 constexpr int kSeriesTerms = 16;   // Stirling-type series length
 constexpr double kShift = 10.0;    // argument shift before the series
-constexpr double kSupportB = 75.0; // tails beyond k*phi = B (or z^2/2 = B) are < 1e-32
-constexpr float kTemmeMinK = 12.f; // FP32: uniform expansion from this shape on
-constexpr float kTemmeTailCut = 80.f;  // FP32 uniform expansion: tails beyond k*phi = 80 are set to 0
+constexpr double kSupportB = 75.0;   // FP64 cells: tails beyond k*phi = B (or z^2/2 = B) are < 1e-32
+constexpr double kSupportB32 = 32.0; // FP32 cells: tails beyond B are < 1e-14 of the column
+constexpr float kTemmeMinK = 12.f;   // FP32: uniform expansion from this shape on
+constexpr float kTemmeTailCut = 40.f;  // FP32 uniform expansion: tails beyond k*phi = 40 are set to 0
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kLnSqrtTwoPi = 0.91893853320467274178032973640562;
 
@@ -261,6 +262,19 @@ BX_HD EdgeVal<R> gg_edge_temme(R t, const GGCol<R>& c) {
   const bool up = t > (R)0;
   const R eta = up ? sqrt((R)2 * ph) : -sqrt((R)2 * ph);
   const R kph = c.k * ph;
+  // The two terms of the tail cancel far out, and beyond k*phi ~ 87 both are
+  // FP32 subnormals, so their sum can even come out negative (which would put
+  // the edge on the wrong side of the median).  Past kTemmeTailCut, beyond the
+  // support cut of every column, the tail (< e^-40) is taken as the side's
+  // zero and nothing else is evaluated; for k >= 2 kTemmeTailCut this also
+  // leaves |eta| < 1 as the only branch inside the cut.
+  const bool far = kph > (R)kTemmeTailCut;
+  EdgeVal<R> o;
+  if (far) {
+    o.v = up ? (R)-0.0 : (R)0.0;
+    if (D) o.d1 = o.d2 = (R)0;
+    return o;
+  }
   const R E = exp(-kph);
   const R w = fabs(eta) * c.skh;
   R h0, h1, h2, h3;
@@ -284,18 +298,9 @@ BX_HD EdgeVal<R> gg_edge_temme(R t, const GGCol<R>& c) {
   const R Hs = h0 + ik * (h1 + ik * (h2 + ik * h3));
   const R Rt = E * c.cR * Hs;
   R T = (R)0.5 * erfc(w) + (up ? Rt : -Rt);
-  // The two terms of T cancel in the far tail, and beyond k*phi ~ 87 both are
-  // FP32 subnormals, so their sum can even come out negative (which would put
-  // the edge on the wrong side of the median).  Past kTemmeTailCut, beyond the
-  // support cut of every column, the tail is below e^-80 and is taken as the
-  // side's zero; a negative rounding result is clamped the same way.
-  const bool far = kph > (R)kTemmeTailCut;
-  if (far || !(T > (R)0)) T = (R)0;
-  EdgeVal<R> o;
+  if (!(T > (R)0)) T = (R)0;  // rounding below zero: the side's zero
   o.v = up ? -T : T;
-  if (D && far) {
-    o.d1 = o.d2 = (R)0;
-  } else if (D) {
+  if (D) {
     const R g = c.k * c.cR * E;  // y^k e^-y / Gamma(k)
     const R dH = ik * ik * (h1 + ik * ((R)2 * h2 + (R)3 * ik * h3));
     const R dQk_eta = E * (-eta * c.ce + c.cR * Hs * ((R)-0.5 * eta * eta - (R)0.5 * ik - c.dlngs) -

@@ -58,11 +58,7 @@ def main():
     n2 = synth.draw_poisson(np.random.default_rng(0), mu2)
     np.savez_compressed(os.path.join(HERE, "c2.npz"), pu_g=g, energy=n2)
 
-    # cells of config 2 above 1e-30 at the benchmark's parameter point: the
-    # algorithmic work of one response sweep
-    th_b = d2.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d2.P))
-    np.savez_compressed(os.path.join(HERE, "c2_support.npz"),
-                        cells=oracle.support_cells(d2, th_b), theta=th_b)
+    # the algorithmic work of one response sweep: make_support.py
 
     # config 3a / 3b
     np.savez_compressed(os.path.join(HERE, "c3a.npz"), **mv_draw(synth.config3a(), 0))

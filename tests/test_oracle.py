@@ -472,3 +472,20 @@ def test_mv_brute_force_radial_and_ps():
             assert abs(mu["ps"][j, k] - acc) < 1e-12 * acc
     for j in [3, 150]:
         assert abs(mu["tagged"][j] - sum(Mp[j, s] * t[s] * r[s] for s in range(d.S))) < 1e-9
+
+
+def test_support_edges_gauss_quantiles():
+    # Gaussian columns: the edges with Phi((x - m)/sigma) in [q, 1 - q] are
+    # those within z = -ndtri(q) standard deviations of the mean; add the
+    # bracketing edge on each side (clipped to the grid).
+    d = synth.config1()
+    q = 1e-12
+    z = -special.ndtri(q)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    x = np.asarray(d.reco_edges, np.float64)
+    expect = 0
+    for m, s in zip(cp.m, cp.sigma):
+        idx = np.flatnonzero((x >= m - z * s) & (x <= m + z * s))
+        if idx.size:
+            expect += min(idx[-1] + 1, len(x) - 1) - max(idx[0] - 1, 0) + 1
+    assert oracle.support_edges(d, d.theta_true, q=q) == expect
