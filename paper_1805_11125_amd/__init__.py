@@ -126,6 +126,8 @@ class Model:
         self._keep = []   # everything was copied by the library
         self._theta = np.zeros(self.P)
         self._grad = np.zeros(self.P)
+        self._v = C.c_double()
+        self._vaddr = C.addressof(self._v)
 
     def _arr(self, a):
         a = _f64(np.asarray(a).reshape(-1))
@@ -155,18 +157,22 @@ class Model:
         check(self._lib.bx_model_lnfact(self._h, C.byref(v)))
         return v.value
 
+    def _theta_addr(self, theta):
+        t = theta if (isinstance(theta, np.ndarray) and theta.dtype == np.float64
+                      and theta.flags.c_contiguous) else np.ascontiguousarray(theta, dtype=np.float64)
+        if t.shape != (self.P,):
+            raise ValueError(f"theta must have {self.P} entries")
+        return t, t.ctypes.data
+
     def nll(self, theta):
-        t = _f64(theta)
-        v = C.c_double()
-        check(self._lib.bx_nll_eval(self._h, dptr(t), C.byref(v)))
-        return v.value
+        t, ta = self._theta_addr(theta)
+        check(self._lib.bx_nll_eval(self._h, ta, self._vaddr))
+        return self._v.value
 
     def nll_grad(self, theta):
-        t = _f64(theta)
-        v = C.c_double()
-        g = np.zeros(self.P)
-        check(self._lib.bx_nll_grad(self._h, dptr(t), C.byref(v), dptr(g)))
-        return v.value, g
+        t, ta = self._theta_addr(theta)
+        check(self._lib.bx_nll_grad(self._h, ta, self._vaddr, self._grad.ctypes.data))
+        return self._v.value, self._grad.copy()
 
     def expected(self, theta):
         """Expected counts of every term over the full reco range."""

@@ -56,8 +56,9 @@ SIGNATURES = {
     "bx_model_free": (C.c_int, [C.c_void_p]),
     "bx_model_nparams": (C.c_int32, [C.c_void_p]),
     "bx_model_lnfact": (C.c_int, [C.c_void_p, _dp]),
-    "bx_nll_eval": (C.c_int, [C.c_void_p, _dp, _dp]),
-    "bx_nll_grad": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    # raw addresses (ints) for the per-evaluation calls: cheaper to marshal
+    "bx_nll_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bx_nll_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bx_nll_grad_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bx_model_expected_size": (C.c_int64, [C.c_void_p]),
     "bx_model_expected": (C.c_int, [C.c_void_p, _dp, _dp]),

@@ -21,6 +21,7 @@ constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG 
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
 constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
 constexpr int kMaxCG = 8;      // true tiles per forward wave
+constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
 
 enum : int { kGauss = 0, kGG = 1 };
 enum : int { kF32 = 0, kF64 = 1 };
@@ -86,8 +87,9 @@ struct FitDev {
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags
-  const double* theta_src;  // pinned host copy of theta to read first, or null
-  double* out_host;         // pinned host result buffer to fill as well, or null
+  const double* theta_src;  // pinned host [P + 1]: theta and the caller's sequence number, or null
+  double* out_host;         // pinned host [3 + P]: the results, then the sequence number as
+                            // completion mark (written last, after a system-scope fence), or null
 };
 
 // Grid sizes of one batched launch (maxima over the fits in it).

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -39,7 +40,22 @@ static bx_status inval(const std::string& m) {
 // ln Gamma(x + a) ~ (x + a - 1/2) ln x - x + ln sqrt(2 pi)
 //                   + sum_n (-1)^(n+1) B_{n+1}(a) / (n (n+1) x^n).
 // ---------------------------------------------------------------------------
-static void make_gg_const(double p, GGConst* c) {
+// Root of e^t - 1 - t = cb on the side sgn of 0 (Newton in FP64 from outside
+// the root, where the function is convex and the iteration stays outside).
+static double support_root(double cb, int sgn) {
+  double t = sgn > 0 ? (cb > 2.0 ? std::log1p(cb) + std::log1p(std::log1p(cb)) : std::sqrt(2.0 * cb))
+                     : -(1.0 + cb);
+  for (int it = 0; it < 200; ++it) {
+    const double e = std::expm1(t);
+    const double d = (e - t - cb) / e;
+    t -= d;
+    if (std::fabs(d) <= 1e-15 * std::fmax(1.0, std::fabs(t))) break;
+  }
+  return t;
+}
+
+// bs: the support cut (k phi = bs) of the model's precision, with margin.
+static void make_gg_const(double p, double bs, GGConst* c) {
   long double bern[kSeriesTerms + 3];
   bern[0] = 1.0L;
   for (int n = 1; n < kSeriesTerms + 3; ++n) {  // sum_{k<=n} C(n+1, k) B_k = 0
@@ -71,7 +87,18 @@ static void make_gg_const(double p, GGConst* c) {
   c->has_tab = 0;
   for (int i = 0; i < kKTab; ++i) {
     const double lt = kKTabLo + i * (kKTabHi - kKTabLo) / (kKTab - 1);
-    c->lnk_tab[i] = (float)std::log(gg_solve_k(*c, std::exp(lt), nullptr));
+    c->lnk_tab[i] = std::log(gg_solve_k(*c, std::exp(lt), nullptr));
+  }
+  // support roots at ln k_i, rounded outward: for k in [k_i, k_i+1) the
+  // roots lie inside those of k_i, so entry i bounds the support from outside
+  for (int i = 0; i < kSupTab; ++i) {
+    const double cb = bs / std::exp(kSupLo + i * (kSupHi - kSupLo) / (kSupTab - 1));
+    const double hi = support_root(cb, 1), lo = support_root(cb, -1);
+    float fh = (float)hi, fl = (float)lo;
+    if ((double)fh < hi) fh = std::nextafterf(fh, INFINITY);
+    if ((double)fl > lo) fl = std::nextafterf(fl, -INFINITY);
+    c->sup_hi[i] = std::nextafterf(fh, INFINITY);
+    c->sup_lo[i] = std::nextafterf(fl, -INFINITY);
   }
   c->has_tab = 1;
 }
@@ -234,7 +261,7 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
       m.F32[(size_t)i * kSP + s] = (float)v;
     }
   }
-  if (m.kind == kGG) make_gg_const(m.p, &m.gg);
+  if (m.kind == kGG) make_gg_const(m.p, 1.05 * (m.prec == kF32 ? kSupportB32 : kSupportB), &m.gg);
   else memset(&m.gg, 0, sizeof m.gg);
   m.tiles = choose_tiles(m.T, m.N, m.kind, m.prec);
   return set_host_data(h, x);
@@ -306,7 +333,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->n_t = c.take<double>(h.N);
   f->n_r = c.take<double>(h.n_rad);
   f->n_p = c.take<double>((size_t)h.N * h.n_ps);
-  *theta = c.take<double>(h.P);
+  *theta = c.take<double>(h.P + 1);  // + the caller's sequence number (host path)
   f->theta = *theta;
   f->cp = c.take<ColPar>(h.T);
   f->tb = c.take<int2>(f->n_ct);
@@ -432,12 +459,33 @@ bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad
       set_error("non-finite parameter");
       return BX_E_DOMAIN;
     }
+  // h_pin = [theta[P] | sequence number] (host-written) ... at kPinOut:
+  // [out[2 + P] | completion mark] (device-written)
   double* hp = m->h_pin;
   memcpy(hp, theta, P * sizeof(double));
+  const double seq = (double)(++m->seq);
+  hp[P] = seq;
   bx_status s = enqueue_eval(m, grad != nullptr, true, m->stream);
   if (s != BX_OK) return s;
-  BX_HIP(hipStreamSynchronize(m->stream), "evaluation");
-  const double* o = hp + P;
+  // The last kernel writes the sequence number after the results (with a
+  // system-scope fence): spin on it, and ask the stream now and then so that
+  // a failed launch ends the wait with its error.
+  const volatile double* mark = hp + kPinOut + 2 + P;
+  for (unsigned it = 1;; ++it) {
+    if (*mark == seq) break;
+    if ((it & 1023u) == 0u) {
+      const hipError_t q = hipStreamQuery(m->stream);
+      if (q == hipSuccess && *mark == seq) break;
+      if (q == hipSuccess) {
+        set_error("evaluation finished without its completion mark");
+        return BX_E_DEVICE;
+      }
+      if (q != hipErrorNotReady) return hip_fail(q, "evaluation");
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  const double* o = hp + kPinOut;
   const int fl = (int)o[1 + P];
   const int hard = fl & (kBadSigma | kBadGG | kBadMu | kBadTheta);
   if (hard || (grad && (fl & kZeroWidth))) {
@@ -498,15 +546,16 @@ bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* h
   m->d_fit_h = m->d_fit + 1;
   // coherent pinned memory: the kernels read theta from it and write the
   // results into it, visible to the host once the stream has synchronised
-  if (hipHostMalloc((void**)&m->h_pin, (2 * m->h.P + 2) * sizeof(double),
+  if (hipHostMalloc((void**)&m->h_pin, kPinDoubles * sizeof(double),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return fail(BX_E_NOMEM);
+  memset(m->h_pin, 0, kPinDoubles * sizeof(double));
   void* d_pin = nullptr;
   if (hipHostGetDevicePointer(&d_pin, m->h_pin, 0) != hipSuccess)
     return fail(hip_fail(hipErrorUnknown, "hipHostGetDevicePointer"));
   FitDev fh = m->df.dev;
   fh.theta_src = (const double*)d_pin;
-  fh.out_host = (double*)d_pin + m->h.P;
+  fh.out_host = (double*)d_pin + kPinOut;
   const int zero = 0;
   if (hipMemcpyAsync(m->d_fit, &m->df.dev, sizeof(FitDev), hipMemcpyHostToDevice, m->stream) != hipSuccess ||
       hipMemcpyAsync(m->d_fit_h, &fh, sizeof(FitDev), hipMemcpyHostToDevice, m->stream) != hipSuccess ||

@@ -98,11 +98,22 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
   const int i = blockIdx.x * kCpBlock + threadIdx.x;
   int jlo = 1 << 30, jhi = -1, bad = 0;
-  // theta straight from pinned host memory when the caller passed it there;
-  // block 0 leaves a device copy for the later kernels
-  const double* th = f.theta_src ? f.theta_src : f.theta;
-  if (f.theta_src && blockIdx.x == 0 && (int)threadIdx.x < f.P)
-    const_cast<double*>(f.theta)[threadIdx.x] = f.theta_src[threadIdx.x];
+  // theta straight from pinned host memory when the caller passed it there,
+  // with system-scope loads (a plain load may hit a line of the previous
+  // evaluation's theta still held in the GPU caches); block 0 leaves a device
+  // copy for the later kernels, with the caller's sequence number after it
+  // (the completion mark of k_final)
+  __shared__ double sth[kMaxP + 1];
+  const double* th = f.theta;
+  if (f.theta_src) {
+    if ((int)threadIdx.x <= f.P) {
+      const double v = __hip_atomic_load(f.theta_src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      sth[threadIdx.x] = v;
+      if (blockIdx.x == 0) const_cast<double*>(f.theta)[threadIdx.x] = v;
+    }
+    __syncthreads();
+    th = sth;
+  }
   if (i < f.T) {
     ColPar c;
     double v = 0.0;
@@ -139,7 +150,8 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
         c.c0 = 0.0; c.c1 = 1.0;
       } else {
         const double tau = log1p(s2 / (m * m));
-        const double k = gg_solve_k(f.gg, tau, nullptr);
+        // FP32 cells need k to ~1e-8: one Newton step from the table start
+        const double k = gg_solve_k(f.gg, tau, nullptr, f.prec == kF32 ? 1e-5 : 1e-9);
         if (!(k > 1e-300) || !(k < 1e12)) bad |= kBadGG;
         const GGShape sh = gg_shape(f.gg, k, true);
         const double p = f.gg.p;
@@ -161,23 +173,33 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
           c.J[0][q] = dk;
           c.J[1][q] = dm * im - sh.dD1 * dk;
         }
-        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p).
-        // FP32 Newton from outside each root stays outside it; B is raised by
-        // 5 % to cover the FP32 rounding (the bounds only need to be conservative)
-        const float cb = (float)(1.05 * (f.prec == kF32 ? kSupportB32 : kSupportB) / k);
-        float th_ = cb > 2.f ? log1pf(cb) + log1pf(log1pf(cb)) : sqrtf(2.f * cb);
-        for (int it = 0; it < 12; ++it) {
-          const float e = expm1f(th_);
-          const float d = (e - th_ - cb) * rcp(e);
-          th_ -= d;
-          if (fabsf(d) < 1e-4f * fmaxf(1.f, th_)) break;
-        }
-        float tl = -(1.f + cb);
-        for (int it = 0; it < 12; ++it) {
-          const float e = expm1f(tl);
-          const float d = (e - tl - cb) * rcp(e);
-          tl -= d;
-          if (fabsf(d) < 1e-4f * fmaxf(1.f, -tl)) break;
+        // support: k (lambda - 1 - ln lambda) <= B, lambda = e^t, x = exp((ct + t)/p),
+        // with B raised by 5 % (the bounds only need to be conservative).  The
+        // roots come from the table of the nearest grid point below ln k,
+        // which bounds them from outside; off the table, FP32 Newton from
+        // outside each root stays outside it.
+        float th_, tl;
+        const double spos = (lnk - kSupLo) * ((kSupTab - 1) / (kSupHi - kSupLo));
+        if (f.gg.has_tab && spos >= 0.0 && spos < kSupTab - 1) {
+          const int si = (int)spos;
+          th_ = f.gg.sup_hi[si];
+          tl = f.gg.sup_lo[si];
+        } else {
+          const float cb = (float)(1.05 * (f.prec == kF32 ? kSupportB32 : kSupportB) / k);
+          th_ = cb > 2.f ? log1pf(cb) + log1pf(log1pf(cb)) : sqrtf(2.f * cb);
+          for (int it = 0; it < 12; ++it) {
+            const float e = expm1f(th_);
+            const float d = (e - th_ - cb) * rcp(e);
+            th_ -= d;
+            if (fabsf(d) < 1e-4f * fmaxf(1.f, th_)) break;
+          }
+          tl = -(1.f + cb);
+          for (int it = 0; it < 12; ++it) {
+            const float e = expm1f(tl);
+            const float d = (e - tl - cb) * rcp(e);
+            tl -= d;
+            if (fabsf(d) < 1e-4f * fmaxf(1.f, -tl)) break;
+          }
         }
         const double xlo = exp((c.c0 + (double)tl) / p), xhi = exp((c.c0 + (double)th_) / p);
         const int2 r = cell_range(f, xlo, xhi);
@@ -697,7 +719,14 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       for (int q = 0; q < f.nresp; ++q) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
     }
   }
-  if (f.out_host) __threadfence_system();
+  if (f.out_host) {  // then the completion mark the caller spins on
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) {
+      f.out_host[2 + f.P] = f.theta[f.P];
+      __threadfence_system();
+    }
+  }
 }
 
 __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {

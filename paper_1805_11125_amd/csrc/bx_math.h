@@ -40,11 +40,18 @@ constexpr double kLnSqrtTwoPi = 0.91893853320467274178032973640562;
 constexpr int kKTab = 512;             // start table of the shape solve
 constexpr double kKTabLo = -14.0;      // ln tau range of the table
 constexpr double kKTabHi = 4.0;
+constexpr int kSupTab = 512;           // support-root table
+constexpr double kSupLo = -9.0;        // ln k range of the table
+constexpr double kSupHi = 16.0;
 struct GGConst {
   double p, ip;                 // p, 1/p
   double cG[kSeriesTerms + 1];  // G(x) = ln Gamma(x) + ln Gamma(x+2/p) - 2 ln Gamma(x+1/p) = sum cG[n] x^-n
   double cD[kSeriesTerms + 1];  // D(x) = ln Gamma(x+1/p) - ln Gamma(x) - ln(x)/p = sum cD[n] x^-n
-  float lnk_tab[kKTab];         // ln k at ln tau = kKTabLo + i (kKTabHi - kKTabLo)/(kKTab - 1)
+  double lnk_tab[kKTab];        // ln k at ln tau = kKTabLo + i (kKTabHi - kKTabLo)/(kKTab - 1)
+  // roots t- < 0 < t+ of e^t - 1 - t = Bs / k (the support bounds in
+  // t = ln(y/k)) at ln k = kSupLo + i (kSupHi - kSupLo)/(kSupTab - 1),
+  // rounded outward; Bs is the support cut of the model's precision
+  float sup_lo[kSupTab], sup_hi[kSupTab];
   int has_tab;
 };
 
@@ -142,16 +149,22 @@ BX_HD GGShape gg_shape(const GGConst& c, double k, bool full) {
 }
 
 // Shape k of the GG with ln(1 + Var/Mean^2) = tau: Newton in u = ln k.
-BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters) {
-  // start: G ~ cG1/k + cG2/k^2 for large k (solve the quadratic), G ~ -ln k
-  // for small k
+// Newton steps stop once a step is below tol (the error left is then of
+// order tol^2).
+BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters, double tol = 1e-9) {
+  // start: cubic interpolation in the table (~1e-7 relative), else
+  // G ~ cG1/k + cG2/k^2 for large k (solve the quadratic), G ~ -ln k for
+  // small k
   double u;
   const double lt = log(tau);
-  if (c.has_tab && lt > kKTabLo && lt < kKTabHi) {  // table start: ~1e-4 relative
-    const double pos = (lt - kKTabLo) * ((kKTab - 1) / (kKTabHi - kKTabLo));
+  const double pos = (lt - kKTabLo) * ((kKTab - 1) / (kKTabHi - kKTabLo));
+  if (c.has_tab && pos >= 1.0 && pos < kKTab - 2) {
     const int i0 = (int)pos;
     const double w = pos - i0;
-    u = (1.0 - w) * (double)c.lnk_tab[i0] + w * (double)c.lnk_tab[i0 + 1];
+    const double ym = c.lnk_tab[i0 - 1], y0 = c.lnk_tab[i0], y1 = c.lnk_tab[i0 + 1], y2 = c.lnk_tab[i0 + 2];
+    // Lagrange cubic through the four neighbours (unit spacing)
+    u = -w * (w - 1.0) * (w - 2.0) * (1.0 / 6.0) * ym + (w + 1.0) * (w - 1.0) * (w - 2.0) * 0.5 * y0 -
+        (w + 1.0) * w * (w - 2.0) * 0.5 * y1 + (w + 1.0) * w * (w - 1.0) * (1.0 / 6.0) * y2;
   } else if (tau < 0.1) {
     const double a1 = c.cG[1], a2 = c.cG[2];
     u = log((a1 + sqrt(fmax(a1 * a1 + 4.0 * tau * a2, 0.0))) / (2.0 * tau));
@@ -165,8 +178,7 @@ BX_HD double gg_solve_k(const GGConst& c, double tau, int* iters) {
     double du = (s.G - tau) / (k * s.dG);
     du = fmax(-2.0, fmin(2.0, du));
     u -= du;
-    // quadratic convergence: after a step below 1e-9 the error is ~1e-18
-    if (fabs(du) < 1e-9) break;
+    if (fabs(du) < tol) break;
   }
   if (iters) *iters = it;
   return exp(u);

@@ -60,6 +60,9 @@ LaunchShape shape_of(const FitDev& f);
 
 }  // namespace bx
 
+constexpr int kPinOut = 64;       // doubles: device-written half of h_pin (512 B in)
+constexpr int kPinDoubles = 128;  // 1 KiB: room for 2 + 32 results and the mark
+
 struct bx_model {
   bx::HostModel h;
   bx::DeviceFit df;
@@ -71,7 +74,12 @@ struct bx_model {
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
   hipGraphExec_t g_eval = nullptr, g_grad = nullptr;  // host-buffer path (d_fit_h)
   hipGraphExec_t g_grad_dev = nullptr;                // device-buffer path (d_fit)
-  double* h_pin = nullptr;       // pinned, coherent: theta[P] | out[2 + P]
+  // pinned, coherent: theta[P] | seq at 0 (written by the host), out[2 + P] |
+  // completion mark at kPinOut (written by the device).  The two halves never
+  // share a cache line: a host line holding a stale copy of a device-written
+  // value would otherwise be written back over it.
+  double* h_pin = nullptr;
+  uint64_t seq = 0;              // evaluations on the host path (completion marks)
   double lnfact = 0.0;
   std::atomic<int> users{0};     // server fits referencing this model
   int device = 0;

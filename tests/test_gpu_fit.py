@@ -146,3 +146,28 @@ def test_admission_under_small_budget(bx):
     s.close()
     s2.close()
     del _abi, C
+
+
+def test_plain_fits_reproducible_around_server_runs(bx):
+    # The plain path exchanges theta and results with the kernels through one
+    # pinned buffer; host-written and device-written values must never share
+    # a cache line (a stale host copy written back over a fresh NLL changed
+    # the path of some fits from run to run).
+    toys = _toys(16)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+
+    def plain():
+        return [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+                for m, (d, x, t) in zip(models, toys)]
+
+    first = plain()
+    for _ in range(2):
+        s = bx.Server()
+        tickets = [s.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+                   for m, (d, x, t) in zip(models, toys)]
+        batched = [s.wait(tk) for tk in tickets]
+        s.close()
+        again = plain()
+        for a, b, c in zip(first, again, batched):
+            assert a.nll == b.nll and np.array_equal(a.x, b.x) and a.n_eval == b.n_eval
+            assert np.array_equal(a.x, c.x)
