@@ -121,7 +121,11 @@ def toy_study(bx, synth, n_toys, n_plain):
     for m, _, _ in toys:
         m.close()
     st = np.array([r.status for r in res])
+    # NLL+gradient evaluations the fits asked for, per second of wall time
+    ev_b = sum(r.n_eval for r in res) / el
+    ev_p = sum(r.n_eval for r in plain) / el_p
     return {"toys": n_toys, "batched_fits_per_s": n_toys / el, "plain_fits_per_s": n_plain / el_p,
+            "batched_evals_per_s": ev_b, "plain_evals_per_s": ev_p,
             "plain_sample": n_plain, "speedup": (n_toys / el) / (n_plain / el_p),
             "converged": int((st == bx.BX_CONVERGED).sum()),
             "median_iters": float(np.median([r.n_iter for r in res])),

@@ -367,7 +367,7 @@ LaunchShape shape_of(const FitDev& f) {
   L.max_fwd_blocks = f.n_rt * f.n_cg;
   L.max_NS = f.N * kSP;
   L.max_rowblk = f.n_rowblk;
-  L.max_bwd_blocks = f.n_ct * f.n_rg;
+  L.max_bwd_blocks = (f.n_ct + 7) / 8 * 8 * f.n_rg;  // true tiles interleaved over the 8 XCDs
   L.kind = f.kind;
   L.prec = f.prec;
   L.any_mv = f.mv;

@@ -59,6 +59,15 @@ template <class R> struct Acc4;
 template <> struct Acc4<float> { typedef v4f T; };
 template <> struct Acc4<double> { typedef v4d T; };
 
+// Workgroups go to the 8 XCDs round-robin (block b to XCD b % 8), each with
+// its own L2.  The backward sweep gives true tile ct to XCD ct % 8 with all
+// of its blocks: the tile's column parameters are fetched into one L2, and
+// neighbouring tiles (similar work) are spread over all eight.
+__device__ __forceinline__ int2 bwd_block(int n_rg) {
+  const int b = blockIdx.x, q = b >> 3;
+  return make_int2((b & 7) + 8 * (q / n_rg), q % n_rg);  // (ct, rg)
+}
+
 __device__ __forceinline__ double sum16(double x) {  // fixed-order sum over a 16-lane row
   x += __shfl_xor(x, 8, 16);
   x += __shfl_xor(x, 4, 16);
@@ -536,14 +545,15 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 }
 
 // ---------------------------------------------------------------------------
-// Block (ct, rg): true tile ct; its support covers the contiguous reco tiles
+// Logical block (ct, rg): true tile ct; its support covers the contiguous reco tiles
 // [rt_a, rt_b], and wave w takes rt = rt_a + (4 rg + w) RG + c, c < RG.  The
 // working blocks of a true tile are thus its first ones; the others write a
 // zero partial and leave.
 template <class R, int KIND>
 __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  const int ct = blockIdx.x / f.n_rg, rg = blockIdx.x % f.n_rg;
+  const int2 cr = bwd_block(f.n_rg);
+  const int ct = cr.x, rg = cr.y, bl = ct * f.n_rg + rg;
   if (ct >= f.n_ct) return;  // block-uniform
   __shared__ double colA[4][16], colB[4][16];
   __shared__ double hst[4 * kMaxRG * kRowStep + kMaxK], htl[4 * kMaxRG * kRowStep], gl[kMaxK];
@@ -554,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
   const int rt_b = b.y >= b.x ? min(b.y / kRowStep, f.n_rt - 1) : -1;
   const int rt_blk = rt_a + 4 * rg * f.RG;  // first reco tile of this block
   if (rt_blk > rt_b) {                      // block-uniform: nothing in range
-    if (threadIdx.x < 4) f.bwdpart[(size_t)blockIdx.x * 4 + threadIdx.x] = 0.0;
+    if (threadIdx.x < 4) f.bwdpart[(size_t)bl * 4 + threadIdx.x] = 0.0;
     return;
   }
   // single histogram: the pile-up adjoint w~ = P^T w of this block's reco
@@ -639,7 +649,7 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
       v = A * c.J[0][q] + B * c.J[1][q];
     }
     v = sum16(v);
-    if (c16 == 0) f.bwdpart[(size_t)blockIdx.x * 4 + q] = v;
+    if (c16 == 0) f.bwdpart[(size_t)bl * 4 + q] = v;
   }
 }
 
