@@ -41,20 +41,21 @@ FLOP_FWD_EDGE = 130
 FLOP_BWD_EDGE = 162
 
 
-def kernel_traffic(name):
-    """HBM bytes per dispatch measured with rocprofv3 counters (profiles/),
-    or None when the kernel sources changed since the counters were taken."""
+def profiled(fname, key, name):
+    """A per-kernel figure measured with rocprofv3 counters (a `key ...` line
+    of profiles/fname), or None when the kernel sources changed since the
+    counters were taken."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1805_11125_amd", "csrc")
     h = hashlib.sha256()
     for f in ("bx_kernels.hip", "bx_math.h", "bx_dev.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     try:
-        text = open(os.path.join(ROOT, "profiles", "config2_hbm_counters.md")).read()
+        text = open(os.path.join(ROOT, "profiles", fname)).read()
     except OSError:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes"):
+        if line.startswith(key + " "):
             kv = dict(t.split("=") for t in line.split()[1:])
             if kv.get("src_sha") == h.hexdigest()[:16] and name in kv:
                 return float(kv[name])
@@ -251,7 +252,8 @@ def main():
     else:
         kname, kms, flops = "k_cells_fwd", fwd_ms, edges * (FLOP_FWD_EDGE + 2 * d.S)
     achieved = flops / (kms * 1e-3)
-    traffic = kernel_traffic(kname)
+    traffic = profiled("config2_hbm_counters.md", "traffic_bytes", kname)
+    valu = profiled("config2_valu_counters.md", "valu_issue", kname)
     res = {
         "metric": METRIC, "value": evals, "unit": "evals/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 / evals,
@@ -265,6 +267,7 @@ def main():
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "edges_per_launch": edges,
+                     "valu_issue_frac": valu,
                      "kernel_ms": kms},
     }
     m.close()

@@ -151,6 +151,14 @@ bx_status bx_model_expected(bx_model* m, const double* theta, double* out);
  * sums, whole evaluation}; a stage the model does not have reads ~0. */
 bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms);
 
+/* Diagnostics: the same per-stage timing for a batch.  `copies` independent
+ * fits of this model (its data, theta) are placed in device memory as the fit
+ * server places them and evaluated together, one launch per stage with
+ * blockIdx.y selecting the fit; ms[9] as above, per batched launch.  Device
+ * memory for the batch is allocated and freed inside the call (BX_E_NOMEM if
+ * it does not fit).  Synchronous on the model's stream. */
+bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies, int32_t reps, double* ms);
+
 /* ---- fitting (Sec. 4, steps 5-7) ---- */
 typedef enum { BX_FIT = 0, BX_EVAL_GRAD = 1 } bx_request_kind;
 typedef enum { BX_CONVERGED = 0, BX_MAXITER = 1, BX_FAILED = 2 } bx_fit_status;

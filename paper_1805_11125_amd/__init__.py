@@ -190,10 +190,19 @@ class Model:
               "cells_bwd", "final", "total"]
 
     def stage_times(self, theta, reps=20):
-        """Average ms per evaluation stage (HIP events, one kernel at a time)."""
+        """Average ms per evaluation stage (HIP events, each stage's kernel
+        launched back to back on its own)."""
         t = _f64(theta)
         ms = np.zeros(9)
         check(self._lib.bx_model_stage_times(self._h, dptr(t), int(reps), dptr(ms)))
+        return dict(zip(self.STAGES, ms))
+
+    def batch_times(self, theta, copies, reps=10):
+        """Average ms per batched launch of each stage for `copies` fits of
+        this model evaluated together (bx_model_batch_times)."""
+        t = _f64(theta)
+        ms = np.zeros(9)
+        check(self._lib.bx_model_batch_times(self._h, dptr(t), int(copies), int(reps), dptr(ms)))
         return dict(zip(self.STAGES, ms))
 
     def nll_grad_dev(self, theta_dev, out_dev, stream=None):

@@ -49,7 +49,7 @@ struct FitDev {
   // shape
   int T, N, S, P, nresp, kind, prec, mv;
   int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
-  int n_rt, n_ct, CG, n_cg, RG, n_rg, n_rowblk;
+  int n_rt, n_ct, CG, n_cg, n_fb, RG, n_rg, n_rowblk;  // n_cg: forward chunks, n_fb: forward blocks per reco tile
   int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
   int uniform;            // reco bins of equal width
   int pad0;
@@ -75,7 +75,7 @@ struct FitDev {
   const double* theta;  // [P]
   ColPar* cp;           // [T]
   int2* tb;             // [n_ct] support of each column tile (cells)
-  void* Mpart;          // [n_cg][N][16] R: one partial per forward block
+  void* Mpart;          // [n_cg][N][16] R: one partial per chunk of 16 listed true tiles
   double* M;            // [N][16] sum of the partials (FP64)
   double* Mp;           // [N][16] after pile-up
   double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part
@@ -96,6 +96,7 @@ struct FitDev {
 struct LaunchShape {
   int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks;
   int kind, prec, any_mv, any_rad;
+  int CG;  // forward tiles per wave (one value per launch)
 };
 constexpr int kStages = 8;  // colparams, cells_fwd, reduce_M, rowterms, radial, adjoint, cells_bwd, final
 void launch_stage(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,

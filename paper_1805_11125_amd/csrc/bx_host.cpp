@@ -103,20 +103,25 @@ static void make_gg_const(double p, double bs, GGConst* c) {
   c->has_tab = 1;
 }
 
-Tiles choose_tiles(int T, int N, int kind, int prec) {
-  // Column tiles per forward wave and row tiles per backward wave.  The
-  // choice depends only on this fit's shape; an on-disk table written by the
-  // tuner (BX_TUNE_CACHE) overrides the defaults.
-  Tiles t{1, 1};
+Tiles choose_tiles(int T, int N, int kind, int prec, int batched) {
+  // True tiles per forward wave (CG) and reco tiles per backward wave (RG),
+  // for one fit evaluated alone (latency: CG 1) or inside a batch (throughput:
+  // fewer, fuller forward blocks).  A table written by the tuner
+  // (BX_TUNE_CACHE: lines "kind prec Tmin Tmax Nmin Nmax batched CG RG")
+  // overrides the defaults; BX_TILES="CG,RG" overrides both for sweeps.  CG
+  // does not change any result bit (the forward partials are summed in a
+  // fixed tree); RG groups the backward partials and does.
+  Tiles t{batched ? 4 : 1, 1};
   const char* path = getenv("BX_TUNE_CACHE");
   if (path && *path) {
     FILE* fp = fopen(path, "r");
     if (fp) {
       char line[256];
       while (fgets(line, sizeof line, fp)) {
-        int k, pr, tmin, tmax, nmin, nmax, cg, rg;
-        if (sscanf(line, "%d %d %d %d %d %d %d %d", &k, &pr, &tmin, &tmax, &nmin, &nmax, &cg, &rg) == 8 &&
-            k == kind && pr == prec && T >= tmin && T <= tmax && N >= nmin && N <= nmax && cg > 0 && rg > 0) {
+        int k, pr, tmin, tmax, nmin, nmax, bt, cg, rg;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d", &k, &pr, &tmin, &tmax, &nmin, &nmax, &bt, &cg, &rg) == 9 &&
+            k == kind && pr == prec && T >= tmin && T <= tmax && N >= nmin && N <= nmax && bt == batched &&
+            cg > 0 && rg > 0) {
           t.CG = cg;
           t.RG = rg;
           break;
@@ -125,13 +130,15 @@ Tiles choose_tiles(int T, int N, int kind, int prec) {
       fclose(fp);
     }
   }
-  const char* ov = getenv("BX_TILES");  // "CG,RG" for sweeps
+  const char* ov = getenv("BX_TILES");
   if (ov && *ov) {
     int cg = 0, rg = 0;
     if (sscanf(ov, "%d,%d", &cg, &rg) == 2 && cg > 0 && rg > 0) t = Tiles{cg, rg};
   }
   t.RG = std::min(t.RG, kMaxRG);
-  t.CG = std::min(t.CG, kMaxCG);
+  int cg = 1;  // a power of two, at most kMaxCG
+  while (cg * 2 <= std::min(t.CG, kMaxCG)) cg *= 2;
+  t.CG = cg;
   return t;
 }
 
@@ -263,7 +270,7 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   }
   if (m.kind == kGG) make_gg_const(m.p, 1.05 * (m.prec == kF32 ? kSupportB32 : kSupportB), &m.gg);
   else memset(&m.gg, 0, sizeof m.gg);
-  m.tiles = choose_tiles(m.T, m.N, m.kind, m.prec);
+  m.tiles = choose_tiles(m.T, m.N, m.kind, m.prec, 0);
   return set_host_data(h, x);
 }
 
@@ -302,9 +309,10 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->n_ct = (h.T + kColTile - 1) / kColTile;
   f->CG = h.tiles.CG;
   f->RG = h.tiles.RG;
-  // a forward block holds 4 waves of CG true tiles; a backward block 4 waves
-  // of RG reco tiles
-  f->n_cg = (f->n_ct + kFwdWaves * f->CG - 1) / (kFwdWaves * f->CG);
+  // forward partials: one per chunk of kFwdWaves listed true tiles; a forward
+  // block holds CG chunks; a backward block 4 waves of RG reco tiles
+  f->n_cg = (f->n_ct + kFwdWaves - 1) / kFwdWaves;
+  f->n_fb = (f->n_cg + f->CG - 1) / f->CG;
   f->n_rg = (f->n_rt + 4 * f->RG - 1) / (4 * f->RG);
   f->n_rowblk = (h.N + 15) / 16;
   f->n_cpblk = (h.T + kCpBlock - 1) / kCpBlock;
@@ -364,7 +372,8 @@ size_t device_fit_bytes(const HostModel& h) {
 LaunchShape shape_of(const FitDev& f) {
   LaunchShape L;
   L.max_T = f.T;
-  L.max_fwd_blocks = f.n_rt * f.n_cg;
+  L.max_fwd_blocks = f.n_rt * f.n_fb;
+  L.CG = f.CG;
   L.max_NS = f.N * kSP;
   L.max_rowblk = f.n_rowblk;
   L.max_bwd_blocks = (f.n_ct + 7) / 8 * 8 * f.n_rg;  // true tiles interleaved over the 8 XCDs
@@ -682,6 +691,71 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "stage timing");
   return BX_OK;
+}
+
+bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies, int32_t reps, double* ms) {
+  if (!m || !theta || !ms || copies < 1 || reps < 1) return inval("bad argument");
+  const int P = m->h.P;
+  for (int q = 0; q < P; ++q)
+    if (!std::isfinite(theta[q])) {
+      set_error("non-finite parameter");
+      return BX_E_DOMAIN;
+    }
+  // `copies` independent fits of this model, placed as the server places
+  // them, evaluated together by one launch per stage (blockIdx.y = fit)
+  const size_t stride = (device_fit_bytes(m->h) + 255) & ~(size_t)255;
+  char* base = nullptr;
+  FitDev* d_fd = nullptr;
+  if (hipMalloc((void**)&base, stride * copies) != hipSuccess) {
+    set_error("hipMalloc of the batch failed");
+    return BX_E_NOMEM;
+  }
+  if (hipMalloc((void**)&d_fd, sizeof(FitDev) * copies) != hipSuccess) {
+    (void)hipFree(base);
+    set_error("hipMalloc of the batch failed");
+    return BX_E_NOMEM;
+  }
+  std::vector<FitDev> fd(copies);
+  bx_status s = BX_OK;
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < copies && s == BX_OK; ++c) {
+    DeviceFit df;
+    s = place_fit(m->h, base + stride * c, &df, m->stream);
+    if (s == BX_OK) e = hipMemcpyAsync(df.d_theta, theta, P * sizeof(double), hipMemcpyHostToDevice, m->stream);
+    if (e != hipSuccess) s = hip_fail(e, "theta upload");
+    fd[c] = df.dev;
+  }
+  if (s == BX_OK) {
+    e = hipMemcpyAsync(d_fd, fd.data(), sizeof(FitDev) * copies, hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) s = hip_fail(e, "batch upload");
+  }
+  if (s == BX_OK) {
+    const LaunchShape L = shape_of(fd[0]);
+    launch_eval(d_fd, nullptr, copies, L, true, m->stream);  // every stage's inputs in place
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int k = 0; k <= kStages && e == hipSuccess; ++k) {
+      e = hipEventRecord(e0, m->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        if (k < kStages) launch_stage(d_fd, nullptr, copies, L, true, k, m->stream);
+        else launch_eval(d_fd, nullptr, copies, L, true, m->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, m->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      ms[k] = (double)t / reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) s = hip_fail(e, "batch timing");
+  }
+  (void)hipStreamSynchronize(m->stream);
+  (void)hipFree(d_fd);
+  (void)hipFree(base);
+  return s;
 }
 
 bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r) {

@@ -248,24 +248,44 @@ __device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
 }
 
 // ---------------------------------------------------------------------------
-// Block (rt, cg): reco rows [15 rt, 15 rt + 15).  The true tiles whose
+// Balanced pairwise sum of item(OFF), ..., item(OFF + N - 1), N a power of
+// two: ((i0 + i1) + (i2 + i3)) + ...  Any aligned sub-range is a subtree, so
+// partial sums formed over sub-ranges and combined the same way give the same
+// bits.
+template <int N, int OFF, class V, class F>
+__device__ __forceinline__ V tree_sum(const F& item) {
+  if constexpr (N == 1) {
+    return item(OFF);
+  } else {
+    const V a = tree_sum<N / 2, OFF, V>(item);
+    const V b = tree_sum<N / 2, OFF + N / 2, V>(item);
+    return a + b;
+  }
+}
+
+// Block (rt, fb): reco rows [15 rt, 15 rt + 15).  The true tiles whose
 // support meets these rows (a contiguous band for a smooth response, about a
-// third of them on the 3000 x 900 grid) are listed in ascending order, and
-// wave w of chunk cg takes list entries (kFwdWaves cg + w) CG + c, c < CG: the
-// working waves fill the first blocks of each reco tile, and the rest find
-// their chunk empty and only write zero partials.
-template <class R, int KIND>
+// third of them on the 3000 x 900 grid) are listed in ascending order; the
+// list is cut into chunks of 16 entries, and each chunk's tiles are summed in
+// the balanced tree of tree_sum into one partial, Mpart[chunk].  A block takes
+// CG chunks: wave w holds entries [w CG, w CG + CG) of its window (a subtree),
+// so the partials do not depend on CG, which sets only how many tiles a wave
+// evaluates in a row.  The working waves fill the first blocks of each reco
+// tile; the rest find their window empty and write zero partials.
+template <class R, int KIND, int CG>
 __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
+  typedef typename Acc4<R>::T V;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  const int rt = blockIdx.x / f.n_cg, cg = blockIdx.x % f.n_cg;
+  const int rt = blockIdx.x / f.n_fb, fb = blockIdx.x % f.n_fb;
   if (rt >= f.n_rt) return;  // block-uniform
   __shared__ R part[kFwdWaves][4][64];
   __shared__ int wcount[kFwdWaves];
-  __shared__ int mylist[kFwdWaves * kMaxCG];
+  __shared__ int mylist[kFwdWaves * CG];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int j0 = rt * kRowStep;
   // this block's window [lo, lo + kFwdWaves CG) of the list of active tiles
-  const int lo = kFwdWaves * f.CG * cg, win = kFwdWaves * f.CG;
+  constexpr int win = kFwdWaves * CG;
+  const int lo = win * fb;
   int n_act = 0;
   for (int c0 = 0; c0 < f.n_ct; c0 += kFwdWaves * 64) {
     const int ct = c0 + (int)threadIdx.x;
@@ -291,36 +311,48 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   const double xe = f.xe[je];
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
-  typename Acc4<R>::T acc = {0, 0, 0, 0};
-  const int e0 = wv * f.CG;
-  const int e_end = min(e0 + f.CG, n_act - lo);
-  for (int e = e0; e < e_end; ++e) {
+  const int n_here = n_act - lo;  // entries of this window in the list
+  // one tile's 16 x 16 contribution (zero past the end of the list)
+  auto tile = [&](int c) -> V {
+    V acc = {0, 0, 0, 0};
+    const int e = wv * CG + c;
+    if (e >= n_here) return acc;  // wave-uniform
     const int ct = mylist[e];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < f.T;
-      const ColPar& c = f.cp[iok ? i : f.T - 1];
+      const ColPar& cpi = f.cp[iok ? i : f.T - 1];
       const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
-      const EdgeVal<R> ev = edge_at<R, KIND, false>(c, xe);
+      const EdgeVal<R> ev = edge_at<R, KIND, false>(cpi, xe);
       const R hi = dpp_from_next(ev.v);
       const R a = (row_ok && iok) ? cell_from(ev.v, hi) : (R)0;
       acc = mfma16(a, bb, acc);
     }
-  }
+    return acc;
+  };
+  const V sub = tree_sum<CG, 0, V>(tile);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
+  for (int r = 0; r < 4; ++r) part[wv][r][lane] = sub[r];
   __syncthreads();
-  if (wv == 0) {
-    R* out = (R*)f.Mpart + (size_t)cg * f.N * kSP;
+  // chunk k of this block = waves [k W, k W + W), W = 16 / CG: wave k adds
+  // their subtrees in the same tree and writes the chunk's partial
+  constexpr int W = kFwdWaves / CG;
+  const int chunk = fb * CG + wv;
+  if (wv < CG && chunk < f.n_cg) {
+    const V v = tree_sum<W, 0, V>([&](int w) -> V {
+      V x;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[r] = part[wv * W + w][r][lane];
+      return x;
+    });
+    R* out = (R*)f.Mpart + (size_t)chunk * f.N * kSP;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      R v = part[0][r][lane];
-      for (int w = 1; w < kFwdWaves; ++w) v += part[w][r][lane];
       // result layout of MFMA 16x16x4: lane l, register r holds row 4(l/16) + r
       // (f32) or row l/16 + 4r (f64), column l%16
       const int row = sizeof(R) == 4 ? 4 * g + r : g + 4 * r;
-      if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = v;
+      if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = v[r];
     }
   }
 }
@@ -744,6 +776,16 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 }
 
 // ---------------------------------------------------------------------------
+template <class R, int KIND>
+static void launch_fwd(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {
+  switch (cg) {
+    case 1: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 1>), grid, blk, 0, st, d_fits, d_active); break;
+    case 2: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 2>), grid, blk, 0, st, d_fits, d_active); break;
+    case 4: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 4>), grid, blk, 0, st, d_fits, d_active); break;
+    default: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 8>), grid, blk, 0, st, d_fits, d_active); break;
+  }
+}
+
 // One stage of an evaluation: 0 colparams, 1 cells_fwd, 2 reduce_M,
 // 3 rowterms, 4 radial, 5 adjoint, 6 cells_bwd, 7 final.  Stages that do not
 // apply (radial/adjoint without multivariate terms, the backward stages
@@ -760,10 +802,10 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
                          d_fits, d_active);
       break;
     case 1:
-      if (f32 && gauss) hipLaunchKernelGGL((k_cells_fwd<float, kGauss>), gf, bf, 0, st, d_fits, d_active);
-      if (f32 && !gauss) hipLaunchKernelGGL((k_cells_fwd<float, kGG>), gf, bf, 0, st, d_fits, d_active);
-      if (!f32 && gauss) hipLaunchKernelGGL((k_cells_fwd<double, kGauss>), gf, bf, 0, st, d_fits, d_active);
-      if (!f32 && !gauss) hipLaunchKernelGGL((k_cells_fwd<double, kGG>), gf, bf, 0, st, d_fits, d_active);
+      if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, gf, bf, st, d_fits, d_active);
+      if (f32 && !gauss) launch_fwd<float, kGG>(L.CG, gf, bf, st, d_fits, d_active);
+      if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, gf, bf, st, d_fits, d_active);
+      if (!f32 && !gauss) launch_fwd<double, kGG>(L.CG, gf, bf, st, d_fits, d_active);
       break;
     case 2:
       if (f32) hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);

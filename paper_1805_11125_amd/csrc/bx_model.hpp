@@ -21,7 +21,7 @@ bx_status hip_fail(hipError_t e, const char* what);
 struct Tiles {
   int CG, RG;
 };
-Tiles choose_tiles(int T, int N, int kind, int prec);
+Tiles choose_tiles(int T, int N, int kind, int prec, int batched);
 
 // Host copy of everything a fit needs, independent of device placement.
 struct HostModel {

@@ -29,6 +29,7 @@ static int64_t now_ns() {
 }
 
 constexpr int kThetaStride = 32;
+constexpr int kGroups = 16;  // launch groups: 2 kinds x 2 precisions x 4 forward tile widths
 constexpr int kOutStride = 34;
 
 struct Req {
@@ -41,6 +42,8 @@ struct Req {
   int slot = -1;
   void* mem = nullptr;
   DeviceFit df;            // host copy of the slot's FitDev (source of its upload)
+  LaunchShape shape{};     // grid needs of this fit (set at admission)
+  int group = 0;           // launch group: (kind, precision, forward tiles per wave)
   bx_fit_result res{};
   bool done = false;
 };
@@ -55,7 +58,7 @@ struct bx_server {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   FitDev* d_fits = nullptr;       // [max_slots]
-  int* d_active = nullptr;        // [max_slots]
+  int* d_active = nullptr;        // [kGroups][max_slots] active lists, one region per launch group
   double* d_theta = nullptr;      // [max_slots][32]
   double* d_out = nullptr;        // [max_slots][34]
   double* h_theta = nullptr;      // pinned
@@ -97,6 +100,10 @@ static void admit(bx_server* s) {
     }
     df.dev.theta = s->d_theta + (size_t)r->slot * kThetaStride;
     df.dev.out = s->d_out + (size_t)r->slot * kOutStride;
+    r->shape = shape_of(df.dev);
+    int cgl = 0;
+    while ((1 << cgl) < r->shape.CG) ++cgl;
+    r->group = (r->shape.kind * 2 + r->shape.prec) * 4 + cgl;
     (void)hipMemcpyAsync(s->d_fits + r->slot, &df.dev, sizeof(FitDev), hipMemcpyHostToDevice, s->stream);
     r->res.t_admit_ns = now_ns();
     s->active.push_back(r);
@@ -126,34 +133,31 @@ static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
   for (auto& r : act) max_slot = std::max(max_slot, r->slot + 1);
   (void)hipMemcpyAsync(s->d_theta, s->h_theta, sizeof(double) * kThetaStride * max_slot, hipMemcpyHostToDevice,
                        s->stream);
-  // one batched launch per (kind, precision) group
-  for (int kind = 0; kind < 2; ++kind)
-    for (int prec = 0; prec < 2; ++prec) {
-      int n = 0;
-      LaunchShape L{};
-      L.kind = kind;
-      L.prec = prec;
-      const int grp = kind * 2 + prec;  // each group stages its list separately
-      int* act_list = s->h_active + (size_t)grp * s->max_slots;
-      int* d_list = s->d_active + (size_t)grp * s->max_slots;
-      for (auto& r : act) {
-        if (r->h.kind != kind || r->h.prec != prec) continue;
-        FitDev f{};
-        derive_tiles(r->h, &f);
-        const LaunchShape l = shape_of(f);
-        L.max_T = std::max(L.max_T, l.max_T);
-        L.max_fwd_blocks = std::max(L.max_fwd_blocks, l.max_fwd_blocks);
-        L.max_NS = std::max(L.max_NS, l.max_NS);
-        L.max_rowblk = std::max(L.max_rowblk, l.max_rowblk);
-        L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
-        L.any_mv |= l.any_mv;
-        L.any_rad |= l.any_rad;
-        act_list[n++] = r->slot;
-      }
-      if (!n) continue;
-      (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
-      launch_eval(s->d_fits, d_list, n, L, true, s->stream);
+  // one batched launch per group of (kind, precision, forward tiles per wave)
+  for (int grp = 0; grp < kGroups; ++grp) {
+    int n = 0;
+    LaunchShape L{};
+    int* act_list = s->h_active + (size_t)grp * s->max_slots;  // each group stages its own list
+    int* d_list = s->d_active + (size_t)grp * s->max_slots;
+    for (auto& r : act) {
+      if (r->group != grp) continue;
+      const LaunchShape& l = r->shape;
+      L.kind = l.kind;
+      L.prec = l.prec;
+      L.CG = l.CG;
+      L.max_T = std::max(L.max_T, l.max_T);
+      L.max_fwd_blocks = std::max(L.max_fwd_blocks, l.max_fwd_blocks);
+      L.max_NS = std::max(L.max_NS, l.max_NS);
+      L.max_rowblk = std::max(L.max_rowblk, l.max_rowblk);
+      L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
+      L.any_mv |= l.any_mv;
+      L.any_rad |= l.any_rad;
+      act_list[n++] = r->slot;
     }
+    if (!n) continue;
+    (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
+    launch_eval(s->d_fits, d_list, n, L, true, s->stream);
+  }
   (void)hipMemcpyAsync(s->h_out, s->d_out, sizeof(double) * kOutStride * max_slot, hipMemcpyDeviceToHost, s->stream);
   (void)hipStreamSynchronize(s->stream);
   for (auto& r : act) {
@@ -226,12 +230,12 @@ bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip
     s->own_stream = true;
   }
   const size_t M = s->max_slots;
-  if (hipMalloc(&s->d_fits, sizeof(FitDev) * M) != hipSuccess || hipMalloc(&s->d_active, sizeof(int) * 4 * M) != hipSuccess ||
+  if (hipMalloc(&s->d_fits, sizeof(FitDev) * M) != hipSuccess || hipMalloc(&s->d_active, sizeof(int) * kGroups * M) != hipSuccess ||
       hipMalloc(&s->d_theta, sizeof(double) * kThetaStride * M) != hipSuccess ||
       hipMalloc(&s->d_out, sizeof(double) * kOutStride * M) != hipSuccess ||
       hipHostMalloc((void**)&s->h_theta, sizeof(double) * kThetaStride * M, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutStride * M, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_active, sizeof(int) * 4 * M, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&s->h_active, sizeof(int) * kGroups * M, hipHostMallocDefault) != hipSuccess) {
     bx_server_destroy(s);
     set_error("server allocation failed");
     return BX_E_NOMEM;
@@ -278,6 +282,7 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   if (st != BX_OK) return st;
   r->pb.f_noise = nll_noise(m->h);
   r->h = m->h;
+  r->h.tiles = choose_tiles(r->h.T, r->h.N, r->h.kind, r->h.prec, 1);  // batched tile widths
   r->bytes = (device_fit_bytes(r->h) + 4095) & ~(size_t)4095;
   if (r->bytes > s->budget) {
     set_error("request larger than the server's memory budget");

@@ -99,6 +99,27 @@ def test_server_eval_grad_equals_plain(bx):
     s.close()
 
 
+def test_server_multivariate_in_a_mixed_batch(bx):
+    # multivariate fits (radial and pulse-shape terms) batched together with
+    # single-histogram fits of the same kind and precision: every result
+    # equals the plain path's
+    cases = [("c3a", F64), ("c1", F64), ("c3b", F32), ("c2", F32)]
+    models, pts, ref = [], [], []
+    for name, prec in cases:
+        d, x = synth.load(name)
+        m = bx.Model(d, x, precision=prec)
+        th = d.theta_true * (1 + 0.01 * np.random.default_rng(7).standard_normal(d.P))
+        models.append(m)
+        pts.append(th)
+        ref.append(m.nll_grad(th))
+    s = bx.Server()
+    tickets = [s.submit(m, th, kind=bx.BX_EVAL_GRAD) for m, th in zip(models, pts)]
+    res = [s.wait(tk) for tk in tickets]
+    s.close()
+    for (name, _), (v, g), r in zip(cases, ref, res):
+        assert r.nll == v and np.array_equal(r.grad, g), name
+
+
 def test_batched_fits_equal_plain_and_isolated(bx):
     toys = _toys(6)
     models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
