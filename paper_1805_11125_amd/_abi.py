@@ -9,6 +9,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbx.so")
+# tile table measured on MI355X by paper_1805_11125_amd.tune (read by the
+# library at model build and server admission unless BX_TUNE_CACHE is set)
+TILE_TABLE = os.path.join(HERE, "tiles_mi355x.txt")
 
 BX_OK, BX_PENDING = 0, 1
 BX_E_INVAL, BX_E_NOMEM, BX_E_DEVICE, BX_E_DOMAIN, BX_E_BUSY, BX_E_NOTFOUND = -1, -2, -3, -4, -5, -6
@@ -91,6 +94,8 @@ def load():
             torch.cuda.is_available()
         except Exception:
             pass
+        if "BX_TUNE_CACHE" not in os.environ and os.path.exists(TILE_TABLE):
+            os.environ["BX_TUNE_CACHE"] = TILE_TABLE
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

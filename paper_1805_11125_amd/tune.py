@@ -1,0 +1,86 @@
+"""Tile autotuner for the cell sweeps.
+
+For each shape class it builds a representative model, times every candidate
+number of true tiles per forward wave (CG) on the device, once for a fit
+evaluated alone (whole-evaluation time of the back-to-back stage launches,
+`bx_model_stage_times`) and once for a batch of resident fits
+(`bx_model_batch_times`, time per fit), and writes the table the library
+reads at model build and at admission to the fit server (BX_TUNE_CACHE):
+
+    kind prec Tmin Tmax Nmin Nmax batched CG RG
+
+CG changes no result bit (the forward partials are summed in a fixed tree),
+so the two modes may differ; RG (reco tiles per backward wave) groups the
+backward partials, so it is kept at 1 in both modes and a fit gives the same
+bits alone and in the server.
+
+    python -m paper_1805_11125_amd.tune --out paper_1805_11125_amd/tiles_mi355x.txt
+"""
+import argparse
+import os
+import sys
+
+import numpy as np
+
+CANDIDATES = (1, 2, 4, 8)
+
+
+def _time(bx, desc, data, prec, theta, cg, copies):
+    os.environ["BX_TILES"] = f"{cg},1"
+    try:
+        m = bx.Model(desc, data, precision=prec)
+        single = m.stage_times(theta, reps=100)["total"]
+        batched = m.batch_times(theta, copies, reps=5)["total"] / copies
+        m.close()
+    finally:
+        del os.environ["BX_TILES"]
+    return single, batched
+
+
+def tune(classes, copies=128, log=print):
+    """classes: list of (kind, prec, Tmin, Tmax, Nmin, Nmax, desc, data, theta).
+    Returns the table lines."""
+    import paper_1805_11125_amd as bx
+    lines = []
+    for kind, prec, tmin, tmax, nmin, nmax, desc, data, theta in classes:
+        res = {cg: _time(bx, desc, data, prec, theta, cg, copies) for cg in CANDIDATES}
+        for batched in (0, 1):
+            best = min(CANDIDATES, key=lambda cg: res[cg][batched])
+            lines.append(f"{kind} {prec} {tmin} {tmax} {nmin} {nmax} {batched} {best} 1")
+            log(f"class kind={kind} prec={prec} T=[{tmin},{tmax}] N=[{nmin},{nmax}] "
+                f"{'batched' if batched else 'single'}: " +
+                " ".join(f"CG{cg}={res[cg][batched] * 1e3:.2f}us" for cg in CANDIDATES) + f" -> CG {best}")
+    return lines
+
+
+def standard_classes():
+    """Shape classes of the synthetic workloads (generator in synth/)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import synth
+    out = []
+    d1, x1 = synth.load("c1")
+    out.append((0, 1, 1, 2000, 1, 2000, d1, x1, d1.theta_true))
+    d2, x2 = synth.load("c2")
+    th2 = d2.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d2.P))
+    base, per_species, theta = synth.catalogue()
+    t = synth.toy(9, per_species, theta)   # a short reco window (303 bins)
+    out.append((1, 0, 1, 100000, 1, 600, synth.toy_desc(base, t), synth.Data(energy=t.counts), t.theta0))
+    out.append((1, 0, 1, 100000, 601, 100000, d2, x2, th2))
+    out.append((1, 1, 1, 100000, 1, 100000, d2, x2, th2))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--copies", type=int, default=128)
+    a = ap.parse_args()
+    lines = tune(standard_classes(), copies=a.copies, log=lambda s: print(s, flush=True))
+    with open(a.out, "w") as f:
+        f.write("# kind prec Tmin Tmax Nmin Nmax batched CG RG  (written by paper_1805_11125_amd.tune)\n")
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()
