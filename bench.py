@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--plain-toys", type=int, default=64, help="toys fitted on the plain path")
     ap.add_argument("--qps", type=str, default="30,300", help="serving arrival rates ('' = skip)")
     ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (reference for HBM byte counters)")
@@ -270,6 +272,21 @@ def main():
                      "valu_issue_frac": valu,
                      "kernel_ms": kms},
     }
+    if a.batch > 0:
+        # one launch per stage over `batch` resident copies (HIP events on the
+        # model's stream): throughput of the batched form of the same evaluation
+        bt = m.batch_times(th, a.batch, reps=10)
+        bk = "cells_bwd" if bt["cells_bwd"] >= bt["cells_fwd"] else "cells_fwd"
+        bflop = FLOP_BWD_EDGE if bk == "cells_bwd" else FLOP_FWD_EDGE + 2 * d.S
+        bach = a.batch * edges * bflop / (bt[bk] * 1e-3)
+        res["batched_eval"] = {
+            "copies": a.batch, "evals_per_s": a.batch / (bt["total"] * 1e-3),
+            "us_per_eval": bt["total"] * 1e3 / a.batch,
+            "stage_us_per_eval": {k: round(v * 1e3 / a.batch, 4) for k, v in bt.items()},
+            "roofline": {"bound": "alu", "kernel": "k_" + bk, "achieved": bach / 1e12,
+                         "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": bach / PEAK_FP32,
+                         "edges_per_launch": a.batch * edges, "kernel_ms": bt[bk]}}
+        print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()
     if a.toys > 0:
         res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)

@@ -702,8 +702,11 @@ bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies,
       return BX_E_DOMAIN;
     }
   // `copies` independent fits of this model, placed as the server places
-  // them, evaluated together by one launch per stage (blockIdx.y = fit)
-  const size_t stride = (device_fit_bytes(m->h) + 255) & ~(size_t)255;
+  // them (with the batched tile widths), evaluated together by one launch per
+  // stage (blockIdx.y = fit)
+  HostModel hb = m->h;
+  hb.tiles = choose_tiles(hb.T, hb.N, hb.kind, hb.prec, 1);
+  const size_t stride = (device_fit_bytes(hb) + 255) & ~(size_t)255;
   char* base = nullptr;
   FitDev* d_fd = nullptr;
   if (hipMalloc((void**)&base, stride * copies) != hipSuccess) {
@@ -720,7 +723,7 @@ bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies,
   hipError_t e = hipSuccess;
   for (int c = 0; c < copies && s == BX_OK; ++c) {
     DeviceFit df;
-    s = place_fit(m->h, base + stride * c, &df, m->stream);
+    s = place_fit(hb, base + stride * c, &df, m->stream);
     if (s == BX_OK) e = hipMemcpyAsync(df.d_theta, theta, P * sizeof(double), hipMemcpyHostToDevice, m->stream);
     if (e != hipSuccess) s = hip_fail(e, "theta upload");
     fd[c] = df.dev;
