@@ -76,6 +76,9 @@ struct FitDev {
   ColPar* cp;           // [T]
   int2* tb;             // [n_ct] support of each column tile (cells)
   void* Mpart;          // [n_cg][N][16] R: one partial per chunk of 16 listed true tiles
+  void* Dcell;          // [n_ct][n_rt][4][64] pairs of R: per active tile, each cell's
+                        // differences of dF/dc1, dF/dc2 across it, in the sweeps' lane
+                        // order (written by the forward sweep when the gradient is wanted)
   double* M;            // [N][16] sum of the partials (FP64)
   double* Mp;           // [N][16] after pile-up
   double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part

@@ -346,6 +346,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->cp = c.take<ColPar>(h.T);
   f->tb = c.take<int2>(f->n_ct);
   f->Mpart = (void*)c.take<char>((size_t)f->n_cg * h.N * kSP * rsz);
+  f->Dcell = (void*)c.take<char>((size_t)f->n_ct * f->n_rt * 4 * 64 * 2 * rsz);
   f->M = c.take<double>((size_t)h.N * kSP);
   f->Mp = c.take<double>((size_t)h.N * kSP);
   f->H = c.take<double>((size_t)h.N * kSP);

@@ -2,12 +2,14 @@
 //
 //   k_colparams   per true bin: response column parameters, support, chain
 //                 factors to the response parameters (Eq. 1's R_x(N_x, E; p)).
-//   k_cells_fwd   per (reco tile, 4 true tiles): each wave evaluates the CDF
-//                 at 16 shared reco edges x 16 true bins, forms the cells by
-//                 differencing neighbour lanes and feeds them straight into
+//   k_cells_fwd   per (reco tile, listed true tiles): each wave evaluates the
+//                 CDF at 16 shared reco edges x 16 true bins, forms the cells
+//                 by differencing neighbour lanes and feeds them straight into
 //                 MFMA 16x16x4 as A with the species spectra as B:
-//                 M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).  The 4 waves'
-//                 tiles are added in LDS; cells never touch HBM.
+//                 M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).  Tiles are added
+//                 in a fixed tree; cells never touch HBM.  When the gradient
+//                 is wanted it also evaluates dF/dc1, dF/dc2 at the edges and
+//                 stores each cell's differences (Dcell).
 //   k_reduce_M    FP64 sum of the forward partials (fixed order).
 //   k_rowterms    pile-up
 //                 M' = (1-p) M + p g^*M (Eq. 2) from LDS, expected counts of
@@ -15,8 +17,8 @@
 //                 terms, the adjoint weights H and per-block partials.
 //   k_radial      radial term (Eq. 4) -- one block per fit.
 //   k_adjoint     H~ = P^T H (the pile-up adjoint), from LDS.
-//   k_cells_bwd   per (true tile, 4 reco tiles): the same CDF sweep with the
-//                 derivatives in the two column parameters; accumulates
+//   k_cells_bwd   per (true tile, 4 reco tiles): reads the cells' derivatives
+//                 in the two column parameters from Dcell; accumulates
 //                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
 //                 W_ji = sum_s H~_js r_s F^_si, and contracts them with the
 //                 column chain factors into a per-block gradient partial.
@@ -58,6 +60,9 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 template <class R> struct Acc4;
 template <> struct Acc4<float> { typedef v4f T; };
 template <> struct Acc4<double> { typedef v4d T; };
+template <class R> struct Pair;
+template <> struct Pair<float> { typedef float2 T; };
+template <> struct Pair<double> { typedef double2 T; };
 
 // Workgroups go to the 8 XCDs round-robin (block b to XCD b % 8), each with
 // its own L2.  The backward sweep gives true tile ct to XCD ct % 8 with all
@@ -271,8 +276,11 @@ __device__ __forceinline__ V tree_sum(const F& item) {
 // CG chunks: wave w holds entries [w CG, w CG + CG) of its window (a subtree),
 // so the partials do not depend on CG, which sets only how many tiles a wave
 // evaluates in a row.  The working waves fill the first blocks of each reco
-// tile; the rest find their window empty and write zero partials.
-template <class R, int KIND, int CG>
+// tile; the rest find their window empty and write zero partials.  With D
+// (the gradient is wanted) the sweep also evaluates dF/dc1, dF/dc2 at the
+// edges and stores each cell's differences for the backward sweep, which
+// then needs no second evaluation of the edges.
+template <class R, int KIND, int CG, bool D>
 __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
   typedef typename Acc4<R>::T V;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
@@ -312,22 +320,32 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
   const int n_here = n_act - lo;  // entries of this window in the list
+  typedef typename Pair<R>::T R2;
   // one tile's 16 x 16 contribution (zero past the end of the list)
   auto tile = [&](int c) -> V {
     V acc = {0, 0, 0, 0};
     const int e = wv * CG + c;
     if (e >= n_here) return acc;  // wave-uniform
     const int ct = mylist[e];
+    R2* dst = D ? (R2*)f.Dcell + ((size_t)ct * f.n_rt + rt) * 4 * 64 : nullptr;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < f.T;
       const ColPar& cpi = f.cp[iok ? i : f.T - 1];
       const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
-      const EdgeVal<R> ev = edge_at<R, KIND, false>(cpi, xe);
+      const EdgeVal<R> ev = edge_at<R, KIND, D>(cpi, xe);
       const R hi = dpp_from_next(ev.v);
-      const R a = (row_ok && iok) ? cell_from(ev.v, hi) : (R)0;
+      const bool ok = row_ok && iok;
+      const R a = ok ? cell_from(ev.v, hi) : (R)0;
       acc = mfma16(a, bb, acc);
+      if (D) {
+        const R d1h = dpp_from_next(ev.d1), d2h = dpp_from_next(ev.d2);
+        R2 dv;
+        dv.x = ok ? d1h - ev.d1 : (R)0;
+        dv.y = ok ? d2h - ev.d2 : (R)0;
+        dst[q * 64 + lane] = dv;
+      }
     }
     return acc;
   };
@@ -580,8 +598,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 // Logical block (ct, rg): true tile ct; its support covers the contiguous reco tiles
 // [rt_a, rt_b], and wave w takes rt = rt_a + (4 rg + w) RG + c, c < RG.  The
 // working blocks of a true tile are thus its first ones; the others write a
-// zero partial and leave.
-template <class R, int KIND>
+// zero partial and leave.  The cells' derivative differences come from the
+// forward sweep of the same evaluation (Dcell).
+template <class R>
 __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int2 cr = bwd_block(f.n_rg);
@@ -628,35 +647,32 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
     }
     __syncthreads();
   }
+  typedef typename Pair<R>::T R2;
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
   const int rt0 = rt_blk + wv * f.RG;
   const int rt_end = min(rt0 + f.RG, rt_b + 1);
   for (int rt = rt0; rt < rt_end; ++rt) {
     const int j0 = rt * kRowStep;
     if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
-    const int je = min(j0 + jr, f.N);
-    const double xe = f.xe[je];
     const int j = j0 + jr;
     const bool row_ok = (jr < kRowStep) && (j < f.N);
     const double w1 = (row_ok && !f.mv) ? htl[j - r0] : 0.0;
+    const R2* src = (const R2*)f.Dcell + ((size_t)ct * f.n_rt + rt) * 4 * 64;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < f.T;
-      const ColPar& c = f.cp[iok ? i : f.T - 1];
-      const EdgeVal<R> ev = edge_at<R, KIND, true>(c, xe);
-      const R d1h = dpp_from_next(ev.d1);
-      const R d2h = dpp_from_next(ev.d2);
       if (row_ok && iok) {
+        const R2 dv = src[q * 64 + lane];
         double W;
         if (!f.mv) {
-          W = w1 * c.v;
+          W = w1 * f.cp[i].v;
         } else {
           W = 0.0;
           for (int s = 0; s < f.S; ++s) W += f.Ht[j * kSP + s] * f.theta[s] * f.F64[i * kSP + s];
         }
-        aA[q] += W * (double)(d1h - ev.d1);
-        aB[q] += W * (double)(d2h - ev.d2);
+        aA[q] += W * (double)dv.x;
+        aB[q] += W * (double)dv.y;
       }
     }
   }
@@ -776,14 +792,20 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 }
 
 // ---------------------------------------------------------------------------
-template <class R, int KIND>
-static void launch_fwd(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {
+template <class R, int KIND, bool D>
+static void launch_fwd_d(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {
   switch (cg) {
-    case 1: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 1>), grid, blk, 0, st, d_fits, d_active); break;
-    case 2: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 2>), grid, blk, 0, st, d_fits, d_active); break;
-    case 4: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 4>), grid, blk, 0, st, d_fits, d_active); break;
-    default: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 8>), grid, blk, 0, st, d_fits, d_active); break;
+    case 1: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 1, D>), grid, blk, 0, st, d_fits, d_active); break;
+    case 2: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 2, D>), grid, blk, 0, st, d_fits, d_active); break;
+    case 4: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 4, D>), grid, blk, 0, st, d_fits, d_active); break;
+    default: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 8, D>), grid, blk, 0, st, d_fits, d_active); break;
   }
+}
+template <class R, int KIND>
+static void launch_fwd(int cg, bool d, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits,
+                       const int* d_active) {
+  if (d) launch_fwd_d<R, KIND, true>(cg, grid, blk, st, d_fits, d_active);
+  else launch_fwd_d<R, KIND, false>(cg, grid, blk, st, d_fits, d_active);
 }
 
 // One stage of an evaluation: 0 colparams, 1 cells_fwd, 2 reduce_M,
@@ -802,10 +824,10 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
                          d_fits, d_active);
       break;
     case 1:
-      if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, gf, bf, st, d_fits, d_active);
-      if (f32 && !gauss) launch_fwd<float, kGG>(L.CG, gf, bf, st, d_fits, d_active);
-      if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, gf, bf, st, d_fits, d_active);
-      if (!f32 && !gauss) launch_fwd<double, kGG>(L.CG, gf, bf, st, d_fits, d_active);
+      if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (f32 && !gauss) launch_fwd<float, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (!f32 && !gauss) launch_fwd<double, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
       break;
     case 2:
       if (f32) hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);
@@ -822,10 +844,8 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 6:
       if (!with_grad) break;
-      if (f32 && gauss) hipLaunchKernelGGL((k_cells_bwd<float, kGauss>), gb, blk, 0, st, d_fits, d_active);
-      if (f32 && !gauss) hipLaunchKernelGGL((k_cells_bwd<float, kGG>), gb, blk, 0, st, d_fits, d_active);
-      if (!f32 && gauss) hipLaunchKernelGGL((k_cells_bwd<double, kGauss>), gb, blk, 0, st, d_fits, d_active);
-      if (!f32 && !gauss) hipLaunchKernelGGL((k_cells_bwd<double, kGG>), gb, blk, 0, st, d_fits, d_active);
+      if (f32) hipLaunchKernelGGL((k_cells_bwd<float>), gb, blk, 0, st, d_fits, d_active);
+      else hipLaunchKernelGGL((k_cells_bwd<double>), gb, blk, 0, st, d_fits, d_active);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);

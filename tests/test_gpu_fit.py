@@ -149,10 +149,11 @@ def test_admission_under_small_budget(bx):
     models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
     ref = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=200)
            for m, (d, x, t) in zip(models, toys)]
-    # room for about one fit at a time: requests queue and are admitted as fits leave
+    # room for one or two of these fits (10-26 MB each) and two slots: requests
+    # queue and are admitted as fits leave
     from paper_1805_11125_amd import _abi
     import ctypes as C
-    s = bx.Server(hbm_budget_bytes=4 << 20, max_slots=2)
+    s = bx.Server(hbm_budget_bytes=40 << 20, max_slots=2)
     tickets = [s.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-9, max_iter=200)
                for m, (d, x, t) in zip(models, toys)]
     res = [s.wait(tk) for tk in tickets]
