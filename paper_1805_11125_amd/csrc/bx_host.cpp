@@ -323,24 +323,35 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->n_rad = h.n_rad;
 }
 
-static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, double** out) {
+// Sub-buffers of one fit in `base`.  With `shared`, the read-only inputs
+// (grids, spectra, templates, histograms) are those of an existing placement
+// of the same model and only the per-evaluation workspace is carved.
+static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, double** out,
+                    const FitDev* shared = nullptr) {
   Carver c{base};
   derive_tiles(h, f);
   const size_t rsz = h.prec == kF32 ? 4 : 8;
-  f->xraw = c.take<double>(h.N + 1);
-  f->xe = c.take<double>(h.N + 1);
-  f->Ec = c.take<double>(h.T);
-  f->Qt = c.take<double>(h.T);
-  f->F32 = c.take<float>((size_t)h.T * kSP);
-  f->F64 = c.take<double>((size_t)h.T * kSP);
-  f->ghat = c.take<double>(h.K);
-  f->tag = c.take<double>(kSP);
-  f->rad = c.take<double>((size_t)kSP * h.n_rad);
-  f->pst = c.take<double>((size_t)kSP * h.n_ps);
-  f->n_e = c.take<double>(h.N);
-  f->n_t = c.take<double>(h.N);
-  f->n_r = c.take<double>(h.n_rad);
-  f->n_p = c.take<double>((size_t)h.N * h.n_ps);
+  if (shared) {
+    f->xraw = shared->xraw; f->xe = shared->xe; f->Ec = shared->Ec; f->Qt = shared->Qt;
+    f->F32 = shared->F32; f->F64 = shared->F64; f->ghat = shared->ghat; f->tag = shared->tag;
+    f->rad = shared->rad; f->pst = shared->pst;
+    f->n_e = shared->n_e; f->n_t = shared->n_t; f->n_r = shared->n_r; f->n_p = shared->n_p;
+  } else {
+    f->xraw = c.take<double>(h.N + 1);
+    f->xe = c.take<double>(h.N + 1);
+    f->Ec = c.take<double>(h.T);
+    f->Qt = c.take<double>(h.T);
+    f->F32 = c.take<float>((size_t)h.T * kSP);
+    f->F64 = c.take<double>((size_t)h.T * kSP);
+    f->ghat = c.take<double>(h.K);
+    f->tag = c.take<double>(kSP);
+    f->rad = c.take<double>((size_t)kSP * h.n_rad);
+    f->pst = c.take<double>((size_t)kSP * h.n_ps);
+    f->n_e = c.take<double>(h.N);
+    f->n_t = c.take<double>(h.N);
+    f->n_r = c.take<double>(h.n_rad);
+    f->n_p = c.take<double>((size_t)h.N * h.n_ps);
+  }
   *theta = c.take<double>(h.P + 1);  // + the caller's sequence number (host path)
   f->theta = *theta;
   f->cp = c.take<ColPar>(h.T);
@@ -364,10 +375,21 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   return (c.off + 255) & ~(size_t)255;
 }
 
-size_t device_fit_bytes(const HostModel& h) {
-  FitDev f{};
+HostModel shape_only(const HostModel& h) {
+  HostModel s;
+  s.T = h.T; s.N = h.N; s.S = h.S; s.P = h.P; s.nresp = h.nresp; s.kind = h.kind; s.prec = h.prec; s.mv = h.mv;
+  s.win_lo = h.win_lo; s.win_hi = h.win_hi; s.K = h.K; s.n_rad = h.n_rad; s.rad_lo = h.rad_lo;
+  s.rad_hi = h.rad_hi; s.n_ps = h.n_ps;
+  s.p = h.p; s.pu_frac = h.pu_frac; s.exposure = h.exposure;
+  s.gg = h.gg;
+  s.tiles = h.tiles;
+  return s;
+}
+
+size_t device_fit_bytes(const HostModel& h, bool shared_inputs) {
+  FitDev f{}, sh{};
   double *t, *o;
-  return carve(h, nullptr, &f, &t, &o);
+  return carve(h, nullptr, &f, &t, &o, shared_inputs ? &sh : nullptr);
 }
 
 LaunchShape shape_of(const FitDev& f) {
@@ -399,16 +421,22 @@ bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st) {
   return BX_OK;
 }
 
-bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st) {
+bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st, const FitDev* shared) {
   FitDev& f = df->dev;
   memset(&f, 0, sizeof f);
   df->base = base;
-  df->bytes = carve(h, (char*)base, &f, &df->d_theta, &df->d_out);
+  df->bytes = carve(h, (char*)base, &f, &df->d_theta, &df->d_out, shared);
   f.T = h.T; f.N = h.N; f.S = h.S; f.P = h.P; f.nresp = h.nresp; f.kind = h.kind; f.prec = h.prec; f.mv = h.mv;
   f.win_lo = h.win_lo; f.win_hi = h.win_hi; f.K = h.K; f.n_rad = h.n_rad; f.rad_lo = h.rad_lo;
   f.rad_hi = h.rad_hi; f.n_ps = h.n_ps;
   f.pu_frac = h.pu_frac;
   f.gg = h.gg;
+  if (shared) {  // inputs (and what is derived from them) already in place
+    f.uniform = shared->uniform;
+    f.x0 = shared->x0;
+    f.inv_w = shared->inv_w;
+    return BX_OK;
+  }
   // equal reco bins allow a direct edge index in the support search
   const double w0 = h.xraw[1] - h.xraw[0];
   bool uni = true;
@@ -705,9 +733,9 @@ bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies,
   // `copies` independent fits of this model, placed as the server places
   // them (with the batched tile widths), evaluated together by one launch per
   // stage (blockIdx.y = fit)
-  HostModel hb = m->h;
+  HostModel hb = shape_only(m->h);  // inputs: the model's own placement
   hb.tiles = choose_tiles(hb.T, hb.N, hb.kind, hb.prec, 1);
-  const size_t stride = (device_fit_bytes(hb) + 255) & ~(size_t)255;
+  const size_t stride = (device_fit_bytes(hb, true) + 255) & ~(size_t)255;
   char* base = nullptr;
   FitDev* d_fd = nullptr;
   if (hipMalloc((void**)&base, stride * copies) != hipSuccess) {
@@ -724,7 +752,7 @@ bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies,
   hipError_t e = hipSuccess;
   for (int c = 0; c < copies && s == BX_OK; ++c) {
     DeviceFit df;
-    s = place_fit(hb, base + stride * c, &df, m->stream);
+    s = place_fit(hb, base + stride * c, &df, m->stream, &m->df.dev);
     if (s == BX_OK) e = hipMemcpyAsync(df.d_theta, theta, P * sizeof(double), hipMemcpyHostToDevice, m->stream);
     if (e != hipSuccess) s = hip_fail(e, "theta upload");
     fd[c] = df.dev;

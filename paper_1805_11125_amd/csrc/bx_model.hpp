@@ -41,6 +41,8 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
 // gradient shows progress).
 inline double nll_noise(const HostModel& h) { return h.prec == kF32 ? 1e-9 : 1e-13; }
 bx_status set_host_data(HostModel* h, const bx_data* x);
+// The scalars, per-model constants and tiles of h, without its arrays.
+HostModel shape_only(const HostModel& h);
 double host_lnfact(const HostModel& h);
 
 // Device placement of one fit: one allocation holding inputs and workspace.
@@ -51,10 +53,14 @@ struct DeviceFit {
   double* d_theta = nullptr;
   double* d_out = nullptr;
 };
-size_t device_fit_bytes(const HostModel& h);
+// shared_inputs: the read-only inputs live in another placement (see place_fit)
+size_t device_fit_bytes(const HostModel& h, bool shared_inputs = false);
 void derive_tiles(const HostModel& h, FitDev* f);
-// Carve `base` (device memory of device_fit_bytes(h)) and upload h; stream-ordered.
-bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st);
+// Carve `base` (device memory of device_fit_bytes(h, shared != null)) and
+// upload h; stream-ordered.  With `shared` (a placed fit of the same model
+// and data), the read-only inputs are that fit's and only the workspace is
+// carved here.
+bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st, const FitDev* shared = nullptr);
 bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st);
 LaunchShape shape_of(const FitDev& f);
 

@@ -7,8 +7,10 @@
 // reduction orders), so its result does not depend on the rest of the batch.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <functional>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -21,6 +23,70 @@
 #include "bx_model.hpp"
 
 namespace bx {
+
+// Parallel for over the fits of a step: the scheduler thread and a few
+// helpers take indices from a shared counter.  Each fit's minimiser state is
+// touched by one thread only, so results do not depend on the pool.
+class StepPool {
+ public:
+  explicit StepPool(int helpers) {
+    for (int k = 0; k < helpers; ++k) th_.emplace_back([this] { loop(); });
+  }
+  ~StepPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    if (th_.empty() || n < 64) {  // small steps: not worth the hand-off
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &f;
+      n_ = n;
+      next_.store(0);
+      busy_ = (int)th_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [this] { return busy_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void work() {
+    for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*job_)(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--busy_ == 0) done_.notify_one();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* job_ = nullptr;
+  int n_ = 0, busy_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
 
 static int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -35,7 +101,7 @@ constexpr int kOutStride = 34;
 struct Req {
   uint64_t ticket = 0;
   bx_model* model = nullptr;
-  HostModel h;             // model arrays with this request's data
+  HostModel h;             // shape and constants of the model (its arrays stay in the model)
   FitProblem pb;
   std::unique_ptr<Bfgs> opt;
   size_t bytes = 0;
@@ -72,6 +138,7 @@ struct bx_server {
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::thread worker;
+  std::unique_ptr<StepPool> pool;  // helpers for the per-fit minimiser updates
   bool stop = false;
   int pending = 0;
   int device = 0;
@@ -93,7 +160,7 @@ static void admit(bx_server* s) {
     s->free_slots.pop_back();
     s->used += r->bytes;
     DeviceFit& df = r->df;
-    if (!got || place_fit(r->h, mem, &df, s->stream) != BX_OK) {
+    if (!got || place_fit(r->h, mem, &df, s->stream, &r->model->df.dev) != BX_OK) {
       r->res.status = BX_FAILED;
       retire(s, r);
       continue;
@@ -123,11 +190,12 @@ static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
 
 static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
   // stage every active fit's next point
-  for (auto& r : act) {
+  s->pool->run((int)act.size(), [&](int k) {
+    auto& r = act[k];
     double x[32];
     r->opt->next(x);
     memcpy(s->h_theta + (size_t)r->slot * kThetaStride, x, sizeof(double) * r->h.P);
-  }
+  });
   // contiguous ranges are small; copy the whole staged array once
   int max_slot = 0;
   for (auto& r : act) max_slot = std::max(max_slot, r->slot + 1);
@@ -160,13 +228,14 @@ static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
   }
   (void)hipMemcpyAsync(s->h_out, s->d_out, sizeof(double) * kOutStride * max_slot, hipMemcpyDeviceToHost, s->stream);
   (void)hipStreamSynchronize(s->stream);
-  for (auto& r : act) {
+  s->pool->run((int)act.size(), [&](int k) {
+    auto& r = act[k];
     const double* o = s->h_out + (size_t)r->slot * kOutStride;
     const int P = r->h.P;
     const int fl = (int)o[1 + P];
     const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
     r->opt->feed(bad ? INFINITY : o[0], o + 1);
-  }
+  });
 }
 
 static void worker_loop(bx_server* s) {
@@ -242,6 +311,8 @@ bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip
   }
   memset(s->h_theta, 0, sizeof(double) * kThetaStride * M);
   for (int i = (int)M - 1; i >= 0; --i) s->free_slots.push_back(i);
+  const unsigned hc = std::thread::hardware_concurrency();
+  s->pool.reset(new StepPool((int)std::min(7u, hc > 1 ? hc - 1 : 0u)));
   s->worker = std::thread(worker_loop, s);
   *out = s;
   return BX_OK;
@@ -281,9 +352,11 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb);
   if (st != BX_OK) return st;
   r->pb.f_noise = nll_noise(m->h);
-  r->h = m->h;
-  r->h.tiles = choose_tiles(r->h.T, r->h.N, r->h.kind, r->h.prec, 1);  // batched tile widths
-  r->bytes = (device_fit_bytes(r->h) + 4095) & ~(size_t)4095;
+  // the fit reads the model's inputs in place (the model stays busy while it
+  // is pending) and gets its own workspace, with the batched tile widths
+  r->h = shape_only(m->h);
+  r->h.tiles = choose_tiles(r->h.T, r->h.N, r->h.kind, r->h.prec, 1);
+  r->bytes = (device_fit_bytes(r->h, true) + 4095) & ~(size_t)4095;
   if (r->bytes > s->budget) {
     set_error("request larger than the server's memory budget");
     return BX_E_BUSY;
