@@ -56,7 +56,8 @@ def fit(desc, data, theta0, float_mask=None, edm_tol=1e-14, max_polish=20, lbfgs
     # rates are bounded at zero; response parameters are free, their domain
     # (sigma^2 >= 0, GG mean and variance > 0) is enforced by the NLL being
     # +inf outside it
-    bounds = [(0.0, None) if q < desc.S else (None, None) for q in idx]
+    pu_q = desc.P - 1 if getattr(desc, "pu_float", False) else -1  # pile-up fraction in [0, 1]
+    bounds = [(0.0, None) if q < desc.S else (0.0, 1.0) if q == pu_q else (None, None) for q in idx]
     res = optimize.minimize(fun, np.ones(len(idx)), jac=True, method="L-BFGS-B",
                             bounds=bounds,
                             options=dict(ftol=0.0, gtol=1e-12, maxiter=lbfgs_maxiter,

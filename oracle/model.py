@@ -218,17 +218,30 @@ def contraction(desc, R):
     return float(desc.exposure) * (R @ normalised_spectra(desc).T)
 
 
-def pileup(desc, M):
-    """M'[:, s] = (1 - p) M[:, s] + p (g_hat * M[:, s]), g_hat = g / sum g,
-    a causal convolution truncated at the top of the reco range."""
-    p = float(desc.pu_frac)
-    if p == 0.0 or desc.pu_g is None:
-        return M.copy()
+def _pileup_conv(desc, M):
+    """g_hat * M[:, s] per column, g_hat = g / sum g, a causal convolution
+    truncated at the top of the reco range."""
     g = np.asarray(desc.pu_g, np.float64)
     ghat = g / math.fsum(g)
     N = M.shape[0]
-    conv = np.stack([np.convolve(M[:, s], ghat)[:N] for s in range(M.shape[1])], axis=1)
-    return (1.0 - p) * M + p * conv
+    return np.stack([np.convolve(M[:, s], ghat)[:N] for s in range(M.shape[1])], axis=1)
+
+
+def pileup(desc, M, p=None):
+    """M'[:, s] = (1 - p) M[:, s] + p (g_hat * M[:, s]) (Eq. 2 as a mixture
+    with the random-trigger spectrum); p defaults to the model's fixed
+    fraction."""
+    p = float(desc.pu_frac) if p is None else float(p)
+    if p == 0.0 or desc.pu_g is None:
+        return M.copy()
+    return (1.0 - p) * M + p * _pileup_conv(desc, M)
+
+
+def pileup_dp(desc, M):
+    """dM'/dp = g_hat * M - M: M' is affine in the pile-up fraction."""
+    if desc.pu_g is None:
+        return np.zeros_like(M)
+    return _pileup_conv(desc, M) - M
 
 
 def expected(desc, Mp, r):
@@ -287,15 +300,28 @@ def split_theta(desc, theta):
         raise ValueError(f"theta must have {desc.P} entries")
     if not np.all(np.isfinite(theta)):
         raise DomainError("non-finite theta")
-    return theta[: desc.S], theta[desc.S:]
+    return theta[: desc.S], theta[desc.S: desc.S + desc.n_resp]
+
+
+def pu_fraction(desc, theta):
+    """The pile-up fraction: the last parameter when it is floated (it must
+    lie in [0, 1]), else the model's fixed value."""
+    if not getattr(desc, "pu_float", False):
+        return float(desc.pu_frac)
+    p = float(np.asarray(theta, np.float64)[-1])
+    if not (0.0 <= p <= 1.0):
+        raise DomainError("pile-up fraction outside [0, 1]")
+    return p
 
 
 def forward(desc, theta):
     r, resp = split_theta(desc, theta)
+    p = pu_fraction(desc, theta)
     cp = column_params(desc, resp)
     R = response_matrix(desc, cp)
-    Mp = pileup(desc, contraction(desc, R))
-    return SimpleNamespace(cp=cp, R=R, Mp=Mp, r=r, resp=resp, mu=expected(desc, Mp, r))
+    M = contraction(desc, R)
+    Mp = pileup(desc, M, p)
+    return SimpleNamespace(cp=cp, R=R, M=M, Mp=Mp, r=r, resp=resp, p=p, mu=expected(desc, Mp, r))
 
 
 def nll(desc, data, theta):
@@ -338,8 +364,10 @@ def nll_grad(desc, data, theta):
         e[s] = 1.0
         g[s] = contract(expected(desc, f.Mp, e))
     for q, dR in enumerate(response_param_derivs(desc, f.cp, f.resp)):
-        dMp = pileup(desc, contraction(desc, dR))
+        dMp = pileup(desc, contraction(desc, dR), f.p)
         g[desc.S + q] = contract(expected(desc, dMp, f.r))
+    if getattr(desc, "pu_float", False):
+        g[desc.P - 1] = contract(expected(desc, pileup_dp(desc, f.M), f.r))
     return val, g
 
 
@@ -392,6 +420,8 @@ def grad_scale(desc, data, theta):
         e[s] = 1.0
         sc[s] = contract(expected(desc, f.Mp, e))
     for q, dR in enumerate(response_param_derivs(desc, f.cp, f.resp)):
-        dMp = pileup(desc, contraction(desc, dR))
+        dMp = pileup(desc, contraction(desc, dR), f.p)
         sc[desc.S + q] = contract(expected(desc, dMp, f.r))
+    if getattr(desc, "pu_float", False):
+        sc[desc.P - 1] = contract(expected(desc, pileup_dp(desc, f.M), f.r))
     return sc

@@ -46,6 +46,7 @@ class ModelDesc:
     quench: Optional[np.ndarray] = None   # [T] quenching factor (GG only)
     pu_frac: float = 0.0            # pile-up fraction p
     pu_g: Optional[np.ndarray] = None     # [K] random-trigger spectrum
+    pu_float: bool = False          # p is a fit parameter (the last entry of theta)
     win: tuple = (0, 0)             # fit window [j_lo, j_hi) over reco bins
     # multivariate fields (None = single energy histogram)
     tag_frac: Optional[np.ndarray] = None  # [S]
@@ -75,7 +76,7 @@ class ModelDesc:
 
     @property
     def P(self):
-        return self.S + self.n_resp
+        return self.S + self.n_resp + (1 if self.pu_float else 0)
 
     @property
     def multivariate(self):

@@ -489,3 +489,76 @@ def test_support_edges_gauss_quantiles():
         if idx.size:
             expect += min(idx[-1] + 1, len(x) - 1) - max(idx[0] - 1, 0) + 1
     assert oracle.support_edges(d, d.theta_true, q=q) == expect
+
+
+# ---------------------------------------------------------------------------
+# Pile-up fraction as a fit parameter (the last entry of theta)
+# ---------------------------------------------------------------------------
+def _pu_float_model():
+    d = tiny_gg(T=60, N=45)
+    d.pu_g, d.pu_frac = np.exp(-np.arange(6) / 2.0), 0.0
+    d.pu_float = True
+    d.theta_true = np.concatenate([d.theta_true, [0.05]])
+    return d
+
+
+def test_pu_float_mu_is_affine_in_p():
+    d = _pu_float_model()
+    th = d.theta_true.copy()
+    mu = {}
+    for p in (0.0, 0.3, 0.7, 1.0):
+        th[-1] = p
+        mu[p] = om.forward(d, th).mu["energy"]
+    np.testing.assert_allclose(mu[0.7] - mu[0.0], (0.7 / 0.3) * (mu[0.3] - mu[0.0]), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(mu[1.0] - mu[0.0], (1.0 / 0.3) * (mu[0.3] - mu[0.0]), rtol=1e-12, atol=1e-12)
+
+
+def test_pu_float_zero_equals_no_pileup():
+    d = _pu_float_model()
+    th = d.theta_true.copy()
+    th[-1] = 0.0
+    d0 = d.copy()
+    d0.pu_float, d0.pu_g, d0.pu_frac = False, None, 0.0
+    assert np.array_equal(om.forward(d, th).mu["energy"], om.forward(d0, th[:-1]).mu["energy"])
+
+
+def test_pu_float_gradient_from_the_two_ends():
+    # mu is affine in p, so dmu/dp = mu(p=1) - mu(p=0) and
+    # dNLL/dp = sum (1 - n/mu(p)) (mu(1) - mu(0)): no derivative formula needed
+    d = _pu_float_model()
+    data = poisson_data(d, d.theta_true)
+    th = d.theta_true * (1 + 0.02 * np.random.default_rng(11).standard_normal(d.P))
+    g = oracle.grad(d, data, th)
+    ends = []
+    for p in (0.0, 1.0):
+        t = th.copy()
+        t[-1] = p
+        ends.append(om.forward(d, t).mu["energy"])
+    mu = om.forward(d, th).mu["energy"]
+    n = data.energy
+    lo, hi = d.win
+    w = np.where(n > 0, 1.0 - n / mu, 1.0)[lo:hi]
+    ref = math.fsum((w * (ends[1] - ends[0])[lo:hi]).tolist())
+    assert abs(g[-1] - ref) <= 1e-12 * np.sum(np.abs(w * (ends[1] - ends[0])[lo:hi]))
+
+
+def test_pu_float_gradient_vs_richardson():
+    d = _pu_float_model()
+    data = poisson_data(d, d.theta_true)
+    th = d.theta_true * (1 + 0.02 * np.random.default_rng(12).standard_normal(d.P))
+    g = oracle.grad(d, data, th)
+    for q in (0, d.S, d.P - 1):
+        def f(v):
+            t = th.copy()
+            t[q] = v
+            return oracle.nll(d, data, t)
+        fd = _richardson(f, th[q], 1e-3 * abs(th[q]))
+        assert abs(g[q] - fd) <= 1e-6 * max(abs(fd), 1e-3) + 1e-7, (q, g[q], fd)
+
+
+def test_pu_float_outside_unit_interval_is_a_domain_error():
+    d = _pu_float_model()
+    th = d.theta_true.copy()
+    th[-1] = 1.5
+    with pytest.raises(oracle.DomainError):
+        om.forward(d, th)
