@@ -83,6 +83,10 @@ typedef struct {
   int32_t rad_lo, rad_hi;     /* reco window whose vetoed counts feed the radial term */
   int32_t n_ps;               /* pulse-shape bins (0..64; 0 = no PS term) */
   const double* ps_tmpl;      /* [S][n_ps] pulse-shape template per species */
+  /* 1: the pile-up fraction is a fit parameter, the last entry of theta
+   * (needs pu_K > 0; pu_frac is then unused); an evaluation with it outside
+   * [0, 1] is a domain error.  0: pu_frac is fixed. */
+  int32_t pu_float;
 } bx_model_desc;
 
 /* Observed histograms (FP64 counts; integers or Asimov values >= 0). */
@@ -167,8 +171,10 @@ typedef struct {
   int32_t kind;            /* bx_request_kind */
   const double* x0;        /* [P] start (FIT) or evaluation point (EVAL_GRAD) */
   const uint8_t* float_mask; /* [P] 1 = varied, 0 = fixed; NULL = all varied */
-  const double* lo;        /* [P] lower bounds or NULL (rates default to 0) */
-  const double* hi;        /* [P] upper bounds or NULL (none) */
+  const double* lo;        /* [P] lower bounds or NULL (rates and a floated pile-up
+                              fraction default to 0) */
+  const double* hi;        /* [P] upper bounds or NULL (a floated pile-up fraction
+                              defaults to 1, the rest to none) */
   double edm_tol;          /* stop when EDM = g^T H^-1 g / 2 < edm_tol (<= 0: 1e-9) */
   int32_t max_iter;        /* quasi-Newton iterations (<= 0: 500) */
   int32_t max_eval;        /* NLL + gradient evaluations (<= 0: 200 + 100 n + 5 n^2,

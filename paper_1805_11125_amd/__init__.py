@@ -94,7 +94,8 @@ class Model:
         d.exposure = float(desc.exposure)
         g = getattr(desc, "pu_g", None)
         pf = float(getattr(desc, "pu_frac", 0.0) or 0.0)
-        if g is not None and pf != 0.0:
+        d.pu_float = 1 if getattr(desc, "pu_float", False) else 0
+        if g is not None and (pf != 0.0 or d.pu_float):
             g = arr(g)
             d.pu_K, d.pu_g, d.pu_frac = len(g), dptr(g), pf
         d.win_lo, d.win_hi = int(desc.win[0]), int(desc.win[1])

@@ -31,7 +31,8 @@ class bx_model_desc(C.Structure):
                 ("pu_frac", C.c_double), ("win_lo", C.c_int32), ("win_hi", C.c_int32),
                 ("precision", C.c_int32), ("multivariate", C.c_int32), ("tag_frac", _dp),
                 ("n_rad", C.c_int32), ("rad_tmpl", _dp), ("rad_lo", C.c_int32),
-                ("rad_hi", C.c_int32), ("n_ps", C.c_int32), ("ps_tmpl", _dp)]
+                ("rad_hi", C.c_int32), ("n_ps", C.c_int32), ("ps_tmpl", _dp),
+                ("pu_float", C.c_int32)]
 
 
 class bx_data(C.Structure):

@@ -52,7 +52,7 @@ struct FitDev {
   int n_rt, n_ct, CG, n_cg, n_fb, RG, n_rg, n_rowblk;  // n_cg: forward chunks, n_fb: forward blocks per reco tile
   int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
   int uniform;            // reco bins of equal width
-  int pad0;
+  int pu_float;           // the pile-up fraction is theta[P - 1] (else pu_frac)
   double x0, inv_w;       // first reco edge, 1 / bin width (uniform bins)
   double pu_frac;
   GGConst gg;
@@ -86,7 +86,9 @@ struct FitDev {
   double* nllpart;      // [n_rowblk]
   int* flagpart;        // [n_rowblk]
   double* gpart;        // [n_rowblk][16] rate-gradient partials
-  double* rad_out;      // [2 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16]
+  double* rad_out;      // [3 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16], pile-up-fraction grad
+  double* Dp;           // [N][16] dM'/dp = g^*M - M (a floated pile-up fraction)
+  double* ppart;        // [n_rowblk] pile-up-fraction gradient partials
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags

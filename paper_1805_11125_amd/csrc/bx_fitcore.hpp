@@ -34,7 +34,9 @@ struct FitProblem {
   double f_noise = 0.0;              // relative rounding noise of the NLL values
 };
 
-inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb) {
+// unit: index of a parameter with default bounds [0, 1] (a floated pile-up
+// fraction), or -1.
+inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb, int unit = -1) {
   if (P > 32 || P < 1) {
     set_error("parameter count out of range");
     return BX_E_INVAL;
@@ -51,8 +53,8 @@ inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb)
       set_error("x0 must be finite");
       return BX_E_INVAL;
     }
-    pb->lo[q] = o->lo ? o->lo[q] : (q < S ? 0.0 : -INFINITY);
-    pb->hi[q] = o->hi ? o->hi[q] : INFINITY;
+    pb->lo[q] = o->lo ? o->lo[q] : (q < S || q == unit ? 0.0 : -INFINITY);
+    pb->hi[q] = o->hi ? o->hi[q] : (q == unit ? 1.0 : INFINITY);
     if (!(pb->lo[q] <= pb->hi[q])) {
       set_error("lower bound above upper bound");
       return BX_E_INVAL;

@@ -2,6 +2,7 @@
 // the plain path (build / eval / grad / expected counts) and the plain
 // quasi-Newton fitter (Sec. 4, workflow steps 1-7 of the paper's package).
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
 
 #include <algorithm>
 #include <atomic>
@@ -195,15 +196,18 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   m.T = d->T; m.N = d->N; m.S = d->S;
   m.kind = d->response == BX_RESP_GAUSS ? kGauss : kGG;
   m.nresp = m.kind == kGauss ? 2 : 4;
-  m.P = m.S + m.nresp;
+  m.pu_float = d->pu_float ? 1 : 0;
+  if (m.pu_float && !(d->pu_K > 0)) return inval("a floated pile-up fraction needs pu_K > 0");
+  m.P = m.S + m.nresp + m.pu_float;
   m.prec = d->precision == BX_PREC_F32 ? kF32 : kF64;
   m.win_lo = d->win_lo; m.win_hi = d->win_hi;
   m.exposure = d->exposure;
   m.p = m.kind == kGG ? d->gg_p : 1.0;
   m.K = 0; m.pu_frac = 0.0;
-  if (d->pu_K > 0 && d->pu_frac != 0.0) {
+  if (d->pu_K > 0 && (d->pu_frac != 0.0 || m.pu_float)) {
     if (!d->pu_g || !finite_nonneg(d->pu_g, d->pu_K)) return inval("pu_g must be finite and >= 0");
-    if (!std::isfinite(d->pu_frac) || d->pu_frac < 0 || d->pu_frac > 1) return inval("pu_frac must be in [0, 1]");
+    if (!m.pu_float && (!std::isfinite(d->pu_frac) || d->pu_frac < 0 || d->pu_frac > 1))
+      return inval("pu_frac must be in [0, 1]");
     long double sg = 0.0L;
     for (int k = 0; k < d->pu_K; ++k) sg += d->pu_g[k];
     if (!(sg > 0)) return inval("pu_g has zero sum");
@@ -213,7 +217,7 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
       if (std::fabs(w - w0) > 1e-9 * std::fabs(w0)) return inval("pile-up needs uniform reco bins");
     }
     m.K = d->pu_K;
-    m.pu_frac = d->pu_frac;
+    m.pu_frac = m.pu_float ? 0.0 : d->pu_frac;
     m.ghat.resize(m.K);
     for (int k = 0; k < m.K; ++k) m.ghat[k] = (double)(d->pu_g[k] / sg);
   }
@@ -365,7 +369,9 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->nllpart = c.take<double>(f->n_rowblk);
   f->flagpart = c.take<int>(f->n_rowblk);
   f->gpart = c.take<double>((size_t)f->n_rowblk * kSP);
-  f->rad_out = c.take<double>(2 + 2 * kSP);
+  f->rad_out = c.take<double>(3 + 2 * kSP);
+  f->Dp = c.take<double>((size_t)h.N * kSP);
+  f->ppart = c.take<double>(f->n_rowblk);
   f->cpflag = c.take<int>(f->n_cpblk);
   f->bwdpart = c.take<double>((size_t)f->n_bwdblk * 4);
   *out = c.take<double>(2 + h.P);
@@ -380,7 +386,7 @@ HostModel shape_only(const HostModel& h) {
   s.T = h.T; s.N = h.N; s.S = h.S; s.P = h.P; s.nresp = h.nresp; s.kind = h.kind; s.prec = h.prec; s.mv = h.mv;
   s.win_lo = h.win_lo; s.win_hi = h.win_hi; s.K = h.K; s.n_rad = h.n_rad; s.rad_lo = h.rad_lo;
   s.rad_hi = h.rad_hi; s.n_ps = h.n_ps;
-  s.p = h.p; s.pu_frac = h.pu_frac; s.exposure = h.exposure;
+  s.p = h.p; s.pu_frac = h.pu_frac; s.pu_float = h.pu_float; s.exposure = h.exposure;
   s.gg = h.gg;
   s.tiles = h.tiles;
   return s;
@@ -430,6 +436,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   f.win_lo = h.win_lo; f.win_hi = h.win_hi; f.K = h.K; f.n_rad = h.n_rad; f.rad_lo = h.rad_lo;
   f.rad_hi = h.rad_hi; f.n_ps = h.n_ps;
   f.pu_frac = h.pu_frac;
+  f.pu_float = h.pu_float;
   f.gg = h.gg;
   if (shared) {  // inputs (and what is derived from them) already in place
     f.uniform = shared->uniform;
@@ -488,6 +495,14 @@ static bx_status enqueue_eval(bx_model* m, bool grad, bool host, hipStream_t st)
 }
 
 namespace bx {
+// Writes back and evicts the CPU cache lines of n doubles at p (then a full
+// fence, so that later loads come from memory and earlier stores have left).
+static void flush_lines(const double* p, int n) {
+  const uintptr_t a = (uintptr_t)p & ~(uintptr_t)63, e = (uintptr_t)(p + n);
+  for (uintptr_t l = a; l < e; l += 64) _mm_clflush((const void*)l);
+  _mm_mfence();
+}
+
 // Evaluate at host theta; fills nll (and grad).  Shared with the plain fitter.
 bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad) {
   const int P = m->h.P;
@@ -503,17 +518,25 @@ bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad
   memcpy(hp, theta, P * sizeof(double));
   const double seq = (double)(++m->seq);
   hp[P] = seq;
+  flush_lines(hp, P + 1);  // theta in memory before the launch
   bx_status s = enqueue_eval(m, grad != nullptr, true, m->stream);
   if (s != BX_OK) return s;
   // The last kernel writes the sequence number after the results (with a
   // system-scope fence): spin on it, and ask the stream now and then so that
-  // a failed launch ends the wait with its error.
+  // a failed launch ends the wait with its error.  Device writes to this
+  // buffer do not reliably invalidate a copy of the line the CPU already
+  // holds (one fetched by its prefetcher while the results were in flight),
+  // so the mark and then the results are read from memory, past the cache.
   const volatile double* mark = hp + kPinOut + 2 + P;
+  auto mark_now = [&]() {
+    flush_lines(hp + kPinOut + 2 + P, 1);
+    return *mark;
+  };
   for (unsigned it = 1;; ++it) {
-    if (*mark == seq) break;
+    if (mark_now() == seq) break;
     if ((it & 1023u) == 0u) {
       const hipError_t q = hipStreamQuery(m->stream);
-      if (q == hipSuccess && *mark == seq) break;
+      if (q == hipSuccess && mark_now() == seq) break;
       if (q == hipSuccess) {
         set_error("evaluation finished without its completion mark");
         return BX_E_DEVICE;
@@ -522,6 +545,7 @@ bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad
     }
     __builtin_ia32_pause();
   }
+  flush_lines(hp + kPinOut, 2 + P);
   std::atomic_thread_fence(std::memory_order_acquire);
   const double* o = hp + kPinOut;
   const int fl = (int)o[1 + P];
@@ -588,6 +612,7 @@ bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* h
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return fail(BX_E_NOMEM);
   memset(m->h_pin, 0, kPinDoubles * sizeof(double));
+  flush_lines(m->h_pin, kPinDoubles);  // no dirty host line left over device results
   void* d_pin = nullptr;
   if (hipHostGetDevicePointer(&d_pin, m->h_pin, 0) != hipSuccess)
     return fail(hip_fail(hipErrorUnknown, "hipHostGetDevicePointer"));
@@ -795,7 +820,7 @@ bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r) {
   const int P = m->h.P;
   if (P > 32) return inval("too many parameters");
   FitProblem pb;
-  bx_status s = fit_problem(P, m->h.S, o, &pb);
+  bx_status s = fit_problem(P, m->h.S, o, &pb, m->h.pu_float ? P - 1 : -1);
   if (s != BX_OK) return s;
   pb.f_noise = nll_noise(m->h);
   memset(r, 0, sizeof *r);

@@ -138,6 +138,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
     const double E = f.Ec[i];
     bool okth = true;
     for (int q = 0; q < f.P; ++q) okth = okth && isfinite(th[q]);
+    if (f.pu_float && !(th[f.P - 1] >= 0.0 && th[f.P - 1] <= 1.0)) okth = false;
     if (!okth) bad |= kBadTheta;
     if (f.kind == kGauss) {
       const double a = th[f.S], b = th[f.S + 1];
@@ -391,7 +392,12 @@ __device__ __forceinline__ double nll_term(double mu, double n, double* w, int* 
 }
 
 __device__ __forceinline__ int pu_len(const FitDev& f) {
-  return (f.K > 0 && f.pu_frac != 0.0) ? f.K : 1;
+  return (f.K > 0 && (f.pu_float || f.pu_frac != 0.0)) ? f.K : 1;
+}
+
+// Pile-up fraction: the last parameter when it is floated, else fixed.
+__device__ __forceinline__ double pu_p(const FitDev& f) {
+  return f.pu_float ? f.theta[f.P - 1] : f.pu_frac;
 }
 
 // M[j, s] = sum over forward blocks of the partials, FP64, fixed order.
@@ -434,16 +440,19 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   __syncthreads();
   const int j = j0 + rl;
   const bool jok = j < f.N;
-  double m = 0.0;
+  double m = 0.0, dmp = 0.0;  // M'_js and dM'_js/dp = (g^*M)_js - M_js
   if (jok) {
     m = Ml[j - r0][s];
     if (K > 1) {
       double acc = 0.0;
       const int kmax = min(j, K - 1);
       for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Ml[j - k - r0][s];
-      m = (1.0 - f.pu_frac) * m + f.pu_frac * acc;
+      const double pp = pu_p(f);
+      dmp = acc - m;
+      m = (1.0 - pp) * m + pp * acc;
     }
     f.Mp[j * kSP + s] = m;
+    if (f.pu_float) f.Dp[j * kSP + s] = dmp;
   }
   mp[rl][s] = m;
   __syncthreads();
@@ -511,24 +520,42 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     for (int r = 0; r < 16; ++r) a += red[r * 16 + threadIdx.x];
     f.gpart[blockIdx.x * kSP + threadIdx.x] = a;
   }
+  if (f.pu_float) {  // block-uniform: dNLL/dp without the radial part, sum_js H_js r_s dM'_js/dp
+    __syncthreads();
+    red[threadIdx.x] = (jok && s < f.S) ? h * r_s * dmp : 0.0;
+    __syncthreads();
+    for (int st = kBlock / 2; st >= 1; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) f.ppart[blockIdx.x] = red[0];
+  }
 }
 
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if (!f.mv || f.n_rad <= 0) return;  // block-uniform
-  __shared__ double part[16][kSP];
-  __shared__ double SW[kSP], A[kSP], wr[128], red[kBlock];
+  __shared__ double part[16][kSP], partd[16][kSP];
+  __shared__ double SW[kSP], SD[kSP], A[kSP], pgs[kSP], wr[128], red[kBlock];
   __shared__ int redf[kBlock];
   const int s = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  double acc = 0.0;
-  for (int j = f.rad_lo + grp; j < f.rad_hi; j += 16) acc += f.Mp[j * kSP + s];
+  double acc = 0.0, accd = 0.0;
+  for (int j = f.rad_lo + grp; j < f.rad_hi; j += 16) {
+    acc += f.Mp[j * kSP + s];
+    if (f.pu_float) accd += f.Dp[j * kSP + s];
+  }
   part[grp][s] = acc;
+  partd[grp][s] = accd;
   __syncthreads();
   if (threadIdx.x < 16) {
-    double t = 0.0;
-    for (int g = 0; g < 16; ++g) t += part[g][threadIdx.x];
+    double t = 0.0, td = 0.0;
+    for (int g = 0; g < 16; ++g) {
+      t += part[g][threadIdx.x];
+      td += partd[g][threadIdx.x];
+    }
     SW[threadIdx.x] = t;
+    SD[threadIdx.x] = td;
     A[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * t : 0.0;
   }
   __syncthreads();
@@ -558,10 +585,16 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
     f.rad_out[2 + threadIdx.x] = rw;
     f.rad_out[2 + 16 + threadIdx.x] =
         (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * SW[threadIdx.x] * rw : 0.0;
+    // radial part of dNLL/dp: sum_s (1 - t_s) r_s (sum_{j in W} dM'_js/dp) rho.w_s
+    pgs[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * SD[threadIdx.x] * rw : 0.0;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     f.rad_out[0] = red[0];
     f.rad_out[1] = (double)redf[0];
+    double pg = 0.0;
+    for (int u = 0; u < 16; ++u) pg += pgs[u];
+    f.rad_out[2 + 32] = pg;
   }
 }
 
@@ -589,7 +622,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
     double acc = 0.0;
     const int kmax = min(K - 1, f.N - 1 - j);
     for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Hl[rl + k][s];
-    h = (1.0 - f.pu_frac) * h + f.pu_frac * acc;
+    h = (1.0 - pu_p(f)) * h + pu_p(f) * acc;
   }
   f.Ht[j * kSP + s] = h;
 }
@@ -642,7 +675,7 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
     }
     for (int e = threadIdx.x; e < nr; e += kBlock) {
       double h = hst[e];
-      if (K > 1) h = (1.0 - f.pu_frac) * h + f.pu_frac * ((pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]));
+      if (K > 1) h = (1.0 - pu_p(f)) * h + pu_p(f) * ((pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]));
       htl[e] = h;
     }
     __syncthreads();
@@ -717,14 +750,17 @@ __device__ __forceinline__ int or64(int x) {
 template <int NT>
 __device__ void final_sums(const FitDev& f, int with_grad) {
   constexpr int NW = NT / 64;
-  __shared__ double wred[NW][5 + kSP];
+  // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient
+  constexpr int NA = 6;
+  __shared__ double wred[NW][NA + kSP];
   __shared__ int wflag[NW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  double acc[5] = {0, 0, 0, 0, 0};
+  double acc[NA] = {0, 0, 0, 0, 0, 0};
   int fl = 0;
   for (int b = t; b < f.n_rowblk; b += NT) {
     acc[0] += f.nllpart[b];
     fl |= f.flagpart[b];
+    if (f.pu_float && with_grad) acc[5] += f.ppart[b];
   }
   for (int b = t; b < f.n_cpblk; b += NT) fl |= f.cpflag[b];
   if (with_grad)
@@ -736,31 +772,33 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   gr += __shfl_xor(gr, 16, 64);
   gr += __shfl_xor(gr, 32, 64);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) acc[q] = sum64(acc[q]);
+  for (int q = 0; q < NA; ++q) acc[q] = sum64(acc[q]);
   fl = or64(fl);
   if (lane == 0) {
-    for (int q = 0; q < 5; ++q) wred[w][q] = acc[q];
+    for (int q = 0; q < NA; ++q) wred[w][q] = acc[q];
     wflag[w] = fl;
   }
-  if (lane < kSP) wred[w][5 + lane] = gr;
+  if (lane < kSP) wred[w][NA + lane] = gr;
   __syncthreads();
   // results go to f.out and, when set, straight into the caller's pinned
   // host buffer as well (no separate copy node)
   if (t < f.S) {
-    double a = wred[0][5 + t];
-    for (int v = 1; v < NW; ++v) a += wred[v][5 + t];
+    double a = wred[0][NA + t];
+    for (int v = 1; v < NW; ++v) a += wred[v][NA + t];
     if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + t];
     f.out[1 + t] = a;
     if (f.out_host) f.out_host[1 + t] = a;
   }
   if (t == 0) {
-    double tot[5];
+    double tot[NA];
     int flags = wflag[0];
-    for (int q = 0; q < 5; ++q) tot[q] = wred[0][q];
+    for (int q = 0; q < NA; ++q) tot[q] = wred[0][q];
     for (int v = 1; v < NW; ++v) {
-      for (int q = 0; q < 5; ++q) tot[q] += wred[v][q];
+      for (int q = 0; q < NA; ++q) tot[q] += wred[v][q];
       flags |= wflag[v];
     }
+    double pg = tot[5];  // dNLL/dp: row terms, then the radial term
+    if (f.mv && f.n_rad > 0) pg += f.rad_out[2 + 32];
     double nll = tot[0];
     if (f.mv && f.n_rad > 0) {
       nll += f.rad_out[0];
@@ -771,10 +809,12 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     f.out[0] = v0;
     f.out[1 + f.P] = (double)flags;
     for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+    if (f.pu_float) f.out[f.P] = with_grad ? pg : 0.0;
     if (f.out_host) {
       f.out_host[0] = v0;
       f.out_host[1 + f.P] = (double)flags;
       for (int q = 0; q < f.nresp; ++q) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+      if (f.pu_float) f.out_host[f.P] = with_grad ? pg : 0.0;
     }
   }
   if (f.out_host) {  // then the completion mark the caller spins on

@@ -28,6 +28,7 @@ struct HostModel {
   int T, N, S, P, nresp, kind, prec, mv;
   int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
   double p, pu_frac, exposure;
+  int pu_float;  // the pile-up fraction is the last parameter
   std::vector<double> xraw, xe, Ec, Qt, F64, ghat, tag, rad, pst;
   std::vector<float> F32;
   std::vector<double> n_e, n_t, n_r, n_p;
@@ -83,7 +84,9 @@ struct bx_model {
   // pinned, coherent: theta[P] | seq at 0 (written by the host), out[2 + P] |
   // completion mark at kPinOut (written by the device).  The two halves never
   // share a cache line: a host line holding a stale copy of a device-written
-  // value would otherwise be written back over it.
+  // value would otherwise be written back over it.  Device writes do not
+  // reliably invalidate lines the CPU holds, so the host flushes its lines of
+  // theta after writing them and those of the mark and results before reading.
   double* h_pin = nullptr;
   uint64_t seq = 0;              // evaluations on the host path (completion marks)
   double lnfact = 0.0;

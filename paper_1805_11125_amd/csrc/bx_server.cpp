@@ -349,7 +349,7 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   }
   auto r = std::make_shared<Req>();
   r->res.t_submit_ns = now_ns();
-  bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb);
+  bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb, m->h.pu_float ? m->h.P - 1 : -1);
   if (st != BX_OK) return st;
   r->pb.f_noise = nll_noise(m->h);
   // the fit reads the model's inputs in place (the model stays busy while it

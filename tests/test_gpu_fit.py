@@ -65,6 +65,25 @@ def test_asimov_fit_recovers_truth(bx):
     np.testing.assert_allclose(r.x, d.theta_true, rtol=1e-7)
 
 
+def test_asimov_fit_recovers_pileup_fraction(bx):
+    # the pile-up fraction floated with the rates and the response: an Asimov
+    # data set (the oracle's expected counts) gives back the truth
+    d, _ = synth.load("c2")
+    d = d.copy()
+    d.pu_float = True
+    d.theta_true = np.concatenate([d.theta_true, [d.pu_frac]])
+    d.float_mask = np.concatenate([d.float_mask, [True]])
+    mu = om.forward(d, d.theta_true).mu["energy"]
+    m = bx.Model(d, synth.Data(energy=mu), precision=F64)
+    th0 = d.theta_true.copy()
+    th0[-1] = 0.035
+    th0[: d.S] *= 1.01
+    r = m.fit(th0, float_mask=d.float_mask, edm_tol=1e-12, max_iter=2000)
+    assert r.status == bx.BX_CONVERGED
+    assert abs(r.x[-1] - d.pu_frac) <= 1e-6 * d.pu_frac
+    np.testing.assert_allclose(r.x[: d.S], d.theta_true[: d.S], rtol=1e-6)
+
+
 def test_autograd_function(bx):
     import torch
     d, x = synth.load("c2")
@@ -168,6 +187,28 @@ def test_admission_under_small_budget(bx):
     s.close()
     s2.close()
     del _abi, C
+
+
+def test_plain_results_never_stale(bx):
+    # Alternating two points on the plain path: every result must be the one
+    # of its own point, bit for bit.  A CPU cache line of the result block
+    # fetched while the device was still writing it once returned the previous
+    # point's NLL and first gradient entries (the line before the mark's).
+    toys = _toys(4, first=12)
+    rng = np.random.default_rng(5)
+    bad = []
+    for i, (d, x, t) in enumerate(toys):
+        m = bx.Model(d, x, precision=F32)
+        A = np.asarray(t.theta0, dtype=np.float64)
+        B = A * (1 + 1e-3 * rng.standard_normal(A.size))
+        ref = [m.nll_grad(A), m.nll_grad(B)]
+        for k in range(8000):
+            v, g = m.nll_grad(B if k & 1 else A)
+            r = ref[k & 1]
+            if v != r[0] or not np.array_equal(g, r[1]):
+                bad.append((i, k, v, r[0]))
+        m.close()
+    assert not bad, bad[:5]
 
 
 def test_plain_fits_reproducible_around_server_runs(bx):

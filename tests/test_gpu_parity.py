@@ -68,6 +68,38 @@ def test_toy_start_parity(bx, b, prec):
     check_point(bx, d, x, t.theta0, prec, f"toy{b}/prec{prec}")
 
 
+def _pu_float(d):
+    d = d.copy()
+    d.pu_float = True
+    d.theta_true = np.concatenate([d.theta_true, [d.pu_frac]])
+    if d.float_mask is not None:
+        d.float_mask = np.concatenate([d.float_mask, [True]])
+    return d
+
+
+# The pile-up fraction as a fit parameter (last entry of theta), with its
+# gradient; the multivariate model carries it through the radial term too.
+@pytest.mark.parametrize("name,prec", [("c2", F32), ("c2", F64), ("c3b", F32)])
+def test_pu_float_parity(bx, name, prec):
+    d, x = synth.load(name)
+    d = _pu_float(d)
+    th = perturbed(d, seed=9)
+    check_point(bx, d, x, th, prec, f"{name}+p/prec{prec}")
+
+
+def test_pu_float_domain(bx):
+    d, x = synth.load("c2")
+    d = _pu_float(d)
+    m = bx.Model(d, x, precision=F32)
+    th = d.theta_true.copy()
+    th[-1] = 1.2
+    with pytest.raises(bx.DomainError):
+        m.nll_grad(th)
+    th[-1] = 0.0  # the boundary is inside the domain
+    v, g = m.nll_grad(th)
+    assert np.isfinite(v) and np.all(np.isfinite(g))
+
+
 @pytest.mark.parametrize("name,prec", [("c1", F64), ("c2", F32), ("c3a", F64)])
 def test_expected_counts_parity(bx, name, prec):
     d, x = synth.load(name)

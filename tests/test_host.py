@@ -64,6 +64,7 @@ def _desc(abi, d, precision=0, **over):
 @pytest.mark.parametrize("field,value", [
     ("T", 0), ("N", 0), ("S", 17), ("precision", 7), ("response", 5), ("exposure", 0.0),
     ("win_lo", 150), ("win_hi", 500), ("pu_K", 300),
+    ("pu_float", 1),  # a floated pile-up fraction without a random-trigger spectrum
 ])
 def test_build_rejects_invalid_descriptions(abi, field, value):
     d = synth.config1()
