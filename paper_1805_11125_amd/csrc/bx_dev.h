@@ -20,6 +20,8 @@ constexpr int kCpBlock = 64;   // threads per block of the column-parameter kern
 constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG true tiles)
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
 constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
+constexpr int kBwdWaves = 4;   // waves per backward block (one reco tile each, times RG)
+constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up adjoint in its own kernel
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
 

@@ -314,10 +314,10 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->CG = h.tiles.CG;
   f->RG = h.tiles.RG;
   // forward partials: one per chunk of kFwdWaves listed true tiles; a forward
-  // block holds CG chunks; a backward block 4 waves of RG reco tiles
+  // block holds CG chunks; a backward block kBwdWaves waves of RG reco tiles
   f->n_cg = (f->n_ct + kFwdWaves - 1) / kFwdWaves;
   f->n_fb = (f->n_cg + f->CG - 1) / f->CG;
-  f->n_rg = (f->n_rt + 4 * f->RG - 1) / (4 * f->RG);
+  f->n_rg = (f->n_rt + kBwdWaves * f->RG - 1) / (kBwdWaves * f->RG);
   f->n_rowblk = (h.N + 15) / 16;
   f->n_cpblk = (h.T + kCpBlock - 1) / kCpBlock;
   f->n_bwdblk = f->n_ct * f->n_rg;

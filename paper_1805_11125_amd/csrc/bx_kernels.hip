@@ -235,6 +235,24 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   if (threadIdx.x == 0) f.cpflag[blockIdx.x] = bad;
 }
 
+// A column's constants as one lane holds them in the forward sweep.
+template <class R>
+struct ColPre {
+  double c0, c1;  // Gauss: m, 1/sigma; GG: ct
+  R s[8];         // GG edge constants
+  R bb;           // spectrum entry F^[i, species of the lane]
+};
+
+template <class R, int KIND, bool D>
+__device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe) {
+  if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
+  GGCol<R> g;
+  g.ct = c.c0;
+  g.k = c.s[0]; g.ik = c.s[1]; g.skh = c.s[2]; g.cR = c.s[3]; g.ce = c.s[4];
+  g.dlngs = c.s[5]; g.lnk_psi = c.s[6]; g.p = c.s[7];
+  return gg_edge<R, D>(xe, g);
+}
+
 // Edge evaluation for one lane.
 template <class R, int KIND, bool D>
 __device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
@@ -300,8 +318,9 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
     const int ct = c0 + (int)threadIdx.x;
     bool act = false;
     if (ct < f.n_ct) {
-      const int2 b = f.tb[ct];
-      act = !(b.y < j0 || b.x > j0 + kRowStep - 1);
+      const __attribute__((address_space(1))) int* tbp = (const __attribute__((address_space(1))) int*)f.tb;
+      const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];  // the tile's support [bx, by]
+      act = !(by < j0 || bx > j0 + kRowStep - 1);
     }
     const unsigned long long m = __ballot(act);
     if (lane == 0) wcount[wv] = __popcll(m);
@@ -317,36 +336,65 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
     __syncthreads();
   }
   const int je = min(j0 + jr, f.N);
-  const double xe = f.xe[je];
+  const double xe = ((__attribute__((address_space(1))) const double*)f.xe)[je];
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
   const int n_here = n_act - lo;  // entries of this window in the list
   typedef typename Pair<R>::T R2;
+  // the constants of a lane's column and its spectrum entry, fetched one
+  // column ahead of their use so that the loads overlap the edge arithmetic
+  // (fields of f in registers: the stores of the cell differences could
+  // alias it, which would make every access after one reload f and wait)
+  // Global-address-space views: flat accesses would make every wait for a
+  // load also wait for all older memory operations.
+  typedef __attribute__((address_space(1))) const ColPar GColPar;
+  typedef __attribute__((address_space(1))) const R GR;
+  typedef __attribute__((address_space(1))) R GRw;
+  GColPar* const cpar = (GColPar*)f.cp;
+  GR* const ftab = (GR*)Ftab;
+  const int T = f.T, n_rt = f.n_rt;
+  GRw* const dcell = (GRw*)f.Dcell;  // pairs (dF/dc1, dF/dc2) differences
+  auto fetch = [&](int i) -> ColPre<R> {
+    ColPre<R> p;
+    const bool iok = i < T;
+    GColPar& cpi = cpar[iok ? i : T - 1];
+    p.c0 = cpi.c0;
+    p.c1 = KIND == kGauss ? cpi.c1 : 0.0;
+    if (KIND != kGauss) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p.s[u] = sizeof(R) == 4 ? (R)cpi.f32[u] : (R)cpi.f64[u];
+    }
+    p.bb = iok ? ftab[i * kSP + jr] : (R)0;
+    return p;
+  };
   // one tile's 16 x 16 contribution (zero past the end of the list)
   auto tile = [&](int c) -> V {
     V acc = {0, 0, 0, 0};
     const int e = wv * CG + c;
     if (e >= n_here) return acc;  // wave-uniform
     const int ct = mylist[e];
-    R2* dst = D ? (R2*)f.Dcell + ((size_t)ct * f.n_rt + rt) * 4 * 64 : nullptr;
+    GRw* dst = D ? dcell + ((size_t)ct * n_rt + rt) * 4 * 64 * 2 : nullptr;
+    ColPre<R> cur = fetch(ct * kColTile + g);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      ColPre<R> nxt;
+      if (q < 3) nxt = fetch(ct * kColTile + 4 * (q + 1) + g);
       const int i = ct * kColTile + 4 * q + g;
-      const bool iok = i < f.T;
-      const ColPar& cpi = f.cp[iok ? i : f.T - 1];
-      const R bb = iok ? Ftab[i * kSP + jr] : (R)0;
-      const EdgeVal<R> ev = edge_at<R, KIND, D>(cpi, xe);
+      const bool iok = i < T;
+      const EdgeVal<R> ev = edge_pre<R, KIND, D>(cur, xe);
       const R hi = dpp_from_next(ev.v);
       const bool ok = row_ok && iok;
       const R a = ok ? cell_from(ev.v, hi) : (R)0;
-      acc = mfma16(a, bb, acc);
+      acc = mfma16(a, cur.bb, acc);
       if (D) {
         const R d1h = dpp_from_next(ev.d1), d2h = dpp_from_next(ev.d2);
         R2 dv;
         dv.x = ok ? d1h - ev.d1 : (R)0;
         dv.y = ok ? d2h - ev.d2 : (R)0;
-        dst[q * 64 + lane] = dv;
+        dst[2 * (q * 64 + lane)] = dv.x;
+        dst[2 * (q * 64 + lane) + 1] = dv.y;
       }
+      if (q < 3) cur = nxt;
     }
     return acc;
   };
@@ -627,85 +675,151 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
   f.Ht[j * kSP + s] = h;
 }
 
+// Single histogram: w~ = P^T w into column 0 of H~, 64 rows per block, four
+// threads per row over the taps k = part (mod 4), the partials added in the
+// same order and with the same explicit fused multiply-adds as in the
+// backward sweep's own prologue (same bits).
+__global__ void __launch_bounds__(kBlock) k_adjoint1(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int j0 = blockIdx.x * 64;
+  if (f.mv || j0 >= f.N) return;  // block-uniform
+  __shared__ double hs[64 + kMaxK - 1], gl[kMaxK];
+  const int K = pu_len(f);
+  const int r1 = min(j0 + 64 + K - 1, f.N);
+  for (int e = threadIdx.x; e < r1 - j0; e += kBlock) hs[e] = f.H[(size_t)(j0 + e) * kSP];
+  for (int e = threadIdx.x; e < K; e += kBlock) gl[e] = K > 1 ? f.ghat[e] : 0.0;
+  __syncthreads();
+  const int e = threadIdx.x >> 2, part = threadIdx.x & 3, j = j0 + e;
+  double acc = 0.0;
+  if (K > 1 && j < f.N) {
+    const int kmax = min(K - 1, f.N - 1 - j);
+    for (int k = part; k <= kmax; k += 4) acc = fma(gl[k], hs[e + k], acc);
+  }
+  const int l0 = (threadIdx.x & 63) & ~3;
+  const double p0 = __shfl(acc, l0, 64), p1 = __shfl(acc, l0 + 1, 64);
+  const double p2 = __shfl(acc, l0 + 2, 64), p3 = __shfl(acc, l0 + 3, 64);
+  if (part == 0 && j < f.N) {
+    double h = hs[e];
+    const double pp = pu_p(f);
+    if (K > 1) h = fma(pp, (p0 + p1) + (p2 + p3), (1.0 - pp) * h);
+    f.Ht[(size_t)j * kSP] = h;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Logical block (ct, rg): true tile ct; its support covers the contiguous reco tiles
-// [rt_a, rt_b], and wave w takes rt = rt_a + (4 rg + w) RG + c, c < RG.  The
-// working blocks of a true tile are thus its first ones; the others write a
-// zero partial and leave.  The cells' derivative differences come from the
-// forward sweep of the same evaluation (Dcell).
+// Logical block (ct, rg): true tile ct; its support covers the contiguous reco
+// tiles [rt_a, rt_b], and wave w of the kBwdWaves takes
+// rt = rt_a + (kBwdWaves rg + w) RG + c, c < RG.  The working blocks of a true
+// tile are thus its first ones (one block for a support of up to kBwdWaves RG
+// reco tiles); the others write a zero partial and leave.  The cells'
+// derivative differences come from the forward sweep of the same evaluation
+// (Dcell); the loads of a wave's first tile and of the chain factors are
+// issued before the pile-up adjoint so that their latency overlaps it.  With
+// pre, a single histogram's adjoint w~ comes from k_adjoint1 (batched
+// launches, where forming it here for every true tile would repeat it for
+// each tile that reaches a row); the two give the same bits.
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const int* active) {
+__global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits, const int* active, int pre) {
+  constexpr int NT = kBwdWaves * 64;
+  constexpr int kRows = kBwdWaves * kMaxRG * kRowStep;
+  typedef __attribute__((address_space(1))) const R GR;
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) const ColPar GColPar;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int2 cr = bwd_block(f.n_rg);
   const int ct = cr.x, rg = cr.y, bl = ct * f.n_rg + rg;
   if (ct >= f.n_ct) return;  // block-uniform
-  __shared__ double colA[4][16], colB[4][16];
-  __shared__ double hst[4 * kMaxRG * kRowStep + kMaxK], htl[4 * kMaxRG * kRowStep], gl[kMaxK];
-  __shared__ double pq[4 * kMaxRG * kRowStep][4];
+  __shared__ double colA[kBwdWaves][16], colB[kBwdWaves][16];
+  __shared__ double hst[kRows + kMaxK], htl[kRows], gl[kMaxK];
+  __shared__ double pq[kRows][4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
-  const int2 b = f.tb[ct];
-  const int rt_a = b.y >= b.x ? max(b.x, 0) / kRowStep : 0;
-  const int rt_b = b.y >= b.x ? min(b.y / kRowStep, f.n_rt - 1) : -1;
-  const int rt_blk = rt_a + 4 * rg * f.RG;  // first reco tile of this block
-  if (rt_blk > rt_b) {                      // block-uniform: nothing in range
+  const int T = f.T, N = f.N, RG = f.RG, mv = f.mv;
+  GColPar* const cpar = (GColPar*)f.cp;
+  GR* const dcell = (GR*)f.Dcell;  // pairs (dF/dc1, dF/dc2) differences
+  GD* const Hg = (GD*)f.H;
+  const int bx = ((GI*)f.tb)[2 * ct], by = ((GI*)f.tb)[2 * ct + 1];  // support [bx, by]
+  const int rt_a = by >= bx ? max(bx, 0) / kRowStep : 0;
+  const int rt_b = by >= bx ? min(by / kRowStep, f.n_rt - 1) : -1;
+  const int rt_blk = rt_a + kBwdWaves * rg * RG;  // first reco tile of this block
+  if (rt_blk > rt_b) {                            // block-uniform: nothing in range
     if (threadIdx.x < 4) f.bwdpart[(size_t)bl * 4 + threadIdx.x] = 0.0;
     return;
   }
+  // chain factors of the column totals (threads < 64: column c16, parameter q)
+  const int c16 = threadIdx.x & 15, qp = (threadIdx.x >> 4) & 3;
+  const int icol = ct * kColTile + c16;
+  double J0 = 0.0, J1 = 0.0;
+  if (threadIdx.x < 64 && icol < T && qp < f.nresp) {
+    J0 = cpar[icol].J[0][qp];
+    J1 = cpar[icol].J[1][qp];
+  }
+  // this wave's first tile: cell differences and column values
+  const int rt0 = rt_blk + wv * RG;
+  const int rt_end = min(rt0 + RG, rt_b + 1);
+  R dx[4], dy[4];
+  double vv[4];
+  auto load_tile = [&](int rt) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ct * kColTile + 4 * q + g;
+      const bool ok = (rt < rt_end) && (jr < kRowStep) && (rt * kRowStep + jr < N) && (i < T);
+      const size_t e = (((size_t)ct * f.n_rt + rt) * 4 * 64 + q * 64 + lane) * 2;
+      dx[q] = ok ? dcell[e] : (R)0;
+      dy[q] = ok ? dcell[e + 1] : (R)0;
+      vv[q] = ok && !mv ? cpar[i].v : 0.0;
+    }
+  };
+  load_tile(rt0);
   // single histogram: the pile-up adjoint w~ = P^T w of this block's reco
   // rows, from the rows it needs staged in LDS (multivariate fits read the
   // full adjoint H~ written by k_adjoint)
   const int r0 = rt_blk * kRowStep;
-  const int nr = max(min(4 * f.RG * kRowStep, f.N - r0), 0);
-  if (!f.mv) {
+  const int nr = max(min((min(rt_b + 1, rt_blk + kBwdWaves * RG) - rt_blk) * kRowStep, N - r0), 0);
+  if (!mv && !pre) {
     const int K = pu_len(f);
-    const int ns = min(nr + K - 1, f.N - r0);
-    for (int e = threadIdx.x; e < ns; e += kBlock) hst[e] = f.H[(r0 + e) * kSP];
-    for (int e = threadIdx.x; e < K; e += kBlock) gl[e] = K > 1 ? f.ghat[e] : 0.0;
+    const int ns = min(nr + K - 1, N - r0);
+    for (int e = threadIdx.x; e < ns; e += NT) hst[e] = Hg[(size_t)(r0 + e) * kSP];
+    for (int e = threadIdx.x; e < K; e += NT) gl[e] = K > 1 ? ((GD*)f.ghat)[e] : 0.0;
     __syncthreads();
     if (K > 1) {
       // four threads per row, taps k = part (mod 4); partials added in a fixed order
-      for (int e4 = threadIdx.x; e4 < 4 * nr; e4 += kBlock) {
+      for (int e4 = threadIdx.x; e4 < 4 * nr; e4 += NT) {
         const int e = e4 >> 2, part = e4 & 3;
-        const int kmax = min(K - 1, f.N - 1 - (r0 + e));
+        const int kmax = min(K - 1, N - 1 - (r0 + e));
         double acc = 0.0;
-        for (int k = part; k <= kmax; k += 4) acc += gl[k] * hst[e + k];
+        for (int k = part; k <= kmax; k += 4) acc = fma(gl[k], hst[e + k], acc);
         pq[e][part] = acc;
       }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < nr; e += kBlock) {
+    const double pp = pu_p(f);
+    for (int e = threadIdx.x; e < nr; e += NT) {
       double h = hst[e];
-      if (K > 1) h = (1.0 - pu_p(f)) * h + pu_p(f) * ((pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]));
+      if (K > 1) h = fma(pp, (pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]), (1.0 - pp) * h);
       htl[e] = h;
     }
     __syncthreads();
   }
-  typedef typename Pair<R>::T R2;
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
-  const int rt0 = rt_blk + wv * f.RG;
-  const int rt_end = min(rt0 + f.RG, rt_b + 1);
   for (int rt = rt0; rt < rt_end; ++rt) {
-    const int j0 = rt * kRowStep;
-    if (b.y < j0 || b.x > j0 + kRowStep - 1) continue;   // wave-uniform skip
-    const int j = j0 + jr;
-    const bool row_ok = (jr < kRowStep) && (j < f.N);
-    const double w1 = (row_ok && !f.mv) ? htl[j - r0] : 0.0;
-    const R2* src = (const R2*)f.Dcell + ((size_t)ct * f.n_rt + rt) * 4 * 64;
+    if (rt > rt0) load_tile(rt);
+    const int j = rt * kRowStep + jr;
+    const bool row_ok = (jr < kRowStep) && (j < N);
+    const double w1 = (row_ok && !mv) ? (pre ? ((GD*)f.Ht)[(size_t)j * kSP] : htl[j - r0]) : 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
-      const bool iok = i < f.T;
-      if (row_ok && iok) {
-        const R2 dv = src[q * 64 + lane];
+      if (row_ok && i < T) {
         double W;
-        if (!f.mv) {
-          W = w1 * f.cp[i].v;
+        if (!mv) {
+          W = w1 * vv[q];
         } else {
           W = 0.0;
           for (int s = 0; s < f.S; ++s) W += f.Ht[j * kSP + s] * f.theta[s] * f.F64[i * kSP + s];
         }
-        aA[q] += W * (double)dv.x;
-        aB[q] += W * (double)dv.y;
+        aA[q] += W * (double)dx[q];
+        aB[q] += W * (double)dy[q];
       }
     }
   }
@@ -718,19 +832,17 @@ __global__ void __launch_bounds__(kBlock) k_cells_bwd(const FitDev* fits, const 
     }
   }
   __syncthreads();
-  // column totals (fixed order over the 4 waves), times the chain factors
+  // column totals (fixed order over the waves), times the chain factors
   if (threadIdx.x < 64) {
-    const int c16 = threadIdx.x & 15, q = threadIdx.x >> 4;  // q: response parameter
-    const int i = ct * kColTile + c16;
-    double v = 0.0;
-    if (i < f.T && q < f.nresp) {
-      const double A = ((colA[0][c16] + colA[1][c16]) + colA[2][c16]) + colA[3][c16];
-      const double B = ((colB[0][c16] + colB[1][c16]) + colB[2][c16]) + colB[3][c16];
-      const ColPar& c = f.cp[i];
-      v = A * c.J[0][q] + B * c.J[1][q];
+    double A = colA[0][c16], B = colB[0][c16];
+#pragma unroll
+    for (int w = 1; w < kBwdWaves; ++w) {
+      A += colA[w][c16];
+      B += colB[w][c16];
     }
+    double v = (icol < T && qp < f.nresp) ? A * J0 + B * J1 : 0.0;
     v = sum16(v);
-    if (c16 == 0) f.bwdpart[(size_t)bl * 4 + q] = v;
+    if (c16 == 0) f.bwdpart[(size_t)bl * 4 + qp] = v;
   }
 }
 
@@ -858,6 +970,8 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
   const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), grow(L.max_rowblk, n);
   const dim3 gred((L.max_NS + kBlock - 1) / kBlock, n), bf(kFwdWaves * 64);
   const bool f32 = L.prec == kF32, gauss = L.kind == kGauss;
+  // batches form a single histogram's pile-up adjoint once per fit
+  const int pre = n >= kPreAdjFits ? 1 : 0;
   switch (stage) {
     case 0:
       hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st,
@@ -879,13 +993,15 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
     case 4:
       if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
       break;
-    case 5:  // the single-histogram adjoint is formed inside k_cells_bwd
+    case 5:  // a single histogram's adjoint: here for batches, else inside k_cells_bwd
       if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
+      if (with_grad && pre)
+        hipLaunchKernelGGL(k_adjoint1, dim3((L.max_rowblk + 3) / 4, n), blk, 0, st, d_fits, d_active);
       break;
     case 6:
       if (!with_grad) break;
-      if (f32) hipLaunchKernelGGL((k_cells_bwd<float>), gb, blk, 0, st, d_fits, d_active);
-      else hipLaunchKernelGGL((k_cells_bwd<double>), gb, blk, 0, st, d_fits, d_active);
+      if (f32) hipLaunchKernelGGL((k_cells_bwd<float>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      else hipLaunchKernelGGL((k_cells_bwd<double>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);

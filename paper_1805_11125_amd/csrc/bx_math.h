@@ -33,6 +33,12 @@ constexpr double kSupportB = 75.0;   // FP64 cells: tails beyond k*phi = B (or z
 constexpr double kSupportB32 = 32.0; // FP32 cells: tails beyond B are < 1e-14 of the column
 constexpr float kTemmeMinK = 12.f;   // FP32: uniform expansion from this shape on
 constexpr float kTemmeTailCut = 40.f;  // FP32 uniform expansion: tails beyond k*phi = 40 are set to 0
+// FP32 uniform expansion: |t| >= 1.25 lies beyond the tail cut from this shape
+// on (k phi(-1.25) = 0.5365 k > 40), so the series of phi below 1.25 suffices
+constexpr float kTemmeFarK = 75.f;
+// FP32 uniform expansion: shapes from which |eta| <= 0.5 inside the tail cut,
+// where h_0..h_3 of low degree keep the truncation below 1e-7 of the tail
+constexpr float kTemmeLowDegK = 320.f;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kLnSqrtTwoPi = 0.91893853320467274178032973640562;
 
@@ -195,18 +201,34 @@ BX_HD float rcp(float x) {
 }
 BX_HD double rcp(double x) { return 1.0 / x; }
 
+// Square root: the FP32 hardware square root (1 ulp) on the GPU.
+BX_HD float sqrt_hw(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+BX_HD double sqrt_hw(double x) { return sqrt(x); }
+
+// phi(t) = e^t - 1 - t from t^2 (1/2! + t/3! + ... + t^10/12!): relative
+// truncation error below 4e-9 for |t| < 1.25.
+template <class R>
+BX_HD R phi_series(R t) {
+  R s = (R)(1.0 / 479001600.0);
+  const R c[10] = {(R)(1.0 / 39916800.0), (R)(1.0 / 3628800.0), (R)(1.0 / 362880.0),
+                   (R)(1.0 / 40320.0),    (R)(1.0 / 5040.0),    (R)(1.0 / 720.0),
+                   (R)(1.0 / 120.0),      (R)(1.0 / 24.0),      (R)(1.0 / 6.0),
+                   (R)(0.5)};
+  for (int i = 0; i < 10; ++i) s = s * t + c[i];
+  return s * t * t;
+}
+
 // phi(t) = e^t - 1 - t (accurate for small t); also returns e^t - 1.
 template <class R>
 BX_HD R phi_t(R t, R* um1) {
   if (fabs(t) < (R)0.5) {
-    // t^2 (1/2! + t/3! + ... ) up to t^12
-    R s = (R)(1.0 / 479001600.0);
-    const R c[10] = {(R)(1.0 / 39916800.0), (R)(1.0 / 3628800.0), (R)(1.0 / 362880.0),
-                     (R)(1.0 / 40320.0),    (R)(1.0 / 5040.0),    (R)(1.0 / 720.0),
-                     (R)(1.0 / 120.0),      (R)(1.0 / 24.0),      (R)(1.0 / 6.0),
-                     (R)(0.5)};
-    for (int i = 0; i < 10; ++i) s = s * t + c[i];
-    const R ph = s * t * t;
+    const R ph = phi_series(t);
     *um1 = ph + t;
     return ph;
   }
@@ -267,12 +289,36 @@ BX_HD R horner(const double* c, int deg, R x) {
   return s;
 }
 
+// Truncated sum h0 + ik (h1 + ik (h2 + ik h3)) and its k-part
+// ik^2 (h1 + ik (2 h2 + 3 ik h3)) at |eta| < 1, h_n of degrees N0..N3.
+template <int N0, int N1, int N2, int N3, class R>
+BX_HD void temme_h(R eta, R ik, R* Hs, R* dH) {
+  const R h0 = horner<R>(bx_temme_h0, N0, eta);
+  const R h1 = horner<R>(bx_temme_h1, N1, eta);
+  const R h2 = horner<R>(bx_temme_h2, N2, eta);
+  const R h3 = horner<R>(bx_temme_h3, N3, eta);
+  *Hs = h0 + ik * (h1 + ik * (h2 + ik * h3));
+  *dH = ik * ik * (h1 + ik * ((R)2 * h2 + (R)3 * ik * h3));
+}
+
+// FP32 only (shapes k >= kTemmeMinK).
 template <class R, bool D>
 BX_HD EdgeVal<R> gg_edge_temme(R t, const GGCol<R>& c) {
-  R u;
-  const R ph = phi_t(t, &u);
   const bool up = t > (R)0;
-  const R eta = up ? sqrt((R)2 * ph) : -sqrt((R)2 * ph);
+  EdgeVal<R> o;
+  o.v = up ? (R)-0.0 : (R)0.0;  // beyond the tail cut: the side's zero
+  o.d1 = o.d2 = (R)0;
+  // phi and u = e^t - 1; |t| >= 1.25 is beyond the cut for k >= kTemmeFarK
+  R ph, u;
+  if (fabs(t) < (R)1.25) {
+    ph = phi_series(t);
+    u = ph + t;
+  } else {
+    if (c.k >= (R)kTemmeFarK) return o;
+    u = expm1(t);
+    ph = u - t;
+  }
+  const R eta = up ? sqrt_hw((R)2 * ph) : -sqrt_hw((R)2 * ph);
   const R kph = c.k * ph;
   // The two terms of the tail cancel far out, and beyond k*phi ~ 87 both are
   // FP32 subnormals, so their sum can even come out negative (which would put
@@ -280,41 +326,32 @@ BX_HD EdgeVal<R> gg_edge_temme(R t, const GGCol<R>& c) {
   // support cut of every column, the tail (< e^-40) is taken as the side's
   // zero and nothing else is evaluated; for k >= 2 kTemmeTailCut this also
   // leaves |eta| < 1 as the only branch inside the cut.
-  const bool far = kph > (R)kTemmeTailCut;
-  EdgeVal<R> o;
-  if (far) {
-    o.v = up ? (R)-0.0 : (R)0.0;
-    if (D) o.d1 = o.d2 = (R)0;
-    return o;
-  }
+  if (kph > (R)kTemmeTailCut) return o;
   const R E = exp(-kph);
   const R w = fabs(eta) * c.skh;
-  R h0, h1, h2, h3;
-  if (fabs(eta) < (R)1) {
-    constexpr bool f32 = sizeof(R) == 4;
-    h0 = horner<R>(bx_temme_h0, f32 ? 13 : BX_TEMME_H0_DEG, eta);
-    h1 = horner<R>(bx_temme_h1, f32 ? 12 : BX_TEMME_H1_DEG, eta);
-    h2 = horner<R>(bx_temme_h2, f32 ? 10 : BX_TEMME_H2_DEG, eta);
-    h3 = horner<R>(bx_temme_h3, f32 ? 8 : BX_TEMME_H3_DEG, eta);
-  } else {
-    const R ie = (R)1 / eta, ie2 = ie * ie, iu = (R)1 / u, iu2 = iu * iu;
-    const R mu = (R)1 + u;
-    h0 = iu - ie;
-    h1 = ie2 * ie - mu * iu2 * iu - (R)(1.0 / 12) * ie;
-    h2 = (R)-3 * ie2 * ie2 * ie + mu * ((R)2 * mu + (R)1) * iu2 * iu2 * iu +
-         (R)(1.0 / 12) * ie2 * ie - (R)bx_temme_dh1_0 * ie;
-    h3 = (R)15 * ie2 * ie2 * ie2 * ie - mu * ((R)6 * mu * mu + (R)8 * mu + (R)1) * iu2 * iu2 * iu2 * iu -
-         (R)0.25 * ie2 * ie2 * ie + (R)bx_temme_dh1_0 * ie2 * ie - (R)bx_temme_dh2_0 * ie;
-  }
   const R ik = c.ik;
-  const R Hs = h0 + ik * (h1 + ik * (h2 + ik * h3));
+  R Hs, dH;
+  if (fabs(eta) < (R)1) {
+    if (c.k >= (R)kTemmeLowDegK) temme_h<6, 3, 0, 0>(eta, ik, &Hs, &dH);
+    else temme_h<10, 8, 5, 3>(eta, ik, &Hs, &dH);
+  } else {
+    const R ie = rcp(eta), ie2 = ie * ie, iu = rcp(u), iu2 = iu * iu;
+    const R mu = (R)1 + u;
+    const R h0 = iu - ie;
+    const R h1 = ie2 * ie - mu * iu2 * iu - (R)(1.0 / 12) * ie;
+    const R h2 = (R)-3 * ie2 * ie2 * ie + mu * ((R)2 * mu + (R)1) * iu2 * iu2 * iu +
+                 (R)(1.0 / 12) * ie2 * ie - (R)bx_temme_dh1_0 * ie;
+    const R h3 = (R)15 * ie2 * ie2 * ie2 * ie - mu * ((R)6 * mu * mu + (R)8 * mu + (R)1) * iu2 * iu2 * iu2 * iu -
+                 (R)0.25 * ie2 * ie2 * ie + (R)bx_temme_dh1_0 * ie2 * ie - (R)bx_temme_dh2_0 * ie;
+    Hs = h0 + ik * (h1 + ik * (h2 + ik * h3));
+    dH = ik * ik * (h1 + ik * ((R)2 * h2 + (R)3 * ik * h3));
+  }
   const R Rt = E * c.cR * Hs;
   R T = (R)0.5 * erfc(w) + (up ? Rt : -Rt);
   if (!(T > (R)0)) T = (R)0;  // rounding below zero: the side's zero
   o.v = up ? -T : T;
   if (D) {
     const R g = c.k * c.cR * E;  // y^k e^-y / Gamma(k)
-    const R dH = ik * ik * (h1 + ik * ((R)2 * h2 + (R)3 * ik * h3));
     const R dQk_eta = E * (-eta * c.ce + c.cR * Hs * ((R)-0.5 * eta * eta - (R)0.5 * ik - c.dlngs) -
                            c.cR * dH);
     o.d1 = -(dQk_eta + g * ik);  // dF/dk at fixed y
