@@ -111,5 +111,6 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
                  bool with_grad, hipStream_t st);
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
+void launch_mark(double* d_mark, double v, hipStream_t st);
 
 }  // namespace bx

@@ -495,14 +495,6 @@ static bx_status enqueue_eval(bx_model* m, bool grad, bool host, hipStream_t st)
 }
 
 namespace bx {
-// Writes back and evicts the CPU cache lines of n doubles at p (then a full
-// fence, so that later loads come from memory and earlier stores have left).
-static void flush_lines(const double* p, int n) {
-  const uintptr_t a = (uintptr_t)p & ~(uintptr_t)63, e = (uintptr_t)(p + n);
-  for (uintptr_t l = a; l < e; l += 64) _mm_clflush((const void*)l);
-  _mm_mfence();
-}
-
 // Evaluate at host theta; fills nll (and grad).  Shared with the plain fitter.
 bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad) {
   const int P = m->h.P;

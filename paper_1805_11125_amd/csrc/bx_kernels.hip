@@ -943,6 +943,19 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
   final_sums<1024>(fits[active ? active[blockIdx.y] : blockIdx.y], with_grad);
 }
 
+// Completion mark of a batched step: launched after its last kernel, it
+// writes v into pinned host memory once everything before it on the stream
+// is done and its results are visible to the host.
+__global__ void k_mark(double* mark, double v) {
+  __threadfence_system();
+  *mark = v;
+  __threadfence_system();
+}
+
+void launch_mark(double* d_mark, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark, dim3(1), dim3(1), 0, st, d_mark, v);
+}
+
 // ---------------------------------------------------------------------------
 template <class R, int KIND, bool D>
 static void launch_fwd_d(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {

@@ -2,6 +2,8 @@
 // and the fit server.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
+#include <stdint.h>
 
 #include <atomic>
 #include <string>
@@ -41,6 +43,17 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
 // NLL, FP64 cells ~1e-15 (the minimiser accepts changes within it when the
 // gradient shows progress).
 inline double nll_noise(const HostModel& h) { return h.prec == kF32 ? 1e-9 : 1e-13; }
+
+// Writes back and evicts the CPU cache lines of n doubles at p, then a full
+// fence, so that later loads come from memory and earlier stores have left.
+// Pinned buffers shared with the kernels need it: device writes do not
+// reliably invalidate a copy of the line the CPU already holds (one fetched
+// by its prefetcher while the results were in flight).
+inline void flush_lines(const double* p, int n) {
+  const uintptr_t a = (uintptr_t)p & ~(uintptr_t)63, e = (uintptr_t)(p + n);
+  for (uintptr_t l = a; l < e; l += 64) _mm_clflush((const void*)l);
+  _mm_mfence();
+}
 bx_status set_host_data(HostModel* h, const bx_data* x);
 // The scalars, per-model constants and tiles of h, without its arrays.
 HostModel shape_only(const HostModel& h);

@@ -94,9 +94,9 @@ static int64_t now_ns() {
       .count();
 }
 
-constexpr int kThetaStride = 32;
-constexpr int kGroups = 16;  // launch groups: 2 kinds x 2 precisions x 4 forward tile widths
-constexpr int kOutStride = 34;
+constexpr int kThetaStride = 40;  // theta[P] and the step number, 5 cache lines
+constexpr int kGroups = 16;       // launch groups: 2 kinds x 2 precisions x 4 forward tile widths
+constexpr int kOutStride = 40;    // nll, grad[P], flags, completion mark
 
 struct Req {
   uint64_t ticket = 0;
@@ -125,10 +125,19 @@ struct bx_server {
   bool own_stream = false;
   FitDev* d_fits = nullptr;       // [max_slots]
   int* d_active = nullptr;        // [kGroups][max_slots] active lists, one region per launch group
-  double* d_theta = nullptr;      // [max_slots][32]
-  double* d_out = nullptr;        // [max_slots][34]
-  double* h_theta = nullptr;      // pinned
-  double* h_out = nullptr;        // pinned
+  double* d_theta = nullptr;      // [max_slots][kThetaStride] device copies of theta
+  double* d_out = nullptr;        // [max_slots][kOutStride]
+  // pinned, coherent: theta and the step number written by the host and read
+  // by k_colparams; the results written by k_final; the step's completion
+  // mark written by k_mark (each in its own allocation, so host-written and
+  // device-written values never share a cache line)
+  double* h_theta = nullptr;
+  double* h_out = nullptr;
+  double* h_mark = nullptr;
+  double* dh_theta = nullptr;     // their device addresses
+  double* dh_out = nullptr;
+  double* dh_mark = nullptr;
+  double seq = 0.0;               // steps so far (completion marks)
   int* h_active = nullptr;        // pinned
   std::vector<int> free_slots;
   std::deque<std::shared_ptr<Req>> queue;
@@ -167,6 +176,8 @@ static void admit(bx_server* s) {
     }
     df.dev.theta = s->d_theta + (size_t)r->slot * kThetaStride;
     df.dev.out = s->d_out + (size_t)r->slot * kOutStride;
+    df.dev.theta_src = s->dh_theta + (size_t)r->slot * kThetaStride;
+    df.dev.out_host = s->dh_out + (size_t)r->slot * kOutStride;
     r->shape = shape_of(df.dev);
     int cgl = 0;
     while ((1 << cgl) < r->shape.CG) ++cgl;
@@ -188,19 +199,20 @@ static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
   --s->pending;
 }
 
-static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
-  // stage every active fit's next point
+// One step: every active fit's next point in one batched launch per group.
+// The kernels read theta from pinned memory and write the results there; the
+// host spins on the step's completion mark, reading it (and then the
+// results) past its own cache.  Returns false when the launch failed.
+static bool step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
+  const double seq = (s->seq += 1.0);
+  // stage every active fit's next point (with the step number after it)
   s->pool->run((int)act.size(), [&](int k) {
     auto& r = act[k];
-    double x[32];
-    r->opt->next(x);
-    memcpy(s->h_theta + (size_t)r->slot * kThetaStride, x, sizeof(double) * r->h.P);
+    double* th = s->h_theta + (size_t)r->slot * kThetaStride;
+    r->opt->next(th);
+    th[r->h.P] = seq;
+    flush_lines(th, r->h.P + 1);
   });
-  // contiguous ranges are small; copy the whole staged array once
-  int max_slot = 0;
-  for (auto& r : act) max_slot = std::max(max_slot, r->slot + 1);
-  (void)hipMemcpyAsync(s->d_theta, s->h_theta, sizeof(double) * kThetaStride * max_slot, hipMemcpyHostToDevice,
-                       s->stream);
   // one batched launch per group of (kind, precision, forward tiles per wave)
   for (int grp = 0; grp < kGroups; ++grp) {
     int n = 0;
@@ -226,16 +238,29 @@ static void step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
     (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
     launch_eval(s->d_fits, d_list, n, L, true, s->stream);
   }
-  (void)hipMemcpyAsync(s->h_out, s->d_out, sizeof(double) * kOutStride * max_slot, hipMemcpyDeviceToHost, s->stream);
-  (void)hipStreamSynchronize(s->stream);
+  launch_mark(s->dh_mark, seq, s->stream);
+  const volatile double* mark = s->h_mark;
+  for (unsigned it = 1;; ++it) {
+    flush_lines(s->h_mark, 1);
+    if (*mark == seq) break;
+    if ((it & 1023u) == 0u) {
+      const hipError_t q = hipStreamQuery(s->stream);
+      flush_lines(s->h_mark, 1);
+      if (*mark == seq) break;
+      if (q != hipErrorNotReady) return false;  // failed, or finished without its mark
+    }
+    __builtin_ia32_pause();
+  }
   s->pool->run((int)act.size(), [&](int k) {
     auto& r = act[k];
     const double* o = s->h_out + (size_t)r->slot * kOutStride;
     const int P = r->h.P;
+    flush_lines(o, 2 + P);
     const int fl = (int)o[1 + P];
     const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
     r->opt->feed(bad ? INFINITY : o[0], o + 1);
   });
+  return true;
 }
 
 static void worker_loop(bx_server* s) {
@@ -250,8 +275,17 @@ static void worker_loop(bx_server* s) {
     }
     std::vector<std::shared_ptr<Req>> act = s->active;
     lk.unlock();
-    step(s, act);
+    const bool ok = step(s, act);
     lk.lock();
+    if (!ok) {  // the device failed: every active fit ends as failed
+      for (auto& r : s->active) {
+        r->res.status = BX_FAILED;
+        retire(s, r);
+      }
+      s->active.clear();
+      s->cv_done.notify_all();
+      continue;
+    }
     std::vector<std::shared_ptr<Req>> keep;
     for (auto& r : s->active) {
       if (r->opt->done()) {
@@ -302,14 +336,24 @@ bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip
   if (hipMalloc(&s->d_fits, sizeof(FitDev) * M) != hipSuccess || hipMalloc(&s->d_active, sizeof(int) * kGroups * M) != hipSuccess ||
       hipMalloc(&s->d_theta, sizeof(double) * kThetaStride * M) != hipSuccess ||
       hipMalloc(&s->d_out, sizeof(double) * kOutStride * M) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_theta, sizeof(double) * kThetaStride * M, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutStride * M, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_active, sizeof(int) * kGroups * M, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&s->h_theta, sizeof(double) * kThetaStride * M, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutStride * M, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_mark, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_active, sizeof(int) * kGroups * M, hipHostMallocDefault) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->dh_theta, s->h_theta, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->dh_out, s->h_out, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->dh_mark, s->h_mark, 0) != hipSuccess) {
     bx_server_destroy(s);
     set_error("server allocation failed");
     return BX_E_NOMEM;
   }
   memset(s->h_theta, 0, sizeof(double) * kThetaStride * M);
+  memset(s->h_out, 0, sizeof(double) * kOutStride * M);
+  memset(s->h_mark, 0, 4096);
+  // no dirty host line may later be written back over device results
+  flush_lines(s->h_theta, kThetaStride * (int)M);
+  flush_lines(s->h_out, kOutStride * (int)M);
+  flush_lines(s->h_mark, 512);
   for (int i = (int)M - 1; i >= 0; --i) s->free_slots.push_back(i);
   const unsigned hc = std::thread::hardware_concurrency();
   s->pool.reset(new StepPool((int)std::min(7u, hc > 1 ? hc - 1 : 0u)));
@@ -336,6 +380,7 @@ bx_status bx_server_destroy(bx_server* s) {
   if (s->d_out) (void)hipFree(s->d_out);
   if (s->h_theta) (void)hipHostFree(s->h_theta);
   if (s->h_out) (void)hipHostFree(s->h_out);
+  if (s->h_mark) (void)hipHostFree(s->h_mark);
   if (s->h_active) (void)hipHostFree(s->h_active);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
