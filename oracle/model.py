@@ -20,6 +20,7 @@ from scipy import special
 
 GAUSS = "gauss"
 GG = "gg"
+TABLE = "table"
 
 
 class DomainError(ValueError):
@@ -54,6 +55,21 @@ def gg_solve_shape(tau, p):
     return np.exp(0.5 * (lo + hi))
 
 
+def table_cell(desc, resp):
+    """Tabulated response: the grid cell [lam_g, lam_g+1] holding the table
+    coordinate lam = resp[0] and the weight w of lam_g+1 in the linear
+    interpolation.  One grid point: no coordinate (g = 0, w = 0)."""
+    grid = np.asarray(desc.table_grid, np.float64)
+    if grid.size == 1:
+        return 0, 0.0
+    lam = float(resp[0])
+    if not (grid[0] <= lam <= grid[-1]):
+        raise DomainError("table coordinate outside the grid")
+    g = int(np.searchsorted(grid, lam, side="right")) - 1
+    g = min(max(g, 0), grid.size - 2)
+    return g, (lam - grid[g]) / (grid[g + 1] - grid[g])
+
+
 def column_params(desc, resp):
     """Per true-bin column parameters.
 
@@ -68,6 +84,9 @@ def column_params(desc, resp):
     resp = np.asarray(resp, np.float64)
     if not np.all(np.isfinite(resp)):
         raise DomainError("non-finite response parameter")
+    if desc.kind == TABLE:
+        g, w = table_cell(desc, resp)
+        return SimpleNamespace(kind=TABLE, E=E, g=g, w=w)
     if desc.kind == GAUSS:
         a, b = resp
         var = a * E + b * E * E
@@ -125,7 +144,14 @@ def cells_from_tails(tail, lower):
 
 
 def response_matrix(desc, cp):
-    """Dense response matrix R [N, T] (Eq. 1 on the true x reco grid)."""
+    """Dense response matrix R [N, T] (Eq. 1 on the true x reco grid).
+    Tabulated response: the linear interpolation (1 - w) R_g + w R_g+1 of the
+    supplied matrices (the Monte Carlo alternative to Eq. 1's analytic R)."""
+    if cp.kind == TABLE:
+        Rt = np.asarray(desc.table_R, np.float64)
+        if Rt.shape[0] == 1:
+            return Rt[0].copy()
+        return (1.0 - cp.w) * Rt[cp.g] + cp.w * Rt[cp.g + 1]
     tail, lower = edge_tails(desc, cp)
     return cells_from_tails(tail, lower)
 
@@ -198,6 +224,12 @@ def _gg_chain(cp, resp, parts):
 
 
 def response_param_derivs(desc, cp, resp):
+    if cp.kind == TABLE:  # R is affine in lam inside a grid cell
+        Rt = np.asarray(desc.table_R, np.float64)
+        if Rt.shape[0] == 1:
+            return []
+        grid = np.asarray(desc.table_grid, np.float64)
+        return [(Rt[cp.g + 1] - Rt[cp.g]) / (grid[cp.g + 1] - grid[cp.g])]
     d = response_derivs(desc, cp)
     if cp.kind == GAUSS:
         return d

@@ -28,6 +28,7 @@ ME = 0.51099895  # electron mass [MeV]
 
 GAUSS = "gauss"
 GG = "gg"
+TABLE = "table"
 
 
 # ---------------------------------------------------------------------------
@@ -53,6 +54,10 @@ class ModelDesc:
     rad_tmpl: Optional[np.ndarray] = None  # [S, n_rad]
     rad_win: tuple = (0, 0)                # reco window feeding the radial term
     ps_tmpl: Optional[np.ndarray] = None   # [S, n_ps]
+    # tabulated response (kind "table"): matrices R_g [G, N, T] at the grid
+    # points lam_g of one response coordinate, interpolated linearly in lam
+    table_grid: Optional[np.ndarray] = None  # [G] increasing
+    table_R: Optional[np.ndarray] = None     # [G, N, T]
     # parameters
     theta_true: Optional[np.ndarray] = None
     float_mask: Optional[np.ndarray] = None
@@ -72,6 +77,8 @@ class ModelDesc:
 
     @property
     def n_resp(self):
+        if self.kind == TABLE:
+            return 1 if len(self.table_grid) > 1 else 0
         return 2 if self.kind == GAUSS else 4
 
     @property
@@ -237,6 +244,56 @@ def config2(pu_g: Optional[np.ndarray] = None, catalogue: bool = False) -> Model
                      pu_g=None if pu_g is None else np.asarray(pu_g, np.float64),
                      win=(0, 900), theta_true=theta, float_mask=mask,
                      param_names=[f"r_{n}" for n in names] + ["L", "v0", "v1", "v2"])
+
+
+# tabulated (Monte Carlo) response ---------------------------------------------
+def mc_response_tables(true_edges, reco_edges, quench, grid_L, n_mc, seed, res=(4.0, 1.1, 4e-4)):
+    """Monte Carlo response matrices R_g [G, N, T]: for each light yield L_g
+    and true bin i, n_mc events with energies uniform in the bin, light
+    m = L_g Q_i E, a gamma-distributed charge of mean m and variance
+    v0 + v1 m + v2 m^2, histogrammed over the reco bins and divided by n_mc
+    (charges outside the reco range are lost).  The stand-in for a detector
+    simulation's response tables; seeded."""
+    rng = np.random.default_rng(seed)
+    te = np.asarray(true_edges, np.float64)
+    re = np.asarray(reco_edges, np.float64)
+    T, N = len(te) - 1, len(re) - 1
+    q = np.asarray(quench, np.float64)
+    v0, v1, v2 = res
+    out = np.zeros((len(grid_L), N, T))
+    for g, L in enumerate(grid_L):
+        E = te[:-1, None] + (te[1:] - te[:-1])[:, None] * rng.random((T, n_mc))
+        m = L * q[:, None] * E
+        s2 = v0 + v1 * m + v2 * m * m
+        x = rng.gamma(m * m / s2, s2 / m)
+        j = np.searchsorted(re, x, side="right") - 1
+        ok = (j >= 0) & (j < N)
+        col = np.broadcast_to(np.arange(T)[:, None], j.shape)
+        np.add.at(out[g], (j[ok], col[ok]), 1.0)
+        out[g] /= n_mc
+    return out
+
+
+def table_config(grid_L=(480.0, 490.0, 500.0, 510.0, 520.0), n_mc=4000, seed=17,
+                 true_step=0.001, reco_step=1.0, pu_g: Optional[np.ndarray] = None) -> ModelDesc:
+    """The config-2 species and binning (or coarser grids) with a tabulated
+    response: Monte Carlo matrices at the light yields grid_L, the fit
+    coordinate being the light yield.  theta = rates, L (then the pile-up
+    fraction when it floats)."""
+    te = true_step * np.arange(int(round(3.0 / true_step)) + 1)
+    re = reco_step * np.arange(int(round(900 / reco_step)) + 1)
+    names, spectra = _c2_shapes(te)
+    q = quench_table(te)
+    R = mc_response_tables(te, re, q, grid_L, n_mc, seed)
+    rates = np.array(_C2_FRAC) * C2_EVENTS
+    grid = np.asarray(grid_L, np.float64)
+    theta = np.concatenate([rates, [0.5 * (grid[len(grid) // 2 - 1] + grid[len(grid) // 2])] if len(grid) > 1 else []])
+    return ModelDesc(kind=TABLE, true_edges=te, reco_edges=re, spectra=spectra, species=names,
+                     pu_frac=C2_PU_FRAC if pu_g is not None else 0.0,
+                     pu_g=None if pu_g is None else np.asarray(pu_g, np.float64),
+                     win=(0, len(re) - 1), table_grid=grid, table_R=R, theta_true=theta,
+                     float_mask=np.ones(len(theta), dtype=bool),
+                     param_names=[f"r_{n}" for n in names] + (["L"] if len(grid) > 1 else []))
 
 
 # multivariate templates ------------------------------------------------------

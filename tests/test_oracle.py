@@ -562,3 +562,122 @@ def test_pu_float_outside_unit_interval_is_a_domain_error():
     th[-1] = 1.5
     with pytest.raises(oracle.DomainError):
         om.forward(d, th)
+
+
+# ---------------------------------------------------------------------------
+# tabulated response (Monte Carlo matrices interpolated in one coordinate)
+# ---------------------------------------------------------------------------
+def tiny_table(G=3, T=6, N=9, S=2, seed=3, pu=False):
+    rng = np.random.default_rng(seed)
+    te = np.linspace(0.1, 1.3, T + 1)
+    re = np.linspace(0.0, 1.6, N + 1)
+    F = rng.random((S, T)) + 0.1
+    F /= F.sum(1, keepdims=True)
+    R = rng.random((G, N, T))
+    R /= R.sum(1, keepdims=True) * 1.05  # columns lose 1/21 of their mass
+    grid = np.cumsum(rng.uniform(0.5, 1.5, G)) + 2.0
+    lam = [0.5 * (grid[0] + grid[1])] if G > 1 else []
+    th = np.concatenate([rng.uniform(50, 200, S), lam, [0.03] if pu else []])
+    g = np.array([0.6, 0.3, 0.1]) if pu else None
+    return synth.ModelDesc(kind="table", true_edges=te, reco_edges=re, spectra=F,
+                           species=[f"s{i}" for i in range(S)], win=(0, N), theta_true=th,
+                           table_grid=grid, table_R=R, pu_g=g, pu_float=pu)
+
+
+def test_table_at_grid_point_is_that_matrix():
+    # at lam = lam_g the model is the single-matrix model of R_g, bit for bit
+    # in M and to rounding in the NLL (a one-point table has no coordinate)
+    d = tiny_table()
+    x = poisson_data(d, d.theta_true)
+    for g in range(3):
+        th = d.theta_true.copy()
+        th[d.S] = d.table_grid[g]
+        one = d.copy()
+        one.table_grid = d.table_grid[g:g + 1]
+        one.table_R = d.table_R[g:g + 1]
+        assert one.P == d.S
+        assert np.array_equal(om.forward(d, th).M, om.forward(one, th[: d.S]).M)
+        assert om.nll(d, x, th) == pytest.approx(om.nll(one, x, th[: d.S]), rel=1e-15)
+
+
+def test_table_of_analytic_matrices_reproduces_analytic_model():
+    # tabulate the generalized-gamma response at light yields L_g; at each
+    # L_g the table model must give the analytic model's NLL (two independent
+    # routes through the oracle: interpolated table vs Eq. 1 cells)
+    a = tiny_gg(T=7, N=9)
+    x = poisson_data(a, a.theta_true)
+    grid = np.array([480.0, 500.0, 515.0])
+    R = []
+    for L in grid:
+        resp = a.theta_true[a.S:].copy()
+        resp[0] = L
+        R.append(om.response_matrix(a, om.column_params(a, resp)))
+    t = synth.ModelDesc(kind="table", true_edges=a.true_edges, reco_edges=a.reco_edges,
+                        spectra=a.spectra, species=a.species, win=a.win,
+                        table_grid=grid, table_R=np.array(R))
+    for L in grid:
+        tha = a.theta_true.copy()
+        tha[a.S] = L
+        tht = np.concatenate([a.theta_true[: a.S], [L]])
+        assert om.nll(t, x, tht) == pytest.approx(om.nll(a, x, tha), rel=1e-13)
+
+
+def test_table_expectations_affine_inside_a_cell():
+    d = tiny_table(G=4)
+    th = d.theta_true.copy()
+    lo, hi = d.table_grid[1], d.table_grid[2]
+    ms = []
+    for lam in (lo, 0.25 * lo + 0.75 * hi, hi):
+        th[d.S] = lam
+        ms.append(om.forward(d, th).M)
+    assert np.allclose(ms[1], 0.25 * ms[0] + 0.75 * ms[2], rtol=1e-14, atol=0)
+
+
+def test_table_gradient_vs_richardson_and_slope_at_grid_point():
+    d = tiny_table(G=4, pu=True)
+    x = poisson_data(d, d.theta_true)
+    th = d.theta_true.copy()
+    th[d.S] = 0.3 * d.table_grid[1] + 0.7 * d.table_grid[2]
+    _, g = om.nll_grad(d, x, th)
+    for q in range(d.P):
+        def f(v, q=q):
+            t = th.copy()
+            t[q] = v
+            return om.nll(d, x, t)
+        h = 1e-3 * abs(th[q]) if q != d.S else 1e-3 * (d.table_grid[2] - d.table_grid[1])
+        assert g[q] == pytest.approx(_richardson(f, th[q], h), rel=1e-7, abs=1e-7)
+    # at an interior grid point the coordinate takes the slope of the cell above
+    th[d.S] = d.table_grid[2]
+    _, g2 = om.nll_grad(d, x, th)
+    t = th.copy()
+    h = 1e-6 * (d.table_grid[3] - d.table_grid[2])
+    t[d.S] += h
+    assert g2[d.S] == pytest.approx((om.nll(d, x, t) - om.nll(d, x, th)) / h, rel=1e-5)
+
+
+def test_table_domain():
+    d = tiny_table(G=3)
+    x = poisson_data(d, d.theta_true)
+    for lam in (d.table_grid[0] - 1e-9, d.table_grid[-1] + 1e-9, np.inf):
+        th = d.theta_true.copy()
+        th[d.S] = lam
+        with pytest.raises(om.DomainError):
+            om.nll(d, x, th)
+    th = d.theta_true.copy()
+    th[d.S] = d.table_grid[-1]  # the top of the grid is inside
+    assert np.isfinite(om.nll(d, x, th))
+
+
+def test_mc_tables_are_column_probabilities():
+    # each column of a Monte Carlo table is a histogram of n_mc events over
+    # the reco bins: multiples of 1/n_mc summing to at most 1
+    te = np.linspace(0.0, 1.0, 11)
+    re = np.linspace(0.0, 600.0, 31)
+    R = synth.mc_response_tables(te, re, np.ones(10), [480.0, 520.0], 500, 5)
+    assert R.shape == (2, 30, 10)
+    assert np.allclose(R * 500, np.round(R * 500))
+    assert np.all(R.sum(axis=1) <= 1.0 + 1e-12)
+    # the light yield moves the mean charge: column means scale with L
+    xc = 0.5 * (re[:-1] + re[1:])
+    m = (R * xc[None, :, None]).sum(1) / R.sum(1)
+    assert np.all(m[1, 2:8] > m[0, 2:8])
