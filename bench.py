@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=512,
                     help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-table", dest="table", action="store_false",
+                    help="skip the tabulated-response leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -134,6 +136,32 @@ def toy_study(bx, synth, n_toys, n_plain):
             "median_iters": float(np.median([r.n_iter for r in res])),
             "median_evals": float(np.median([r.n_eval for r in res])),
             "batched_equals_plain_bitwise": bool(same), "edm_tol": 1e-8}
+
+
+def table_leg(bx, synth, x, steps, warmup):
+    """Tabulated (Monte Carlo) response on the config-2 grid: five 900 x 3000
+    tables at light yields 480-520 p.e./MeV, the light yield the fitted
+    coordinate.  The build forms M_g = R_g F^T once (FP64 MFMA); each
+    evaluation interpolates M and runs the row terms."""
+    d = synth.table_config()
+    t0 = time.perf_counter()
+    m = bx.Model(d, x, precision=bx.BX_PREC_F64)
+    build_s = time.perf_counter() - t0
+    th = d.theta_true.copy()
+    th[d.S] = 503.7
+    for _ in range(warmup):
+        m.nll_grad(th)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        m.nll_grad(th)
+    evals = steps / (time.perf_counter() - t1)
+    st = m.stage_times(th, reps=200)
+    m.close()
+    G, N, T = d.table_R.shape
+    return {"workload": f"{G} tables {N} x {T}, {d.S} species, FP64", "evals_per_s": evals,
+            "build_s": build_s, "build_gemm_flop": 2 * G * N * T * 16, "build_gemm_bytes": G * N * T * 8,
+            "stage_ms": {("table" if k == "colparams" else k): round(v, 5) for k, v in st.items()
+                         if v > 0 or k == "total"}}
 
 
 def serving(bx, synth, qps_list, n_req):
@@ -288,6 +316,9 @@ def main():
                          "edges_per_launch": a.batch * edges, "kernel_ms": bt[bk]}}
         print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()
+    if a.table:
+        res["tabulated_response"] = table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)
+        print(f"table: {res['tabulated_response']}", file=sys.stderr, flush=True)
     if a.toys > 0:
         res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)
         print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)

@@ -53,7 +53,7 @@ typedef enum {
   BX_E_NOTFOUND = -6     /* unknown ticket */
 } bx_status;
 
-typedef enum { BX_RESP_GAUSS = 0, BX_RESP_GG = 1 } bx_response;
+typedef enum { BX_RESP_GAUSS = 0, BX_RESP_GG = 1, BX_RESP_TABLE = 2 } bx_response;
 typedef enum { BX_PREC_F32 = 0, BX_PREC_F64 = 1 } bx_precision;
 
 /* Model description (Sec. 4, workflow step 2: spectra, response, dataset and
@@ -74,7 +74,8 @@ typedef struct {
   const double* pu_g;         /* [pu_K] >= 0 with positive sum (normalised at build) */
   double pu_frac;             /* pile-up fraction p in [0, 1]; needs uniform reco bins */
   int32_t win_lo, win_hi;     /* fit window [win_lo, win_hi) over reco bins */
-  int32_t precision;          /* bx_precision of the response cells; sums are FP64 */
+  int32_t precision;          /* bx_precision of the response cells; sums are FP64
+                                 (a tabulated response is evaluated in FP64) */
   /* multivariate terms (Eqs. 3-4); multivariate = 0 ignores the rest */
   int32_t multivariate;
   const double* tag_frac;     /* [S] TFC tag fraction of each species, in [0, 1] */
@@ -87,6 +88,21 @@ typedef struct {
    * (needs pu_K > 0; pu_frac is then unused); an evaluation with it outside
    * [0, 1] is a domain error.  0: pu_frac is fixed. */
   int32_t pu_float;
+  /* Tabulated response (response = BX_RESP_TABLE): the Monte Carlo
+   * alternative to the analytic response of Eq. 1 (Sec. 4 names both).
+   * n_grid matrices R_g [N][T] (rtab, row-major, g slowest; R_g[j][i] is the
+   * probability that an event deposited in true bin i is reconstructed in
+   * reco bin j, >= 0, columns may lose mass) given at the strictly increasing
+   * values grid[g] of one response coordinate lam.  theta = rates, lam (when
+   * n_grid >= 2), then the pile-up fraction when it floats; R(lam) is the
+   * linear interpolation between the two grid points around lam (the cell
+   * above at an interior grid point, for the gradient), and lam outside
+   * [grid[0], grid[n_grid - 1]] is a domain error.  n_grid = 1: a fixed
+   * matrix, no response parameter.  1 <= n_grid <= 64.  Ignored for the
+   * analytic responses. */
+  int32_t n_grid;
+  const double* grid;         /* [n_grid] */
+  const double* rtab;         /* [n_grid][N][T] */
 } bx_model_desc;
 
 /* Observed histograms (FP64 counts; integers or Asimov values >= 0). */
@@ -115,7 +131,8 @@ bx_status bx_model_set_data(bx_model* m, const bx_data* data);
 /* Release the model and its device memory.  BX_E_BUSY while a server fit uses it. */
 bx_status bx_model_free(bx_model* m);
 
-/* Number of parameters P = S + (2 Gaussian | 4 GG). */
+/* Number of parameters P = S + (2 Gaussian | 4 GG | 1 table with n_grid >= 2
+ * | 0 one-matrix table) + (1 when the pile-up fraction floats). */
 int32_t bx_model_nparams(const bx_model* m);
 
 /* Sum of ln Gamma(n+1) over every bin in the NLL (FP64, computed at build and

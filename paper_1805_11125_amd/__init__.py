@@ -87,7 +87,12 @@ class Model:
         S = int(np.asarray(desc.spectra).shape[0])
         d.T, d.N, d.S = len(te) - 1, len(re) - 1, S
         d.true_edges, d.reco_edges, d.spectra = dptr(te), dptr(re), dptr(sp)
-        d.response = _abi.BX_RESP_GAUSS if desc.kind == "gauss" else _abi.BX_RESP_GG
+        d.response = {"gauss": _abi.BX_RESP_GAUSS, "gg": _abi.BX_RESP_GG,
+                      "table": _abi.BX_RESP_TABLE}[desc.kind]
+        if desc.kind == "table":
+            grid = arr(desc.table_grid)
+            rtab = arr(np.asarray(desc.table_R, np.float64))
+            d.n_grid, d.grid, d.rtab = len(grid), dptr(grid), dptr(rtab)
         d.gg_p = float(getattr(desc, "gg_p", 1.0))
         q = getattr(desc, "quench", None)
         d.quench = dptr(arr(q)) if q is not None else None

@@ -15,7 +15,7 @@ TILE_TABLE = os.path.join(HERE, "tiles_mi355x.txt")
 
 BX_OK, BX_PENDING = 0, 1
 BX_E_INVAL, BX_E_NOMEM, BX_E_DEVICE, BX_E_DOMAIN, BX_E_BUSY, BX_E_NOTFOUND = -1, -2, -3, -4, -5, -6
-BX_RESP_GAUSS, BX_RESP_GG = 0, 1
+BX_RESP_GAUSS, BX_RESP_GG, BX_RESP_TABLE = 0, 1, 2
 BX_PREC_F32, BX_PREC_F64 = 0, 1
 BX_FIT, BX_EVAL_GRAD = 0, 1
 BX_CONVERGED, BX_MAXITER, BX_FAILED = 0, 1, 2
@@ -32,7 +32,7 @@ class bx_model_desc(C.Structure):
                 ("precision", C.c_int32), ("multivariate", C.c_int32), ("tag_frac", _dp),
                 ("n_rad", C.c_int32), ("rad_tmpl", _dp), ("rad_lo", C.c_int32),
                 ("rad_hi", C.c_int32), ("n_ps", C.c_int32), ("ps_tmpl", _dp),
-                ("pu_float", C.c_int32)]
+                ("pu_float", C.c_int32), ("n_grid", C.c_int32), ("grid", _dp), ("rtab", _dp)]
 
 
 class bx_data(C.Structure):

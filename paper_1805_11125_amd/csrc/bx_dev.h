@@ -25,7 +25,8 @@ constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up ad
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
 
-enum : int { kGauss = 0, kGG = 1 };
+enum : int { kGauss = 0, kGG = 1, kTable = 2 };
+constexpr int kMaxGrid = 64;   // grid points of a tabulated response
 enum : int { kF32 = 0, kF64 = 1 };
 enum : int {                   // domain flags
   kBadSigma = 1,               // Gaussian sigma^2 < 0
@@ -55,6 +56,7 @@ struct FitDev {
   int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
   int uniform;            // reco bins of equal width
   int pu_float;           // the pile-up fraction is theta[P - 1] (else pu_frac)
+  int n_grid;             // tabulated response: grid points (kind kTable)
   double x0, inv_w;       // first reco edge, 1 / bin width (uniform bins)
   double pu_frac;
   GGConst gg;
@@ -73,6 +75,8 @@ struct FitDev {
   const double* n_t;    // [N] tagged
   const double* n_r;    // [n_rad]
   const double* n_p;    // [N][n_ps]
+  const double* grid;   // [n_grid] tabulated response: coordinate of each matrix
+  const double* Mg;     // [n_grid][N][16] exposure * R_g F^T, formed at build
   // per-evaluation state
   const double* theta;  // [P]
   ColPar* cp;           // [T]
@@ -88,9 +92,13 @@ struct FitDev {
   double* nllpart;      // [n_rowblk]
   int* flagpart;        // [n_rowblk]
   double* gpart;        // [n_rowblk][16] rate-gradient partials
-  double* rad_out;      // [3 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16], pile-up-fraction grad
+  double* rad_out;      // [4 + 2*16]: nll_rad, flag, rho.w[16], rate grad[16], pile-up-fraction
+                        // grad, table-coordinate grad
   double* Dp;           // [N][16] dM'/dp = g^*M - M (a floated pile-up fraction)
   double* ppart;        // [n_rowblk] pile-up-fraction gradient partials
+  double* Dt;           // [N][16] tabulated response: dM/dlam in the current grid cell
+  double* Dtp;          // [N][16] dM'/dlam (after pile-up)
+  double* tpart;        // [n_rowblk] table-coordinate gradient partials
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags
@@ -112,5 +120,6 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
                  bool with_grad, hipStream_t st);
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
+void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
 
 }  // namespace bx

@@ -181,7 +181,8 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   if (!d->true_edges || !increasing(d->true_edges, d->T + 1)) return inval("true_edges must be finite and strictly increasing");
   if (!d->reco_edges || !increasing(d->reco_edges, d->N + 1)) return inval("reco_edges must be finite and strictly increasing");
   if (!d->spectra || !finite_nonneg(d->spectra, (size_t)d->S * d->T)) return inval("spectra must be finite and >= 0");
-  if (d->response != BX_RESP_GAUSS && d->response != BX_RESP_GG) return inval("unknown response kind");
+  if (d->response != BX_RESP_GAUSS && d->response != BX_RESP_GG && d->response != BX_RESP_TABLE)
+    return inval("unknown response kind");
   if (d->precision != BX_PREC_F32 && d->precision != BX_PREC_F64) return inval("unknown precision");
   if (!std::isfinite(d->exposure) || !(d->exposure > 0)) return inval("exposure must be > 0");
   if (d->response == BX_RESP_GG) {
@@ -190,16 +191,27 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
     for (int i = 0; i < d->T; ++i)
       if (!std::isfinite(d->quench[i]) || !(d->quench[i] > 0)) return inval("quench must be finite and > 0");
   }
+  if (d->response == BX_RESP_TABLE) {
+    if (d->n_grid < 1 || d->n_grid > kMaxGrid) return inval("n_grid must be in [1, 64]");
+    if (!d->grid || !increasing(d->grid, d->n_grid)) return inval("grid must be finite and strictly increasing");
+    if (!d->rtab || !finite_nonneg(d->rtab, (size_t)d->n_grid * d->N * d->T)) return inval("rtab must be finite and >= 0");
+  }
   if (d->win_lo < 0 || d->win_hi > d->N || d->win_lo >= d->win_hi) return inval("fit window out of range");
   if (d->pu_K < 0 || d->pu_K > kMaxK) return inval("pu_K must be in [0, 256]");
   HostModel& m = *h;
   m.T = d->T; m.N = d->N; m.S = d->S;
-  m.kind = d->response == BX_RESP_GAUSS ? kGauss : kGG;
-  m.nresp = m.kind == kGauss ? 2 : 4;
+  m.kind = d->response == BX_RESP_GAUSS ? kGauss : d->response == BX_RESP_GG ? kGG : kTable;
+  m.nresp = m.kind == kGauss ? 2 : m.kind == kGG ? 4 : (d->n_grid > 1 ? 1 : 0);
+  m.n_grid = 0;
+  if (m.kind == kTable) {
+    m.n_grid = d->n_grid;
+    m.grid.assign(d->grid, d->grid + d->n_grid);
+    m.rtab.assign(d->rtab, d->rtab + (size_t)d->n_grid * d->N * d->T);
+  }
   m.pu_float = d->pu_float ? 1 : 0;
   if (m.pu_float && !(d->pu_K > 0)) return inval("a floated pile-up fraction needs pu_K > 0");
   m.P = m.S + m.nresp + m.pu_float;
-  m.prec = d->precision == BX_PREC_F32 ? kF32 : kF64;
+  m.prec = d->precision == BX_PREC_F32 && m.kind != kTable ? kF32 : kF64;
   m.win_lo = d->win_lo; m.win_hi = d->win_hi;
   m.exposure = d->exposure;
   m.p = m.kind == kGG ? d->gg_p : 1.0;
@@ -310,7 +322,7 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->T = h.T;
   f->N = h.N;
   f->n_rt = (h.N + kRowStep - 1) / kRowStep;
-  f->n_ct = (h.T + kColTile - 1) / kColTile;
+  f->n_ct = h.kind == kTable ? 0 : (h.T + kColTile - 1) / kColTile;  // a table has no cell sweeps
   f->CG = h.tiles.CG;
   f->RG = h.tiles.RG;
   // forward partials: one per chunk of kFwdWaves listed true tiles; a forward
@@ -319,7 +331,7 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->n_fb = (f->n_cg + f->CG - 1) / f->CG;
   f->n_rg = (f->n_rt + kBwdWaves * f->RG - 1) / (kBwdWaves * f->RG);
   f->n_rowblk = (h.N + 15) / 16;
-  f->n_cpblk = (h.T + kCpBlock - 1) / kCpBlock;
+  f->n_cpblk = h.kind == kTable ? 1 : (h.T + kCpBlock - 1) / kCpBlock;  // k_table writes one flag
   f->n_bwdblk = f->n_ct * f->n_rg;
   f->kind = h.kind;
   f->prec = h.prec;
@@ -356,9 +368,18 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->n_r = c.take<double>(h.n_rad);
     f->n_p = c.take<double>((size_t)h.N * h.n_ps);
   }
+  if (h.kind == kTable) {
+    if (shared) {
+      f->grid = shared->grid;
+      f->Mg = shared->Mg;
+    } else {
+      f->grid = c.take<double>(h.n_grid);
+      f->Mg = c.take<double>((size_t)h.n_grid * h.N * kSP);
+    }
+  }
   *theta = c.take<double>(h.P + 1);  // + the caller's sequence number (host path)
   f->theta = *theta;
-  f->cp = c.take<ColPar>(h.T);
+  f->cp = c.take<ColPar>(h.kind == kTable ? 0 : h.T);
   f->tb = c.take<int2>(f->n_ct);
   f->Mpart = (void*)c.take<char>((size_t)f->n_cg * h.N * kSP * rsz);
   f->Dcell = (void*)c.take<char>((size_t)f->n_ct * f->n_rt * 4 * 64 * 2 * rsz);
@@ -369,9 +390,14 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->nllpart = c.take<double>(f->n_rowblk);
   f->flagpart = c.take<int>(f->n_rowblk);
   f->gpart = c.take<double>((size_t)f->n_rowblk * kSP);
-  f->rad_out = c.take<double>(3 + 2 * kSP);
+  f->rad_out = c.take<double>(4 + 2 * kSP);
   f->Dp = c.take<double>((size_t)h.N * kSP);
   f->ppart = c.take<double>(f->n_rowblk);
+  if (h.kind == kTable) {
+    f->Dt = c.take<double>((size_t)h.N * kSP);
+    f->Dtp = c.take<double>((size_t)h.N * kSP);
+    f->tpart = c.take<double>(f->n_rowblk);
+  }
   f->cpflag = c.take<int>(f->n_cpblk);
   f->bwdpart = c.take<double>((size_t)f->n_bwdblk * 4);
   *out = c.take<double>(2 + h.P);
@@ -387,6 +413,7 @@ HostModel shape_only(const HostModel& h) {
   s.win_lo = h.win_lo; s.win_hi = h.win_hi; s.K = h.K; s.n_rad = h.n_rad; s.rad_lo = h.rad_lo;
   s.rad_hi = h.rad_hi; s.n_ps = h.n_ps;
   s.p = h.p; s.pu_frac = h.pu_frac; s.pu_float = h.pu_float; s.exposure = h.exposure;
+  s.n_grid = h.n_grid;
   s.gg = h.gg;
   s.tiles = h.tiles;
   return s;
@@ -437,6 +464,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   f.rad_hi = h.rad_hi; f.n_ps = h.n_ps;
   f.pu_frac = h.pu_frac;
   f.pu_float = h.pu_float;
+  f.n_grid = h.n_grid;
   f.gg = h.gg;
   if (shared) {  // inputs (and what is derived from them) already in place
     f.uniform = shared->uniform;
@@ -461,6 +489,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   BX_HIP(up(f.tag, h.tag, st), "upload");
   BX_HIP(up(f.rad, h.rad, st), "upload");
   BX_HIP(up(f.pst, h.pst, st), "upload");
+  if (h.kind == kTable) BX_HIP(up(f.grid, h.grid, st), "upload");
   return upload_data(h, *df, st);
 }
 
@@ -595,6 +624,23 @@ bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* h
   }
   s = place_fit(m->h, base, &m->df, m->stream);
   if (s != BX_OK) return fail(s);
+  if (m->h.kind == kTable) {  // M_g = R_g F^T once; the matrices themselves are not kept
+    const size_t nb = m->h.rtab.size() * sizeof(double);
+    double* d_R = nullptr;
+    if (hipMalloc(&d_R, nb) != hipSuccess) {
+      set_error("hipMalloc of the response tables failed");
+      return fail(BX_E_NOMEM);
+    }
+    const FitDev& fd = m->df.dev;
+    hipError_t e = hipMemcpyAsync(d_R, m->h.rtab.data(), nb, hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) {
+      launch_table_gemm(d_R, fd.F64, const_cast<double*>(fd.Mg), m->h.n_grid, m->h.N, m->h.T, m->stream);
+      e = hipStreamSynchronize(m->stream);
+    }
+    (void)hipFree(d_R);
+    if (e != hipSuccess) return fail(hip_fail(e, "response tables"));
+    std::vector<double>().swap(m->h.rtab);
+  }
   if (hipMalloc(&m->d_fit, 2 * sizeof(FitDev)) != hipSuccess || hipMalloc(&m->d_active, sizeof(int)) != hipSuccess)
     return fail(BX_E_NOMEM);
   m->d_fit_h = m->d_fit + 1;

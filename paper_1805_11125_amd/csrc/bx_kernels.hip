@@ -253,6 +253,103 @@ __device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe) {
   return gg_edge<R, D>(xe, g);
 }
 
+// ---------------------------------------------------------------------------
+// Tabulated response (the Monte Carlo alternative to the analytic R of
+// Eq. 1).  At build: M_g = R_g F^T for every grid matrix, FP64 MFMA 16x16x4.
+// Block = (16 reco rows, g), 8 waves; wave w takes the 16-column chunks
+// c = w, w + 8, ... of the true axis (each lane loads its MFMA operands
+// straight from R_g and F: the four steps of a chunk read 16 rows x 128
+// contiguous bytes), and the 8 partial products are added in a fixed order.
+constexpr int kGemmWaves = 8;
+__global__ void __launch_bounds__(kGemmWaves * 64) k_table_gemm(const double* R, const double* F64, double* Mg,
+                                                                 int N, int T) {
+  typedef __attribute__((address_space(1))) const double GD;
+  __shared__ double part[kGemmWaves][4][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, g = blockIdx.y, j0 = blockIdx.x * 16;
+  const int m = lane & 15, kq = lane >> 4;
+  GD* Rrow = (GD*)R + ((size_t)g * N + min(j0 + m, N - 1)) * T;
+  GD* F = (GD*)F64;
+  const bool rok = j0 + m < N;
+  v4d acc = {0, 0, 0, 0};
+  for (int i0 = 16 * wv; i0 < T; i0 += 16 * kGemmWaves) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int i = i0 + 4 * kk + kq;
+      const double A = (rok && i < T) ? Rrow[i] : 0.0;                // A[m = reco row][k]
+      const double B = i < T ? F[(size_t)i * kSP + m] : 0.0;          // B[k][n = species]
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = part[0][r][lane];
+      for (int w = 1; w < kGemmWaves; ++w) v += part[w][r][lane];
+      const int j = j0 + (lane >> 4) + 4 * r;  // FP64 result layout: row l/16 + 4r, column l%16
+      if (j < N) Mg[((size_t)g * N + j) * kSP + (lane & 15)] = v;
+    }
+  }
+}
+
+void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st) {
+  hipLaunchKernelGGL(k_table_gemm, dim3((N + 15) / 16, G), dim3(kGemmWaves * 64), 0, st, d_R, d_F64, d_Mg, N, T);
+}
+
+// Per evaluation: M = (1 - w) M_g + w M_g+1 for the grid cell [lam_g, lam_g+1]
+// holding lam = theta[S] (the cell above at an interior grid point), and
+// dM/dlam = (M_g+1 - M_g) / (lam_g+1 - lam_g).  theta comes from pinned host
+// memory when the caller passed it there (block 0 leaves the device copy and
+// the domain flags).
+__global__ void __launch_bounds__(kBlock) k_table(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if ((int)blockIdx.x * kBlock >= f.N * kSP) return;  // block-uniform
+  __shared__ double sth[kMaxP + 1];
+  __shared__ int sg, sbad;
+  __shared__ double sw, sdl;
+  if ((int)threadIdx.x <= f.P) {
+    const double v = f.theta_src ? __hip_atomic_load(f.theta_src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)
+                                 : f.theta[threadIdx.x];
+    sth[threadIdx.x] = v;
+    if (f.theta_src && blockIdx.x == 0) const_cast<double*>(f.theta)[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int q = 0; q < f.P; ++q)
+      if (!isfinite(sth[q])) bad |= kBadTheta;
+    if (f.pu_float && !(sth[f.P - 1] >= 0.0 && sth[f.P - 1] <= 1.0)) bad |= kBadTheta;
+    int g = 0;
+    double w = 0.0, dl = 1.0;
+    const int G = f.n_grid;
+    if (G > 1) {
+      const double lam = sth[f.S];
+      if (!(lam >= f.grid[0] && lam <= f.grid[G - 1])) bad |= kBadTheta;
+      while (g + 1 < G - 1 && f.grid[g + 1] <= lam) ++g;  // last grid point <= lam, at most G - 2
+      dl = f.grid[g + 1] - f.grid[g];
+      w = bad ? 0.0 : (lam - f.grid[g]) / dl;
+    }
+    sg = g;
+    sw = w;
+    sdl = dl;
+    sbad = bad;
+    if (blockIdx.x == 0) f.cpflag[0] = bad;
+  }
+  __syncthreads();
+  if (t >= f.N * kSP) return;
+  const double* M0 = f.Mg + (size_t)sg * f.N * kSP;
+  if (f.n_grid > 1) {
+    const double a = M0[t], b = M0[(size_t)f.N * kSP + t];
+    f.M[t] = (1.0 - sw) * a + sw * b;
+    f.Dt[t] = (b - a) / sdl;
+  } else {
+    f.M[t] = M0[t];
+  }
+}
+
 // Edge evaluation for one lane.
 template <class R, int KIND, bool D>
 __device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
@@ -504,6 +601,25 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   }
   mp[rl][s] = m;
   __syncthreads();
+  // tabulated response: dM'/dlam, the pile-up applied to dM/dlam (rows
+  // staged in the same LDS rows as M)
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  double dmt = 0.0;
+  if (tab) {  // block-uniform
+    for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = f.Dt[(size_t)r0 * kSP + e];
+    __syncthreads();
+    if (jok) {
+      dmt = Ml[j - r0][s];
+      if (K > 1) {
+        double acc = 0.0;
+        const int kmax = min(j, K - 1);
+        for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Ml[j - k - r0][s];
+        const double pp = pu_p(f);
+        dmt = (1.0 - pp) * dmt + pp * acc;
+      }
+      f.Dtp[j * kSP + s] = dmt;
+    }
+  }
   const double* th = f.theta;
   const double r_s = s < f.S ? th[s] : 0.0;
   const bool inwin = jok && j >= f.win_lo && j < f.win_hi;
@@ -578,32 +694,47 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     }
     if (threadIdx.x == 0) f.ppart[blockIdx.x] = red[0];
   }
+  if (tab) {  // block-uniform: dNLL/dlam without the radial part, sum_js H_js r_s dM'_js/dlam
+    __syncthreads();
+    red[threadIdx.x] = (jok && s < f.S) ? h * r_s * dmt : 0.0;
+    __syncthreads();
+    for (int st = kBlock / 2; st >= 1; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) f.tpart[blockIdx.x] = red[0];
+  }
 }
 
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if (!f.mv || f.n_rad <= 0) return;  // block-uniform
-  __shared__ double part[16][kSP], partd[16][kSP];
-  __shared__ double SW[kSP], SD[kSP], A[kSP], pgs[kSP], wr[128], red[kBlock];
+  __shared__ double part[16][kSP], partd[16][kSP], partt[16][kSP];
+  __shared__ double SW[kSP], SD[kSP], ST[kSP], A[kSP], pgs[kSP], tgs[kSP], wr[128], red[kBlock];
   __shared__ int redf[kBlock];
   const int s = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  double acc = 0.0, accd = 0.0;
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  double acc = 0.0, accd = 0.0, acct = 0.0;
   for (int j = f.rad_lo + grp; j < f.rad_hi; j += 16) {
     acc += f.Mp[j * kSP + s];
     if (f.pu_float) accd += f.Dp[j * kSP + s];
+    if (tab) acct += f.Dtp[j * kSP + s];
   }
   part[grp][s] = acc;
   partd[grp][s] = accd;
+  partt[grp][s] = acct;
   __syncthreads();
   if (threadIdx.x < 16) {
-    double t = 0.0, td = 0.0;
+    double t = 0.0, td = 0.0, tt = 0.0;
     for (int g = 0; g < 16; ++g) {
       t += part[g][threadIdx.x];
       td += partd[g][threadIdx.x];
+      tt += partt[g][threadIdx.x];
     }
     SW[threadIdx.x] = t;
     SD[threadIdx.x] = td;
+    ST[threadIdx.x] = tt;
     A[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * t : 0.0;
   }
   __syncthreads();
@@ -635,14 +766,20 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
         (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * SW[threadIdx.x] * rw : 0.0;
     // radial part of dNLL/dp: sum_s (1 - t_s) r_s (sum_{j in W} dM'_js/dp) rho.w_s
     pgs[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * SD[threadIdx.x] * rw : 0.0;
+    // and of dNLL/dlam (tabulated response) with dM'/dlam
+    tgs[threadIdx.x] = (int)threadIdx.x < f.S ? (1.0 - f.tag[threadIdx.x]) * f.theta[threadIdx.x] * ST[threadIdx.x] * rw : 0.0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     f.rad_out[0] = red[0];
     f.rad_out[1] = (double)redf[0];
-    double pg = 0.0;
-    for (int u = 0; u < 16; ++u) pg += pgs[u];
+    double pg = 0.0, tg = 0.0;
+    for (int u = 0; u < 16; ++u) {
+      pg += pgs[u];
+      tg += tgs[u];
+    }
     f.rad_out[2 + 32] = pg;
+    f.rad_out[2 + 33] = tg;
   }
 }
 
@@ -862,17 +999,20 @@ __device__ __forceinline__ int or64(int x) {
 template <int NT>
 __device__ void final_sums(const FitDev& f, int with_grad) {
   constexpr int NW = NT / 64;
-  // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient
-  constexpr int NA = 6;
+  // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient,
+  // table-coordinate gradient
+  constexpr int NA = 7;
   __shared__ double wred[NW][NA + kSP];
   __shared__ int wflag[NW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  double acc[NA] = {0, 0, 0, 0, 0, 0};
+  double acc[NA] = {0, 0, 0, 0, 0, 0, 0};
   int fl = 0;
+  const bool tab = f.kind == kTable && f.nresp > 0;
   for (int b = t; b < f.n_rowblk; b += NT) {
     acc[0] += f.nllpart[b];
     fl |= f.flagpart[b];
     if (f.pu_float && with_grad) acc[5] += f.ppart[b];
+    if (tab && with_grad) acc[6] += f.tpart[b];
   }
   for (int b = t; b < f.n_cpblk; b += NT) fl |= f.cpflag[b];
   if (with_grad)
@@ -911,6 +1051,10 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     }
     double pg = tot[5];  // dNLL/dp: row terms, then the radial term
     if (f.mv && f.n_rad > 0) pg += f.rad_out[2 + 32];
+    if (tab) {  // the table coordinate takes the response gradient's place
+      tot[1] = tot[6];
+      if (f.mv && f.n_rad > 0) tot[1] += f.rad_out[2 + 33];
+    }
     double nll = tot[0];
     if (f.mv && f.n_rad > 0) {
       nll += f.rad_out[0];
@@ -985,6 +1129,25 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
   const bool f32 = L.prec == kF32, gauss = L.kind == kGauss;
   // batches form a single histogram's pile-up adjoint once per fit
   const int pre = n >= kPreAdjFits ? 1 : 0;
+  if (L.kind == kTable) {  // no cell sweeps: the interpolated table, then the row terms
+    switch (stage) {
+      case 0:
+        hipLaunchKernelGGL(k_table, dim3((L.max_NS + kBlock - 1) / kBlock, n), blk, 0, st, d_fits, d_active);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
+        break;
+      case 4:
+        if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
+        break;
+      case 7:
+        hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+        break;
+      default:
+        break;
+    }
+    return;
+  }
   switch (stage) {
     case 0:
       hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st,

@@ -31,6 +31,8 @@ struct HostModel {
   int win_lo, win_hi, K, n_rad, rad_lo, rad_hi, n_ps;
   double p, pu_frac, exposure;
   int pu_float;  // the pile-up fraction is the last parameter
+  int n_grid = 0;                 // tabulated response: grid points
+  std::vector<double> grid, rtab;  // its coordinates; the matrices (kept only until build)
   std::vector<double> xraw, xe, Ec, Qt, F64, ghat, tag, rad, pst;
   std::vector<float> F32;
   std::vector<double> n_e, n_t, n_r, n_p;
