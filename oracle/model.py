@@ -16,11 +16,12 @@ import math
 from types import SimpleNamespace
 
 import numpy as np
-from scipy import special
+from scipy import special, stats
 
 GAUSS = "gauss"
 GG = "gg"
 TABLE = "table"
+COUNT = "count"
 
 
 class DomainError(ValueError):
@@ -87,6 +88,15 @@ def column_params(desc, resp):
     if desc.kind == TABLE:
         g, w = table_cell(desc, resp)
         return SimpleNamespace(kind=TABLE, E=E, g=g, w=w)
+    if desc.kind == COUNT:
+        # count estimator: mean m = L Q E counts, variance s^2 = v0 + v1 m +
+        # v2 m^2 > m, negative binomial with r = m^2 / (s^2 - m)
+        L, v0, v1, v2 = resp
+        m = L * np.asarray(desc.quench, np.float64) * E
+        s2 = v0 + v1 * m + v2 * m * m
+        if np.any(m <= 0) or np.any(s2 <= m):
+            raise DomainError("count mean <= 0 or variance <= mean")
+        return SimpleNamespace(kind=COUNT, E=E, m=m, s2=s2, r=m * m / (s2 - m))
     if desc.kind == GAUSS:
         a, b = resp
         var = a * E + b * E * E
@@ -152,6 +162,9 @@ def response_matrix(desc, cp):
         if Rt.shape[0] == 1:
             return Rt[0].copy()
         return (1.0 - cp.w) * Rt[cp.g] + cp.w * Rt[cp.g + 1]
+    if cp.kind == COUNT:  # reco bin j is the single count n_j = x_j
+        n = np.asarray(desc.reco_edges, np.float64)[:-1]
+        return stats.nbinom.pmf(n[:, None], cp.r[None, :], (cp.r / (cp.r + cp.m))[None, :])
     tail, lower = edge_tails(desc, cp)
     return cells_from_tails(tail, lower)
 
@@ -223,7 +236,30 @@ def _gg_chain(cp, resp, parts):
     return out
 
 
+def count_derivs(desc, cp, resp):
+    """Count estimator: dR/d(L, v0, v1, v2) from
+    d ln P/dm = n/m - (n + r)/(r + m) and
+    d ln P/dr = psi(n + r) - psi(r) + ln(r/(r + m)) + (m - n)/(r + m),
+    with m = L Q E, s^2 = v0 + v1 m + v2 m^2, r = m^2/(s^2 - m)."""
+    L, v0, v1, v2 = resp
+    n = np.asarray(desc.reco_edges, np.float64)[:-1][:, None]
+    m, s2, r = cp.m[None, :], cp.s2[None, :], cp.r[None, :]
+    P = response_matrix(desc, cp)
+    dP_dm = P * (n / m - (n + r) / (r + m))
+    dP_dr = P * (special.digamma(n + r) - special.digamma(r) + np.log(r / (r + m)) + (m - n) / (r + m))
+    d = s2 - m
+    dm = [m / L, 0 * m, 0 * m, 0 * m]
+    out = []
+    for q in range(4):
+        ds2 = [0 * m, 1 + 0 * m, m, m * m][q] + (v1 + 2 * v2 * m) * dm[q]
+        dr = (2 * m * dm[q] * d - m * m * (ds2 - dm[q])) / (d * d)
+        out.append(dP_dm * dm[q] + dP_dr * dr)
+    return out
+
+
 def response_param_derivs(desc, cp, resp):
+    if cp.kind == COUNT:
+        return count_derivs(desc, cp, np.asarray(resp, np.float64))
     if cp.kind == TABLE:  # R is affine in lam inside a grid cell
         Rt = np.asarray(desc.table_R, np.float64)
         if Rt.shape[0] == 1:

@@ -29,6 +29,7 @@ ME = 0.51099895  # electron mass [MeV]
 GAUSS = "gauss"
 GG = "gg"
 TABLE = "table"
+COUNT = "count"
 
 
 # ---------------------------------------------------------------------------
@@ -79,7 +80,7 @@ class ModelDesc:
     def n_resp(self):
         if self.kind == TABLE:
             return 1 if len(self.table_grid) > 1 else 0
-        return 2 if self.kind == GAUSS else 4
+        return 2 if self.kind == GAUSS else 4  # the count estimator: L, v0, v1, v2 as the GG
 
     @property
     def P(self):
@@ -294,6 +295,27 @@ def table_config(grid_L=(480.0, 490.0, 500.0, 510.0, 520.0), n_mc=4000, seed=17,
                      win=(0, len(re) - 1), table_grid=grid, table_R=R, theta_true=theta,
                      float_mask=np.ones(len(theta), dtype=bool),
                      param_names=[f"r_{n}" for n in names] + (["L"] if len(grid) > 1 else []))
+
+
+# count estimator (number of fired PMTs) -------------------------------------
+# light yield in fired PMTs per MeV and the count variance v0 + v1 m + v2 m^2
+# (v1 = 1: Poisson, v0 and v2 the extra spread)
+COUNT_RESP = np.array([300.0, 2.0, 1.0, 2e-3])
+
+
+def count_config(T=3000, N=1000) -> ModelDesc:
+    """The config-2 species measured by a second, discrete estimator: the
+    number of fired PMTs, one reco bin per count value 0..N-1."""
+    te = (3.0 / T) * np.arange(T + 1)
+    re = np.arange(N + 1, dtype=np.float64)
+    names, spectra = _c2_shapes(te)
+    rates = np.array(_C2_FRAC) * C2_EVENTS
+    theta = np.concatenate([rates, COUNT_RESP])
+    mask = np.ones(len(theta), dtype=bool)
+    mask[len(rates) + 1] = False  # v0 fixed
+    return ModelDesc(kind=COUNT, true_edges=te, reco_edges=re, spectra=spectra, species=names,
+                     quench=quench_table(te), win=(0, N), theta_true=theta, float_mask=mask,
+                     param_names=[f"r_{n}" for n in names] + ["L", "v0", "v1", "v2"])
 
 
 # multivariate templates ------------------------------------------------------

@@ -681,3 +681,77 @@ def test_mc_tables_are_column_probabilities():
     xc = 0.5 * (re[:-1] + re[1:])
     m = (R * xc[None, :, None]).sum(1) / R.sum(1)
     assert np.all(m[1, 2:8] > m[0, 2:8])
+
+
+# ---------------------------------------------------------------------------
+# count estimator (negative binomial in the number of fired PMTs)
+# ---------------------------------------------------------------------------
+def tiny_count(T=6, N=60, S=2, seed=4, resp=(40.0, 2.0, 1.0, 0.02)):
+    rng = np.random.default_rng(seed)
+    te = np.linspace(0.1, 1.3, T + 1)
+    re = np.arange(N + 1, dtype=float)
+    F = rng.random((S, T)) + 0.1
+    F /= F.sum(1, keepdims=True)
+    Q = 1 - 0.25 * np.exp(-0.5 * (te[:-1] + te[1:]) / 0.2)
+    th = np.concatenate([rng.uniform(50, 200, S), resp])
+    return synth.ModelDesc(kind="count", true_edges=te, reco_edges=re, spectra=F, quench=Q,
+                           species=[f"s{i}" for i in range(S)], win=(0, N), theta_true=th)
+
+
+def test_count_cells_vs_mpmath():
+    d = tiny_count(T=4, N=12)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    mp.mp.dps = 30
+    for i in range(4):
+        m, r = mp.mpf(cp.m[i]), mp.mpf(cp.r[i])
+        for j in range(12):
+            n = mp.mpf(j)
+            ref = mp.exp(mp.loggamma(n + r) - mp.loggamma(r) - mp.loggamma(n + 1)
+                         + r * mp.log(r / (r + m)) + n * mp.log(m / (r + m)))
+            assert R[j, i] == pytest.approx(float(ref), rel=1e-12, abs=1e-300)
+
+
+def test_count_poisson_limit():
+    # v0 -> 0+, v2 = 0, v1 = 1: the variance tends to the mean and the law to
+    # Poisson (here r ~ 1e9: the two differ by ~n^2/2r, below 2e-5)
+    d = tiny_count(resp=(40.0, 1e-6, 1.0, 0.0))
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    n = np.arange(d.N)
+    P = stats.poisson.pmf(n[:, None], cp.m[None, :])
+    assert np.allclose(R, P, rtol=2e-5, atol=1e-15)
+
+
+def test_count_columns_have_the_moments():
+    d = tiny_count(N=200)
+    cp = om.column_params(d, d.theta_true[d.S:])
+    R = om.response_matrix(d, cp)
+    n = np.arange(d.N)[:, None]
+    assert np.allclose(R.sum(0), 1.0, rtol=0, atol=1e-12)
+    assert np.allclose((n * R).sum(0), cp.m, rtol=1e-11)
+    assert np.allclose(((n - cp.m) ** 2 * R).sum(0), cp.s2, rtol=1e-10)
+
+
+def test_count_gradient_vs_richardson():
+    d = tiny_count()
+    x = poisson_data(d, d.theta_true)
+    th = d.theta_true * 1.01
+    _, g = om.nll_grad(d, x, th)
+    for q in range(d.P):
+        def f(v, q=q):
+            t = th.copy()
+            t[q] = v
+            return om.nll(d, x, t)
+        assert g[q] == pytest.approx(_richardson(f, th[q], 1e-3 * abs(th[q])), rel=1e-7, abs=1e-7)
+
+
+def test_count_domain():
+    d = tiny_count()
+    x = poisson_data(d, d.theta_true)
+    th = d.theta_true.copy()
+    th[d.S + 2] = 0.5  # v1 < 1 with v0, v2 small: variance below the mean somewhere
+    th[d.S + 1] = 0.0
+    th[d.S + 3] = 0.0
+    with pytest.raises(om.DomainError):
+        om.nll(d, x, th)
