@@ -53,7 +53,14 @@ typedef enum {
   BX_E_NOTFOUND = -6     /* unknown ticket */
 } bx_status;
 
-typedef enum { BX_RESP_GAUSS = 0, BX_RESP_GG = 1, BX_RESP_TABLE = 2 } bx_response;
+/* Detector response of Eq. 1: Gaussian in the energy (a, b); generalized
+ * gamma in photoelectrons (L, v0, v1, v2); a tabulated (Monte Carlo) response;
+ * or the count estimator: reco bin j is the single count n_j = reco_edges[j]
+ * (integer edges of unit width, e.g. the number of fired PMTs), negative
+ * binomial with mean m = L Q E and variance v0 + v1 m + v2 m^2 > m (the same
+ * four parameters as the generalized gamma; mean <= 0 or variance <= mean is
+ * a domain error).  The count estimator is evaluated in FP64. */
+typedef enum { BX_RESP_GAUSS = 0, BX_RESP_GG = 1, BX_RESP_TABLE = 2, BX_RESP_COUNT = 3 } bx_response;
 typedef enum { BX_PREC_F32 = 0, BX_PREC_F64 = 1 } bx_precision;
 
 /* Model description (Sec. 4, workflow step 2: spectra, response, dataset and
@@ -68,7 +75,7 @@ typedef struct {
                                  (normalised to unit sum in FP64 at build) */
   int32_t response;           /* bx_response */
   double gg_p;                /* GG exponent p > 0 (GG only) */
-  const double* quench;       /* [T] quenching factor at bin centres (GG only) */
+  const double* quench;       /* [T] quenching factor at bin centres (GG and count) */
   double exposure;            /* > 0 */
   int32_t pu_K;               /* random-trigger spectrum length, 0 = no pile-up */
   const double* pu_g;         /* [pu_K] >= 0 with positive sum (normalised at build) */
@@ -131,7 +138,7 @@ bx_status bx_model_set_data(bx_model* m, const bx_data* data);
 /* Release the model and its device memory.  BX_E_BUSY while a server fit uses it. */
 bx_status bx_model_free(bx_model* m);
 
-/* Number of parameters P = S + (2 Gaussian | 4 GG | 1 table with n_grid >= 2
+/* Number of parameters P = S + (2 Gaussian | 4 GG or count | 1 table with n_grid >= 2
  * | 0 one-matrix table) + (1 when the pile-up fraction floats). */
 int32_t bx_model_nparams(const bx_model* m);
 

@@ -88,7 +88,7 @@ class Model:
         d.T, d.N, d.S = len(te) - 1, len(re) - 1, S
         d.true_edges, d.reco_edges, d.spectra = dptr(te), dptr(re), dptr(sp)
         d.response = {"gauss": _abi.BX_RESP_GAUSS, "gg": _abi.BX_RESP_GG,
-                      "table": _abi.BX_RESP_TABLE}[desc.kind]
+                      "table": _abi.BX_RESP_TABLE, "count": _abi.BX_RESP_COUNT}[desc.kind]
         if desc.kind == "table":
             grid = arr(desc.table_grid)
             rtab = arr(np.asarray(desc.table_R, np.float64))

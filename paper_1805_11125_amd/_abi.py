@@ -15,7 +15,7 @@ TILE_TABLE = os.path.join(HERE, "tiles_mi355x.txt")
 
 BX_OK, BX_PENDING = 0, 1
 BX_E_INVAL, BX_E_NOMEM, BX_E_DEVICE, BX_E_DOMAIN, BX_E_BUSY, BX_E_NOTFOUND = -1, -2, -3, -4, -5, -6
-BX_RESP_GAUSS, BX_RESP_GG, BX_RESP_TABLE = 0, 1, 2
+BX_RESP_GAUSS, BX_RESP_GG, BX_RESP_TABLE, BX_RESP_COUNT = 0, 1, 2, 3
 BX_PREC_F32, BX_PREC_F64 = 0, 1
 BX_FIT, BX_EVAL_GRAD = 0, 1
 BX_CONVERGED, BX_MAXITER, BX_FAILED = 0, 1, 2

@@ -25,23 +25,24 @@ constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up ad
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
 
-enum : int { kGauss = 0, kGG = 1, kTable = 2 };
+enum : int { kGauss = 0, kGG = 1, kTable = 2, kCount = 3 };
 constexpr int kMaxGrid = 64;   // grid points of a tabulated response
 enum : int { kF32 = 0, kF64 = 1 };
 enum : int {                   // domain flags
   kBadSigma = 1,               // Gaussian sigma^2 < 0
-  kBadGG = 2,                  // GG mean or variance <= 0, or shape out of range
+  kBadGG = 2,                  // GG mean or variance <= 0, or shape out of range; count
+                               // estimator mean <= 0 or variance <= mean
   kBadMu = 4,                  // an expected count < 0, or 0 with counts > 0
   kBadTheta = 8,               // non-finite parameter
   kZeroWidth = 16              // sigma = 0 somewhere: response derivative undefined
 };
 
 struct ColPar {
-  double c0;        // Gauss: m;        GG: ct = p ln a + ln k
-  double c1;        // Gauss: 1/sigma;  GG: k
+  double c0;        // Gauss: m;        GG: ct = p ln a + ln k;  count: m
+  double c1;        // Gauss: 1/sigma;  GG: k;                 count: r
   double v;         // sum_s r_s F^_si  (expected deposited counts in true bin i)
   float f32[8];     // GG edge constants (k, 1/k, sqrt(k/2), cR, ce, dlnG*, ln k - psi, p)
-  double f64[8];    // the same in FP64
+  double f64[8];    // the same in FP64 (count: m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)), psi(r))
   double J[2][kMaxResp];  // d(c1, c2)/d(response parameter q)
   int jlo, jhi;     // cells that may be non-zero (support)
   int bad;          // domain flags

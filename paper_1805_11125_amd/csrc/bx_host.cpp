@@ -181,13 +181,22 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   if (!d->true_edges || !increasing(d->true_edges, d->T + 1)) return inval("true_edges must be finite and strictly increasing");
   if (!d->reco_edges || !increasing(d->reco_edges, d->N + 1)) return inval("reco_edges must be finite and strictly increasing");
   if (!d->spectra || !finite_nonneg(d->spectra, (size_t)d->S * d->T)) return inval("spectra must be finite and >= 0");
-  if (d->response != BX_RESP_GAUSS && d->response != BX_RESP_GG && d->response != BX_RESP_TABLE)
+  if (d->response != BX_RESP_GAUSS && d->response != BX_RESP_GG && d->response != BX_RESP_TABLE &&
+      d->response != BX_RESP_COUNT)
     return inval("unknown response kind");
   if (d->precision != BX_PREC_F32 && d->precision != BX_PREC_F64) return inval("unknown precision");
   if (!std::isfinite(d->exposure) || !(d->exposure > 0)) return inval("exposure must be > 0");
-  if (d->response == BX_RESP_GG) {
-    if (!std::isfinite(d->gg_p) || !(d->gg_p > 0.05) || d->gg_p > 20) return inval("gg_p must be in (0.05, 20]");
-    if (!d->quench) return inval("GG response needs the quenching table");
+  if (d->response == BX_RESP_COUNT) {
+    // one reco bin per count value: integer edges of unit width from >= 0
+    if (!(d->reco_edges[0] >= 0) || d->reco_edges[0] != std::floor(d->reco_edges[0]))
+      return inval("count estimator: reco edges must be integers >= 0");
+    for (int j = 0; j < d->N; ++j)
+      if (d->reco_edges[j + 1] != d->reco_edges[j] + 1.0) return inval("count estimator: one count per reco bin");
+  }
+  if (d->response == BX_RESP_GG || d->response == BX_RESP_COUNT) {
+    if (d->response == BX_RESP_GG && (!std::isfinite(d->gg_p) || !(d->gg_p > 0.05) || d->gg_p > 20))
+      return inval("gg_p must be in (0.05, 20]");
+    if (!d->quench) return inval("this response needs the quenching table");
     for (int i = 0; i < d->T; ++i)
       if (!std::isfinite(d->quench[i]) || !(d->quench[i] > 0)) return inval("quench must be finite and > 0");
   }
@@ -200,8 +209,9 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   if (d->pu_K < 0 || d->pu_K > kMaxK) return inval("pu_K must be in [0, 256]");
   HostModel& m = *h;
   m.T = d->T; m.N = d->N; m.S = d->S;
-  m.kind = d->response == BX_RESP_GAUSS ? kGauss : d->response == BX_RESP_GG ? kGG : kTable;
-  m.nresp = m.kind == kGauss ? 2 : m.kind == kGG ? 4 : (d->n_grid > 1 ? 1 : 0);
+  m.kind = d->response == BX_RESP_GAUSS ? kGauss : d->response == BX_RESP_GG ? kGG
+         : d->response == BX_RESP_TABLE ? kTable : kCount;
+  m.nresp = m.kind == kGauss ? 2 : m.kind == kTable ? (d->n_grid > 1 ? 1 : 0) : 4;
   m.n_grid = 0;
   if (m.kind == kTable) {
     m.n_grid = d->n_grid;
@@ -211,7 +221,7 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   m.pu_float = d->pu_float ? 1 : 0;
   if (m.pu_float && !(d->pu_K > 0)) return inval("a floated pile-up fraction needs pu_K > 0");
   m.P = m.S + m.nresp + m.pu_float;
-  m.prec = d->precision == BX_PREC_F32 && m.kind != kTable ? kF32 : kF64;
+  m.prec = d->precision == BX_PREC_F32 && m.kind != kTable && m.kind != kCount ? kF32 : kF64;
   m.win_lo = d->win_lo; m.win_hi = d->win_hi;
   m.exposure = d->exposure;
   m.p = m.kind == kGG ? d->gg_p : 1.0;
@@ -266,11 +276,11 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   m.xraw.assign(d->reco_edges, d->reco_edges + m.N + 1);
   m.xe.resize(m.N + 1);
   for (int j = 0; j <= m.N; ++j)
-    m.xe[j] = m.kind == kGauss ? m.xraw[j] : (m.xraw[j] > 0 ? std::log(m.xraw[j]) : -INFINITY);
+    m.xe[j] = m.kind != kGG ? m.xraw[j] : (m.xraw[j] > 0 ? std::log(m.xraw[j]) : -INFINITY);
   m.Ec.resize(m.T);
   for (int i = 0; i < m.T; ++i) m.Ec[i] = 0.5 * (d->true_edges[i] + d->true_edges[i + 1]);
   m.Qt.assign(m.T, 1.0);
-  if (m.kind == kGG) m.Qt.assign(d->quench, d->quench + m.T);
+  if (m.kind == kGG || m.kind == kCount) m.Qt.assign(d->quench, d->quench + m.T);
   // spectra: unit rows (FP64), times exposure, species padded to 16
   m.F64.assign((size_t)m.T * kSP, 0.0);
   m.F32.assign((size_t)m.T * kSP, 0.f);

@@ -156,6 +156,52 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
       const double zb = sqrt(2.0 * (f.prec == kF32 ? kSupportB32 : kSupportB));
       const int2 r = cell_range(f, E - zb * sig, E + zb * sig);
       jlo = r.x; jhi = r.y;
+    } else if (f.kind == kCount) {
+      // count estimator: negative binomial with mean m = L Q E and shape
+      // r = m^2 / (s^2 - m); c1 = m, c2 = r
+      const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
+      const double m = L * f.Qt[i] * E;
+      const double s2 = v0 + v1 * m + v2 * m * m;
+      if (!(m > 0.0) || !(s2 > m) || !isfinite(s2)) {
+        bad |= kBadGG;
+        c.c0 = 1.0; c.c1 = 1.0;
+      } else {
+        const double d = s2 - m, r = m * m / d;
+        const double lq = log(r / (r + m)), lp = log(m / (r + m)), lgr = lgamma(r);
+        const double cst[8] = {m, r, lgr, lq, lp, digamma_pos(r), 0.0, 0.0};
+        for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
+        c.c0 = m;
+        c.c1 = r;
+        for (int q = 0; q < 4; ++q) {
+          const double dm = (q == 0) ? m / L : 0.0;
+          const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + (v1 + 2.0 * v2 * m) * dm;
+          c.J[0][q] = dm;
+          c.J[1][q] = (2.0 * m * dm * d - m * m * (ds2 - dm)) / (d * d);
+        }
+        // support: counts with ln P(n) >= ln P(mode) - B (ln P is unimodal in
+        // n), bracketed by bisection on the continuous extension
+        auto lnP = [&](double n) { return lgamma(n + r) - lgr - lgamma(n + 1.0) + r * lq + n * lp; };
+        const double B = 1.05 * kSupportB;
+        const double mode = r > 1.0 ? floor((r - 1.0) * m / r) : 0.0;
+        const double top = lnP(mode) - B;
+        double lo = 0.0;
+        if (lnP(0.0) < top) {
+          double a = 0.0, b = mode;  // lnP(a) < top <= lnP(b)
+          for (int it = 0; it < 60 && b - a > 0.5; ++it) {
+            const double c2 = 0.5 * (a + b);
+            if (lnP(c2) < top) a = c2; else b = c2;
+          }
+          lo = a;
+        }
+        double a = mode, b = mode + 10.0 * sqrt(s2) + 10.0;
+        for (int it = 0; it < 40 && lnP(b) >= top; ++it) b = mode + 2.0 * (b - mode);
+        for (int it = 0; it < 60 && b - a > 0.5; ++it) {  // lnP(a) >= top > lnP(b)
+          const double c2 = 0.5 * (a + b);
+          if (lnP(c2) >= top) a = c2; else b = c2;
+        }
+        const int2 rr = cell_range(f, lo, b + 1.0);
+        jlo = rr.x; jhi = rr.y;
+      }
     } else {
       const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
       const double m = L * f.Qt[i] * E;
@@ -245,12 +291,16 @@ struct ColPre {
 
 template <class R, int KIND, bool D>
 __device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe) {
-  if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
-  GGCol<R> g;
-  g.ct = c.c0;
-  g.k = c.s[0]; g.ik = c.s[1]; g.skh = c.s[2]; g.cR = c.s[3]; g.ce = c.s[4];
-  g.dlngs = c.s[5]; g.lnk_psi = c.s[6]; g.p = c.s[7];
-  return gg_edge<R, D>(xe, g);
+  if constexpr (KIND == kCount) {
+    return count_cell<D>(xe, c.s);  // FP64 only: the cell at count xe itself
+  } else {
+    if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
+    GGCol<R> g;
+    g.ct = c.c0;
+    g.k = c.s[0]; g.ik = c.s[1]; g.skh = c.s[2]; g.cR = c.s[3]; g.ce = c.s[4];
+    g.dlngs = c.s[5]; g.lnk_psi = c.s[6]; g.p = c.s[7];
+    return gg_edge<R, D>(xe, g);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -479,15 +529,27 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < T;
       const EdgeVal<R> ev = edge_pre<R, KIND, D>(cur, xe);
-      const R hi = dpp_from_next(ev.v);
       const bool ok = row_ok && iok;
-      const R a = ok ? cell_from(ev.v, hi) : (R)0;
+      // edges: the cell is the difference to the next edge (row_shl:1, all
+      // lanes); counts: the lane's value is the cell itself
+      R a;
+      if constexpr (KIND == kCount) {
+        a = ok ? ev.v : (R)0;
+      } else {
+        const R hi = dpp_from_next(ev.v);
+        a = ok ? cell_from(ev.v, hi) : (R)0;
+      }
       acc = mfma16(a, cur.bb, acc);
       if (D) {
-        const R d1h = dpp_from_next(ev.d1), d2h = dpp_from_next(ev.d2);
         R2 dv;
-        dv.x = ok ? d1h - ev.d1 : (R)0;
-        dv.y = ok ? d2h - ev.d2 : (R)0;
+        if constexpr (KIND == kCount) {
+          dv.x = ok ? ev.d1 : (R)0;
+          dv.y = ok ? ev.d2 : (R)0;
+        } else {
+          const R d1h = dpp_from_next(ev.d1), d2h = dpp_from_next(ev.d2);
+          dv.x = ok ? d1h - ev.d1 : (R)0;
+          dv.y = ok ? d2h - ev.d2 : (R)0;
+        }
         dst[2 * (q * 64 + lane)] = dv.x;
         dst[2 * (q * 64 + lane) + 1] = dv.y;
       }
@@ -1155,9 +1217,10 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 1:
       if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (f32 && !gauss) launch_fwd<float, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (f32 && L.kind == kGG) launch_fwd<float, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
       if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (!f32 && !gauss) launch_fwd<double, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
       break;
     case 2:
       if (f32) hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);

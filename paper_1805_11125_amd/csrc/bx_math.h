@@ -97,6 +97,17 @@ BX_HD double digamma_big(double x) {
   return log(x) - 0.5 * ix - s * ix2;
 }
 
+// digamma for x > 0: the recurrence psi(x) = psi(x + 1) - 1/x up to x >= 10,
+// then the asymptotic series.
+BX_HD double digamma_pos(double x) {
+  double acc = 0.0;
+  while (x < 10.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  return acc + digamma_big(x);
+}
+
 // Column quantities of the GG shape k (all FP64).
 struct GGShape {
   double G, dG;      // G(k), G'(k)
@@ -435,6 +446,26 @@ BX_HD EdgeVal<R> gg_edge(double lnx, const GGCol<R>& c) {
   constexpr bool f32 = sizeof(R) == 4;
   if (f32 && c.k >= (R)kTemmeMinK) return gg_edge_temme<R, D>(t, c);
   return gg_edge_small<R, D>(t, c);
+}
+
+// Count estimator (FP64): reco bin j holds the single count n; negative
+// binomial P(n) = Gamma(n + r) / (Gamma(r) n!) (r/(r+m))^r (m/(r+m))^n with
+// mean m and shape r.  c = {m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)),
+// psi(r)}.  v = P(n), d1 = dP/dm, d2 = dP/dr.
+template <bool D>
+BX_HD EdgeVal<double> count_cell(double n, const double* c) {
+  EdgeVal<double> o;
+  o.v = o.d1 = o.d2 = 0.0;
+  const double m = c[0], r = c[1];
+  if (!(n >= 0.0) || !(m > 0.0)) return o;
+  const double P = exp(lgamma(n + r) - c[2] - lgamma(n + 1.0) + r * c[3] + n * c[4]);
+  o.v = P;
+  if (D) {
+    const double irm = 1.0 / (r + m);
+    o.d1 = P * (n / m - (n + r) * irm);
+    o.d2 = P * (digamma_pos(n + r) - c[5] + c[3] + (m - n) * irm);
+  }
+  return o;
 }
 
 // Cell from two neighbouring encoded edge values (lower edge lo, upper hi).

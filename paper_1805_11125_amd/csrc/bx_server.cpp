@@ -95,7 +95,7 @@ static int64_t now_ns() {
 }
 
 constexpr int kThetaStride = 40;  // theta[P] and the step number, 5 cache lines
-constexpr int kGroups = 24;       // launch groups: 3 kinds x 2 precisions x 4 forward tile widths
+constexpr int kGroups = 32;       // launch groups: 4 kinds x 2 precisions x 4 forward tile widths
 constexpr int kOutStride = 40;    // nll, grad[P], flags, completion mark
 
 struct Req {
