@@ -75,7 +75,7 @@ def parse():
                     help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-table", dest="table", action="store_false",
-                    help="skip the tabulated-response leg")
+                    help="skip the tabulated-response and count-estimator legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -162,6 +162,25 @@ def table_leg(bx, synth, x, steps, warmup):
             "build_s": build_s, "build_gemm_flop": 2 * G * N * T * 16, "build_gemm_bytes": G * N * T * 8,
             "stage_ms": {("table" if k == "colparams" else k): round(v, 5) for k, v in st.items()
                          if v > 0 or k == "total"}}
+
+
+def count_leg(bx, synth, steps, warmup):
+    """Count estimator (fired PMTs, one reco bin per count) on the config-2
+    species: 3000 true bins x 1000 counts, negative-binomial cells in FP64."""
+    d = synth.count_config()
+    x = synth.count_events(d, d.theta_true, seed=0)
+    m = bx.Model(d, x, precision=bx.BX_PREC_F64)
+    th = d.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d.P))
+    for _ in range(warmup):
+        m.nll_grad(th)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        m.nll_grad(th)
+    evals = steps / (time.perf_counter() - t1)
+    st = m.stage_times(th, reps=100)
+    m.close()
+    return {"workload": f"{d.T} true bins x {d.N} counts, {d.S} species, FP64", "evals_per_s": evals,
+            "stage_ms": {k: round(v, 5) for k, v in st.items() if v > 0 or k == "total"}}
 
 
 def serving(bx, synth, qps_list, n_req):
@@ -319,6 +338,8 @@ def main():
     if a.table:
         res["tabulated_response"] = table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)
         print(f"table: {res['tabulated_response']}", file=sys.stderr, flush=True)
+        res["count_estimator"] = count_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))
+        print(f"count: {res['count_estimator']}", file=sys.stderr, flush=True)
     if a.toys > 0:
         res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)
         print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)

@@ -318,6 +318,30 @@ def count_config(T=3000, N=1000) -> ModelDesc:
                      param_names=[f"r_{n}" for n in names] + ["L", "v0", "v1", "v2"])
 
 
+def count_events(d: ModelDesc, theta, seed=0) -> Data:
+    """A histogram of the count estimator from simulated events: for each
+    species a Poisson number of events (mean r_s), true energies from its
+    deposited spectrum, fired-PMT counts drawn around L Q E with the
+    variance v0 + v1 m + v2 m^2 (negative binomial); counts beyond the
+    reco range are lost."""
+    rng = np.random.default_rng(seed)
+    te = np.asarray(d.true_edges, np.float64)
+    ec = 0.5 * (te[:-1] + te[1:])
+    L, v0, v1, v2 = np.asarray(theta, np.float64)[d.S:d.S + 4]
+    hist = np.zeros(d.N)
+    for s in range(d.S):
+        n_ev = rng.poisson(theta[s])
+        i = rng.choice(len(ec), size=n_ev, p=d.spectra[s] / d.spectra[s].sum())
+        m = L * np.asarray(d.quench)[i] * ec[i]
+        s2 = v0 + v1 * m + v2 * m * m
+        r = m * m / (s2 - m)
+        c = rng.negative_binomial(r, r / (r + m))
+        j = c - int(d.reco_edges[0])
+        ok = (j >= 0) & (j < d.N)
+        hist += np.bincount(j[ok], minlength=d.N)[: d.N]
+    return Data(energy=hist)
+
+
 # multivariate templates ------------------------------------------------------
 N_RAD = 100
 N_PS = 50
