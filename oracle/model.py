@@ -320,7 +320,10 @@ def expected(desc, Mp, r):
       vetoed mu_sub = M' c_sub, tagged mu_tag = M' c_tag (Eq. 3);
       radial nu_k = sum_s c_sub,s (sum_{j in radial window} M'_js) rho_sk;
       pulse shape lambda_jk = sum_s M'_js c_sub,s T_sk (rows of the fit
-      window), all built from the TFC-vetoed expectation."""
+      window), all built from the TFC-vetoed expectation.
+    Joint (the alternative to the additive terms): the vetoed events in one
+    energy x radius x pulse-shape histogram with lambda_jkl = sum_s M'_js
+    c_sub,s rho_sk T_sl, plus the tagged term."""
     r = np.asarray(r, np.float64)
     j0, j1 = desc.win
     if not desc.multivariate:
@@ -328,6 +331,13 @@ def expected(desc, Mp, r):
     t = np.asarray(desc.tag_frac, np.float64)
     c_sub = (1.0 - t) * r
     c_tag = t * r
+    if getattr(desc, "joint", False):
+        # joint energy x radius x pulse-shape PDF of the vetoed events instead
+        # of three additive terms: lambda_jkl = sum_s M'_js c_sub,s rho_sk T_sl
+        rho = np.asarray(desc.rad_tmpl, np.float64)
+        T = np.asarray(desc.ps_tmpl, np.float64)
+        lam = np.einsum("js,sk,sl->jkl", Mp[j0:j1] * c_sub[None, :], rho, T)
+        return {"joint": lam, "tagged": (Mp @ c_tag)[j0:j1]}
     out = {"energy": (Mp @ c_sub)[j0:j1], "tagged": (Mp @ c_tag)[j0:j1]}
     if desc.rad_tmpl is not None:
         rw0, rw1 = desc.rad_win
@@ -340,6 +350,9 @@ def expected(desc, Mp, r):
 
 def observed(desc, data):
     j0, j1 = desc.win
+    if getattr(desc, "joint", False):
+        return {"joint": np.asarray(data.joint, np.float64)[j0:j1],
+                "tagged": np.asarray(data.tagged, np.float64)[j0:j1]}
     out = {"energy": np.asarray(data.energy, np.float64)[j0:j1]}
     if desc.multivariate:
         out["tagged"] = np.asarray(data.tagged, np.float64)[j0:j1]

@@ -55,6 +55,9 @@ class ModelDesc:
     rad_tmpl: Optional[np.ndarray] = None  # [S, n_rad]
     rad_win: tuple = (0, 0)                # reco window feeding the radial term
     ps_tmpl: Optional[np.ndarray] = None   # [S, n_ps]
+    # joint energy x radius x pulse-shape term of the vetoed events instead of
+    # the three additive terms (needs both templates; data in Data.joint)
+    joint: bool = False
     # tabulated response (kind "table"): matrices R_g [G, N, T] at the grid
     # points lam_g of one response coordinate, interpolated linearly in lam
     table_grid: Optional[np.ndarray] = None  # [G] increasing
@@ -101,6 +104,7 @@ class Data:
     tagged: Optional[np.ndarray] = None   # [N]
     radial: Optional[np.ndarray] = None   # [n_rad]
     ps: Optional[np.ndarray] = None       # [N, n_ps]
+    joint: Optional[np.ndarray] = None    # [N, n_rad, n_ps] (joint term)
 
 
 # ---------------------------------------------------------------------------

@@ -755,3 +755,73 @@ def test_count_domain():
     th[d.S + 3] = 0.0
     with pytest.raises(om.DomainError):
         om.nll(d, x, th)
+
+
+# ---------------------------------------------------------------------------
+# joint energy x radius x pulse-shape term
+# ---------------------------------------------------------------------------
+def tiny_joint(n_rad=3, n_ps=4, seed=5):
+    d = tiny_gauss(T=7, N=9, S=3, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    d.tag_frac = np.array([0.9, 0.0, 0.2])
+    d.rad_tmpl = rng.random((3, n_rad)) + 0.05
+    d.rad_tmpl /= d.rad_tmpl.sum(1, keepdims=True)
+    d.ps_tmpl = rng.random((3, n_ps)) + 0.05
+    d.ps_tmpl /= d.ps_tmpl.sum(1, keepdims=True)
+    d.rad_win = (0, d.N)
+    d.joint = True
+    return d
+
+
+def joint_data(d, theta, seed=2):
+    mu = om.forward(d, theta).mu
+    rng = np.random.default_rng(seed)
+    return synth.Data(energy=np.zeros(d.N), tagged=rng.poisson(mu["tagged"]).astype(float),
+                      joint=rng.poisson(mu["joint"]).astype(float))
+
+
+def test_joint_expectations_brute_force_loops():
+    d = tiny_joint()
+    f = om.forward(d, d.theta_true)
+    r, t = f.r, d.tag_frac
+    lam = f.mu["joint"]
+    for j in range(d.N):
+        for k in range(3):
+            for l in range(4):
+                ref = math.fsum(f.Mp[j, s] * (1 - t[s]) * r[s] * d.rad_tmpl[s, k] * d.ps_tmpl[s, l]
+                                for s in range(3))
+                assert lam[j, k, l] == pytest.approx(ref, rel=1e-14)
+
+
+def test_joint_marginal_is_vetoed_energy_term():
+    d = tiny_joint()
+    lam = om.forward(d, d.theta_true).mu["joint"]
+    flat = d.copy()
+    flat.joint = False
+    flat.rad_tmpl = flat.ps_tmpl = None
+    assert np.allclose(lam.sum(axis=(1, 2)), om.forward(flat, d.theta_true).mu["energy"], rtol=1e-13)
+
+
+def test_joint_single_bin_templates_reduce_to_energy_and_tagged_terms():
+    d = tiny_joint(n_rad=1, n_ps=1)
+    x = joint_data(d, d.theta_true)
+    flat = d.copy()
+    flat.joint = False
+    flat.rad_tmpl = flat.ps_tmpl = None
+    xf = synth.Data(energy=x.joint[:, 0, 0], tagged=x.tagged)
+    th = d.theta_true * 1.02
+    assert om.nll(d, x, th) == pytest.approx(om.nll(flat, xf, th), rel=1e-14)
+    assert np.allclose(om.grad(d, x, th), om.grad(flat, xf, th), rtol=1e-11, atol=1e-9)
+
+
+def test_joint_gradient_vs_richardson():
+    d = tiny_joint()
+    x = joint_data(d, d.theta_true)
+    th = d.theta_true * 1.01
+    g = om.grad(d, x, th)
+    for q in range(d.P):
+        def f(v, q=q):
+            t = th.copy()
+            t[q] = v
+            return om.nll(d, x, t)
+        assert g[q] == pytest.approx(_richardson(f, th[q], 1e-3 * abs(th[q])), rel=1e-7, abs=1e-7)
