@@ -110,6 +110,14 @@ typedef struct {
   int32_t n_grid;
   const double* grid;         /* [n_grid] */
   const double* rtab;         /* [n_grid][N][T] */
+  /* 1: a joint energy x radius x pulse-shape term replaces the vetoed
+   * energy, radial and pulse-shape terms (the alternative the paper names to
+   * its additive terms, Sec. 3): the vetoed events of the fit window in one
+   * histogram bx_data.joint [N][n_rad][n_ps] with expected counts
+   * lambda_jkl = sum_s M'_js (1 - t_s) r_s rad_tmpl[s][k] ps_tmpl[s][l]; the
+   * tagged term stays.  Needs multivariate = 1, n_rad >= 1 and n_ps >= 1;
+   * rad_lo, rad_hi and bx_data.energy, radial, ps are then unused. */
+  int32_t joint;
 } bx_model_desc;
 
 /* Observed histograms (FP64 counts; integers or Asimov values >= 0). */
@@ -118,6 +126,7 @@ typedef struct {
   const double* tagged;       /* [N] TFC-tagged histogram (multivariate) */
   const double* radial;       /* [n_rad] */
   const double* ps;           /* [N][n_ps] energy x pulse-shape histogram */
+  const double* joint;        /* [N][n_rad][n_ps] vetoed events (joint term only) */
 } bx_data;
 
 typedef struct bx_model bx_model;

@@ -109,6 +109,7 @@ class Model:
         self.multivariate = tag is not None
         if self.multivariate:
             d.multivariate = 1
+            d.joint = 1 if getattr(desc, "joint", False) else 0
             d.tag_frac = dptr(arr(tag))
             rt = getattr(desc, "rad_tmpl", None)
             if rt is not None:
@@ -142,8 +143,9 @@ class Model:
 
     def _data_struct(self, data):
         x = _abi.bx_data()
-        x.energy = dptr(self._arr(data.energy))
-        for name in ("tagged", "radial", "ps"):
+        if getattr(data, "energy", None) is not None:
+            x.energy = dptr(self._arr(data.energy))
+        for name in ("tagged", "radial", "ps", "joint"):
             v = getattr(data, name, None)
             if v is not None:
                 setattr(x, name, dptr(self._arr(np.asarray(v).reshape(-1))))

@@ -32,11 +32,12 @@ class bx_model_desc(C.Structure):
                 ("precision", C.c_int32), ("multivariate", C.c_int32), ("tag_frac", _dp),
                 ("n_rad", C.c_int32), ("rad_tmpl", _dp), ("rad_lo", C.c_int32),
                 ("rad_hi", C.c_int32), ("n_ps", C.c_int32), ("ps_tmpl", _dp),
-                ("pu_float", C.c_int32), ("n_grid", C.c_int32), ("grid", _dp), ("rtab", _dp)]
+                ("pu_float", C.c_int32), ("n_grid", C.c_int32), ("grid", _dp), ("rtab", _dp),
+                ("joint", C.c_int32)]
 
 
 class bx_data(C.Structure):
-    _fields_ = [("energy", _dp), ("tagged", _dp), ("radial", _dp), ("ps", _dp)]
+    _fields_ = [("energy", _dp), ("tagged", _dp), ("radial", _dp), ("ps", _dp), ("joint", _dp)]
 
 
 class bx_fit_opts(C.Structure):

@@ -58,6 +58,7 @@ struct FitDev {
   int uniform;            // reco bins of equal width
   int pu_float;           // the pile-up fraction is theta[P - 1] (else pu_frac)
   int n_grid;             // tabulated response: grid points (kind kTable)
+  int joint;              // joint energy x radius x PS term replaces the vetoed/radial/PS terms
   double x0, inv_w;       // first reco edge, 1 / bin width (uniform bins)
   double pu_frac;
   GGConst gg;
@@ -76,6 +77,7 @@ struct FitDev {
   const double* n_t;    // [N] tagged
   const double* n_r;    // [n_rad]
   const double* n_p;    // [N][n_ps]
+  const double* n_jt;   // [N][n_rad][n_ps] joint histogram of the vetoed events
   const double* grid;   // [n_grid] tabulated response: coordinate of each matrix
   const double* Mg;     // [n_grid][N][16] exposure * R_g F^T, formed at build
   // per-evaluation state
@@ -100,6 +102,11 @@ struct FitDev {
   double* Dt;           // [N][16] tabulated response: dM/dlam in the current grid cell
   double* Dtp;          // [N][16] dM'/dlam (after pile-up)
   double* tpart;        // [n_rowblk] table-coordinate gradient partials
+  double* jnll;         // [N] joint term per reco row: NLL, flags, rate gradient [N][16],
+  int* jflag;           //   pile-up-fraction and table-coordinate gradients
+  double* jg;
+  double* jpp;
+  double* jtp;
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][4] response-gradient partials
   double* out;          // [2 + P]: nll, grad[P], flags
@@ -111,7 +118,7 @@ struct FitDev {
 // Grid sizes of one batched launch (maxima over the fits in it).
 struct LaunchShape {
   int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks;
-  int kind, prec, any_mv, any_rad;
+  int kind, prec, any_mv, any_rad, any_joint;
   int CG;  // forward tiles per wave (one value per launch)
 };
 constexpr int kStages = 8;  // colparams, cells_fwd, reduce_M, rowterms, radial, adjoint, cells_bwd, final

@@ -156,7 +156,19 @@ static bool increasing(const double* v, size_t n) {
 }
 
 bx_status set_host_data(HostModel* h, const bx_data* x) {
-  if (!x || !x->energy) return inval("data: energy histogram is NULL");
+  if (!x) return inval("data is NULL");
+  if (h->joint) {  // the joint histogram replaces the vetoed energy, radial and PS histograms
+    const size_t nj = (size_t)h->N * h->n_rad * h->n_ps;
+    if (!x->joint || !finite_nonneg(x->joint, nj)) return inval("data: joint histogram missing or invalid");
+    h->n_j.assign(x->joint, x->joint + nj);
+    if (!x->tagged || !finite_nonneg(x->tagged, h->N)) return inval("data: tagged histogram missing or invalid");
+    h->n_t.assign(x->tagged, x->tagged + h->N);
+    h->n_e.assign(h->N, 0.0);
+    h->n_r.assign(h->n_rad, 0.0);
+    h->n_p.assign((size_t)h->N * h->n_ps, 0.0);
+    return BX_OK;
+  }
+  if (!x->energy) return inval("data: energy histogram is NULL");
   if (!finite_nonneg(x->energy, h->N)) return inval("data: energy counts must be finite and >= 0");
   h->n_e.assign(x->energy, x->energy + h->N);
   if (h->mv) {
@@ -259,12 +271,15 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
     m.n_ps = d->n_ps;
     if (m.n_rad > 0) {
       if (!d->rad_tmpl || !finite_nonneg(d->rad_tmpl, (size_t)m.S * m.n_rad)) return inval("rad_tmpl invalid");
-      if (d->rad_lo < 0 || d->rad_hi > m.N || d->rad_lo >= d->rad_hi) return inval("radial window out of range");
+      if (!d->joint && (d->rad_lo < 0 || d->rad_hi > m.N || d->rad_lo >= d->rad_hi)) return inval("radial window out of range");
       m.rad_lo = d->rad_lo; m.rad_hi = d->rad_hi;
       m.rad.assign((size_t)kSP * m.n_rad, 0.0);
       for (int s = 0; s < m.S; ++s)
         for (int k = 0; k < m.n_rad; ++k) m.rad[s * m.n_rad + k] = d->rad_tmpl[s * m.n_rad + k];
     }
+    m.joint = d->joint ? 1 : 0;
+    if (m.joint && (m.n_rad < 1 || m.n_ps < 1)) return inval("the joint term needs n_rad >= 1 and n_ps >= 1");
+    if (m.joint) { m.rad_lo = 0; m.rad_hi = m.N; }
     if (m.n_ps > 0) {
       if (!d->ps_tmpl || !finite_nonneg(d->ps_tmpl, (size_t)m.S * m.n_ps)) return inval("ps_tmpl invalid");
       m.pst.assign((size_t)kSP * m.n_ps, 0.0);
@@ -302,6 +317,14 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
 
 double host_lnfact(const HostModel& h) {
   long double s = 0.0L;
+  if (h.joint) {
+    const size_t nb = (size_t)h.n_rad * h.n_ps;
+    for (int j = h.win_lo; j < h.win_hi; ++j) {
+      s += std::lgamma(h.n_t[j] + 1.0);
+      for (size_t b = 0; b < nb; ++b) s += std::lgamma(h.n_j[(size_t)j * nb + b] + 1.0);
+    }
+    return (double)s;
+  }
   for (int j = h.win_lo; j < h.win_hi; ++j) {
     s += std::lgamma(h.n_e[j] + 1.0);
     if (h.mv) s += std::lgamma(h.n_t[j] + 1.0);
@@ -362,6 +385,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->F32 = shared->F32; f->F64 = shared->F64; f->ghat = shared->ghat; f->tag = shared->tag;
     f->rad = shared->rad; f->pst = shared->pst;
     f->n_e = shared->n_e; f->n_t = shared->n_t; f->n_r = shared->n_r; f->n_p = shared->n_p;
+    f->n_jt = shared->n_jt;
   } else {
     f->xraw = c.take<double>(h.N + 1);
     f->xe = c.take<double>(h.N + 1);
@@ -377,6 +401,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->n_t = c.take<double>(h.N);
     f->n_r = c.take<double>(h.n_rad);
     f->n_p = c.take<double>((size_t)h.N * h.n_ps);
+    f->n_jt = c.take<double>(h.joint ? (size_t)h.N * h.n_rad * h.n_ps : 0);
   }
   if (h.kind == kTable) {
     if (shared) {
@@ -403,6 +428,13 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->rad_out = c.take<double>(4 + 2 * kSP);
   f->Dp = c.take<double>((size_t)h.N * kSP);
   f->ppart = c.take<double>(f->n_rowblk);
+  if (h.joint) {
+    f->jnll = c.take<double>(h.N);
+    f->jflag = c.take<int>(h.N);
+    f->jg = c.take<double>((size_t)h.N * kSP);
+    f->jpp = c.take<double>(h.N);
+    f->jtp = c.take<double>(h.N);
+  }
   if (h.kind == kTable) {
     f->Dt = c.take<double>((size_t)h.N * kSP);
     f->Dtp = c.take<double>((size_t)h.N * kSP);
@@ -424,6 +456,7 @@ HostModel shape_only(const HostModel& h) {
   s.rad_hi = h.rad_hi; s.n_ps = h.n_ps;
   s.p = h.p; s.pu_frac = h.pu_frac; s.pu_float = h.pu_float; s.exposure = h.exposure;
   s.n_grid = h.n_grid;
+  s.joint = h.joint;
   s.gg = h.gg;
   s.tiles = h.tiles;
   return s;
@@ -446,7 +479,8 @@ LaunchShape shape_of(const FitDev& f) {
   L.kind = f.kind;
   L.prec = f.prec;
   L.any_mv = f.mv;
-  L.any_rad = f.mv && f.n_rad > 0;
+  L.any_rad = f.mv && f.n_rad > 0 && !f.joint;
+  L.any_joint = f.mv && f.joint;
   return L;
 }
 
@@ -461,6 +495,7 @@ bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st) {
   BX_HIP(up(df.dev.n_t, h.n_t, st), "upload data");
   BX_HIP(up(df.dev.n_r, h.n_r, st), "upload data");
   BX_HIP(up(df.dev.n_p, h.n_p, st), "upload data");
+  if (h.joint) BX_HIP(up(df.dev.n_jt, h.n_j, st), "upload data");
   return BX_OK;
 }
 
@@ -475,6 +510,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   f.pu_frac = h.pu_frac;
   f.pu_float = h.pu_float;
   f.n_grid = h.n_grid;
+  f.joint = h.joint;
   f.gg = h.gg;
   if (shared) {  // inputs (and what is derived from them) already in place
     f.uniform = shared->uniform;

@@ -701,12 +701,13 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     const double mutag = sum16(m * t_s * r_s);
     double wsub = 0.0, wtag = 0.0;
     if (inwin) {
-      const double t1 = nll_term(musub, f.n_e[j], &wsub, &bad);
+      // with the joint term (k_joint) the vetoed events are not a term here
+      const double t1 = f.joint ? 0.0 : nll_term(musub, f.n_e[j], &wsub, &bad);
       const double t2 = nll_term(mutag, f.n_t[j], &wtag, &bad);
       if (s == 0) term = t1 + t2;
     }
     // pulse-shape row j: lambda_jk = sum_s M'_js (1 - t_s) r_s T_sk
-    for (int k = s; k < f.n_ps; k += 16) {
+    for (int k = s; k < (f.joint ? 0 : f.n_ps); k += 16) {
       double w = 0.0;
       if (inwin) {
         double lam = 0.0;
@@ -717,7 +718,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     }
     __syncthreads();
     double hps = 0.0;
-    if (s < f.S)
+    if (s < f.S && !f.joint)
       for (int k = 0; k < f.n_ps; ++k) hps += wps[rl][k] * f.pst[s * f.n_ps + k];
     // H_js = w_sub (1 - t_s) + w_tag t_s + (1 - t_s) sum_k w_ps,jk T_sk
     h = wsub * (1.0 - t_s) + wtag * t_s + (1.0 - t_s) * hps;
@@ -771,7 +772,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  if (!f.mv || f.n_rad <= 0) return;  // block-uniform
+  if (!f.mv || f.n_rad <= 0 || f.joint) return;  // block-uniform
   __shared__ double part[16][kSP], partd[16][kSP], partt[16][kSP];
   __shared__ double SW[kSP], SD[kSP], ST[kSP], A[kSP], pgs[kSP], tgs[kSP], wr[128], red[kBlock];
   __shared__ int redf[kBlock];
@@ -853,7 +854,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
   const int j0 = blockIdx.x * 16;
   const int K = pu_len(f);
   const int r1 = min(j0 + 16 + K - 1, f.N);
-  const bool rad = f.mv && f.n_rad > 0;
+  const bool rad = f.mv && f.n_rad > 0 && !f.joint;
   for (int e = threadIdx.x; e < (r1 - j0) * kSP; e += kBlock) {
     const int jj = j0 + (e >> 4), s = e & 15;
     double h = f.H[jj * kSP + s];
@@ -1080,9 +1081,19 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   if (with_grad)
     for (int b = t; b < f.n_bwdblk; b += NT)
       for (int q = 0; q < 4; ++q) acc[1 + q] += f.bwdpart[(size_t)b * 4 + q];
+  const bool jt = f.mv && f.joint;
+  if (jt)  // joint term: one partial per reco row
+    for (int b = t; b < f.N; b += NT) {
+      acc[0] += f.jnll[b];
+      fl |= f.jflag[b];
+      if (f.pu_float && with_grad) acc[5] += f.jpp[b];
+      if (tab && with_grad) acc[6] += f.jtp[b];
+    }
   // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
   double gr = 0.0;
   for (int b = t >> 4; b < f.n_rowblk; b += NT / 16) gr += f.gpart[b * kSP + (t & 15)];
+  if (jt)
+    for (int b = t >> 4; b < f.N; b += NT / 16) gr += f.jg[b * kSP + (t & 15)];
   gr += __shfl_xor(gr, 16, 64);
   gr += __shfl_xor(gr, 32, 64);
 #pragma unroll
@@ -1099,7 +1110,7 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   if (t < f.S) {
     double a = wred[0][NA + t];
     for (int v = 1; v < NW; ++v) a += wred[v][NA + t];
-    if (f.mv && f.n_rad > 0) a += f.rad_out[2 + 16 + t];
+    if (f.mv && f.n_rad > 0 && !f.joint) a += f.rad_out[2 + 16 + t];
     f.out[1 + t] = a;
     if (f.out_host) f.out_host[1 + t] = a;
   }
@@ -1112,13 +1123,13 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       flags |= wflag[v];
     }
     double pg = tot[5];  // dNLL/dp: row terms, then the radial term
-    if (f.mv && f.n_rad > 0) pg += f.rad_out[2 + 32];
+    if (f.mv && f.n_rad > 0 && !f.joint) pg += f.rad_out[2 + 32];
     if (tab) {  // the table coordinate takes the response gradient's place
       tot[1] = tot[6];
-      if (f.mv && f.n_rad > 0) tot[1] += f.rad_out[2 + 33];
+      if (f.mv && f.n_rad > 0 && !f.joint) tot[1] += f.rad_out[2 + 33];
     }
     double nll = tot[0];
-    if (f.mv && f.n_rad > 0) {
+    if (f.mv && f.n_rad > 0 && !f.joint) {
       nll += f.rad_out[0];
       flags |= (int)f.rad_out[1];
     }
@@ -1147,6 +1158,93 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
 
 __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
   final_sums<1024>(fits[active ? active[blockIdx.y] : blockIdx.y], with_grad);
+}
+
+// Joint energy x radius x pulse-shape term (the alternative to the additive
+// terms): block = one reco row j of one fit.  lambda_jkl = sum_s P_sk T_sl
+// with P_sk = M'_js (1 - t_s) r_s rho_sk, over the n_rad x n_ps bins of the
+// row; per thread a strided share of the bins, the Poisson terms and
+// G_s = sum_kl w_jkl rho_sk T_sl (w = 1 - n/lambda), then fixed-order block
+// sums.  The term's part of H_js = dNLL/d(r_s M'_js), (1 - t_s) G_s, is added
+// to H (k_rowterms wrote the tagged part) before the adjoint and the
+// backward sweep read it; the row's NLL, flags and the rate, pile-up and
+// table-coordinate gradient parts go to per-row partials.
+__global__ void __launch_bounds__(kBlock) k_joint(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int j = blockIdx.x;
+  if (!f.mv || !f.joint || j >= f.N) return;  // block-uniform
+  constexpr int NW = kBlock / 64;
+  __shared__ double P[kSP][128], Rh[kSP][128], Tl[kSP][64], wsum[NW][kSP + 1];
+  __shared__ int wfl[NW];
+  const int nr = f.n_rad, np = f.n_ps, nb = nr * np, S = f.S;
+  const bool inwin = j >= f.win_lo && j < f.win_hi;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = t; e < kSP * nr; e += kBlock) {
+    const int s = e / nr, k = e - s * nr;
+    const double rho = s < S ? f.rad[s * nr + k] : 0.0;
+    Rh[s][k] = rho;
+    P[s][k] = (inwin && s < S) ? f.Mp[j * kSP + s] * (1.0 - f.tag[s]) * f.theta[s] * rho : 0.0;
+  }
+  for (int e = t; e < kSP * np; e += kBlock) {
+    const int s = e / np, l = e - s * np;
+    Tl[s][l] = s < S ? f.pst[s * np + l] : 0.0;
+  }
+  __syncthreads();
+  double term = 0.0, G[kSP];
+#pragma unroll
+  for (int s = 0; s < kSP; ++s) G[s] = 0.0;
+  int bad = 0;
+  if (inwin) {
+    const double* nrow = f.n_jt + (size_t)j * nb;
+    for (int b = t; b < nb; b += kBlock) {
+      const int k = b / np, l = b - k * np;
+      double lam = 0.0;
+#pragma unroll
+      for (int s = 0; s < kSP; ++s) lam += P[s][k] * Tl[s][l];
+      double wv;
+      term += nll_term(lam, nrow[b], &wv, &bad);
+#pragma unroll
+      for (int s = 0; s < kSP; ++s) G[s] += wv * Rh[s][k] * Tl[s][l];
+    }
+  }
+  // fixed-order sums: within each wave, then over the waves
+  term = sum64(term);
+  bad = or64(bad);
+#pragma unroll
+  for (int s = 0; s < kSP; ++s) G[s] = sum64(G[s]);
+  if (lane == 0) {
+    wsum[w][kSP] = term;
+    wfl[w] = bad;
+#pragma unroll
+    for (int s = 0; s < kSP; ++s) wsum[w][s] = G[s];
+  }
+  __syncthreads();
+  if (t < kSP) {
+    double g = wsum[0][t];
+    for (int v = 1; v < NW; ++v) g += wsum[v][t];
+    const double hadd = t < S ? (1.0 - f.tag[t]) * g : 0.0;  // dNLL/d(r_s M'_js) of this term
+    f.H[j * kSP + t] += hadd;
+    f.jg[j * kSP + t] = hadd * f.Mp[j * kSP + t];
+    wsum[0][t] = hadd;  // read below by thread 0 only
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tot = wsum[0][kSP];
+    int fl = wfl[0];
+    for (int v = 1; v < NW; ++v) {
+      tot += wsum[v][kSP];
+      fl |= wfl[v];
+    }
+    f.jnll[j] = tot;
+    f.jflag[j] = fl;
+    double pp = 0.0, tp = 0.0;
+    for (int s = 0; s < S; ++s) {
+      if (f.pu_float) pp += wsum[0][s] * f.theta[s] * f.Dp[j * kSP + s];
+      if (f.kind == kTable && f.nresp > 0) tp += wsum[0][s] * f.theta[s] * f.Dtp[j * kSP + s];
+    }
+    if (f.pu_float) f.jpp[j] = pp;
+    if (f.kind == kTable && f.nresp > 0) f.jtp[j] = tp;
+  }
 }
 
 // Completion mark of a batched step: launched after its last kernel, it
@@ -1201,6 +1299,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
         break;
       case 4:
         if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
+        if (L.any_joint) hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), blk, 0, st, d_fits, d_active);
         break;
       case 7:
         hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
@@ -1231,6 +1330,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 4:
       if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
+      if (L.any_joint) hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), blk, 0, st, d_fits, d_active);
       break;
     case 5:  // a single histogram's adjoint: here for batches, else inside k_cells_bwd
       if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);

@@ -36,6 +36,8 @@ struct HostModel {
   std::vector<double> xraw, xe, Ec, Qt, F64, ghat, tag, rad, pst;
   std::vector<float> F32;
   std::vector<double> n_e, n_t, n_r, n_p;
+  int joint = 0;             // joint energy x radius x PS term (multivariate)
+  std::vector<double> n_j;   // its histogram [N][n_rad][n_ps]
   GGConst gg;
   Tiles tiles;
 };

@@ -232,6 +232,7 @@ static bool step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
       L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
       L.any_mv |= l.any_mv;
       L.any_rad |= l.any_rad;
+      L.any_joint |= l.any_joint;
       act_list[n++] = r->slot;
     }
     if (!n) continue;
