@@ -75,7 +75,7 @@ def parse():
                     help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-table", dest="table", action="store_false",
-                    help="skip the tabulated-response and count-estimator legs")
+                    help="skip the tabulated-response, count-estimator and joint-term legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -181,6 +181,31 @@ def count_leg(bx, synth, steps, warmup):
     m.close()
     return {"workload": f"{d.T} true bins x {d.N} counts, {d.S} species, FP64", "evals_per_s": evals,
             "stage_ms": {k: round(v, 5) for k, v in st.items() if v > 0 or k == "total"}}
+
+
+def joint_leg(bx, synth, steps, warmup):
+    """Joint energy x radius x pulse-shape term on the config-3b model (900 reco
+    bins x 100 radial x 50 pulse-shape bins = 4.5e6 bins, generalized-gamma
+    cells in FP32), histograms from simulated events."""
+    d = synth.config3b(synth.pileup_spectrum())
+    d.joint = True
+    x = synth.joint_events(d, d.theta_true, seed=0)
+    m = bx.Model(d, x, precision=bx.BX_PREC_F32)
+    th = d.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d.P))
+    for _ in range(warmup):
+        m.nll_grad(th)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        m.nll_grad(th)
+    evals = steps / (time.perf_counter() - t1)
+    st = m.stage_times(th, reps=100)
+    m.close()
+    nb = d.N * d.rad_tmpl.shape[1] * d.ps_tmpl.shape[1]
+    jms = st["radial"]  # stage 4: the joint kernel
+    return {"workload": f"{d.N} x {d.rad_tmpl.shape[1]} x {d.ps_tmpl.shape[1]} joint bins, {d.S} species",
+            "evals_per_s": evals, "stage_ms": {("joint" if k == "radial" else k): round(v, 5) for k, v in st.items()},
+            "joint_kernel": {"bins": nb, "hist_bytes": 8 * nb, "ms": jms,
+                             "GB_per_s": 8 * nb / (jms * 1e-3) / 1e9 if jms > 0 else None}}
 
 
 def serving(bx, synth, qps_list, n_req):
@@ -336,10 +361,17 @@ def main():
         print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()
     if a.table:
-        res["tabulated_response"] = table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)
-        print(f"table: {res['tabulated_response']}", file=sys.stderr, flush=True)
-        res["count_estimator"] = count_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))
-        print(f"count: {res['count_estimator']}", file=sys.stderr, flush=True)
+        # the other response kinds and likelihood forms (reported beside the
+        # headline; a failure is recorded, not fatal to the line)
+        legs = (("tabulated_response", lambda: table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)),
+                ("count_estimator", lambda: count_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))),
+                ("joint_term", lambda: joint_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))))
+        for key, fn in legs:
+            try:
+                res[key] = fn()
+            except Exception as e:  # noqa: BLE001
+                res[key] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"{key}: {res[key]}", file=sys.stderr, flush=True)
     if a.toys > 0:
         res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)
         print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)

@@ -1163,9 +1163,9 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 // Joint energy x radius x pulse-shape term (the alternative to the additive
 // terms): block = one reco row j of one fit.  lambda_jkl = sum_s P_sk T_sl
 // with P_sk = M'_js (1 - t_s) r_s rho_sk, over the n_rad x n_ps bins of the
-// row; per thread a strided share of the bins, the Poisson terms and
-// G_s = sum_kl w_jkl rho_sk T_sl (w = 1 - n/lambda), then fixed-order block
-// sums.  The term's part of H_js = dNLL/d(r_s M'_js), (1 - t_s) G_s, is added
+// row; a thread takes one pulse-shape bin l and every ngrp-th radial bin,
+// forming the Poisson terms and its part of G_s = sum_kl w_jkl rho_sk T_sl
+// (w = 1 - n/lambda), then fixed-order block sums.  The term's part of H_js = dNLL/d(r_s M'_js), (1 - t_s) G_s, is added
 // to H (k_rowterms wrote the tagged part) before the adjoint and the
 // backward sweep read it; the row's NLL, flags and the rate, pile-up and
 // table-coordinate gradient parts go to per-row partials.
@@ -1190,22 +1190,29 @@ __global__ void __launch_bounds__(kBlock) k_joint(const FitDev* fits, const int*
     Tl[s][l] = s < S ? f.pst[s * np + l] : 0.0;
   }
   __syncthreads();
+  // thread -> pulse-shape bin l of the radial bins k = kg, kg + ngrp, ...:
+  // T_sl stays in registers, and G_s = T_sl sum_k w_kl rho_sk per thread
   double term = 0.0, G[kSP];
 #pragma unroll
   for (int s = 0; s < kSP; ++s) G[s] = 0.0;
   int bad = 0;
-  if (inwin) {
+  const int ngrp = kBlock / np, l = t % np, kg = t / np;
+  if (inwin && kg < ngrp) {
     const double* nrow = f.n_jt + (size_t)j * nb;
-    for (int b = t; b < nb; b += kBlock) {
-      const int k = b / np, l = b - k * np;
+    double Ts[kSP];
+#pragma unroll
+    for (int s = 0; s < kSP; ++s) Ts[s] = Tl[s][l];
+    for (int k = kg; k < nr; k += ngrp) {
       double lam = 0.0;
 #pragma unroll
-      for (int s = 0; s < kSP; ++s) lam += P[s][k] * Tl[s][l];
+      for (int s = 0; s < kSP; ++s) lam += P[s][k] * Ts[s];
       double wv;
-      term += nll_term(lam, nrow[b], &wv, &bad);
+      term += nll_term(lam, nrow[k * np + l], &wv, &bad);
 #pragma unroll
-      for (int s = 0; s < kSP; ++s) G[s] += wv * Rh[s][k] * Tl[s][l];
+      for (int s = 0; s < kSP; ++s) G[s] += wv * Rh[s][k];
     }
+#pragma unroll
+    for (int s = 0; s < kSP; ++s) G[s] *= Ts[s];
   }
   // fixed-order sums: within each wave, then over the waves
   term = sum64(term);

@@ -346,6 +346,39 @@ def count_events(d: ModelDesc, theta, seed=0) -> Data:
     return Data(energy=hist)
 
 
+def joint_events(d: ModelDesc, theta, seed=0) -> Data:
+    """Simulated histograms of a multivariate generalized-gamma model with the
+    joint term: per species a Poisson number of events, true energies from
+    its spectrum, a gamma-distributed charge around L Q E with variance
+    v0 + v1 m + v2 m^2 (1 p.e. reco bins), tagged with probability t_s (the
+    tagged energy histogram), else a radial bin from rho_s and a pulse-shape
+    bin from T_s (the joint histogram).  A stand-in for a detector
+    simulation, seeded."""
+    rng = np.random.default_rng(seed)
+    te = np.asarray(d.true_edges, np.float64)
+    ec = 0.5 * (te[:-1] + te[1:])
+    th = np.asarray(theta, np.float64)
+    L, v0, v1, v2 = th[d.S:d.S + 4]
+    n_rad, n_ps = d.rad_tmpl.shape[1], d.ps_tmpl.shape[1]
+    joint = np.zeros((d.N, n_rad, n_ps))
+    tagged = np.zeros(d.N)
+    for s in range(d.S):
+        n_ev = rng.poisson(th[s])
+        i = rng.choice(len(ec), size=n_ev, p=d.spectra[s] / d.spectra[s].sum())
+        m = L * np.asarray(d.quench)[i] * ec[i]
+        s2 = v0 + v1 * m + v2 * m * m
+        q = rng.gamma(m * m / s2, s2 / m)
+        j = np.searchsorted(d.reco_edges, q, side="right") - 1
+        ok = (j >= 0) & (j < d.N)
+        tag = rng.random(n_ev) < d.tag_frac[s]
+        tagged += np.bincount(j[ok & tag], minlength=d.N)[: d.N]
+        v = ok & ~tag
+        k = rng.choice(n_rad, size=int(v.sum()), p=d.rad_tmpl[s] / d.rad_tmpl[s].sum())
+        l = rng.choice(n_ps, size=int(v.sum()), p=d.ps_tmpl[s] / d.ps_tmpl[s].sum())
+        np.add.at(joint, (j[v], k, l), 1.0)
+    return Data(energy=None, tagged=tagged, joint=joint)
+
+
 # multivariate templates ------------------------------------------------------
 N_RAD = 100
 N_PS = 50
