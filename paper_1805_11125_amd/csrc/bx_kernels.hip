@@ -1118,6 +1118,7 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     double tot[NA];
     int flags = wflag[0];
     for (int q = 0; q < NA; ++q) tot[q] = wred[0][q];
+#pragma unroll 1  // one wave's row at a time (a full unroll spills)
     for (int v = 1; v < NW; ++v) {
       for (int q = 0; q < NA; ++q) tot[q] += wred[v][q];
       flags |= wflag[v];
@@ -1137,12 +1138,16 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     const double v0 = (flags & ~kZeroWidth) ? INFINITY : nll;
     f.out[0] = v0;
     f.out[1 + f.P] = (double)flags;
-    for (int q = 0; q < f.nresp; ++q) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxResp; ++q)  // static indices keep tot[] in registers
+      if (q < f.nresp) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
     if (f.pu_float) f.out[f.P] = with_grad ? pg : 0.0;
     if (f.out_host) {
       f.out_host[0] = v0;
       f.out_host[1 + f.P] = (double)flags;
-      for (int q = 0; q < f.nresp; ++q) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kMaxResp; ++q)
+        if (q < f.nresp) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
       if (f.pu_float) f.out_host[f.P] = with_grad ? pg : 0.0;
     }
   }
