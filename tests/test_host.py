@@ -102,6 +102,55 @@ def test_build_rejects_bad_arrays(abi):
     assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
 
 
+def test_build_rejects_invalid_tables(abi):
+    # tabulated response: grid size, order, and matrices
+    lib = abi.load()
+    d = synth.config1()
+    G = 3
+    R = np.full((G, d.N, d.T), 1.0 / d.N)
+    for n_grid, grid, rtab in [(0, [1.0], R), (65, [1.0], R), (G, [1.0, 3.0, 2.0], R),
+                               (G, [1.0, 2.0, 3.0], -R), (G, [1.0, 2.0, np.nan], R)]:
+        s, x, keep = _desc(abi, d, grid=np.asarray(grid, np.float64), rtab=np.asarray(rtab))
+        s.response, s.n_grid = abi.BX_RESP_TABLE, n_grid
+        h = C.c_void_p()
+        assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL, (n_grid, grid)
+
+
+def test_build_rejects_invalid_count_estimator(abi):
+    # one count per reco bin, integer edges from >= 0, and the quenching table
+    lib = abi.load()
+    d = synth.count_config(T=20, N=30)
+    for edges in (np.arange(31) * 2.0, np.arange(31) + 0.5, np.arange(31) - 1.0):
+        s, x, keep = _desc(abi, d, reco_edges=edges, quench=d.quench)
+        s.response = abi.BX_RESP_COUNT
+        h = C.c_void_p()
+        assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL, edges[:3]
+    s, x, keep = _desc(abi, d)
+    s.response = abi.BX_RESP_COUNT
+    s.quench = None
+    h = C.c_void_p()
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+
+
+def test_build_rejects_joint_without_templates_or_histogram(abi):
+    lib = abi.load()
+    d = synth.config3a()
+    S = d.S
+    # the joint term needs both templates
+    s, x, keep = _desc(abi, d, tag_frac=d.tag_frac, rad_tmpl=d.rad_tmpl)
+    s.multivariate, s.joint, s.n_rad, s.n_ps = 1, 1, d.rad_tmpl.shape[1], 0
+    h = C.c_void_p()
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+    # and its histogram
+    s, x, keep = _desc(abi, d, tag_frac=d.tag_frac, rad_tmpl=d.rad_tmpl, ps_tmpl=d.ps_tmpl)
+    s.multivariate, s.joint, s.n_rad, s.n_ps = 1, 1, d.rad_tmpl.shape[1], d.ps_tmpl.shape[1]
+    t = np.ones(d.N)
+    x.tagged = t.ctypes.data_as(C.POINTER(C.c_double))
+    assert S == d.rad_tmpl.shape[0]
+    assert lib.bx_model_build(C.byref(s), C.byref(x), None, C.byref(h)) == abi.BX_E_INVAL
+    assert b"joint" in lib.bx_last_error()
+
+
 def test_null_arguments(abi):
     lib = abi.load()
     v = C.c_double()
