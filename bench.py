@@ -31,14 +31,19 @@ WORKLOAD = ("single fit, 3000 true x 900 reco bins (1 keV x 1 p.e.), 12 species,
 PEAK_FP32 = 157.3e12   # MI355X published dense FP32 vector FLOP/s
 # Algorithmic operations per CDF edge evaluation on the dominant code path
 # (the uniform expansion of the incomplete gamma, |eta| < 1), counted from the
-# formula: add/mul/transcendental = 1, FMA = 2.  Forward: one edge CDF (130)
-# plus the species contraction of its cell, 2 S; backward: the edge CDF with
-# the two column-parameter derivatives and the adjoint weight (162).  The
-# edges counted are those the method needs (oracle-counted: each column's
-# [1e-12, 1 - 1e-12] quantile support plus its two bracketing edges), not the
-# ones a kernel happens to evaluate.
-FLOP_FWD_EDGE = 130
-FLOP_BWD_EDGE = 162
+# formula: add/mul/transcendental = 1, FMA = 2.  The forward sweep of an
+# NLL+gradient evaluation forms the edge CDF (130) and its two column-
+# parameter derivatives (27), plus the species contraction of its cell, 2 S;
+# the backward sweep then only weights the stored derivative differences by
+# the adjoint (5 per edge: one product, two multiply-adds) and is bound by
+# reading them (one FP32 pair, 8 bytes, per edge).  The edges counted are
+# those the method needs (oracle-counted: each column's [1e-12, 1 - 1e-12]
+# quantile support plus its two bracketing edges), not the ones a kernel
+# happens to evaluate.
+FLOP_FWD_EDGE = 157
+FLOP_BWD_EDGE = 5
+BYTES_BWD_EDGE = 8
+PEAK_HBM = 8.0e12      # MI355X published HBM3E bandwidth, bytes/s
 
 
 def profiled(fname, key, name):
@@ -321,11 +326,15 @@ def main():
     st = m.stage_times(th, reps=200)
     edges = support_edges()
     fwd_ms, bwd_ms = st["cells_fwd"], st["cells_bwd"]
-    if bwd_ms >= fwd_ms:
-        kname, kms, flops = "k_cells_bwd", bwd_ms, edges * FLOP_BWD_EDGE
+    if bwd_ms >= fwd_ms:  # the backward sweep reads the stored differences: HBM-bound
+        kname, kms = "k_cells_bwd", bwd_ms
+        rl = {"bound": "hbm", "achieved": edges * BYTES_BWD_EDGE / (kms * 1e-3) / 1e9,
+              "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     else:
-        kname, kms, flops = "k_cells_fwd", fwd_ms, edges * (FLOP_FWD_EDGE + 2 * d.S)
-    achieved = flops / (kms * 1e-3)
+        kname, kms = "k_cells_fwd", fwd_ms
+        rl = {"bound": "alu", "achieved": edges * (FLOP_FWD_EDGE + 2 * d.S) / (kms * 1e-3) / 1e12,
+              "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s"}
+    rl["frac"] = rl["achieved"] / rl["peak"]
     traffic = profiled("config2_hbm_counters.md", "traffic_bytes", kname)
     valu = profiled("config2_valu_counters.md", "valu_issue", kname)
     res = {
@@ -337,10 +346,9 @@ def main():
                    "path": "plain (host theta in, NLL+grad out, per evaluation)"},
         "dev_path_evals_per_s": dev_evals,
         "stage_ms": {k: round(v, 5) for k, v in st.items()},
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
-                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": traffic,
+        "roofline": {**rl, "kernel": kname, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "edges_per_launch": edges,
+                     "flop_per_edge": FLOP_FWD_EDGE + 2 * d.S if kname == "k_cells_fwd" else FLOP_BWD_EDGE,
                      "valu_issue_frac": valu,
                      "kernel_ms": kms},
     }
@@ -349,15 +357,23 @@ def main():
         # model's stream): throughput of the batched form of the same evaluation
         bt = m.batch_times(th, a.batch, reps=10)
         bk = "cells_bwd" if bt["cells_bwd"] >= bt["cells_fwd"] else "cells_fwd"
-        bflop = FLOP_BWD_EDGE if bk == "cells_bwd" else FLOP_FWD_EDGE + 2 * d.S
-        bach = a.batch * edges * bflop / (bt[bk] * 1e-3)
+        if bk == "cells_bwd":
+            brl = {"bound": "hbm", "achieved": a.batch * edges * BYTES_BWD_EDGE / (bt[bk] * 1e-3) / 1e9,
+                   "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+        else:
+            brl = {"bound": "alu", "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                   "achieved": a.batch * edges * (FLOP_FWD_EDGE + 2 * d.S) / (bt[bk] * 1e-3) / 1e12}
+        brl["frac"] = brl["achieved"] / brl["peak"]
+        fwd_tf = a.batch * edges * (FLOP_FWD_EDGE + 2 * d.S) / (bt["cells_fwd"] * 1e-3) / 1e12
+        bwd_gb = a.batch * edges * BYTES_BWD_EDGE / (bt["cells_bwd"] * 1e-3) / 1e9
         res["batched_eval"] = {
             "copies": a.batch, "evals_per_s": a.batch / (bt["total"] * 1e-3),
             "us_per_eval": bt["total"] * 1e3 / a.batch,
             "stage_us_per_eval": {k: round(v * 1e3 / a.batch, 4) for k, v in bt.items()},
-            "roofline": {"bound": "alu", "kernel": "k_" + bk, "achieved": bach / 1e12,
-                         "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": bach / PEAK_FP32,
-                         "edges_per_launch": a.batch * edges, "kernel_ms": bt[bk]}}
+            "roofline": {**brl, "kernel": "k_" + bk, "edges_per_launch": a.batch * edges,
+                         "kernel_ms": bt[bk]},
+            "forward_TFLOP_s": fwd_tf, "forward_frac": fwd_tf * 1e12 / PEAK_FP32,
+            "backward_GB_s": bwd_gb, "backward_frac": bwd_gb * 1e9 / PEAK_HBM}
         print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()
     if a.table:
