@@ -185,7 +185,9 @@ bx_status bx_model_expected(bx_model* m, const double* theta, double* out);
  * kernel by kernel (no graph) the same way.  ms[9] = {column parameters,
  * forward cell sweep + species contraction, partial-sum reduction, pile-up +
  * likelihood terms, radial term, pile-up adjoint, backward cell sweep, final
- * sums, whole evaluation}; a stage the model does not have reads ~0. */
+ * sums, whole evaluation}; a stage the model does not have reads ~0.  A
+ * tabulated response reports its interpolation as the first stage; the
+ * joint term's kernel is timed with the radial stage. */
 bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms);
 
 /* Diagnostics: the same per-stage timing for a batch.  `copies` independent

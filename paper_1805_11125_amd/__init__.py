@@ -72,10 +72,16 @@ def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0,
 class Model:
     """A spectral model plus its observed histograms, resident on the GPU.
 
-    desc: object with the fields of a model description (kind "gauss"/"gg",
-    true_edges, reco_edges, spectra[S, T], exposure, gg_p, quench, pu_frac,
-    pu_g, win, and optionally tag_frac, rad_tmpl, rad_win, ps_tmpl);
-    data: object with energy (and tagged, radial, ps)."""
+    desc: object with the fields of a model description: kind ("gauss",
+    "gg", "table" or "count"), true_edges, reco_edges, spectra[S, T],
+    exposure, gg_p, quench, pu_frac, pu_g, pu_float, win; optionally the
+    multivariate fields tag_frac, rad_tmpl, rad_win, ps_tmpl and joint; and
+    for kind "table" the grid table_grid[G] and matrices table_R[G, N, T].
+    data: object with energy (and tagged, radial, ps, or joint[N, n_rad,
+    n_ps] for the joint term).  The parameter vector is the rates, then the
+    response parameters (Gaussian a, b; generalized gamma and count
+    estimator L, v0, v1, v2; table: the grid coordinate when G > 1), then
+    the pile-up fraction when it floats."""
 
     def __init__(self, desc, data, precision=BX_PREC_F32, stream=None):
         self._lib = _abi.load()
@@ -199,7 +205,9 @@ class Model:
 
     def stage_times(self, theta, reps=20):
         """Average ms per evaluation stage (HIP events, each stage's kernel
-        launched back to back on its own)."""
+        launched back to back on its own).  For a tabulated response stage
+        "colparams" is the table interpolation; "radial" also holds the
+        joint term's kernel."""
         t = _f64(theta)
         ms = np.zeros(9)
         check(self._lib.bx_model_stage_times(self._h, dptr(t), int(reps), dptr(ms)))
