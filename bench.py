@@ -335,6 +335,13 @@ def main():
         rl = {"bound": "alu", "achieved": edges * (FLOP_FWD_EDGE + 2 * d.S) / (kms * 1e-3) / 1e12,
               "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s"}
     rl["frac"] = rl["achieved"] / rl["peak"]
+    # measured ceiling: the edge arithmetic alone, same column/edge mix
+    ceil_eps = m.edge_ceiling(th, reps=64)
+    fwd_eps = edges / (fwd_ms * 1e-3)
+    ceiling = {"edges_per_s": ceil_eps, "TFLOP_s": ceil_eps * FLOP_FWD_EDGE / 1e12,
+               "forward_edges_per_s": fwd_eps, "forward_frac_of_ceiling": fwd_eps / ceil_eps,
+               "what": "registers-only evaluation of the edge CDF and its two derivatives in the "
+                       "forward sweep's lane layout, one (true tile, reco tile) of the workload per wave"}
     traffic = profiled("config2_hbm_counters.md", "traffic_bytes", kname)
     valu = profiled("config2_valu_counters.md", "valu_issue", kname)
     res = {
@@ -350,7 +357,7 @@ def main():
                      "traffic_unit": "bytes per launch", "edges_per_launch": edges,
                      "flop_per_edge": FLOP_FWD_EDGE + 2 * d.S if kname == "k_cells_fwd" else FLOP_BWD_EDGE,
                      "valu_issue_frac": valu,
-                     "kernel_ms": kms},
+                     "kernel_ms": kms, "measured_ceiling": ceiling},
     }
     if a.batch > 0:
         # one launch per stage over `batch` resident copies (HIP events on the
@@ -373,6 +380,7 @@ def main():
             "roofline": {**brl, "kernel": "k_" + bk, "edges_per_launch": a.batch * edges,
                          "kernel_ms": bt[bk]},
             "forward_TFLOP_s": fwd_tf, "forward_frac": fwd_tf * 1e12 / PEAK_FP32,
+            "forward_frac_of_ceiling": a.batch * edges / (bt["cells_fwd"] * 1e-3) / ceil_eps,
             "backward_GB_s": bwd_gb, "backward_frac": bwd_gb * 1e9 / PEAK_HBM}
         print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()

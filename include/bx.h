@@ -198,6 +198,18 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
  * it does not fit).  Synchronous on the model's stream. */
 bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies, int32_t reps, double* ms);
 
+/* Diagnostics: the rate (edge evaluations per second) that the edge
+ * arithmetic of this model's response reaches on its own (CDF value and its
+ * two column-parameter derivatives; the per-cell pmf for the count
+ * estimator), measured with the column constants and supports at theta:
+ * 256 x 8 workgroups of 4 waves, each wave one (true tile, reco tile) pair
+ * of the workload in the forward sweep's lane layout (4 edges per lane),
+ * evaluated `reps` times from registers (no tile lists, contraction or
+ * memory traffic).  It is the measured ceiling of the cell sweeps.
+ * BX_E_INVAL for a tabulated response (no edge function).
+ * Synchronous on the model's stream. */
+bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, double* edges_per_s);
+
 /* ---- fitting (Sec. 4, steps 5-7) ---- */
 typedef enum { BX_FIT = 0, BX_EVAL_GRAD = 1 } bx_request_kind;
 typedef enum { BX_CONVERGED = 0, BX_MAXITER = 1, BX_FAILED = 2 } bx_fit_status;

@@ -221,6 +221,15 @@ class Model:
         check(self._lib.bx_model_batch_times(self._h, dptr(t), int(copies), int(reps), dptr(ms)))
         return dict(zip(self.STAGES, ms))
 
+    def edge_ceiling(self, theta, reps=64):
+        """Edge evaluations per second the response's edge arithmetic reaches
+        on its own at theta (bx_model_edge_ceiling): the measured ceiling of
+        the cell sweeps."""
+        t = _f64(theta)
+        v = C.c_double()
+        check(self._lib.bx_model_edge_ceiling(self._h, dptr(t), int(reps), C.byref(v)))
+        return v.value
+
     def nll_grad_dev(self, theta_dev, out_dev, stream=None):
         """Stream-ordered: theta_dev, out_dev are device addresses (ints)."""
         check(self._lib.bx_nll_grad_dev(self._h, C.c_void_p(theta_dev), C.c_void_p(out_dev),

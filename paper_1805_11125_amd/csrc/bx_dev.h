@@ -129,5 +129,7 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
 void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
+void launch_edge_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
+                         hipStream_t st);
 
 }  // namespace bx

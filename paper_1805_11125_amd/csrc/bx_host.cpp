@@ -831,6 +831,37 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   return BX_OK;
 }
 
+bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, double* edges_per_s) {
+  if (!m || !theta || !edges_per_s || reps < 1) return inval("bad argument");
+  if (m->h.kind == kTable) return inval("a tabulated response has no edge function");
+  double nll;
+  bx_status s = model_eval(m, theta, &nll, nullptr);  // column constants and supports at theta
+  if (s != BX_OK) return s;
+  const int blocks = 256 * 8;  // 8 workgroups of 4 waves per CU
+  double* d_sink = nullptr;
+  BX_HIP(hipMalloc(&d_sink, sizeof(double)), "hipMalloc");
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    launch_edge_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, 4, d_sink, m->stream);  // warm-up
+    e = hipEventRecord(e0, m->stream);
+  }
+  if (e == hipSuccess) {
+    launch_edge_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, reps, d_sink, m->stream);
+    e = hipEventRecord(e1, m->stream);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_sink);
+  if (e != hipSuccess) return hip_fail(e, "edge ceiling");
+  *edges_per_s = (double)blocks * 256.0 * 4.0 * reps / (t * 1e-3);  // four edges per lane per repetition
+  return BX_OK;
+}
+
 bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies, int32_t reps, double* ms) {
   if (!m || !theta || !ms || copies < 1 || reps < 1) return inval("bad argument");
   const int P = m->h.P;

@@ -1259,6 +1259,64 @@ __global__ void __launch_bounds__(kBlock) k_joint(const FitDev* fits, const int*
   }
 }
 
+// Ceiling microbenchmark of the edge arithmetic, with the forward sweep's
+// lane layout: each wave takes one (true tile, reco tile) pair inside a tile
+// support (chosen by a hash of its index, so the mix of shapes and arguments
+// is the workload's), lane (j = l%16, g = l/16) holds the constants of
+// columns 4q+g, q = 0..3, and the edge x_j in registers, and evaluates the
+// four edges (value and the two column-parameter derivatives) `reps` times.
+// No list building, contraction, stored differences or memory traffic in the
+// loop: the rate the sweep's edge arithmetic alone reaches.  eps is 0 at run
+// time (it only keeps each repetition's argument from being hoisted); sink
+// is written only if the sum equals `never`, which keeps the results live.
+template <class R, int KIND>
+__global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int reps, double eps, double never,
+                                                      double* sink) {
+  const FitDev& f = fits[0];
+  const unsigned wid = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int ct = (int)((wid * 2654435761u) % (unsigned)f.n_ct);
+  const int2 b = f.tb[ct];
+  const int rt_a = b.y >= b.x ? max(b.x, 0) / kRowStep : 0;
+  const int rt_b = b.y >= b.x ? min(b.y / kRowStep, f.n_rt - 1) : 0;
+  const int rt = rt_a + (int)((wid / 7u) % (unsigned)(rt_b - rt_a + 1));
+  const double xe = f.xe[min(rt * kRowStep + jr, f.N)];
+  ColPre<R> c[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const ColPar& cp = f.cp[min(ct * kColTile + 4 * q + g, f.T - 1)];
+    c[q].c0 = cp.c0;
+    c[q].c1 = cp.c1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[q].s[u] = sizeof(R) == 4 ? (R)cp.f32[u] : (R)cp.f64[u];
+    c[q].bb = (R)0;
+  }
+  R acc = (R)0;
+  for (int r = 0; r < reps; ++r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const EdgeVal<R> ev = edge_pre<R, KIND, true>(c[q], xe + eps * r);
+      acc += ev.v + ev.d1 + ev.d2;
+    }
+  }
+  if ((double)acc == never) sink[0] = (double)acc;
+}
+
+void launch_edge_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
+                         hipStream_t st) {
+  const double eps = 0.0, never = -1.2345e300;
+  if (kind == kGG && prec == kF32)
+    hipLaunchKernelGGL((k_edge_ceiling<float, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+  else if (kind == kGG)
+    hipLaunchKernelGGL((k_edge_ceiling<double, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+  else if (kind == kGauss && prec == kF32)
+    hipLaunchKernelGGL((k_edge_ceiling<float, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+  else if (kind == kGauss)
+    hipLaunchKernelGGL((k_edge_ceiling<double, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+  else if (kind == kCount)
+    hipLaunchKernelGGL((k_edge_ceiling<double, kCount>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+}
+
 // Completion mark of a batched step: launched after its last kernel, it
 // writes v into pinned host memory once everything before it on the stream
 // is done and its results are visible to the host.
