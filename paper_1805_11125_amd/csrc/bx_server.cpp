@@ -202,8 +202,11 @@ static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
 // One step: every active fit's next point in one batched launch per group.
 // The kernels read theta from pinned memory and write the results there; the
 // host spins on the step's completion mark, reading it (and then the
-// results) past its own cache.  Returns false when the launch failed.
-static bool step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
+// results) past its own cache.  launch_step stages and enqueues (returning
+// the step number), finish_step waits and hands the results to the
+// minimisers (false when the launch failed); the worker admits new fits in
+// between, while the step runs on the GPU.
+static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
   const double seq = (s->seq += 1.0);
   // stage every active fit's next point (with the step number after it)
   s->pool->run((int)act.size(), [&](int k) {
@@ -240,6 +243,10 @@ static bool step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
     launch_eval(s->d_fits, d_list, n, L, true, s->stream);
   }
   launch_mark(s->dh_mark, seq, s->stream);
+  return seq;
+}
+
+static bool finish_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act, double seq) {
   const volatile double* mark = s->h_mark;
   for (unsigned it = 1;; ++it) {
     flush_lines(s->h_mark, 1);
@@ -276,7 +283,11 @@ static void worker_loop(bx_server* s) {
     }
     std::vector<std::shared_ptr<Req>> act = s->active;
     lk.unlock();
-    const bool ok = step(s, act);
+    const double seq = launch_step(s, act);
+    lk.lock();
+    admit(s);  // while the step runs; the new fits join the next one
+    lk.unlock();
+    const bool ok = finish_step(s, act, seq);
     lk.lock();
     if (!ok) {  // the device failed: every active fit ends as failed
       for (auto& r : s->active) {
