@@ -137,8 +137,11 @@ Tiles choose_tiles(int T, int N, int kind, int prec, int batched) {
     if (sscanf(ov, "%d,%d", &cg, &rg) == 2 && cg > 0 && rg > 0) t = Tiles{cg, rg};
   }
   t.RG = std::min(t.RG, kMaxRG);
-  int cg = 1;  // a power of two, at most kMaxCG
-  while (cg * 2 <= std::min(t.CG, kMaxCG)) cg *= 2;
+  // a power of two, at most kMaxCG; the FP64 count-estimator sweep at 8 tiles
+  // needs more than the 128 VGPRs of a 16-wave block and spills, so 4 there
+  const int cg_max = (kind == kCount && prec == kF64) ? 4 : kMaxCG;
+  int cg = 1;
+  while (cg * 2 <= std::min(t.CG, cg_max)) cg *= 2;
   t.CG = cg;
   return t;
 }

@@ -400,24 +400,6 @@ __global__ void __launch_bounds__(kBlock) k_table(const FitDev* fits, const int*
   }
 }
 
-// Edge evaluation for one lane.
-template <class R, int KIND, bool D>
-__device__ __forceinline__ EdgeVal<R> edge_at(const ColPar& c, double xe) {
-  if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
-  GGCol<R> g;
-  g.ct = c.c0;
-  if (sizeof(R) == 4) {
-    const float* s = c.f32;
-    g.k = (R)s[0]; g.ik = (R)s[1]; g.skh = (R)s[2]; g.cR = (R)s[3]; g.ce = (R)s[4];
-    g.dlngs = (R)s[5]; g.lnk_psi = (R)s[6]; g.p = (R)s[7];
-  } else {
-    const double* d = c.f64;
-    g.k = (R)d[0]; g.ik = (R)d[1]; g.skh = (R)d[2]; g.cR = (R)d[3]; g.ce = (R)d[4];
-    g.dlngs = (R)d[5]; g.lnk_psi = (R)d[6]; g.p = (R)d[7];
-  }
-  return gg_edge<R, D>(xe, g);
-}
-
 // ---------------------------------------------------------------------------
 // Balanced pairwise sum of item(OFF), ..., item(OFF + N - 1), N a power of
 // two: ((i0 + i1) + (i2 + i3)) + ...  Any aligned sub-range is a subtree, so
@@ -1174,23 +1156,24 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 // to H (k_rowterms wrote the tagged part) before the adjoint and the
 // backward sweep read it; the row's NLL, flags and the rate, pile-up and
 // table-coordinate gradient parts go to per-row partials.
-__global__ void __launch_bounds__(kBlock) k_joint(const FitDev* fits, const int* active) {
+constexpr int kJointBlock = 256;
+__global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int j = blockIdx.x;
   if (!f.mv || !f.joint || j >= f.N) return;  // block-uniform
-  constexpr int NW = kBlock / 64;
+  constexpr int NW = kJointBlock / 64;
   __shared__ double P[kSP][128], Rh[kSP][128], Tl[kSP][64], wsum[NW][kSP + 1];
   __shared__ int wfl[NW];
   const int nr = f.n_rad, np = f.n_ps, nb = nr * np, S = f.S;
   const bool inwin = j >= f.win_lo && j < f.win_hi;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < kSP * nr; e += kBlock) {
+  for (int e = t; e < kSP * nr; e += kJointBlock) {
     const int s = e / nr, k = e - s * nr;
     const double rho = s < S ? f.rad[s * nr + k] : 0.0;
     Rh[s][k] = rho;
     P[s][k] = (inwin && s < S) ? f.Mp[j * kSP + s] * (1.0 - f.tag[s]) * f.theta[s] * rho : 0.0;
   }
-  for (int e = t; e < kSP * np; e += kBlock) {
+  for (int e = t; e < kSP * np; e += kJointBlock) {
     const int s = e / np, l = e - s * np;
     Tl[s][l] = s < S ? f.pst[s * np + l] : 0.0;
   }
@@ -1201,7 +1184,7 @@ __global__ void __launch_bounds__(kBlock) k_joint(const FitDev* fits, const int*
 #pragma unroll
   for (int s = 0; s < kSP; ++s) G[s] = 0.0;
   int bad = 0;
-  const int ngrp = kBlock / np, l = t % np, kg = t / np;
+  const int ngrp = kJointBlock / np, l = t % np, kg = t / np;
   if (inwin && kg < ngrp) {
     const double* nrow = f.n_jt + (size_t)j * nb;
     double Ts[kSP];
@@ -1369,7 +1352,8 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
         break;
       case 4:
         if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
-        if (L.any_joint) hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), blk, 0, st, d_fits, d_active);
+        if (L.any_joint)
+          hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), dim3(kJointBlock), 0, st, d_fits, d_active);
         break;
       case 7:
         hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
@@ -1400,7 +1384,8 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 4:
       if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
-      if (L.any_joint) hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), blk, 0, st, d_fits, d_active);
+      if (L.any_joint)
+        hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), dim3(kJointBlock), 0, st, d_fits, d_active);
       break;
     case 5:  // a single histogram's adjoint: here for batches, else inside k_cells_bwd
       if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);
