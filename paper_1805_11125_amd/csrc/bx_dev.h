@@ -77,7 +77,10 @@ struct FitDev {
   const double* n_t;    // [N] tagged
   const double* n_r;    // [n_rad]
   const double* n_p;    // [N][n_ps]
-  const double* n_jt;   // [N][n_rad][n_ps] joint histogram of the vetoed events
+  const int* jrow;      // [N + 1] joint histogram of the vetoed events ([N][n_rad][n_ps]) as
+  const uint32_t* jent; //   its non-zero bins per row: entries jrow[j] .. jrow[j+1]-1 hold
+  const double* jval;   //   (k << 16 | l) and the count (room for every bin)
+  const double* jsig;   // [16] (sum_k rho_sk)(sum_l T_sl) of the joint term's templates
   const double* grid;   // [n_grid] tabulated response: coordinate of each matrix
   const double* Mg;     // [n_grid][N][16] exposure * R_g F^T, formed at build
   // per-evaluation state

@@ -164,6 +164,22 @@ bx_status set_host_data(HostModel* h, const bx_data* x) {
     const size_t nj = (size_t)h->N * h->n_rad * h->n_ps;
     if (!x->joint || !finite_nonneg(x->joint, nj)) return inval("data: joint histogram missing or invalid");
     h->n_j.assign(x->joint, x->joint + nj);
+    // the non-zero bins of each row, in bin order
+    const int nr = h->n_rad, np = h->n_ps;
+    h->jrow.assign(h->N + 1, 0);
+    h->jent.clear();
+    h->jval.clear();
+    for (int j = 0; j < h->N; ++j) {
+      for (int k = 0; k < nr; ++k)
+        for (int l = 0; l < np; ++l) {
+          const double v = x->joint[((size_t)j * nr + k) * np + l];
+          if (v > 0.0) {
+            h->jent.push_back((uint32_t)k << 16 | (uint32_t)l);
+            h->jval.push_back(v);
+          }
+        }
+      h->jrow[j + 1] = (int)h->jent.size();
+    }
     if (!x->tagged || !finite_nonneg(x->tagged, h->N)) return inval("data: tagged histogram missing or invalid");
     h->n_t.assign(x->tagged, x->tagged + h->N);
     h->n_e.assign(h->N, 0.0);
@@ -282,12 +298,22 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
     }
     m.joint = d->joint ? 1 : 0;
     if (m.joint && (m.n_rad < 1 || m.n_ps < 1)) return inval("the joint term needs n_rad >= 1 and n_ps >= 1");
+    if (m.joint && (size_t)m.N * m.n_rad * m.n_ps > 0x7fffffff) return inval("joint histogram above 2^31 bins");
     if (m.joint) { m.rad_lo = 0; m.rad_hi = m.N; }
     if (m.n_ps > 0) {
       if (!d->ps_tmpl || !finite_nonneg(d->ps_tmpl, (size_t)m.S * m.n_ps)) return inval("ps_tmpl invalid");
       m.pst.assign((size_t)kSP * m.n_ps, 0.0);
       for (int s = 0; s < m.S; ++s)
         for (int k = 0; k < m.n_ps; ++k) m.pst[s * m.n_ps + k] = d->ps_tmpl[s * m.n_ps + k];
+    }
+    if (m.joint) {  // sum over a row's bins of rho_sk T_sl
+      m.jsig.assign(kSP, 0.0);
+      for (int s = 0; s < m.S; ++s) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < m.n_rad; ++k) a += m.rad[s * m.n_rad + k];
+        for (int l = 0; l < m.n_ps; ++l) b += m.pst[s * m.n_ps + l];
+        m.jsig[s] = a * b;
+      }
     }
   }
   // grids
@@ -388,7 +414,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->F32 = shared->F32; f->F64 = shared->F64; f->ghat = shared->ghat; f->tag = shared->tag;
     f->rad = shared->rad; f->pst = shared->pst;
     f->n_e = shared->n_e; f->n_t = shared->n_t; f->n_r = shared->n_r; f->n_p = shared->n_p;
-    f->n_jt = shared->n_jt;
+    f->jrow = shared->jrow; f->jent = shared->jent; f->jval = shared->jval; f->jsig = shared->jsig;
   } else {
     f->xraw = c.take<double>(h.N + 1);
     f->xe = c.take<double>(h.N + 1);
@@ -404,7 +430,11 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->n_t = c.take<double>(h.N);
     f->n_r = c.take<double>(h.n_rad);
     f->n_p = c.take<double>((size_t)h.N * h.n_ps);
-    f->n_jt = c.take<double>(h.joint ? (size_t)h.N * h.n_rad * h.n_ps : 0);
+    const size_t nj = h.joint ? (size_t)h.N * h.n_rad * h.n_ps : 0;  // any data fits
+    f->jrow = c.take<int>(h.joint ? h.N + 1 : 0);
+    f->jent = c.take<uint32_t>(nj);
+    f->jval = c.take<double>(nj);
+    f->jsig = c.take<double>(h.joint ? kSP : 0);
   }
   if (h.kind == kTable) {
     if (shared) {
@@ -498,7 +528,11 @@ bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st) {
   BX_HIP(up(df.dev.n_t, h.n_t, st), "upload data");
   BX_HIP(up(df.dev.n_r, h.n_r, st), "upload data");
   BX_HIP(up(df.dev.n_p, h.n_p, st), "upload data");
-  if (h.joint) BX_HIP(up(df.dev.n_jt, h.n_j, st), "upload data");
+  if (h.joint) {
+    BX_HIP(up(df.dev.jrow, h.jrow, st), "upload data");
+    BX_HIP(up(df.dev.jent, h.jent, st), "upload data");
+    BX_HIP(up(df.dev.jval, h.jval, st), "upload data");
+  }
   return BX_OK;
 }
 
@@ -538,6 +572,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   BX_HIP(up(f.tag, h.tag, st), "upload");
   BX_HIP(up(f.rad, h.rad, st), "upload");
   BX_HIP(up(f.pst, h.pst, st), "upload");
+  if (h.joint) BX_HIP(up(f.jsig, h.jsig, st), "upload");
   if (h.kind == kTable) BX_HIP(up(f.grid, h.grid, st), "upload");
   return upload_data(h, *df, st);
 }

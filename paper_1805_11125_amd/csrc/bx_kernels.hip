@@ -290,9 +290,9 @@ struct ColPre {
 };
 
 template <class R, int KIND, bool D>
-__device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe) {
+__device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe, double lnf) {
   if constexpr (KIND == kCount) {
-    return count_cell<D>(xe, c.s);  // FP64 only: the cell at count xe itself
+    return count_cell<D>(xe, lnf, c.s);  // FP64 only: the cell at count xe itself
   } else {
     if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
     GGCol<R> g;
@@ -466,6 +466,7 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   }
   const int je = min(j0 + jr, f.N);
   const double xe = ((__attribute__((address_space(1))) const double*)f.xe)[je];
+  const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;  // count estimator: ln n! of the row
   const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
   const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
   const int n_here = n_act - lo;  // entries of this window in the list
@@ -510,7 +511,7 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
       if (q < 3) nxt = fetch(ct * kColTile + 4 * (q + 1) + g);
       const int i = ct * kColTile + 4 * q + g;
       const bool iok = i < T;
-      const EdgeVal<R> ev = edge_pre<R, KIND, D>(cur, xe);
+      const EdgeVal<R> ev = edge_pre<R, KIND, D>(cur, xe, lnf);
       const bool ok = row_ok && iok;
       // edges: the cell is the difference to the next edge (row_shl:1, all
       // lanes); counts: the lane's value is the cell itself
@@ -939,6 +940,22 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
   // this wave's first tile: cell differences and column values
   const int rt0 = rt_blk + wv * RG;
   const int rt_end = min(rt0 + RG, rt_b + 1);
+  // multivariate: the weights W_ji = sum_s H~_js r_s F_is of a tile are the
+  // FP64 MFMA product of F (16 columns x 16 species; lane: column lane%16,
+  // species 4 kb + lane/16) and (H~ r)^T, whose result layout (lane l,
+  // register q: column l/16 + 4q, row l%16) is the cells' lane layout
+  const int S = f.S;
+  double fa[4] = {0, 0, 0, 0}, thv[4] = {0, 0, 0, 0};
+  double hb0 = 0.0, hb1 = 0.0, hb2 = 0.0, hb3 = 0.0;  // (H~ r)^T operands of the tile
+  if (mv) {
+    const int i = ct * kColTile + jr;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const int s = 4 * kb + g;
+      fa[kb] = (i < T && s < S) ? ((GD*)f.F64)[(size_t)i * kSP + s] : 0.0;
+      thv[kb] = s < S ? ((GD*)f.theta)[s] : 0.0;
+    }
+  }
   R dx[4], dy[4];
   double vv[4];
   auto load_tile = [&](int rt) {
@@ -950,6 +967,15 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
       dx[q] = ok ? dcell[e] : (R)0;
       dy[q] = ok ? dcell[e + 1] : (R)0;
       vv[q] = ok && !mv ? cpar[i].v : 0.0;
+    }
+    if (mv) {
+      const int j = rt * kRowStep + jr;
+      const bool rok = rt < rt_end && j < N;
+      GD* hr = (GD*)f.Ht + (size_t)min(j, N - 1) * kSP + g;
+      hb0 = (rok && g < S) ? hr[0] : 0.0;
+      hb1 = (rok && 4 + g < S) ? hr[4] : 0.0;
+      hb2 = (rok && 8 + g < S) ? hr[8] : 0.0;
+      hb3 = (rok && 12 + g < S) ? hr[12] : 0.0;
     }
   };
   load_tile(rt0);
@@ -989,17 +1015,18 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
     const int j = rt * kRowStep + jr;
     const bool row_ok = (jr < kRowStep) && (j < N);
     const double w1 = (row_ok && !mv) ? (pre ? ((GD*)f.Ht)[(size_t)j * kSP] : htl[j - r0]) : 0.0;
+    v4d Wm = {0, 0, 0, 0};
+    if (mv) {  // wave-uniform
+      Wm = mfma16(fa[0], hb0 * thv[0], Wm);
+      Wm = mfma16(fa[1], hb1 * thv[1], Wm);
+      Wm = mfma16(fa[2], hb2 * thv[2], Wm);
+      Wm = mfma16(fa[3], hb3 * thv[3], Wm);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
       if (row_ok && i < T) {
-        double W;
-        if (!mv) {
-          W = w1 * vv[q];
-        } else {
-          W = 0.0;
-          for (int s = 0; s < f.S; ++s) W += f.Ht[j * kSP + s] * f.theta[s] * f.F64[i * kSP + s];
-        }
+        const double W = mv ? Wm[q] : w1 * vv[q];
         aA[q] += W * (double)dx[q];
         aB[q] += W * (double)dy[q];
       }
@@ -1074,7 +1101,7 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
   double gr = 0.0;
   for (int b = t >> 4; b < f.n_rowblk; b += NT / 16) gr += f.gpart[b * kSP + (t & 15)];
-  if (jt)
+  if (jt && with_grad)
     for (int b = t >> 4; b < f.N; b += NT / 16) gr += f.jg[b * kSP + (t & 15)];
   gr += __shfl_xor(gr, 16, 64);
   gr += __shfl_xor(gr, 32, 64);
@@ -1148,97 +1175,165 @@ __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* a
 }
 
 // Joint energy x radius x pulse-shape term (the alternative to the additive
-// terms): block = one reco row j of one fit.  lambda_jkl = sum_s P_sk T_sl
-// with P_sk = M'_js (1 - t_s) r_s rho_sk, over the n_rad x n_ps bins of the
-// row; a thread takes one pulse-shape bin l and every ngrp-th radial bin,
-// forming the Poisson terms and its part of G_s = sum_kl w_jkl rho_sk T_sl
-// (w = 1 - n/lambda), then fixed-order block sums.  The term's part of H_js = dNLL/d(r_s M'_js), (1 - t_s) G_s, is added
-// to H (k_rowterms wrote the tagged part) before the adjoint and the
-// backward sweep read it; the row's NLL, flags and the rate, pile-up and
-// table-coordinate gradient parts go to per-row partials.
+// terms) of reco row j: lambda_jkl = sum_s c_s rho_sk T_sl with
+// c_s = M'_js (1 - t_s) r_s over the n_rad x n_ps bins of the row.  The
+// expected counts of a row sum to sum_s c_s sigma_s, sigma_s =
+// (sum_k rho_sk)(sum_l T_sl), so the Poisson NLL sum_kl (lambda - n ln lambda)
+// and G_s = dNLL/dc_s = sigma_s - sum_kl (n / lambda) rho_sk T_sl need the
+// logarithm and the ratio at the bins with counts only: the histogram is held
+// as the list of its non-zero bins per row.  With every c_s >= 0 (the
+// templates are >= 0) no bin can have lambda < 0; otherwise the whole row is
+// scanned for the domain check.  kJointWPR waves share a row (entries
+// round-robin over their lanes), then fixed-order sums.  The term's part of
+// H_js = dNLL/d(r_s M'_js), (1 - t_s) G_s, is added to H (k_rowterms wrote
+// the tagged part) before the adjoint and the backward sweep read it; the
+// row's NLL, flags and the rate, pile-up and table-coordinate gradient parts
+// go to per-row partials.
 constexpr int kJointBlock = 256;
+constexpr int kJointWPR = 2;                                       // waves per row
+constexpr int kJointRows = kJointBlock / 64 / kJointWPR;           // rows per block
+template <bool D>
 __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const int* active) {
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) const uint32_t GU;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  const int j = blockIdx.x;
-  if (!f.mv || !f.joint || j >= f.N) return;  // block-uniform
+  if (!f.mv || !f.joint || (int)blockIdx.x * kJointRows >= f.N) return;  // block-uniform
   constexpr int NW = kJointBlock / 64;
-  __shared__ double P[kSP][128], Rh[kSP][128], Tl[kSP][64], wsum[NW][kSP + 1];
+  // rows of 18 doubles (144 B): lanes reading different radial or pulse-shape
+  // bins start 4 banks apart
+  __shared__ __align__(16) double Rk[128][kSP + 2];
+  __shared__ __align__(16) double Tl[64][kSP + 2];
+  __shared__ double wsum[NW][kSP + 2], hs[kJointRows][kSP], ht[kJointRows][kSP];
   __shared__ int wfl[NW];
-  const int nr = f.n_rad, np = f.n_ps, nb = nr * np, S = f.S;
-  const bool inwin = j >= f.win_lo && j < f.win_hi;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < kSP * nr; e += kJointBlock) {
-    const int s = e / nr, k = e - s * nr;
-    const double rho = s < S ? f.rad[s * nr + k] : 0.0;
-    Rh[s][k] = rho;
-    P[s][k] = (inwin && s < S) ? f.Mp[j * kSP + s] * (1.0 - f.tag[s]) * f.theta[s] * rho : 0.0;
+  const int nr = f.n_rad, np = f.n_ps, S = f.S;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int r = w / kJointWPR, sub = w - r * kJointWPR;
+  const int j = blockIdx.x * kJointRows + r;
+  const bool inwin = j < f.N && j >= f.win_lo && j < f.win_hi;
+  // the row's coefficients and first entries are loaded before the staging
+  double c[kSP];
+#pragma unroll
+  for (int s = 0; s < kSP; ++s)
+    c[s] = (inwin && s < S) ? ((GD*)f.Mp)[j * kSP + s] * (1.0 - ((GD*)f.tag)[s]) * ((GD*)f.theta)[s] : 0.0;
+  const int e0 = inwin ? ((GI*)f.jrow)[j] : 0, e1 = inwin ? ((GI*)f.jrow)[j + 1] : 0;
+  int e = e0 + sub * 64 + lane;
+  uint32_t bn = 0;
+  double nn = 0.0;
+  if (e < e1) {
+    bn = ((GU*)f.jent)[e];
+    nn = ((GD*)f.jval)[e];
   }
-  for (int e = t; e < kSP * np; e += kJointBlock) {
-    const int s = e / np, l = e - s * np;
-    Tl[s][l] = s < S ? f.pst[s * np + l] : 0.0;
+  for (int x = t; x < kSP * 128; x += kJointBlock) {
+    const int s = x >> 7, k = x & 127;
+    if (k < nr) Rk[k][s] = s < S ? ((GD*)f.rad)[s * nr + k] : 0.0;
+  }
+  for (int x = t; x < kSP * 64; x += kJointBlock) {
+    const int s = x >> 6, l = x & 63;
+    if (l < np) Tl[l][s] = s < S ? ((GD*)f.pst)[s * np + l] : 0.0;
+  }
+  bool dense = false;
+  double mu = 0.0;  // sum_kl lambda_jkl = sum_s c_s sigma_s
+#pragma unroll
+  for (int s = 0; s < kSP; ++s) {
+    dense |= !(c[s] >= 0.0) || !isfinite(c[s]);
+    mu += c[s] * ((GD*)f.jsig)[s];
   }
   __syncthreads();
-  // thread -> pulse-shape bin l of the radial bins k = kg, kg + ngrp, ...:
-  // T_sl stays in registers, and G_s = T_sl sum_k w_kl rho_sk per thread
-  double term = 0.0, G[kSP];
+  double term = 0.0, A[kSP];
 #pragma unroll
-  for (int s = 0; s < kSP; ++s) G[s] = 0.0;
+  for (int s = 0; s < kSP; ++s) A[s] = 0.0;
   int bad = 0;
-  const int ngrp = kJointBlock / np, l = t % np, kg = t / np;
-  if (inwin && kg < ngrp) {
-    const double* nrow = f.n_jt + (size_t)j * nb;
-    double Ts[kSP];
+  for (; e < e1; e += 64 * kJointWPR) {
+    const uint32_t b = bn;
+    const double n = nn;  // > 0
+    if (e + 64 * kJointWPR < e1) {  // next entry in flight
+      bn = ((GU*)f.jent)[e + 64 * kJointWPR];
+      nn = ((GD*)f.jval)[e + 64 * kJointWPR];
+    }
+    const double2* rk = (const double2*)&Rk[b >> 16][0];
+    const double2* tl = (const double2*)&Tl[b & 0xffff][0];
+    double q[kSP], lam = 0.0;
 #pragma unroll
-    for (int s = 0; s < kSP; ++s) Ts[s] = Tl[s][l];
-    for (int k = kg; k < nr; k += ngrp) {
+    for (int h = 0; h < kSP / 2; ++h) {
+      const double2 u = rk[h], v = tl[h];
+      q[2 * h] = u.x * v.x;
+      q[2 * h + 1] = u.y * v.y;
+    }
+#pragma unroll
+    for (int s = 0; s < kSP; ++s) lam += c[s] * q[s];
+    if (!(lam > 0.0) || !isfinite(lam)) {
+      bad |= kBadMu;
+      continue;
+    }
+    term += n * log(lam);
+    if (D) {
+      const double g = n / lam;
+#pragma unroll
+      for (int s = 0; s < kSP; ++s) A[s] += g * q[s];
+    }
+  }
+  if (inwin && dense)  // some c_s < 0 (or not finite): lambda >= 0 at every bin?
+    for (int x = sub * 64 + lane; x < nr * np; x += 64 * kJointWPR) {
+      const int k = x / np, l = x - k * np;
       double lam = 0.0;
 #pragma unroll
-      for (int s = 0; s < kSP; ++s) lam += P[s][k] * Ts[s];
-      double wv;
-      term += nll_term(lam, nrow[k * np + l], &wv, &bad);
-#pragma unroll
-      for (int s = 0; s < kSP; ++s) G[s] += wv * Rh[s][k];
+      for (int s = 0; s < kSP; ++s) lam += c[s] * (Rk[k][s] * Tl[l][s]);
+      if (!(lam >= 0.0) || !isfinite(lam)) bad |= kBadMu;
     }
-#pragma unroll
-    for (int s = 0; s < kSP; ++s) G[s] *= Ts[s];
-  }
-  // fixed-order sums: within each wave, then over the waves
   term = sum64(term);
   bad = or64(bad);
+  if (D) {
 #pragma unroll
-  for (int s = 0; s < kSP; ++s) G[s] = sum64(G[s]);
+    for (int s = 0; s < kSP; ++s) A[s] = sum64(A[s]);
+  }
   if (lane == 0) {
     wsum[w][kSP] = term;
+    wsum[w][kSP + 1] = mu;
     wfl[w] = bad;
+    if (D) {
 #pragma unroll
-    for (int s = 0; s < kSP; ++s) wsum[w][s] = G[s];
+      for (int s = 0; s < kSP; ++s) wsum[w][s] = A[s];
+    }
   }
   __syncthreads();
-  if (t < kSP) {
-    double g = wsum[0][t];
-    for (int v = 1; v < NW; ++v) g += wsum[v][t];
-    const double hadd = t < S ? (1.0 - f.tag[t]) * g : 0.0;  // dNLL/d(r_s M'_js) of this term
-    f.H[j * kSP + t] += hadd;
-    f.jg[j * kSP + t] = hadd * f.Mp[j * kSP + t];
-    wsum[0][t] = hadd;  // read below by thread 0 only
+  // per row: sub-wave partials in order
+  if (D && t < kJointRows * kSP) {
+    const int rr = t / kSP, s = t - rr * kSP, jj = blockIdx.x * kJointRows + rr;
+    const bool in = jj < f.N && jj >= f.win_lo && jj < f.win_hi;
+    double a = wsum[rr * kJointWPR][s];
+    for (int v = 1; v < kJointWPR; ++v) a += wsum[rr * kJointWPR + v][s];
+    const double hadd = (in && s < S) ? (1.0 - f.tag[s]) * (f.jsig[s] - a) : 0.0;  // (1 - t_s) G_s
+    if (jj < f.N) {
+      f.H[jj * kSP + s] += hadd;
+      f.jg[jj * kSP + s] = hadd * f.Mp[jj * kSP + s];
+    }
+    // pile-up-fraction and table-coordinate parts, summed over s below
+    hs[rr][s] = f.pu_float && jj < f.N ? hadd * f.theta[s] * f.Dp[jj * kSP + s] : 0.0;
+    ht[rr][s] = f.kind == kTable && f.nresp > 0 && jj < f.N ? hadd * f.theta[s] * f.Dtp[jj * kSP + s] : 0.0;
   }
-  __syncthreads();
-  if (t == 0) {
-    double tot = wsum[0][kSP];
-    int fl = wfl[0];
-    for (int v = 1; v < NW; ++v) {
-      tot += wsum[v][kSP];
-      fl |= wfl[v];
+  if (D) __syncthreads();
+  if (t < kJointRows) {
+    const int jj = blockIdx.x * kJointRows + t;
+    if (jj >= f.N) return;
+    double lt = wsum[t * kJointWPR][kSP];
+    int fl = wfl[t * kJointWPR];
+    for (int v = 1; v < kJointWPR; ++v) {
+      lt += wsum[t * kJointWPR + v][kSP];
+      fl |= wfl[t * kJointWPR + v];
     }
-    f.jnll[j] = tot;
-    f.jflag[j] = fl;
-    double pp = 0.0, tp = 0.0;
-    for (int s = 0; s < S; ++s) {
-      if (f.pu_float) pp += wsum[0][s] * f.theta[s] * f.Dp[j * kSP + s];
-      if (f.kind == kTable && f.nresp > 0) tp += wsum[0][s] * f.theta[s] * f.Dtp[j * kSP + s];
+    f.jnll[jj] = wsum[t * kJointWPR][kSP + 1] - lt;
+    f.jflag[jj] = fl;
+    if (D) {
+      double pp = 0.0, tp = 0.0;
+      for (int s = 0; s < S; ++s) {
+        pp += hs[t][s];
+        tp += ht[t][s];
+      }
+      if (f.pu_float) f.jpp[jj] = pp;
+      if (f.kind == kTable && f.nresp > 0) f.jtp[jj] = tp;
     }
-    if (f.pu_float) f.jpp[j] = pp;
-    if (f.kind == kTable && f.nresp > 0) f.jtp[j] = tp;
   }
 }
 
@@ -1264,6 +1359,7 @@ __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int re
   const int rt_b = b.y >= b.x ? min(b.y / kRowStep, f.n_rt - 1) : 0;
   const int rt = rt_a + (int)((wid / 7u) % (unsigned)(rt_b - rt_a + 1));
   const double xe = f.xe[min(rt * kRowStep + jr, f.N)];
+  const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;
   ColPre<R> c[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -1278,7 +1374,7 @@ __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int re
   for (int r = 0; r < reps; ++r) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const EdgeVal<R> ev = edge_pre<R, KIND, true>(c[q], xe + eps * r);
+      const EdgeVal<R> ev = edge_pre<R, KIND, true>(c[q], xe + eps * r, lnf);
       acc += ev.v + ev.d1 + ev.d2;
     }
   }
@@ -1334,6 +1430,13 @@ static void launch_fwd(int cg, bool d, dim3 grid, dim3 blk, hipStream_t st, cons
 // 3 rowterms, 4 radial, 5 adjoint, 6 cells_bwd, 7 final.  Stages that do not
 // apply (radial/adjoint without multivariate terms, the backward stages
 // without the gradient) launch nothing.
+static void launch_joint(const LaunchShape& L, int n, bool with_grad, hipStream_t st, const FitDev* d_fits,
+                         const int* d_active) {
+  const dim3 g((L.max_NS / kSP + kJointRows - 1) / kJointRows, n);
+  if (with_grad) hipLaunchKernelGGL(k_joint<true>, g, dim3(kJointBlock), 0, st, d_fits, d_active);
+  else hipLaunchKernelGGL(k_joint<false>, g, dim3(kJointBlock), 0, st, d_fits, d_active);
+}
+
 void launch_stage(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
                   int stage, hipStream_t st) {
   const dim3 blk(kBlock);
@@ -1353,7 +1456,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       case 4:
         if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
         if (L.any_joint)
-          hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), dim3(kJointBlock), 0, st, d_fits, d_active);
+          launch_joint(L, n, with_grad, st, d_fits, d_active);
         break;
       case 7:
         hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
@@ -1385,7 +1488,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
     case 4:
       if (L.any_rad) hipLaunchKernelGGL(k_radial, dim3(1, n), blk, 0, st, d_fits, d_active);
       if (L.any_joint)
-        hipLaunchKernelGGL(k_joint, dim3(L.max_NS / kSP, n), dim3(kJointBlock), 0, st, d_fits, d_active);
+        launch_joint(L, n, with_grad, st, d_fits, d_active);
       break;
     case 5:  // a single histogram's adjoint: here for batches, else inside k_cells_bwd
       if (with_grad && L.any_mv) hipLaunchKernelGGL(k_adjoint, grow, blk, 0, st, d_fits, d_active);

@@ -451,14 +451,15 @@ BX_HD EdgeVal<R> gg_edge(double lnx, const GGCol<R>& c) {
 // Count estimator (FP64): reco bin j holds the single count n; negative
 // binomial P(n) = Gamma(n + r) / (Gamma(r) n!) (r/(r+m))^r (m/(r+m))^n with
 // mean m and shape r.  c = {m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)),
-// psi(r)}.  v = P(n), d1 = dP/dm, d2 = dP/dr.
+// psi(r)}; lnf = ln n! (a property of the row, formed once per lane).
+// v = P(n), d1 = dP/dm, d2 = dP/dr.
 template <bool D>
-BX_HD EdgeVal<double> count_cell(double n, const double* c) {
+BX_HD EdgeVal<double> count_cell(double n, double lnf, const double* c) {
   EdgeVal<double> o;
   o.v = o.d1 = o.d2 = 0.0;
   const double m = c[0], r = c[1];
   if (!(n >= 0.0) || !(m > 0.0)) return o;
-  const double P = exp(lgamma(n + r) - c[2] - lgamma(n + 1.0) + r * c[3] + n * c[4]);
+  const double P = exp(lgamma(n + r) - c[2] - lnf + r * c[3] + n * c[4]);
   o.v = P;
   if (D) {
     const double irm = 1.0 / (r + m);

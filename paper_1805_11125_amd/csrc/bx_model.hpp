@@ -38,6 +38,10 @@ struct HostModel {
   std::vector<double> n_e, n_t, n_r, n_p;
   int joint = 0;             // joint energy x radius x PS term (multivariate)
   std::vector<double> n_j;   // its histogram [N][n_rad][n_ps]
+  std::vector<int> jrow;     // and its non-zero bins per row (row starts [N + 1],
+  std::vector<uint32_t> jent;  // k << 16 | l, counts)
+  std::vector<double> jval;
+  std::vector<double> jsig;   // [16] (sum_k rho_sk)(sum_l T_sl)
   GGConst gg;
   Tiles tiles;
 };
