@@ -115,3 +115,30 @@ def test_joint_server_equals_plain(bx):
     s.close()
     for a, b in zip(plain, srv):
         assert a.status == b.status and a.nll == b.nll and np.array_equal(a.x, b.x)
+
+
+def test_joint_negative_rate_domain(bx):
+    # A negative rate makes some coefficients c_s < 0.  The kernel handles
+    # the bins with counts one by one, and the empty ones only through the
+    # closed-form sum, so a row with c_s < 0 is scanned bin by bin for
+    # lambda >= 0.  Two cases: lambda stays >= 0 everywhere (parity holds),
+    # and lambda < 0 only in empty bins (a domain error, as in the oracle).
+    d = to_joint(synth.config3a())
+    x = draw(d, d.theta_true)
+    ok = d.theta_true.copy()
+    ok[2] = -1e-3 * ok[2]
+    lam = om.forward(d, ok).mu["joint"]
+    assert lam.min() >= 0.0
+    check(bx, d, x, ok, F64, "joint/negative rate, lambda >= 0")
+    bad = d.theta_true.copy()
+    bad[0] = -1e-3 * bad[0]
+    lam = om.forward(d, bad).mu["joint"]
+    j0, j1 = d.win
+    neg = lam < 0
+    assert neg.any() and not np.any(x.joint[j0:j1][neg] > 0)  # negative only where empty
+    m = bx.Model(d, x, precision=F64)
+    with pytest.raises(bx.DomainError):
+        m.nll(bad)
+    with pytest.raises(bx.DomainError):
+        m.nll_grad(bad)
+    assert np.isfinite(m.nll(d.theta_true))
