@@ -901,7 +901,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint1(const FitDev* fits, const i
 // pre, a single histogram's adjoint w~ comes from k_adjoint1 (batched
 // launches, where forming it here for every true tile would repeat it for
 // each tile that reaches a row); the two give the same bits.
-template <class R>
+// MV: the launch holds multivariate fits (without it their code is compiled
+// out, which keeps the single-histogram sweep's registers and schedule).
+template <class R, bool MV>
 __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits, const int* active, int pre) {
   constexpr int NT = kBwdWaves * 64;
   constexpr int kRows = kBwdWaves * kMaxRG * kRowStep;
@@ -917,7 +919,7 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
   __shared__ double hst[kRows + kMaxK], htl[kRows], gl[kMaxK];
   __shared__ double pq[kRows][4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
-  const int T = f.T, N = f.N, RG = f.RG, mv = f.mv;
+  const int T = f.T, N = f.N, RG = f.RG, mv = MV ? f.mv : 0;
   GColPar* const cpar = (GColPar*)f.cp;
   GR* const dcell = (GR*)f.Dcell;  // pairs (dF/dc1, dF/dc2) differences
   GD* const Hg = (GD*)f.H;
@@ -1497,8 +1499,14 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 6:
       if (!with_grad) break;
-      if (f32) hipLaunchKernelGGL((k_cells_bwd<float>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
-      else hipLaunchKernelGGL((k_cells_bwd<double>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      if (f32 && L.any_mv)
+        hipLaunchKernelGGL((k_cells_bwd<float, true>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      else if (f32)
+        hipLaunchKernelGGL((k_cells_bwd<float, false>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      else if (L.any_mv)
+        hipLaunchKernelGGL((k_cells_bwd<double, true>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      else
+        hipLaunchKernelGGL((k_cells_bwd<double, false>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
