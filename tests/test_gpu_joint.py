@@ -142,3 +142,27 @@ def test_joint_negative_rate_domain(bx):
     with pytest.raises(bx.DomainError):
         m.nll_grad(bad)
     assert np.isfinite(m.nll(d.theta_true))
+
+
+def test_joint_set_data_rebuilds_the_bin_lists(bx):
+    # The non-zero bins are listed again on new data: from a sparse
+    # histogram to one with counts in every bin and back, each against the
+    # oracle and against a model built on that data.
+    d = to_joint(synth.config3a())
+    th = d.theta_true * 1.002
+    sparse = draw(d, d.theta_true, seed=21)
+    full = synth.Data(energy=None, tagged=sparse.tagged.copy(), joint=sparse.joint + 1.0)
+    assert np.all(full.joint > 0) and np.mean(sparse.joint > 0) < 0.2
+    m = bx.Model(d, sparse, precision=F64)
+    v1, g1 = m.nll_grad(th)
+    for x in (full, sparse):
+        m.set_data(x)
+        v, g = m.nll_grad(th)
+        v0, g0 = oracle.nll_grad(d, x, th)
+        sc = oracle.grad_scale(d, x, th)
+        assert abs(v - v0) <= 1e-9 * abs(v0)
+        assert np.all(np.abs(g - g0) / sc <= 1e-6)
+        fresh = bx.Model(d, x, precision=F64)
+        assert fresh.nll_grad(th)[0] == v
+        fresh.close()
+    assert v == v1 and np.array_equal(g, g1)
