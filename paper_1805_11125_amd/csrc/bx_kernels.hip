@@ -16,14 +16,24 @@
 //                 every likelihood term per reco row (Eqs. 3-4), Poisson NLL
 //                 terms, the adjoint weights H and per-block partials.
 //   k_radial      radial term (Eq. 4) -- one block per fit.
-//   k_adjoint     H~ = P^T H (the pile-up adjoint), from LDS.
+//   k_joint       joint energy x radius x pulse-shape term per reco row, over
+//                 the histogram's non-zero bins (closed-form sum of the
+//                 expected counts for the rest).
+//   k_adjoint     H~ = P^T H (the pile-up adjoint), from LDS; k_adjoint1 the
+//                 single-histogram w~ once per fit for batched launches.
 //   k_cells_bwd   per (true tile, 4 reco tiles): reads the cells' derivatives
 //                 in the two column parameters from Dcell; accumulates
 //                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
-//                 W_ji = sum_s H~_js r_s F^_si, and contracts them with the
+//                 W_ji = sum_s H~_js r_s F^_si (FP64 MFMA per tile with
+//                 several species histograms), and contracts them with the
 //                 column chain factors into a per-block gradient partial.
 //   k_final       fixed-order totals: NLL, rate gradient, response gradient;
 //                 also written to the caller's pinned host buffer when set.
+//   k_table_gemm  tabulated response, at build: M_g = R_g F^T (FP64 MFMA);
+//   k_table       per evaluation: M and dM/dlam interpolated between grid
+//                 points (replaces k_colparams .. k_reduce_M).
+//   k_mark        a server step's completion mark; k_edge_ceiling the edge
+//                 arithmetic alone, for the measured ceiling.
 //
 // No reduction uses atomics: every sum has a fixed order, so a fit's result
 // does not depend on what else runs in the same launch.  Cross-block sums are
