@@ -117,6 +117,148 @@ __device__ int2 cell_range(const FitDev& f, double xlo, double xhi) {
 }
 
 // ---------------------------------------------------------------------------
+// Column parameters of the count estimator: negative binomial with mean
+// m = L Q E and shape r = m^2 / (s^2 - m) (c1 = m, c2 = r).  Its support, the
+// counts with ln P(n) >= ln P(mode) - B, is bracketed on the continuous
+// extension of ln P (unimodal in n).  Each column takes 8 lanes: 4 search
+// the lower end and 4 the upper end at once, each round testing 4 interior
+// points of the bracket and keeping the sub-interval where the test changes,
+// so the bracket shrinks 5-fold per round (a single thread's bisection needs
+// ~10 sequential rounds of two lgamma per end).  A block covers the same 64
+// columns as a k_colparams block, so the flag partials and tile supports are
+// laid out alike.
+constexpr int kCpLanes = 8;                      // lanes per column (half per end)
+constexpr int kCpCountBlock = kCpLanes * kCpBlock;
+__global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
+  constexpr int NE = kCpLanes / 2;  // test points per end and round
+  const int t = threadIdx.x, lane = t & 63, u = lane & (kCpLanes - 1);
+  const int col = t / kCpLanes;  // 0..63 within the block
+  const int i = blockIdx.x * kCpBlock + col;
+  __shared__ double sth[kMaxP + 1];
+  __shared__ int slo[kCpBlock], shi[kCpBlock], sbad[kCpBlock];
+  // theta as in k_colparams (pinned host source, device copy by block 0)
+  const double* th = f.theta;
+  if (f.theta_src) {
+    if (t <= f.P) {
+      const double v = __hip_atomic_load(f.theta_src + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      sth[t] = v;
+      if (blockIdx.x == 0) const_cast<double*>(f.theta)[t] = v;
+    }
+    __syncthreads();
+    th = sth;
+  }
+  const bool valid = i < f.T;
+  const int ic = valid ? i : f.T - 1;
+  int bad = 0;
+  bool okth = true;
+  for (int q = 0; q < f.P; ++q) okth = okth && isfinite(th[q]);
+  if (f.pu_float && !(th[f.P - 1] >= 0.0 && th[f.P - 1] <= 1.0)) okth = false;
+  if (!okth) bad |= kBadTheta;
+  const double E = f.Ec[ic];
+  const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
+  const double m = L * f.Qt[ic] * E;
+  const double s2 = v0 + v1 * m + v2 * m * m;
+  const bool dom = (m > 0.0) && (s2 > m) && isfinite(s2);
+  if (!dom) bad |= kBadGG;
+  const double d = s2 - m, r = dom ? m * m / d : 1.0;
+  const double lq = dom ? log(r / (r + m)) : 0.0, lp = dom ? log(m / (r + m)) : 0.0;
+  const double lgr = lgamma(r);
+  auto lnP = [&](double n) { return lgamma(n + r) - lgr - lgamma(n + 1.0) + r * lq + n * lp; };
+  const double B = 1.05 * kSupportB;
+  const double mode = r > 1.0 ? floor((r - 1.0) * m / r) : 0.0;
+  const double top = lnP(mode) - B;
+  // first half of the column's lanes: lower end, lnP(a) < top <= lnP(b);
+  // second half: upper end, lnP(a) >= top > lnP(b); the test is "lnP(x) on
+  // a's side" for either
+  const bool upper = u >= NE;
+  const int k8 = u & (NE - 1);
+  double a, bb;
+  bool search;
+  if (upper) {
+    a = mode;
+    bb = mode + 10.0 * sqrt(fmax(s2, 0.0)) + 10.0;
+    for (int it = 0; it < 40 && dom && lnP(bb) >= top; ++it) bb = mode + 2.0 * (bb - mode);
+    search = dom;
+  } else {
+    a = 0.0;
+    bb = mode;
+    search = dom && lnP(0.0) < top;
+  }
+  for (int it = 0; it < 30; ++it) {
+    const bool go = search && bb - a > 0.5;
+    if (!__any(go)) break;
+    const double w9 = (bb - a) / (double)(NE + 1);
+    const double x = a + w9 * (double)(k8 + 1);
+    const double lx = go ? lnP(x) : 0.0;
+    const bool pred = upper ? (lx >= top) : (lx < top);
+    const unsigned long long bal = __ballot(go && pred);
+    const unsigned m8 = (unsigned)(bal >> (lane & ~(NE - 1))) & ((1u << NE) - 1u);  // this end's tests
+    if (go) {
+      const int tf = __builtin_ctz(~m8 | (1u << NE));  // first point not on a's side (NE: none)
+      const double na = tf > 0 ? a + w9 * (double)tf : a;
+      const double nb = tf < NE ? a + w9 * (double)(tf + 1) : bb;
+      a = na;
+      bb = nb;
+    }
+  }
+  // the lower end's a (0 without a search) and the upper end's b, to lane 0
+  // of the column's lanes
+  const double lo_end = search ? a : 0.0;
+  const double lo = __shfl(lo_end, lane & ~(kCpLanes - 1), 64);
+  const double hi = __shfl(bb, (lane & ~(kCpLanes - 1)) + NE, 64);
+  int jlo = 1 << 30, jhi = -1;
+  if (u == 0 && valid) {
+    ColPar& c = f.cp[i];  // fields stored as formed
+    double v = 0.0;
+    for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
+    c.v = v;
+    for (int q = 0; q < kMaxResp; ++q) c.J[0][q] = c.J[1][q] = 0.0;
+    for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
+    if (!dom) {
+      c.c0 = 1.0; c.c1 = 1.0;
+    } else {
+      const double cst[8] = {m, r, lgr, lq, lp, digamma_pos(r), 0.0, 0.0};
+      for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
+      c.c0 = m;
+      c.c1 = r;
+      for (int q = 0; q < 4; ++q) {
+        const double dm = (q == 0) ? m / L : 0.0;
+        const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + (v1 + 2.0 * v2 * m) * dm;
+        c.J[0][q] = dm;
+        c.J[1][q] = (2.0 * m * dm * d - m * m * (ds2 - dm)) / (d * d);
+      }
+      const int2 rr = cell_range(f, lo, hi + 1.0);
+      jlo = rr.x; jhi = rr.y;
+    }
+    if (bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
+    c.jlo = jlo; c.jhi = jhi; c.bad = bad; c.pad = 0;
+  }
+  if (u == 0) {
+    slo[col] = jlo;
+    shi[col] = jhi;
+    sbad[col] = valid ? bad : 0;
+  }
+  __syncthreads();
+  // support of each 16-column tile, domain flags of the block
+  if (t < kCpBlock / 16) {
+    int tl = 1 << 30, th_ = -1;
+    for (int q = 0; q < 16; ++q) {
+      tl = min(tl, slo[16 * t + q]);
+      th_ = max(th_, shi[16 * t + q]);
+    }
+    const int i0 = blockIdx.x * kCpBlock + 16 * t;
+    if (i0 < f.T) f.tb[i0 >> 4] = make_int2(tl, th_);
+  }
+  if (t == 0) {
+    int fl = 0;
+    for (int q = 0; q < kCpBlock; ++q) fl |= sbad[q];
+    f.cpflag[blockIdx.x] = fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
@@ -166,52 +308,6 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
       const double zb = sqrt(2.0 * (f.prec == kF32 ? kSupportB32 : kSupportB));
       const int2 r = cell_range(f, E - zb * sig, E + zb * sig);
       jlo = r.x; jhi = r.y;
-    } else if (f.kind == kCount) {
-      // count estimator: negative binomial with mean m = L Q E and shape
-      // r = m^2 / (s^2 - m); c1 = m, c2 = r
-      const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
-      const double m = L * f.Qt[i] * E;
-      const double s2 = v0 + v1 * m + v2 * m * m;
-      if (!(m > 0.0) || !(s2 > m) || !isfinite(s2)) {
-        bad |= kBadGG;
-        c.c0 = 1.0; c.c1 = 1.0;
-      } else {
-        const double d = s2 - m, r = m * m / d;
-        const double lq = log(r / (r + m)), lp = log(m / (r + m)), lgr = lgamma(r);
-        const double cst[8] = {m, r, lgr, lq, lp, digamma_pos(r), 0.0, 0.0};
-        for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
-        c.c0 = m;
-        c.c1 = r;
-        for (int q = 0; q < 4; ++q) {
-          const double dm = (q == 0) ? m / L : 0.0;
-          const double ds2 = (q == 1 ? 1.0 : q == 2 ? m : q == 3 ? m * m : 0.0) + (v1 + 2.0 * v2 * m) * dm;
-          c.J[0][q] = dm;
-          c.J[1][q] = (2.0 * m * dm * d - m * m * (ds2 - dm)) / (d * d);
-        }
-        // support: counts with ln P(n) >= ln P(mode) - B (ln P is unimodal in
-        // n), bracketed by bisection on the continuous extension
-        auto lnP = [&](double n) { return lgamma(n + r) - lgr - lgamma(n + 1.0) + r * lq + n * lp; };
-        const double B = 1.05 * kSupportB;
-        const double mode = r > 1.0 ? floor((r - 1.0) * m / r) : 0.0;
-        const double top = lnP(mode) - B;
-        double lo = 0.0;
-        if (lnP(0.0) < top) {
-          double a = 0.0, b = mode;  // lnP(a) < top <= lnP(b)
-          for (int it = 0; it < 60 && b - a > 0.5; ++it) {
-            const double c2 = 0.5 * (a + b);
-            if (lnP(c2) < top) a = c2; else b = c2;
-          }
-          lo = a;
-        }
-        double a = mode, b = mode + 10.0 * sqrt(s2) + 10.0;
-        for (int it = 0; it < 40 && lnP(b) >= top; ++it) b = mode + 2.0 * (b - mode);
-        for (int it = 0; it < 60 && b - a > 0.5; ++it) {  // lnP(a) >= top > lnP(b)
-          const double c2 = 0.5 * (a + b);
-          if (lnP(c2) >= top) a = c2; else b = c2;
-        }
-        const int2 rr = cell_range(f, lo, b + 1.0);
-        jlo = rr.x; jhi = rr.y;
-      }
     } else {
       const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
       const double m = L * f.Qt[i] * E;
@@ -1480,8 +1576,12 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
   }
   switch (stage) {
     case 0:
-      hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st,
-                         d_fits, d_active);
+      if (L.kind == kCount)
+        hipLaunchKernelGGL(k_colparams_count, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpCountBlock), 0,
+                           st, d_fits, d_active);
+      else
+        hipLaunchKernelGGL(k_colparams, dim3((L.max_T + kCpBlock - 1) / kCpBlock, n), dim3(kCpBlock), 0, st,
+                           d_fits, d_active);
       break;
     case 1:
       if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
