@@ -42,7 +42,8 @@ struct ColPar {
   double c1;        // Gauss: 1/sigma;  GG: k;                 count: r
   double v;         // sum_s r_s F^_si  (expected deposited counts in true bin i)
   float f32[8];     // GG edge constants (k, 1/k, sqrt(k/2), cR, ce, dlnG*, ln k - psi, p)
-  double f64[8];    // the same in FP64 (count: m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)), psi(r))
+  double f64[8];    // the same in FP64 (count: m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)), psi(r),
+                    // 1/(r+m), 1/m)
   double J[2][kMaxResp];  // d(c1, c2)/d(response parameter q)
   int jlo, jhi;     // cells that may be non-zero (support)
   int bad;          // domain flags

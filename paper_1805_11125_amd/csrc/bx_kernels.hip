@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev*
     if (!dom) {
       c.c0 = 1.0; c.c1 = 1.0;
     } else {
-      const double cst[8] = {m, r, lgr, lq, lp, digamma_pos(r), 0.0, 0.0};
+      const double cst[8] = {m, r, lgr, lq, lp, digamma_pos(r), 1.0 / (r + m), 1.0 / m};
       for (int q = 0; q < 8; ++q) { c.f64[q] = cst[q]; c.f32[q] = (float)cst[q]; }
       c.c0 = m;
       c.c1 = r;

@@ -451,7 +451,8 @@ BX_HD EdgeVal<R> gg_edge(double lnx, const GGCol<R>& c) {
 // Count estimator (FP64): reco bin j holds the single count n; negative
 // binomial P(n) = Gamma(n + r) / (Gamma(r) n!) (r/(r+m))^r (m/(r+m))^n with
 // mean m and shape r.  c = {m, r, ln Gamma(r), ln(r/(r+m)), ln(m/(r+m)),
-// psi(r)}; lnf = ln n! (a property of the row, formed once per lane).
+// psi(r), 1/(r+m), 1/m} (per column); lnf = ln n! (a property of the row,
+// formed once per lane).
 // v = P(n), d1 = dP/dm, d2 = dP/dr.
 template <bool D>
 BX_HD EdgeVal<double> count_cell(double n, double lnf, const double* c) {
@@ -462,8 +463,8 @@ BX_HD EdgeVal<double> count_cell(double n, double lnf, const double* c) {
   const double P = exp(lgamma(n + r) - c[2] - lnf + r * c[3] + n * c[4]);
   o.v = P;
   if (D) {
-    const double irm = 1.0 / (r + m);
-    o.d1 = P * (n / m - (n + r) * irm);
+    const double irm = c[6];
+    o.d1 = P * (n * c[7] - (n + r) * irm);
     o.d2 = P * (digamma_pos(n + r) - c[5] + c[3] + (m - n) * irm);
   }
   return o;
