@@ -1179,40 +1179,77 @@ __device__ __forceinline__ int or64(int x) {
 template <int NT>
 __device__ void final_sums(const FitDev& f, int with_grad) {
   constexpr int NW = NT / 64;
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) double GDw;
   // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient,
   // table-coordinate gradient
   constexpr int NA = 7;
   __shared__ double wred[NW][NA + kSP];
   __shared__ int wflag[NW];
+  // every field used is read into registers before the first store (a store
+  // through a generic pointer could alias f and force reloads after it)
+  const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N, S = f.S, P = f.P;
+  const int nresp = f.nresp, pu_float = f.pu_float;
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  const bool jt = f.mv && f.joint;
+  const bool rad = f.mv && f.n_rad > 0 && !f.joint;
+  GD* const nllpart = (GD*)f.nllpart;
+  GI* const flagpart = (GI*)f.flagpart;
+  GD* const ppart = (GD*)f.ppart;
+  GD* const tpart = (GD*)f.tpart;
+  GI* const cpflag = (GI*)f.cpflag;
+  GD* const bwdpart = (GD*)f.bwdpart;
+  GD* const gpart = (GD*)f.gpart;
+  GD* const jnll = (GD*)f.jnll;
+  GI* const jflag = (GI*)f.jflag;
+  GD* const jpp = (GD*)f.jpp;
+  GD* const jtp = (GD*)f.jtp;
+  GD* const jg = (GD*)f.jg;
+  GD* const rad_out = (GD*)f.rad_out;
+  GDw* const out = (GDw*)f.out;
+  double* const out_host = f.out_host;
+  const double* const theta = f.theta;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   double acc[NA] = {0, 0, 0, 0, 0, 0, 0};
   int fl = 0;
-  const bool tab = f.kind == kTable && f.nresp > 0;
-  for (int b = t; b < f.n_rowblk; b += NT) {
-    acc[0] += f.nllpart[b];
-    fl |= f.flagpart[b];
-    if (f.pu_float && with_grad) acc[5] += f.ppart[b];
-    if (tab && with_grad) acc[6] += f.tpart[b];
+  for (int b = t; b < n_rowblk; b += NT) {
+    acc[0] += nllpart[b];
+    fl |= flagpart[b];
+    if (pu_float && with_grad) acc[5] += ppart[b];
+    if (tab && with_grad) acc[6] += tpart[b];
   }
-  for (int b = t; b < f.n_cpblk; b += NT) fl |= f.cpflag[b];
+  for (int b = t; b < n_cpblk; b += NT) fl |= cpflag[b];
   if (with_grad)
-    for (int b = t; b < f.n_bwdblk; b += NT)
-      for (int q = 0; q < 4; ++q) acc[1 + q] += f.bwdpart[(size_t)b * 4 + q];
-  const bool jt = f.mv && f.joint;
+    for (int b = t; b < n_bwdblk; b += NT)
+      for (int q = 0; q < 4; ++q) acc[1 + q] += bwdpart[(size_t)b * 4 + q];
   if (jt)  // joint term: one partial per reco row
-    for (int b = t; b < f.N; b += NT) {
-      acc[0] += f.jnll[b];
-      fl |= f.jflag[b];
-      if (f.pu_float && with_grad) acc[5] += f.jpp[b];
-      if (tab && with_grad) acc[6] += f.jtp[b];
+    for (int b = t; b < N; b += NT) {
+      acc[0] += jnll[b];
+      fl |= jflag[b];
+      if (pu_float && with_grad) acc[5] += jpp[b];
+      if (tab && with_grad) acc[6] += jtp[b];
     }
   // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
   double gr = 0.0;
-  for (int b = t >> 4; b < f.n_rowblk; b += NT / 16) gr += f.gpart[b * kSP + (t & 15)];
+  for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
   if (jt && with_grad)
-    for (int b = t >> 4; b < f.N; b += NT / 16) gr += f.jg[b * kSP + (t & 15)];
+    for (int b = t >> 4; b < N; b += NT / 16) gr += jg[b * kSP + (t & 15)];
   gr += __shfl_xor(gr, 16, 64);
   gr += __shfl_xor(gr, 32, 64);
+  // the radial term's parts (one block wrote them) and the caller's sequence
+  // number, loaded now so that their latency overlaps the sums
+  double rad_g = 0.0, rad_nll = 0.0, rad_fl = 0.0, rad_p = 0.0, rad_t = 0.0, seq = 0.0;
+  if (rad) {
+    if (t < S) rad_g = rad_out[2 + 16 + t];
+    if (t == 0) {
+      rad_nll = rad_out[0];
+      rad_fl = rad_out[1];
+      rad_p = rad_out[2 + 32];
+      rad_t = rad_out[2 + 33];
+    }
+  }
+  if (out_host && t == 0) seq = theta[P];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = sum64(acc[q]);
   fl = or64(fl);
@@ -1224,12 +1261,12 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   __syncthreads();
   // results go to f.out and, when set, straight into the caller's pinned
   // host buffer as well (no separate copy node)
-  if (t < f.S) {
+  if (t < S) {
     double a = wred[0][NA + t];
     for (int v = 1; v < NW; ++v) a += wred[v][NA + t];
-    if (f.mv && f.n_rad > 0 && !f.joint) a += f.rad_out[2 + 16 + t];
-    f.out[1 + t] = a;
-    if (f.out_host) f.out_host[1 + t] = a;
+    if (rad) a += rad_g;
+    out[1 + t] = a;
+    if (out_host) out_host[1 + t] = a;
   }
   if (t == 0) {
     double tot[NA];
@@ -1241,38 +1278,38 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       flags |= wflag[v];
     }
     double pg = tot[5];  // dNLL/dp: row terms, then the radial term
-    if (f.mv && f.n_rad > 0 && !f.joint) pg += f.rad_out[2 + 32];
+    if (rad) pg += rad_p;
     if (tab) {  // the table coordinate takes the response gradient's place
       tot[1] = tot[6];
-      if (f.mv && f.n_rad > 0 && !f.joint) tot[1] += f.rad_out[2 + 33];
+      if (rad) tot[1] += rad_t;
     }
     double nll = tot[0];
-    if (f.mv && f.n_rad > 0 && !f.joint) {
-      nll += f.rad_out[0];
-      flags |= (int)f.rad_out[1];
+    if (rad) {
+      nll += rad_nll;
+      flags |= (int)rad_fl;
     }
     if (!with_grad) flags &= ~kZeroWidth;
     const double v0 = (flags & ~kZeroWidth) ? INFINITY : nll;
-    f.out[0] = v0;
-    f.out[1 + f.P] = (double)flags;
+    out[0] = v0;
+    out[1 + P] = (double)flags;
 #pragma unroll
     for (int q = 0; q < kMaxResp; ++q)  // static indices keep tot[] in registers
-      if (q < f.nresp) f.out[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
-    if (f.pu_float) f.out[f.P] = with_grad ? pg : 0.0;
-    if (f.out_host) {
-      f.out_host[0] = v0;
-      f.out_host[1 + f.P] = (double)flags;
+      if (q < nresp) out[1 + S + q] = with_grad ? tot[1 + q] : 0.0;
+    if (pu_float) out[P] = with_grad ? pg : 0.0;
+    if (out_host) {
+      out_host[0] = v0;
+      out_host[1 + P] = (double)flags;
 #pragma unroll
       for (int q = 0; q < kMaxResp; ++q)
-        if (q < f.nresp) f.out_host[1 + f.S + q] = with_grad ? tot[1 + q] : 0.0;
-      if (f.pu_float) f.out_host[f.P] = with_grad ? pg : 0.0;
+        if (q < nresp) out_host[1 + S + q] = with_grad ? tot[1 + q] : 0.0;
+      if (pu_float) out_host[P] = with_grad ? pg : 0.0;
     }
   }
-  if (f.out_host) {  // then the completion mark the caller spins on
+  if (out_host) {  // then the completion mark the caller spins on
     __threadfence_system();
     __syncthreads();
     if (t == 0) {
-      f.out_host[2 + f.P] = f.theta[f.P];
+      out_host[2 + P] = seq;
       __threadfence_system();
     }
   }
