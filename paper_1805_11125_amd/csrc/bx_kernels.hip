@@ -722,6 +722,34 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
 __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) double GDw;
+  typedef __attribute__((address_space(1))) int GIw;
+  // every field used is read into registers before the first store (a store
+  // through a generic pointer could alias f and force reloads after it)
+  const int N = f.N, S = f.S, mv = f.mv, joint = f.joint, n_ps = f.n_ps, pu_float = f.pu_float;
+  const int win_lo = f.win_lo, win_hi = f.win_hi;
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  const int K = pu_len(f);
+  const double pp = pu_p(f);
+  GD* const Mg = (GD*)f.M;
+  GD* const ghat = (GD*)f.ghat;
+  GD* const Dt = (GD*)f.Dt;
+  GD* const th = (GD*)f.theta;
+  GD* const tag = (GD*)f.tag;
+  GD* const pst = (GD*)f.pst;
+  GD* const n_e = (GD*)f.n_e;
+  GD* const n_t = (GD*)f.n_t;
+  GD* const n_p = (GD*)f.n_p;
+  GDw* const Mp = (GDw*)f.Mp;
+  GDw* const Dp = (GDw*)f.Dp;
+  GDw* const Dtp = (GDw*)f.Dtp;
+  GDw* const H = (GDw*)f.H;
+  GDw* const nllpart = (GDw*)f.nllpart;
+  GIw* const flagpart = (GIw*)f.flagpart;
+  GDw* const gpart = (GDw*)f.gpart;
+  GDw* const ppart = (GDw*)f.ppart;
+  GDw* const tpart = (GDw*)f.tpart;
   __shared__ double Ml[16 + kMaxK - 1][kSP];
   __shared__ double mp[16][kSP];
   __shared__ double red[kBlock];
@@ -729,90 +757,85 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   __shared__ double wps[16][64];
   const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
   const int j0 = blockIdx.x * 16;
-  const int K = pu_len(f);
-  const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, f.N);
+  const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, N);
   // M rows [r0, r1) staged in LDS for the pile-up sums
-  for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = f.M[(size_t)r0 * kSP + e];
+  for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = Mg[(size_t)r0 * kSP + e];
   __syncthreads();
   const int j = j0 + rl;
-  const bool jok = j < f.N;
+  const bool jok = j < N;
   double m = 0.0, dmp = 0.0;  // M'_js and dM'_js/dp = (g^*M)_js - M_js
   if (jok) {
     m = Ml[j - r0][s];
     if (K > 1) {
       double acc = 0.0;
       const int kmax = min(j, K - 1);
-      for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Ml[j - k - r0][s];
-      const double pp = pu_p(f);
+      for (int k = 0; k <= kmax; ++k) acc += ghat[k] * Ml[j - k - r0][s];
       dmp = acc - m;
       m = (1.0 - pp) * m + pp * acc;
     }
-    f.Mp[j * kSP + s] = m;
-    if (f.pu_float) f.Dp[j * kSP + s] = dmp;
+    Mp[j * kSP + s] = m;
+    if (pu_float) Dp[j * kSP + s] = dmp;
   }
   mp[rl][s] = m;
   __syncthreads();
   // tabulated response: dM'/dlam, the pile-up applied to dM/dlam (rows
   // staged in the same LDS rows as M)
-  const bool tab = f.kind == kTable && f.nresp > 0;
   double dmt = 0.0;
   if (tab) {  // block-uniform
-    for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = f.Dt[(size_t)r0 * kSP + e];
+    for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = Dt[(size_t)r0 * kSP + e];
     __syncthreads();
     if (jok) {
       dmt = Ml[j - r0][s];
       if (K > 1) {
         double acc = 0.0;
         const int kmax = min(j, K - 1);
-        for (int k = 0; k <= kmax; ++k) acc += f.ghat[k] * Ml[j - k - r0][s];
-        const double pp = pu_p(f);
+        for (int k = 0; k <= kmax; ++k) acc += ghat[k] * Ml[j - k - r0][s];
         dmt = (1.0 - pp) * dmt + pp * acc;
       }
-      f.Dtp[j * kSP + s] = dmt;
+      Dtp[j * kSP + s] = dmt;
     }
   }
-  const double* th = f.theta;
-  const double r_s = s < f.S ? th[s] : 0.0;
-  const bool inwin = jok && j >= f.win_lo && j < f.win_hi;
+  const double r_s = s < S ? th[s] : 0.0;
+  const bool inwin = jok && j >= win_lo && j < win_hi;
   double term = 0.0, h = 0.0;
   int bad = 0;
-  if (!f.mv) {
+  if (!mv) {
     const double mu = sum16(m * r_s);
     double w = 0.0;
     if (inwin) {
-      const double t = nll_term(mu, f.n_e[j], &w, &bad);
+      const double t = nll_term(mu, n_e[j], &w, &bad);
       if (s == 0) term = t;
     }
     h = w;
   } else {
-    const double t_s = s < f.S ? f.tag[s] : 0.0;
+    const double t_s = s < S ? tag[s] : 0.0;
     const double musub = sum16(m * (1.0 - t_s) * r_s);
     const double mutag = sum16(m * t_s * r_s);
     double wsub = 0.0, wtag = 0.0;
     if (inwin) {
       // with the joint term (k_joint) the vetoed events are not a term here
-      const double t1 = f.joint ? 0.0 : nll_term(musub, f.n_e[j], &wsub, &bad);
-      const double t2 = nll_term(mutag, f.n_t[j], &wtag, &bad);
+      const double t1 = joint ? 0.0 : nll_term(musub, n_e[j], &wsub, &bad);
+      const double t2 = nll_term(mutag, n_t[j], &wtag, &bad);
       if (s == 0) term = t1 + t2;
     }
     // pulse-shape row j: lambda_jk = sum_s M'_js (1 - t_s) r_s T_sk
-    for (int k = s; k < (f.joint ? 0 : f.n_ps); k += 16) {
+    for (int k = s; k < (joint ? 0 : n_ps); k += 16) {
       double w = 0.0;
       if (inwin) {
         double lam = 0.0;
-        for (int u = 0; u < f.S; ++u) lam += mp[rl][u] * (1.0 - f.tag[u]) * th[u] * f.pst[u * f.n_ps + k];
-        term += nll_term(lam, f.n_p[(size_t)j * f.n_ps + k], &w, &bad);
+        for (int u = 0; u < S; ++u) lam += mp[rl][u] * (1.0 - tag[u]) * th[u] * pst[u * n_ps + k];
+        term += nll_term(lam, n_p[(size_t)j * n_ps + k], &w, &bad);
       }
       wps[rl][k] = w;
     }
     __syncthreads();
     double hps = 0.0;
-    if (s < f.S && !f.joint)
-      for (int k = 0; k < f.n_ps; ++k) hps += wps[rl][k] * f.pst[s * f.n_ps + k];
+    if (s < S && !joint)
+      for (int k = 0; k < n_ps; ++k) hps += wps[rl][k] * pst[s * n_ps + k];
     // H_js = w_sub (1 - t_s) + w_tag t_s + (1 - t_s) sum_k w_ps,jk T_sk
     h = wsub * (1.0 - t_s) + wtag * t_s + (1.0 - t_s) * hps;
   }
-  if (jok) f.H[j * kSP + s] = (s < f.S) ? h : 0.0;
+  if (jok) H[j * kSP + s] = (s < S) ? h : 0.0;
   // block partials: NLL (fixed tree), flags, rate gradient sum_j H_js M'_js
   red[threadIdx.x] = term;
   redf[threadIdx.x] = bad;
@@ -825,36 +848,36 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    f.nllpart[blockIdx.x] = red[0];
-    f.flagpart[blockIdx.x] = redf[0];
+    nllpart[blockIdx.x] = red[0];
+    flagpart[blockIdx.x] = redf[0];
   }
   __syncthreads();
-  red[threadIdx.x] = (jok && s < f.S) ? h * m : 0.0;
+  red[threadIdx.x] = (jok && s < S) ? h * m : 0.0;
   __syncthreads();
   if (threadIdx.x < 16) {
     double a = 0.0;
     for (int r = 0; r < 16; ++r) a += red[r * 16 + threadIdx.x];
-    f.gpart[blockIdx.x * kSP + threadIdx.x] = a;
+    gpart[blockIdx.x * kSP + threadIdx.x] = a;
   }
-  if (f.pu_float) {  // block-uniform: dNLL/dp without the radial part, sum_js H_js r_s dM'_js/dp
+  if (pu_float) {  // block-uniform: dNLL/dp without the radial part, sum_js H_js r_s dM'_js/dp
     __syncthreads();
-    red[threadIdx.x] = (jok && s < f.S) ? h * r_s * dmp : 0.0;
+    red[threadIdx.x] = (jok && s < S) ? h * r_s * dmp : 0.0;
     __syncthreads();
     for (int st = kBlock / 2; st >= 1; st >>= 1) {
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) f.ppart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) ppart[blockIdx.x] = red[0];
   }
   if (tab) {  // block-uniform: dNLL/dlam without the radial part, sum_js H_js r_s dM'_js/dlam
     __syncthreads();
-    red[threadIdx.x] = (jok && s < f.S) ? h * r_s * dmt : 0.0;
+    red[threadIdx.x] = (jok && s < S) ? h * r_s * dmt : 0.0;
     __syncthreads();
     for (int st = kBlock / 2; st >= 1; st >>= 1) {
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) f.tpart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) tpart[blockIdx.x] = red[0];
   }
 }
 
