@@ -264,6 +264,12 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
   const int i = blockIdx.x * kCpBlock + threadIdx.x;
   int jlo = 1 << 30, jhi = -1, bad = 0;
+  // output pointers and T read before the first store (a store through a
+  // generic pointer could alias f and force reloads after it)
+  ColPar* const cpo = f.cp;
+  int2* const tbo = f.tb;
+  int* const cpflag = f.cpflag;
+  const int T = f.T;
   // theta straight from pinned host memory when the caller passed it there,
   // with system-scope loads (a plain load may hit a line of the previous
   // evaluation's theta still held in the GPU caches); block 0 leaves a device
@@ -375,16 +381,16 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
     }
     if (bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
     c.jlo = jlo; c.jhi = jhi; c.bad = bad; c.pad = 0;
-    f.cp[i] = c;
+    cpo[i] = c;
   }
   // support of each 16-column tile, domain flags of the block
   for (int m = 8; m >= 1; m >>= 1) {
     jlo = min(jlo, __shfl_xor(jlo, m, 16));
     jhi = max(jhi, __shfl_xor(jhi, m, 16));
   }
-  if ((threadIdx.x & 15) == 0 && i < f.T) f.tb[i >> 4] = make_int2(jlo, jhi);
+  if ((threadIdx.x & 15) == 0 && i < T) tbo[i >> 4] = make_int2(jlo, jhi);
   for (int m = 32; m >= 1; m >>= 1) bad |= __shfl_xor(bad, m, 64);
-  if (threadIdx.x == 0) f.cpflag[blockIdx.x] = bad;
+  if (threadIdx.x == 0) cpflag[blockIdx.x] = bad;
 }
 
 // A column's constants as one lane holds them in the forward sweep.
