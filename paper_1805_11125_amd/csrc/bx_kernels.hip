@@ -1381,38 +1381,61 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
   __shared__ double wsum[NW][kSP + 2], hs[kJointRows][kSP], ht[kJointRows][kSP];
   __shared__ int wfl[NW];
   const int nr = f.n_rad, np = f.n_ps, S = f.S;
+  // every field used is read into registers before the first store (a store
+  // through a generic pointer could alias f and force reloads after it)
+  typedef __attribute__((address_space(1))) double GDw;
+  typedef __attribute__((address_space(1))) int GIw;
+  const int N = f.N, win_lo = f.win_lo, win_hi = f.win_hi, pu_float = f.pu_float;
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  GD* const Mp = (GD*)f.Mp;
+  GD* const tag = (GD*)f.tag;
+  GD* const th = (GD*)f.theta;
+  GD* const jsig = (GD*)f.jsig;
+  GD* const Dp = (GD*)f.Dp;
+  GD* const Dtp = (GD*)f.Dtp;
+  GD* const rad = (GD*)f.rad;
+  GD* const pst = (GD*)f.pst;
+  GI* const jrow = (GI*)f.jrow;
+  GU* const jent = (GU*)f.jent;
+  GD* const jval = (GD*)f.jval;
+  GDw* const H = (GDw*)f.H;
+  GDw* const jg = (GDw*)f.jg;
+  GDw* const jnll = (GDw*)f.jnll;
+  GIw* const jflag = (GIw*)f.jflag;
+  GDw* const jpp = (GDw*)f.jpp;
+  GDw* const jtp = (GDw*)f.jtp;
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int r = w / kJointWPR, sub = w - r * kJointWPR;
   const int j = blockIdx.x * kJointRows + r;
-  const bool inwin = j < f.N && j >= f.win_lo && j < f.win_hi;
+  const bool inwin = j < N && j >= win_lo && j < win_hi;
   // the row's coefficients and first entries are loaded before the staging
   double c[kSP];
 #pragma unroll
   for (int s = 0; s < kSP; ++s)
-    c[s] = (inwin && s < S) ? ((GD*)f.Mp)[j * kSP + s] * (1.0 - ((GD*)f.tag)[s]) * ((GD*)f.theta)[s] : 0.0;
-  const int e0 = inwin ? ((GI*)f.jrow)[j] : 0, e1 = inwin ? ((GI*)f.jrow)[j + 1] : 0;
+    c[s] = (inwin && s < S) ? Mp[j * kSP + s] * (1.0 - tag[s]) * th[s] : 0.0;
+  const int e0 = inwin ? jrow[j] : 0, e1 = inwin ? jrow[j + 1] : 0;
   int e = e0 + sub * 64 + lane;
   uint32_t bn = 0;
   double nn = 0.0;
   if (e < e1) {
-    bn = ((GU*)f.jent)[e];
-    nn = ((GD*)f.jval)[e];
+    bn = jent[e];
+    nn = jval[e];
   }
   for (int x = t; x < kSP * 128; x += kJointBlock) {
     const int s = x >> 7, k = x & 127;
-    if (k < nr) Rk[k][s] = s < S ? ((GD*)f.rad)[s * nr + k] : 0.0;
+    if (k < nr) Rk[k][s] = s < S ? rad[s * nr + k] : 0.0;
   }
   for (int x = t; x < kSP * 64; x += kJointBlock) {
     const int s = x >> 6, l = x & 63;
-    if (l < np) Tl[l][s] = s < S ? ((GD*)f.pst)[s * np + l] : 0.0;
+    if (l < np) Tl[l][s] = s < S ? pst[s * np + l] : 0.0;
   }
   bool dense = false;
   double mu = 0.0;  // sum_kl lambda_jkl = sum_s c_s sigma_s
 #pragma unroll
   for (int s = 0; s < kSP; ++s) {
     dense |= !(c[s] >= 0.0) || !isfinite(c[s]);
-    mu += c[s] * ((GD*)f.jsig)[s];
+    mu += c[s] * jsig[s];
   }
   __syncthreads();
   double term = 0.0, A[kSP];
@@ -1423,8 +1446,8 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
     const uint32_t b = bn;
     const double n = nn;  // > 0
     if (e + 64 * kJointWPR < e1) {  // next entry in flight
-      bn = ((GU*)f.jent)[e + 64 * kJointWPR];
-      nn = ((GD*)f.jval)[e + 64 * kJointWPR];
+      bn = jent[e + 64 * kJointWPR];
+      nn = jval[e + 64 * kJointWPR];
     }
     const double2* rk = (const double2*)&Rk[b >> 16][0];
     const double2* tl = (const double2*)&Tl[b & 0xffff][0];
@@ -1475,38 +1498,40 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
   // per row: sub-wave partials in order
   if (D && t < kJointRows * kSP) {
     const int rr = t / kSP, s = t - rr * kSP, jj = blockIdx.x * kJointRows + rr;
-    const bool in = jj < f.N && jj >= f.win_lo && jj < f.win_hi;
+    const bool in = jj < N && jj >= win_lo && jj < win_hi;
     double a = wsum[rr * kJointWPR][s];
     for (int v = 1; v < kJointWPR; ++v) a += wsum[rr * kJointWPR + v][s];
-    const double hadd = (in && s < S) ? (1.0 - f.tag[s]) * (f.jsig[s] - a) : 0.0;  // (1 - t_s) G_s
-    if (jj < f.N) {
-      f.H[jj * kSP + s] += hadd;
-      f.jg[jj * kSP + s] = hadd * f.Mp[jj * kSP + s];
+    const double hadd = (in && s < S) ? (1.0 - tag[s]) * (jsig[s] - a) : 0.0;  // (1 - t_s) G_s
+    // pile-up-fraction and table-coordinate parts (summed over s below),
+    // loaded before the stores
+    hs[rr][s] = pu_float && jj < N ? hadd * th[s] * Dp[jj * kSP + s] : 0.0;
+    ht[rr][s] = tab && jj < N ? hadd * th[s] * Dtp[jj * kSP + s] : 0.0;
+    if (jj < N) {
+      const double mpv = Mp[jj * kSP + s];
+      H[jj * kSP + s] += hadd;
+      jg[jj * kSP + s] = hadd * mpv;
     }
-    // pile-up-fraction and table-coordinate parts, summed over s below
-    hs[rr][s] = f.pu_float && jj < f.N ? hadd * f.theta[s] * f.Dp[jj * kSP + s] : 0.0;
-    ht[rr][s] = f.kind == kTable && f.nresp > 0 && jj < f.N ? hadd * f.theta[s] * f.Dtp[jj * kSP + s] : 0.0;
   }
   if (D) __syncthreads();
   if (t < kJointRows) {
     const int jj = blockIdx.x * kJointRows + t;
-    if (jj >= f.N) return;
+    if (jj >= N) return;
     double lt = wsum[t * kJointWPR][kSP];
     int fl = wfl[t * kJointWPR];
     for (int v = 1; v < kJointWPR; ++v) {
       lt += wsum[t * kJointWPR + v][kSP];
       fl |= wfl[t * kJointWPR + v];
     }
-    f.jnll[jj] = wsum[t * kJointWPR][kSP + 1] - lt;
-    f.jflag[jj] = fl;
+    jnll[jj] = wsum[t * kJointWPR][kSP + 1] - lt;
+    jflag[jj] = fl;
     if (D) {
       double pp = 0.0, tp = 0.0;
       for (int s = 0; s < S; ++s) {
         pp += hs[t][s];
         tp += ht[t][s];
       }
-      if (f.pu_float) f.jpp[jj] = pp;
-      if (f.kind == kTable && f.nresp > 0) f.jtp[jj] = tp;
+      if (pu_float) jpp[jj] = pp;
+      if (tab) jtp[jj] = tp;
     }
   }
 }
