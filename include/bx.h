@@ -115,8 +115,11 @@ typedef struct {
    * its additive terms, Sec. 3): the vetoed events of the fit window in one
    * histogram bx_data.joint [N][n_rad][n_ps] with expected counts
    * lambda_jkl = sum_s M'_js (1 - t_s) r_s rad_tmpl[s][k] ps_tmpl[s][l]; the
-   * tagged term stays.  Needs multivariate = 1, n_rad >= 1 and n_ps >= 1;
-   * rad_lo, rad_hi and bx_data.energy, radial, ps are then unused. */
+   * tagged term stays.  Needs multivariate = 1, n_rad >= 1, n_ps >= 1 and
+   * N * n_rad * n_ps < 2^31; rad_lo, rad_hi and bx_data.energy, radial, ps
+   * are then unused.  The device holds the histogram as the list of its
+   * non-zero bins per row, with room for every bin (12 bytes per bin), so
+   * bx_model_set_data accepts any new histogram of the same shape. */
   int32_t joint;
 } bx_model_desc;
 
