@@ -25,11 +25,11 @@ realism of the synthetic inputs (parity unpinned: no detector data exist here).
 """
 from .model import (DomainError, column_params, edge_tails, response_matrix,
                     response_derivs, contraction, pileup, expected, nll, nll_terms,
-                    grad, nll_grad, grad_scale, lnfact, per_species_expected,
+                    grad, nll_grad, grad_scale, grad_scale_abs, lnfact, per_species_expected,
                     support_cells, support_edges)
 from .fit import fit
 
 __all__ = ["DomainError", "column_params", "edge_tails", "response_matrix",
            "response_derivs", "contraction", "pileup", "expected", "nll",
-           "nll_terms", "grad", "nll_grad", "grad_scale", "lnfact", "per_species_expected",
+           "nll_terms", "grad", "nll_grad", "grad_scale", "grad_scale_abs", "lnfact", "per_species_expected",
            "support_cells", "support_edges", "fit"]

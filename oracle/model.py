@@ -480,17 +480,14 @@ def support_edges(desc, theta, q=1e-12):
     return total
 
 
-def grad_scale(desc, data, theta):
-    """Magnitude scale of each gradient component: sum over bins of
-    |dmu_b/dq| (1 + n_b/mu_b), the size of the two terms that cancel in
-    dNLL/dq = sum (1 - n/mu) dmu/dq.  Gradient tolerances are relative to it
-    (the gradient itself goes to zero at the minimum)."""
+def _scale(desc, data, theta, weight):
+    """sum over bins of weight_b |dmu_b/dq| for every parameter q."""
     f = forward(desc, theta)
     obs = observed(desc, data)
     a = {}
     for key in f.mu:
         with np.errstate(divide="ignore", invalid="ignore"):
-            a[key] = np.where(obs[key] > 0, 1.0 + obs[key] / f.mu[key], 1.0)
+            a[key] = weight(f.mu[key], obs[key])
 
     def contract(dmu):
         return math.fsum(math.fsum((a[key] * np.abs(dmu[key])).ravel()) for key in a)
@@ -506,3 +503,20 @@ def grad_scale(desc, data, theta):
     if getattr(desc, "pu_float", False):
         sc[desc.P - 1] = contract(expected(desc, pileup_dp(desc, f.M), f.r))
     return sc
+
+
+def grad_scale(desc, data, theta):
+    """Magnitude scale of each gradient component q: the sum over bins of the
+    absolute summands of dNLL/dq = sum_b (1 - n_b/mu_b) dmu_b/dq, that is
+    sum_b |1 - n_b/mu_b| |dmu_b/dq| (a bin with n_b = 0 has weight 1).
+    Gradient tolerances are relative to it, because the gradient itself goes
+    to zero at the minimum."""
+    return _scale(desc, data, theta, lambda mu, n: np.where(n > 0, np.abs(1.0 - n / mu), 1.0))
+
+
+def grad_scale_abs(desc, data, theta):
+    """A looser scale, reported beside grad_scale: sum over bins of
+    |dmu_b/dq| (1 + n_b/mu_b), the size of the two terms that cancel in each
+    summand (1 - n_b/mu_b) dmu_b/dq.  Near the minimum it is roughly
+    2 sum_b |dmu_b/dq|, one to two orders above grad_scale."""
+    return _scale(desc, data, theta, lambda mu, n: np.where(n > 0, 1.0 + n / mu, 1.0))

@@ -24,6 +24,7 @@ constexpr int kBwdWaves = 4;   // waves per backward block (one reco tile each, 
 constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up adjoint in its own kernel
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
+constexpr int kBwdPart = 4 + kSP;  // backward partials per block: response parameters, then rates
 
 enum : int { kGauss = 0, kGG = 1, kTable = 2, kCount = 3 };
 constexpr int kMaxGrid = 64;   // grid points of a tabulated response
@@ -57,6 +58,11 @@ struct FitDev {
   int n_rt, n_ct, CG, n_cg, n_fb, RG, n_rg, n_rowblk;  // n_cg: forward chunks, n_fb: forward blocks per reco tile
   int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
   int uniform;            // reco bins of equal width
+  int vsum;               // one energy histogram with analytic cells: the sweeps contract the cells
+                          // with v_i = sum_s r_s F^_si (mu0 = R v) and the rate gradient is
+                          // F^T (R^T w~); otherwise per-species M = R F^T (FP64 MFMA)
+  int sup_prec;           // precision whose support cut the column supports use (the model's);
+                          // prec is the precision of this evaluation's cells
   int pu_float;           // the pile-up fraction is theta[P - 1] (else pu_frac)
   int n_grid;             // tabulated response: grid points (kind kTable)
   int joint;              // joint energy x radius x PS term replaces the vetoed/radial/PS terms
@@ -83,15 +89,21 @@ struct FitDev {
   const double* jval;   //   (k << 16 | l) and the count (room for every bin)
   const double* jsig;   // [16] (sum_k rho_sk)(sum_l T_sl) of the joint term's templates
   const double* grid;   // [n_grid] tabulated response: coordinate of each matrix
+  // quadrature of the cells (analytic responses): per reco bin j the centre
+  // qpum[j] = p (ln x_j + ln x_j+1)/2 and half-width qhw[j] = p/2 ln(x_j+1/x_j)
+  // in t (GG, +inf for a bin from x <= 0; Gaussian: qhw = (x_j+1 - x_j)/2)
+  // and the GG node constants QRowGG in FP32 (4 nodes) and FP64 (5 nodes)
+  const double* qpum;   // [N]
+  const double* qhw;    // [N]
+  const float* qrow32;  // [N][3 kNQ32]
+  const double* qrow64; // [N][3 kNQ64]
   const double* Mg;     // [n_grid][N][16] exposure * R_g F^T, formed at build
   // per-evaluation state
   const double* theta;  // [P]
   ColPar* cp;           // [T]
   int2* tb;             // [n_ct] support of each column tile (cells)
-  void* Mpart;          // [n_cg][N][16] R: one partial per chunk of 16 listed true tiles
-  void* Dcell;          // [n_ct][n_rt][4][64] pairs of R: per active tile, each cell's
-                        // differences of dF/dc1, dF/dc2 across it, in the sweeps' lane
-                        // order (written by the forward sweep when the gradient is wanted)
+  double* Mpart;        // [n_cg][N][16] (multivariate) or [n_cg][N] (vsum): one partial per
+                        // chunk of 16 listed true tiles
   double* M;            // [N][16] sum of the partials (FP64)
   double* Mp;           // [N][16] after pile-up
   double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part
@@ -112,7 +124,8 @@ struct FitDev {
   double* jpp;
   double* jtp;
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
-  double* bwdpart;      // [n_bwdblk][4] response-gradient partials
+  double* bwdpart;      // [n_bwdblk][kBwdPart] response-gradient partials, then (vsum) the
+                        // rate-gradient partials sum_i F^_si u_i, u = R^T w~
   double* out;          // [2 + P]: nll, grad[P], flags
   const double* theta_src;  // pinned host [P + 1]: theta and the caller's sequence number, or null
   double* out_host;         // pinned host [3 + P]: the results, then the sequence number as

@@ -325,6 +325,27 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
   for (int i = 0; i < m.T; ++i) m.Ec[i] = 0.5 * (d->true_edges[i] + d->true_edges[i + 1]);
   m.Qt.assign(m.T, 1.0);
   if (m.kind == kGG || m.kind == kCount) m.Qt.assign(d->quench, d->quench + m.T);
+  // quadrature constants of the reco bins (bx_math.h: gg_cell_quad,
+  // gauss_cell_quad): a GG bin from x <= 0 has no finite width in ln x and is
+  // always a CDF difference
+  m.qpum.assign(m.N, 0.0);
+  m.qhw.assign(m.N, INFINITY);
+  m.qrow32.assign((size_t)m.N * 3 * kNQ32, 0.f);
+  m.qrow64.assign((size_t)m.N * 3 * kNQ64, 0.0);
+  for (int j = 0; j < m.N; ++j) {
+    if (m.kind == kGG && m.xraw[j] > 0.0) {
+      m.qpum[j] = 0.5 * m.p * (m.xe[j] + m.xe[j + 1]);
+      m.qhw[j] = 0.5 * m.p * (m.xe[j + 1] - m.xe[j]);
+      const QRowGG<float, kNQ32> r32 = qrow_gg<float, kNQ32>(m.xe[j], m.xe[j + 1], m.p);
+      const QRowGG<double, kNQ64> r64 = qrow_gg<double, kNQ64>(m.xe[j], m.xe[j + 1], m.p);
+      static_assert(sizeof r32 == 3 * kNQ32 * sizeof(float) && sizeof r64 == 3 * kNQ64 * sizeof(double),
+                    "row table layout");
+      memcpy(&m.qrow32[(size_t)j * 3 * kNQ32], &r32, sizeof r32);
+      memcpy(&m.qrow64[(size_t)j * 3 * kNQ64], &r64, sizeof r64);
+    } else if (m.kind == kGauss) {
+      m.qhw[j] = 0.5 * (m.xraw[j + 1] - m.xraw[j]);
+    }
+  }
   // spectra: unit rows (FP64), times exposure, species padded to 16
   m.F64.assign((size_t)m.T * kSP, 0.0);
   m.F32.assign((size_t)m.T * kSP, 0.f);
@@ -397,7 +418,9 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->n_bwdblk = f->n_ct * f->n_rg;
   f->kind = h.kind;
   f->prec = h.prec;
+  f->sup_prec = h.prec;
   f->mv = h.mv;
+  f->vsum = (!h.mv && h.kind != kTable) ? 1 : 0;
   f->n_rad = h.n_rad;
 }
 
@@ -408,13 +431,13 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
                     const FitDev* shared = nullptr) {
   Carver c{base};
   derive_tiles(h, f);
-  const size_t rsz = h.prec == kF32 ? 4 : 8;
   if (shared) {
     f->xraw = shared->xraw; f->xe = shared->xe; f->Ec = shared->Ec; f->Qt = shared->Qt;
     f->F32 = shared->F32; f->F64 = shared->F64; f->ghat = shared->ghat; f->tag = shared->tag;
     f->rad = shared->rad; f->pst = shared->pst;
     f->n_e = shared->n_e; f->n_t = shared->n_t; f->n_r = shared->n_r; f->n_p = shared->n_p;
     f->jrow = shared->jrow; f->jent = shared->jent; f->jval = shared->jval; f->jsig = shared->jsig;
+    f->qpum = shared->qpum; f->qhw = shared->qhw; f->qrow32 = shared->qrow32; f->qrow64 = shared->qrow64;
   } else {
     f->xraw = c.take<double>(h.N + 1);
     f->xe = c.take<double>(h.N + 1);
@@ -435,6 +458,10 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->jent = c.take<uint32_t>(nj);
     f->jval = c.take<double>(nj);
     f->jsig = c.take<double>(h.joint ? kSP : 0);
+    f->qpum = c.take<double>(h.N);
+    f->qhw = c.take<double>(h.N);
+    f->qrow32 = c.take<float>((size_t)h.N * 3 * kNQ32);
+    f->qrow64 = c.take<double>((size_t)h.N * 3 * kNQ64);
   }
   if (h.kind == kTable) {
     if (shared) {
@@ -449,8 +476,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->theta = *theta;
   f->cp = c.take<ColPar>(h.kind == kTable ? 0 : h.T);
   f->tb = c.take<int2>(f->n_ct);
-  f->Mpart = (void*)c.take<char>((size_t)f->n_cg * h.N * kSP * rsz);
-  f->Dcell = (void*)c.take<char>((size_t)f->n_ct * f->n_rt * 4 * 64 * 2 * rsz);
+  f->Mpart = c.take<double>((size_t)f->n_cg * h.N * (f->vsum ? 1 : kSP));
   f->M = c.take<double>((size_t)h.N * kSP);
   f->Mp = c.take<double>((size_t)h.N * kSP);
   f->H = c.take<double>((size_t)h.N * kSP);
@@ -474,7 +500,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->tpart = c.take<double>(f->n_rowblk);
   }
   f->cpflag = c.take<int>(f->n_cpblk);
-  f->bwdpart = c.take<double>((size_t)f->n_bwdblk * 4);
+  f->bwdpart = c.take<double>((size_t)f->n_bwdblk * kBwdPart);
   *out = c.take<double>(2 + h.P);
   f->out = *out;
   f->theta_src = nullptr;
@@ -573,6 +599,10 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   BX_HIP(up(f.rad, h.rad, st), "upload");
   BX_HIP(up(f.pst, h.pst, st), "upload");
   if (h.joint) BX_HIP(up(f.jsig, h.jsig, st), "upload");
+  BX_HIP(up(f.qpum, h.qpum, st), "upload");
+  BX_HIP(up(f.qhw, h.qhw, st), "upload");
+  BX_HIP(up(f.qrow32, h.qrow32, st), "upload");
+  BX_HIP(up(f.qrow64, h.qrow64, st), "upload");
   if (h.kind == kTable) BX_HIP(up(f.grid, h.grid, st), "upload");
   return upload_data(h, *df, st);
 }

@@ -42,6 +42,8 @@
 // kernel boundary inside a graph.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bx_dev.h"
 
 namespace bx {
@@ -311,7 +313,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
       } else {
         bad |= kZeroWidth;
       }
-      const double zb = sqrt(2.0 * (f.prec == kF32 ? kSupportB32 : kSupportB));
+      const double zb = sqrt(2.0 * (f.sup_prec == kF32 ? kSupportB32 : kSupportB));
       const int2 r = cell_range(f, E - zb * sig, E + zb * sig);
       jlo = r.x; jhi = r.y;
     } else {
@@ -358,7 +360,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
           th_ = f.gg.sup_hi[si];
           tl = f.gg.sup_lo[si];
         } else {
-          const float cb = (float)(1.05 * (f.prec == kF32 ? kSupportB32 : kSupportB) / k);
+          const float cb = (float)(1.05 * (f.sup_prec == kF32 ? kSupportB32 : kSupportB) / k);
           th_ = cb > 2.f ? log1pf(cb) + log1pf(log1pf(cb)) : sqrtf(2.f * cb);
           for (int it = 0; it < 12; ++it) {
             const float e = expm1f(th_);
@@ -393,26 +395,124 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   if (threadIdx.x == 0) cpflag[blockIdx.x] = bad;
 }
 
-// A column's constants as one lane holds them in the forward sweep.
+// A column's constants as one lane holds them in the sweeps.
+typedef __attribute__((address_space(1))) const ColPar GColPar;
+
 template <class R>
 struct ColPre {
-  double c0, c1;  // Gauss: m, 1/sigma; GG: ct
-  R s[8];         // GG edge constants
-  R bb;           // spectrum entry F^[i, species of the lane]
+  double c0, c1;  // Gauss: m, 1/sigma; GG: ct, k cR (the quadrature's column scale, FP64)
+  R s[8];         // GG constants (count: its FP64 constants)
+  double v;       // single histogram: v_i = sum_s r_s F^_si; multivariate: F^[i, species of the lane]
+  GColPar* cp;    // the column's parameters (FP64 constants of the CDF at the edges)
 };
 
-template <class R, int KIND, bool D>
-__device__ __forceinline__ EdgeVal<R> edge_pre(const ColPre<R>& c, double xe, double lnf) {
-  if constexpr (KIND == kCount) {
-    return count_cell<D>(xe, lnf, c.s);  // FP64 only: the cell at count xe itself
+// The CDF at a reco edge (GG, Gaussian), in FP64 whatever the cell precision:
+// it serves only bins too wide for the quadrature (or a GG bin from x <= 0,
+// whose cell is the single value F(x_1)), where FP32 would leave the
+// per-column rounding of its constants in the cell.
+template <int KIND, bool D>
+__device__ __forceinline__ EdgeVal<double> edge64(GColPar* cp, double xe) {
+  if constexpr (KIND == kGauss) {
+    return gauss_edge<double, D>(xe, cp->c0, cp->c1);
   } else {
-    if (KIND == kGauss) return gauss_edge<R, D>(xe, c.c0, c.c1);
-    GGCol<R> g;
-    g.ct = c.c0;
-    g.k = c.s[0]; g.ik = c.s[1]; g.skh = c.s[2]; g.cR = c.s[3]; g.ce = c.s[4];
-    g.dlngs = c.s[5]; g.lnk_psi = c.s[6]; g.p = c.s[7];
-    return gg_edge<R, D>(xe, g);
+    GGCol<double> g;
+    g.ct = cp->c0;
+    g.k = cp->f64[0]; g.ik = cp->f64[1]; g.skh = cp->f64[2]; g.cR = cp->f64[3]; g.ce = cp->f64[4];
+    g.dlngs = cp->f64[5]; g.lnk_psi = cp->f64[6]; g.p = cp->f64[7];
+    return gg_edge<double, D>(xe, g);
   }
+}
+
+// Quadrature constants of a lane's reco bin: GG the bin centre in p ln x, its
+// half-width in t and the node constants (FP32: 4 nodes, FP64: 5); Gaussian
+// the bin's centre and half-width.
+template <class R>
+struct RowQ {
+  static constexpr int NQ = sizeof(R) == 4 ? kNQ32 : kNQ64;
+  double a, b;
+  QRowGG<R, NQ> g;
+};
+
+template <class R, int KIND>
+__device__ __forceinline__ RowQ<R> load_rowq(const FitDev& f, int j) {
+  typedef __attribute__((address_space(1))) const double GD;
+  RowQ<R> r;
+  r.a = r.b = 0.0;
+  if constexpr (KIND == kGG) {
+    constexpr int NQ = RowQ<R>::NQ;
+    typedef __attribute__((address_space(1))) const R GR;
+    GR* q;
+    if constexpr (sizeof(R) == 4) q = (GR*)f.qrow32 + (size_t)j * 3 * NQ;
+    else q = (GR*)f.qrow64 + (size_t)j * 3 * NQ;
+    r.a = ((GD*)f.qpum)[j];
+    r.b = ((GD*)f.qhw)[j];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {  // the layout of QRowGG: d, fd, ed
+      r.g.d[u] = q[u];
+      r.g.fd[u] = q[NQ + u];
+      r.g.ed[u] = q[2 * NQ + u];
+    }
+  } else if constexpr (KIND == kGauss) {
+    const double x0 = ((GD*)f.xraw)[j], x1 = ((GD*)f.xraw)[j + 1];
+    r.a = 0.5 * (x0 + x1);
+    r.b = 0.5 * (x1 - x0);
+  }
+  return r;
+}
+
+// The cell R_ji of the lane's reco bin j for column c, and with D its
+// derivatives in the column parameters (Gaussian: m, sigma; GG: k, ln a;
+// count: m, r).  Analytic responses integrate the density over the bin by
+// Gauss-Legendre quadrature, with a composite rule of up to kMaxSub intervals
+// when the bin is wide against the column (quad_intervals); a bin wider than
+// that (or a GG bin from x <= 0) is the difference of the CDF at its edges,
+// the upper one from the next lane of the row (DPP row_shl:1).  Every lane of
+// a row evaluates its edge when any lane of the row needs one.  The count
+// estimator's cell is its pmf at the lane's count.  ok = false (no such bin
+// or column) gives zeros.  Called by all lanes of the wave.
+template <class R, int KIND, bool D>
+__device__ __forceinline__ CellVal<R> cell_eval(const ColPre<R>& c, const RowQ<R>& rq, double xe, double lnf,
+                                                bool ok) {
+  CellVal<R> o;
+  o.v = 0.0;
+  o.d1 = o.d2 = (R)0;
+  if constexpr (KIND == kCount) {
+    const EdgeVal<R> e = count_cell<D>(xe, lnf, c.s);
+    o.v = e.v;
+    o.d1 = e.d1;
+    o.d2 = e.d2;
+  } else {
+    // inverse width of the column in the quadrature variable: GG sqrt(k) in
+    // t = ln(y/k); Gaussian 1/sigma (none for a zero width)
+    const double iw = KIND == kGG ? 1.4142135623730950488 * (double)c.s[2] : (c.c1 > 0.0 ? c.c1 : NAN);
+    const int ns = ok ? quad_intervals(rq.b, iw) : 1;  // lanes without a cell side with quadrature
+    const unsigned long long eb = __ballot(ns == 0);
+    const bool row_edge = ((eb >> (threadIdx.x & 48)) & 0xffffull) != 0;  // row-uniform
+    if (ns > 0) {
+      if constexpr (KIND == kGG)
+        o = gg_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, rq.g, c.s[0], c.c1, c.s[6], c.s[7] * c.s[0], ns);
+      else
+        o = gauss_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, c.c1, ns);
+    }
+    if (row_edge) {
+      const EdgeVal<double> e = edge64<KIND, D>(c.cp, xe);
+      const double vh = dpp_from_next(e.v);
+      const double d1h = D ? dpp_from_next(e.d1) : 0.0;
+      const double d2h = D ? dpp_from_next(e.d2) : 0.0;
+      if (ns == 0) {
+        o.v = cell_from(e.v, vh);
+        if (D) {
+          o.d1 = (R)(d1h - e.d1);
+          o.d2 = (R)(d2h - e.d2);
+        }
+      }
+    }
+  }
+  if (!ok) {
+    o.v = 0.0;
+    o.d1 = o.d2 = (R)0;
+  }
+  return o;
 }
 
 // ---------------------------------------------------------------------------
@@ -536,17 +636,23 @@ __device__ __forceinline__ V tree_sum(const F& item) {
 // CG chunks: wave w holds entries [w CG, w CG + CG) of its window (a subtree),
 // so the partials do not depend on CG, which sets only how many tiles a wave
 // evaluates in a row.  The working waves fill the first blocks of each reco
-// tile; the rest find their window empty and write zero partials.  With D
-// (the gradient is wanted) the sweep also evaluates dF/dc1, dF/dc2 at the
-// edges and stores each cell's differences for the backward sweep, which
-// then needs no second evaluation of the edges.
-template <class R, int KIND, int CG, bool D>
+// tile; the rest find their window empty and write zero partials.
+// Lane (j = l%16, g = l/16) holds reco bin j of the tile and column 4q + g of
+// the true tile at step q.  The cells are contracted in FP64: with a single
+// histogram (vsum) each lane accumulates R_ji v_i, summed over its four
+// column groups at the end; with several species histograms (MV) the cells
+// are the A operand of FP64 MFMA 16x16x4 with B = F^[i, s] (M = R F^T).
+template <class R, int KIND, int CG, bool MV>
 __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits, const int* active) {
-  typedef typename Acc4<R>::T V;
+  typedef typename std::conditional<MV, v4d, double>::type V;
+  constexpr int NR = MV ? 4 : 1;
+  typedef __attribute__((address_space(1))) const double GD;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int rt = blockIdx.x / f.n_fb, fb = blockIdx.x % f.n_fb;
-  if (rt >= f.n_rt) return;  // block-uniform
-  __shared__ R part[kFwdWaves][4][64];
+  // block-uniform; a launch holds fits of one contraction kind only (a fit of
+  // the other kind is left alone rather than written with the wrong layout)
+  if (rt >= f.n_rt || f.vsum == (int)MV) return;
+  __shared__ double part[kFwdWaves][NR][64];
   __shared__ int wcount[kFwdWaves];
   __shared__ int mylist[kFwdWaves * CG];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
@@ -560,8 +666,8 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
     bool act = false;
     if (ct < f.n_ct) {
       const __attribute__((address_space(1))) int* tbp = (const __attribute__((address_space(1))) int*)f.tb;
-      const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];  // the tile's support [bx, by]
-      act = !(by < j0 || bx > j0 + kRowStep - 1);
+      const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];  // the tile's support [bx, by] (by < bx: empty)
+      act = by >= bx && !(by < j0 || bx > j0 + kRowStep - 1);
     }
     const unsigned long long m = __ballot(act);
     if (lane == 0) wcount[wv] = __popcll(m);
@@ -576,104 +682,91 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
     n_act = tot;
     __syncthreads();
   }
-  const int je = min(j0 + jr, f.N);
-  const double xe = ((__attribute__((address_space(1))) const double*)f.xe)[je];
-  const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;  // count estimator: ln n! of the row
-  const bool row_ok = (jr < kRowStep) && (j0 + jr < f.N);
-  const R* Ftab = (sizeof(R) == 4) ? (const R*)f.F32 : (const R*)f.F64;
-  const int n_here = n_act - lo;  // entries of this window in the list
-  typedef typename Pair<R>::T R2;
-  // the constants of a lane's column and its spectrum entry, fetched one
-  // column ahead of their use so that the loads overlap the edge arithmetic
-  // (fields of f in registers: the stores of the cell differences could
-  // alias it, which would make every access after one reload f and wait)
-  // Global-address-space views: flat accesses would make every wait for a
-  // load also wait for all older memory operations.
-  typedef __attribute__((address_space(1))) const ColPar GColPar;
-  typedef __attribute__((address_space(1))) const R GR;
-  typedef __attribute__((address_space(1))) R GRw;
+  // Fields of f in registers, accesses through global-address-space views
+  // (flat accesses would make every wait for a load also wait for all older
+  // memory operations).
   GColPar* const cpar = (GColPar*)f.cp;
-  GR* const ftab = (GR*)Ftab;
-  const int T = f.T, n_rt = f.n_rt;
-  GRw* const dcell = (GRw*)f.Dcell;  // pairs (dF/dc1, dF/dc2) differences
+  GD* const F64 = (GD*)f.F64;
+  const int T = f.T, N = f.N, n_cg = f.n_cg;
+  double* const Mpart = f.Mpart;
+  const int je = min(j0 + jr, N);
+  const double xe = ((GD*)f.xe)[je];
+  const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;  // count estimator: ln n! of the row
+  const bool row_ok = (jr < kRowStep) && (j0 + jr < N);
+  const RowQ<R> rq = load_rowq<R, KIND>(f, min(j0 + jr, N - 1));
+  const int n_here = n_act - lo;  // entries of this window in the list
+  // a lane's column constants, fetched one column ahead of their use so that
+  // the loads overlap the cell arithmetic
   auto fetch = [&](int i) -> ColPre<R> {
     ColPre<R> p;
     const bool iok = i < T;
     GColPar& cpi = cpar[iok ? i : T - 1];
+    p.cp = &cpi;
     p.c0 = cpi.c0;
-    p.c1 = KIND == kGauss ? cpi.c1 : 0.0;
+    p.c1 = KIND == kGauss ? cpi.c1 : KIND == kGG ? cpi.c1 * cpi.f64[3] : 0.0;
     if (KIND != kGauss) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) p.s[u] = sizeof(R) == 4 ? (R)cpi.f32[u] : (R)cpi.f64[u];
     }
-    p.bb = iok ? ftab[i * kSP + jr] : (R)0;
+    p.v = !iok ? 0.0 : MV ? F64[i * kSP + jr] : cpi.v;
     return p;
   };
-  // one tile's 16 x 16 contribution (zero past the end of the list)
+  // one tile's contribution (zero past the end of the list)
   auto tile = [&](int c) -> V {
-    V acc = {0, 0, 0, 0};
+    V acc = {};
     const int e = wv * CG + c;
     if (e >= n_here) return acc;  // wave-uniform
     const int ct = mylist[e];
-    GRw* dst = D ? dcell + ((size_t)ct * n_rt + rt) * 4 * 64 * 2 : nullptr;
     ColPre<R> cur = fetch(ct * kColTile + g);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ColPre<R> nxt;
       if (q < 3) nxt = fetch(ct * kColTile + 4 * (q + 1) + g);
       const int i = ct * kColTile + 4 * q + g;
-      const bool iok = i < T;
-      const EdgeVal<R> ev = edge_pre<R, KIND, D>(cur, xe, lnf);
-      const bool ok = row_ok && iok;
-      // edges: the cell is the difference to the next edge (row_shl:1, all
-      // lanes); counts: the lane's value is the cell itself
-      R a;
-      if constexpr (KIND == kCount) {
-        a = ok ? ev.v : (R)0;
-      } else {
-        const R hi = dpp_from_next(ev.v);
-        a = ok ? cell_from(ev.v, hi) : (R)0;
-      }
-      acc = mfma16(a, cur.bb, acc);
-      if (D) {
-        R2 dv;
-        if constexpr (KIND == kCount) {
-          dv.x = ok ? ev.d1 : (R)0;
-          dv.y = ok ? ev.d2 : (R)0;
-        } else {
-          const R d1h = dpp_from_next(ev.d1), d2h = dpp_from_next(ev.d2);
-          dv.x = ok ? d1h - ev.d1 : (R)0;
-          dv.y = ok ? d2h - ev.d2 : (R)0;
-        }
-        dst[2 * (q * 64 + lane)] = dv.x;
-        dst[2 * (q * 64 + lane) + 1] = dv.y;
-      }
+      const CellVal<R> ev = cell_eval<R, KIND, false>(cur, rq, xe, lnf, row_ok && i < T);
+      if constexpr (MV) acc = mfma16(ev.v, cur.v, acc);
+      else acc = fma(ev.v, cur.v, acc);
       if (q < 3) cur = nxt;
     }
     return acc;
   };
   const V sub = tree_sum<CG, 0, V>(tile);
+  if constexpr (MV) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) part[wv][r][lane] = sub[r];
+    for (int r = 0; r < 4; ++r) part[wv][r][lane] = sub[r];
+  } else {
+    part[wv][0][lane] = sub;
+  }
   __syncthreads();
   // chunk k of this block = waves [k W, k W + W), W = 16 / CG: wave k adds
   // their subtrees in the same tree and writes the chunk's partial
   constexpr int W = kFwdWaves / CG;
   const int chunk = fb * CG + wv;
-  if (wv < CG && chunk < f.n_cg) {
+  if (wv < CG && chunk < n_cg) {
     const V v = tree_sum<W, 0, V>([&](int w) -> V {
       V x;
+      if constexpr (MV) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) x[r] = part[wv * W + w][r][lane];
+        for (int r = 0; r < 4; ++r) x[r] = part[wv * W + w][r][lane];
+      } else {
+        x = part[wv * W + w][0][lane];
+      }
       return x;
     });
-    R* out = (R*)f.Mpart + (size_t)chunk * f.N * kSP;
+    if constexpr (MV) {
+      double* out = Mpart + (size_t)chunk * N * kSP;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      // result layout of MFMA 16x16x4: lane l, register r holds row 4(l/16) + r
-      // (f32) or row l/16 + 4r (f64), column l%16
-      const int row = sizeof(R) == 4 ? 4 * g + r : g + 4 * r;
-      if (row < kRowStep && j0 + row < f.N) out[(size_t)(j0 + row) * kSP + jr] = v[r];
+      for (int r = 0; r < 4; ++r) {
+        // FP64 MFMA 16x16x4 result layout: lane l, register r holds row l/16 + 4r, column l%16
+        const int row = g + 4 * r;
+        if (row < kRowStep && j0 + row < N) out[(size_t)(j0 + row) * kSP + jr] = v[r];
+      }
+    } else {
+      // the four column groups of row jr, added in a fixed order
+      double x = v;
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      if (g == 0 && row_ok) Mpart[(size_t)chunk * N + j0 + jr] = x;
     }
   }
 }
@@ -702,25 +795,34 @@ __device__ __forceinline__ double pu_p(const FitDev& f) {
   return f.pu_float ? f.theta[f.P - 1] : f.pu_frac;
 }
 
-// M[j, s] = sum over forward blocks of the partials, FP64, fixed order.
-template <class R>
+// M[j, s] = sum over the forward chunks of the partials, FP64, fixed order.
+// A single histogram (vsum) has one partial per row: mu0_j goes to M[j, 0]
+// and the other species columns are zero.
 __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= f.N * kSP) return;
-  const R* p = (const R*)f.Mpart + t;
-  const size_t stride = (size_t)f.N * kSP;
   const int n = f.n_cg;
+  size_t stride = (size_t)f.N * kSP;
+  const double* p = f.Mpart + t;
+  if (f.vsum) {
+    if ((t & 15) != 0) {
+      f.M[t] = 0.0;
+      return;
+    }
+    stride = (size_t)f.N;
+    p = f.Mpart + (t >> 4);
+  }
   double s = 0.0;
   int c = 0;
   for (; c + 4 <= n; c += 4) {  // four independent loads in flight
-    const R a0 = p[c * stride], a1 = p[(c + 1) * stride], a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
-    s += (double)a0;
-    s += (double)a1;
-    s += (double)a2;
-    s += (double)a3;
+    const double a0 = p[c * stride], a1 = p[(c + 1) * stride], a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
   }
-  for (; c < n; ++c) s += (double)p[c * stride];
+  for (; c < n; ++c) s += p[c * stride];
   f.M[t] = s;
 }
 
@@ -733,7 +835,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   typedef __attribute__((address_space(1))) int GIw;
   // every field used is read into registers before the first store (a store
   // through a generic pointer could alias f and force reloads after it)
-  const int N = f.N, S = f.S, mv = f.mv, joint = f.joint, n_ps = f.n_ps, pu_float = f.pu_float;
+  const int N = f.N, S = f.S, mv = f.mv, joint = f.joint, n_ps = f.n_ps, pu_float = f.pu_float, vsum = f.vsum;
   const int win_lo = f.win_lo, win_hi = f.win_hi;
   const bool tab = f.kind == kTable && f.nresp > 0;
   const int K = pu_len(f);
@@ -801,7 +903,8 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
       Dtp[j * kSP + s] = dmt;
     }
   }
-  const double r_s = s < S ? th[s] : 0.0;
+  // vsum: M' holds mu0 after pile-up in species column 0 (the rates are in v)
+  const double r_s = vsum ? (s == 0 ? 1.0 : 0.0) : s < S ? th[s] : 0.0;
   const bool inwin = jok && j >= win_lo && j < win_hi;
   double term = 0.0, h = 0.0;
   int bad = 0;
@@ -1029,41 +1132,46 @@ __global__ void __launch_bounds__(kBlock) k_adjoint1(const FitDev* fits, const i
 // tiles [rt_a, rt_b], and wave w of the kBwdWaves takes
 // rt = rt_a + (kBwdWaves rg + w) RG + c, c < RG.  The working blocks of a true
 // tile are thus its first ones (one block for a support of up to kBwdWaves RG
-// reco tiles); the others write a zero partial and leave.  The cells'
-// derivative differences come from the forward sweep of the same evaluation
-// (Dcell); the loads of a wave's first tile and of the chain factors are
-// issued before the pile-up adjoint so that their latency overlaps it.  With
-// pre, a single histogram's adjoint w~ comes from k_adjoint1 (batched
-// launches, where forming it here for every true tile would repeat it for
-// each tile that reaches a row); the two give the same bits.
-// MV: the launch holds multivariate fits (without it their code is compiled
-// out, which keeps the single-histogram sweep's registers and schedule).
-template <class R, bool MV>
+// reco tiles); the others write zero partials and leave.  Each lane holds the
+// constants of its four columns (4q + g) for all of its reco tiles and
+// evaluates each cell's derivatives in the two column parameters again (by
+// quadrature, or from the CDF's edge derivatives), weighted by
+// W_ji = dNLL/dmu0_j dmu0_j/dR_ji: alpha_i = sum_j W_ji dR_ji/dc1,
+// beta_i = sum_j W_ji dR_ji/dc2 in FP64, contracted with the column chain
+// factors into the block's response-gradient partial.  Single histogram:
+// W_ji = w~_j v_i with w~ = P^T w (the pile-up adjoint, formed here from the
+// block's rows staged in LDS, or read from k_adjoint1 for batched launches,
+// with the same bits), and the same pass accumulates u_i = sum_j w~_j R_ji for
+// the rate gradient sum_i F^_si u_i.  Multivariate (MV): W_ji = sum_s H~_js
+// r_s F^_is, the FP64 MFMA product of F (16 columns x 16 species) and
+// (H~ r)^T, whose result layout (lane l, register q: column l/16 + 4q, row
+// l%16) is the cells' lane layout.
+template <class R, int KIND, bool MV>
 __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits, const int* active, int pre) {
   constexpr int NT = kBwdWaves * 64;
   constexpr int kRows = kBwdWaves * kMaxRG * kRowStep;
-  typedef __attribute__((address_space(1))) const R GR;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  typedef __attribute__((address_space(1))) const ColPar GColPar;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int2 cr = bwd_block(f.n_rg);
   const int ct = cr.x, rg = cr.y, bl = ct * f.n_rg + rg;
-  if (ct >= f.n_ct) return;  // block-uniform
-  __shared__ double colA[kBwdWaves][16], colB[kBwdWaves][16];
+  if (ct >= f.n_ct || f.mv != (int)MV) return;  // block-uniform (one contraction kind per launch)
+  __shared__ double colA[kBwdWaves][16], colB[kBwdWaves][16], colU[kBwdWaves][16];
   __shared__ double hst[kRows + kMaxK], htl[kRows], gl[kMaxK];
   __shared__ double pq[kRows][4];
+  __shared__ double rsum[16][kSP];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
-  const int T = f.T, N = f.N, RG = f.RG, mv = MV ? f.mv : 0;
+  const int T = f.T, N = f.N, RG = f.RG;
   GColPar* const cpar = (GColPar*)f.cp;
-  GR* const dcell = (GR*)f.Dcell;  // pairs (dF/dc1, dF/dc2) differences
   GD* const Hg = (GD*)f.H;
+  GD* const F64 = (GD*)f.F64;
+  double* const bwdpart = f.bwdpart + (size_t)bl * kBwdPart;
   const int bx = ((GI*)f.tb)[2 * ct], by = ((GI*)f.tb)[2 * ct + 1];  // support [bx, by]
   const int rt_a = by >= bx ? max(bx, 0) / kRowStep : 0;
   const int rt_b = by >= bx ? min(by / kRowStep, f.n_rt - 1) : -1;
   const int rt_blk = rt_a + kBwdWaves * rg * RG;  // first reco tile of this block
   if (rt_blk > rt_b) {                            // block-uniform: nothing in range
-    if (threadIdx.x < 4) f.bwdpart[(size_t)bl * 4 + threadIdx.x] = 0.0;
+    if (threadIdx.x < kBwdPart) bwdpart[threadIdx.x] = 0.0;
     return;
   }
   // chain factors of the column totals (threads < 64: column c16, parameter q)
@@ -1074,54 +1182,40 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
     J0 = cpar[icol].J[0][qp];
     J1 = cpar[icol].J[1][qp];
   }
-  // this wave's first tile: cell differences and column values
+  // the constants of the lane's four columns, for all of its reco tiles
+  ColPre<R> col[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = min(ct * kColTile + 4 * q + g, T - 1);
+    GColPar& cpi = cpar[i];
+    col[q].cp = &cpi;
+    col[q].c0 = cpi.c0;
+    col[q].c1 = KIND == kGauss ? cpi.c1 : KIND == kGG ? cpi.c1 * cpi.f64[3] : 0.0;
+    if (KIND != kGauss) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) col[q].s[u] = sizeof(R) == 4 ? (R)cpi.f32[u] : (R)cpi.f64[u];
+    }
+    col[q].v = MV ? 0.0 : cpi.v;
+  }
   const int rt0 = rt_blk + wv * RG;
   const int rt_end = min(rt0 + RG, rt_b + 1);
-  // multivariate: the weights W_ji = sum_s H~_js r_s F_is of a tile are the
-  // FP64 MFMA product of F (16 columns x 16 species; lane: column lane%16,
-  // species 4 kb + lane/16) and (H~ r)^T, whose result layout (lane l,
-  // register q: column l/16 + 4q, row l%16) is the cells' lane layout
   const int S = f.S;
   double fa[4] = {0, 0, 0, 0}, thv[4] = {0, 0, 0, 0};
-  double hb0 = 0.0, hb1 = 0.0, hb2 = 0.0, hb3 = 0.0;  // (H~ r)^T operands of the tile
-  if (mv) {
+  if (MV) {  // F operands of the weights (lane: column lane%16, species 4 kb + lane/16)
     const int i = ct * kColTile + jr;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
       const int s = 4 * kb + g;
-      fa[kb] = (i < T && s < S) ? ((GD*)f.F64)[(size_t)i * kSP + s] : 0.0;
+      fa[kb] = (i < T && s < S) ? F64[(size_t)i * kSP + s] : 0.0;
       thv[kb] = s < S ? ((GD*)f.theta)[s] : 0.0;
     }
   }
-  R dx[4], dy[4];
-  double vv[4];
-  auto load_tile = [&](int rt) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ct * kColTile + 4 * q + g;
-      const bool ok = (rt < rt_end) && (jr < kRowStep) && (rt * kRowStep + jr < N) && (i < T);
-      const size_t e = (((size_t)ct * f.n_rt + rt) * 4 * 64 + q * 64 + lane) * 2;
-      dx[q] = ok ? dcell[e] : (R)0;
-      dy[q] = ok ? dcell[e + 1] : (R)0;
-      vv[q] = ok && !mv ? cpar[i].v : 0.0;
-    }
-    if (mv) {
-      const int j = rt * kRowStep + jr;
-      const bool rok = rt < rt_end && j < N;
-      GD* hr = (GD*)f.Ht + (size_t)min(j, N - 1) * kSP + g;
-      hb0 = (rok && g < S) ? hr[0] : 0.0;
-      hb1 = (rok && 4 + g < S) ? hr[4] : 0.0;
-      hb2 = (rok && 8 + g < S) ? hr[8] : 0.0;
-      hb3 = (rok && 12 + g < S) ? hr[12] : 0.0;
-    }
-  };
-  load_tile(rt0);
   // single histogram: the pile-up adjoint w~ = P^T w of this block's reco
   // rows, from the rows it needs staged in LDS (multivariate fits read the
   // full adjoint H~ written by k_adjoint)
   const int r0 = rt_blk * kRowStep;
   const int nr = max(min((min(rt_b + 1, rt_blk + kBwdWaves * RG) - rt_blk) * kRowStep, N - r0), 0);
-  if (!mv && !pre) {
+  if (!MV && !pre) {
     const int K = pu_len(f);
     const int ns = min(nr + K - 1, N - r0);
     for (int e = threadIdx.x; e < ns; e += NT) hst[e] = Hg[(size_t)(r0 + e) * kSP];
@@ -1146,14 +1240,21 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
     }
     __syncthreads();
   }
-  double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0};
+  double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
   for (int rt = rt0; rt < rt_end; ++rt) {
-    if (rt > rt0) load_tile(rt);
     const int j = rt * kRowStep + jr;
     const bool row_ok = (jr < kRowStep) && (j < N);
-    const double w1 = (row_ok && !mv) ? (pre ? ((GD*)f.Ht)[(size_t)j * kSP] : htl[j - r0]) : 0.0;
+    const double xe = ((GD*)f.xe)[min(j, N)];
+    const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;
+    const RowQ<R> rq = load_rowq<R, KIND>(f, min(j, N - 1));
+    const double w1 = (row_ok && !MV) ? (pre ? ((GD*)f.Ht)[(size_t)j * kSP] : htl[j - r0]) : 0.0;
     v4d Wm = {0, 0, 0, 0};
-    if (mv) {  // wave-uniform
+    if (MV) {  // wave-uniform
+      GD* hr = (GD*)f.Ht + (size_t)min(j, N - 1) * kSP + g;
+      const double hb0 = (row_ok && g < S) ? hr[0] : 0.0;
+      const double hb1 = (row_ok && 4 + g < S) ? hr[4] : 0.0;
+      const double hb2 = (row_ok && 8 + g < S) ? hr[8] : 0.0;
+      const double hb3 = (row_ok && 12 + g < S) ? hr[12] : 0.0;
       Wm = mfma16(fa[0], hb0 * thv[0], Wm);
       Wm = mfma16(fa[1], hb1 * thv[1], Wm);
       Wm = mfma16(fa[2], hb2 * thv[2], Wm);
@@ -1162,19 +1263,21 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
-      if (row_ok && i < T) {
-        const double W = mv ? Wm[q] : w1 * vv[q];
-        aA[q] += W * (double)dx[q];
-        aB[q] += W * (double)dy[q];
-      }
+      const CellVal<R> ev = cell_eval<R, KIND, true>(col[q], rq, xe, lnf, row_ok && i < T);
+      const double Wq = MV ? Wm[q] : w1 * col[q].v;
+      aA[q] = fma(Wq, (double)ev.d1, aA[q]);
+      aB[q] = fma(Wq, (double)ev.d2, aB[q]);
+      if (!MV) aU[q] = fma(w1, ev.v, aU[q]);
     }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double A = sum16(aA[q]), B = sum16(aB[q]);
+    const double U = MV ? 0.0 : sum16(aU[q]);
     if (jr == 0) {
       colA[wv][4 * q + g] = A;
       colB[wv][4 * q + g] = B;
+      colU[wv][4 * q + g] = U;
     }
   }
   __syncthreads();
@@ -1188,7 +1291,23 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
     }
     double v = (icol < T && qp < f.nresp) ? A * J0 + B * J1 : 0.0;
     v = sum16(v);
-    if (c16 == 0) f.bwdpart[(size_t)bl * 4 + qp] = v;
+    if (c16 == 0) bwdpart[qp] = v;
+  }
+  if (!MV) {  // rate partials sum_i F^_si u_i over the tile's 16 columns
+    const int s = threadIdx.x & 15, c = threadIdx.x >> 4;  // 256 threads: (column c, species s)
+    const int i = ct * kColTile + c;
+    double u = colU[0][c];
+#pragma unroll
+    for (int w = 1; w < kBwdWaves; ++w) u += colU[w][c];
+    rsum[c][s] = (i < T && s < S) ? F64[(size_t)i * kSP + s] * u : 0.0;
+    __syncthreads();
+    if (threadIdx.x < kSP) {
+      double a = 0.0;
+      for (int cc = 0; cc < 16; ++cc) a += rsum[cc][threadIdx.x];
+      bwdpart[4 + threadIdx.x] = a;
+    }
+  } else if (threadIdx.x < kSP) {
+    bwdpart[4 + threadIdx.x] = 0.0;
   }
 }
 
@@ -1219,7 +1338,7 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   // every field used is read into registers before the first store (a store
   // through a generic pointer could alias f and force reloads after it)
   const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N, S = f.S, P = f.P;
-  const int nresp = f.nresp, pu_float = f.pu_float;
+  const int nresp = f.nresp, pu_float = f.pu_float, vsum = f.vsum;
   const bool tab = f.kind == kTable && f.nresp > 0;
   const bool jt = f.mv && f.joint;
   const bool rad = f.mv && f.n_rad > 0 && !f.joint;
@@ -1251,7 +1370,7 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   for (int b = t; b < n_cpblk; b += NT) fl |= cpflag[b];
   if (with_grad)
     for (int b = t; b < n_bwdblk; b += NT)
-      for (int q = 0; q < 4; ++q) acc[1 + q] += bwdpart[(size_t)b * 4 + q];
+      for (int q = 0; q < 4; ++q) acc[1 + q] += bwdpart[(size_t)b * kBwdPart + q];
   if (jt)  // joint term: one partial per reco row
     for (int b = t; b < N; b += NT) {
       acc[0] += jnll[b];
@@ -1260,8 +1379,14 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       if (tab && with_grad) acc[6] += jtp[b];
     }
   // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
+  // (vsum: from the backward sweep's partials sum_i F^_si u_i)
   double gr = 0.0;
-  for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
+  if (vsum) {
+    if (with_grad)
+      for (int b = t >> 4; b < n_bwdblk; b += NT / 16) gr += bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
+  } else {
+    for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
+  }
   if (jt && with_grad)
     for (int b = t >> 4; b < N; b += NT / 16) gr += jg[b * kSP + (t & 15)];
   gr += __shfl_xor(gr, 16, 64);
@@ -1536,16 +1661,17 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
   }
 }
 
-// Ceiling microbenchmark of the edge arithmetic, with the forward sweep's
-// lane layout: each wave takes one (true tile, reco tile) pair inside a tile
-// support (chosen by a hash of its index, so the mix of shapes and arguments
-// is the workload's), lane (j = l%16, g = l/16) holds the constants of
-// columns 4q+g, q = 0..3, and the edge x_j in registers, and evaluates the
-// four edges (value and the two column-parameter derivatives) `reps` times.
-// No list building, contraction, stored differences or memory traffic in the
-// loop: the rate the sweep's edge arithmetic alone reaches.  eps is 0 at run
-// time (it only keeps each repetition's argument from being hoisted); sink
-// is written only if the sum equals `never`, which keeps the results live.
+// Ceiling microbenchmark of the cell arithmetic, with the sweeps' lane
+// layout: each wave takes one (true tile, reco tile) pair inside a tile
+// support (chosen by a hash of its index, so the mix of shapes, arguments and
+// paths is the workload's), lane (j = l%16, g = l/16) holds the constants of
+// columns 4q+g, q = 0..3, and its bin's constants in registers, and evaluates
+// the four cells (value and the two column-parameter derivatives, by the same
+// path as the backward sweep) `reps` times.  No list building, contraction or
+// memory traffic in the loop: the rate the cell arithmetic alone reaches.
+// eps is 0 at run time (it only keeps each repetition's arguments from being
+// hoisted); sink is written only if the sum equals `never`, which keeps the
+// results live.
 template <class R, int KIND>
 __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int reps, double eps, double never,
                                                       double* sink) {
@@ -1559,22 +1685,27 @@ __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int re
   const int rt = rt_a + (int)((wid / 7u) % (unsigned)(rt_b - rt_a + 1));
   const double xe = f.xe[min(rt * kRowStep + jr, f.N)];
   const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;
+  const RowQ<R> rq = load_rowq<R, KIND>(f, min(rt * kRowStep + jr, f.N - 1));
+  const bool ok = rt * kRowStep + jr < f.N && jr < kRowStep;
   ColPre<R> c[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const ColPar& cp = f.cp[min(ct * kColTile + 4 * q + g, f.T - 1)];
+    GColPar& cp = ((GColPar*)f.cp)[min(ct * kColTile + 4 * q + g, f.T - 1)];
+    c[q].cp = &cp;
     c[q].c0 = cp.c0;
-    c[q].c1 = cp.c1;
+    c[q].c1 = KIND == kGauss ? cp.c1 : KIND == kGG ? cp.c1 * cp.f64[3] : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) c[q].s[u] = sizeof(R) == 4 ? (R)cp.f32[u] : (R)cp.f64[u];
-    c[q].bb = (R)0;
+    c[q].v = 0.0;
   }
-  R acc = (R)0;
+  double acc = 0.0;
   for (int r = 0; r < reps; ++r) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const EdgeVal<R> ev = edge_pre<R, KIND, true>(c[q], xe + eps * r, lnf);
-      acc += ev.v + ev.d1 + ev.d2;
+      ColPre<R> cc = c[q];
+      cc.c0 += eps * r;
+      const CellVal<R> ev = cell_eval<R, KIND, true>(cc, rq, xe + eps * r, lnf, ok);
+      acc += ev.v + (double)(ev.d1 + ev.d2);
     }
   }
   if ((double)acc == never) sink[0] = (double)acc;
@@ -1609,20 +1740,25 @@ void launch_mark(double* d_mark, double v, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-template <class R, int KIND, bool D>
-static void launch_fwd_d(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {
+template <class R, int KIND, bool MV>
+static void launch_fwd_m(int cg, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits, const int* d_active) {
   switch (cg) {
-    case 1: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 1, D>), grid, blk, 0, st, d_fits, d_active); break;
-    case 2: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 2, D>), grid, blk, 0, st, d_fits, d_active); break;
-    case 4: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 4, D>), grid, blk, 0, st, d_fits, d_active); break;
-    default: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 8, D>), grid, blk, 0, st, d_fits, d_active); break;
+    case 1: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 1, MV>), grid, blk, 0, st, d_fits, d_active); break;
+    case 2: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 2, MV>), grid, blk, 0, st, d_fits, d_active); break;
+    case 4: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 4, MV>), grid, blk, 0, st, d_fits, d_active); break;
+    default: hipLaunchKernelGGL((k_cells_fwd<R, KIND, 8, MV>), grid, blk, 0, st, d_fits, d_active); break;
   }
 }
 template <class R, int KIND>
-static void launch_fwd(int cg, bool d, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits,
+static void launch_fwd(int cg, bool mv, dim3 grid, dim3 blk, hipStream_t st, const FitDev* d_fits,
                        const int* d_active) {
-  if (d) launch_fwd_d<R, KIND, true>(cg, grid, blk, st, d_fits, d_active);
-  else launch_fwd_d<R, KIND, false>(cg, grid, blk, st, d_fits, d_active);
+  if (mv) launch_fwd_m<R, KIND, true>(cg, grid, blk, st, d_fits, d_active);
+  else launch_fwd_m<R, KIND, false>(cg, grid, blk, st, d_fits, d_active);
+}
+template <class R, int KIND>
+static void launch_bwd(bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active, int pre) {
+  if (mv) hipLaunchKernelGGL((k_cells_bwd<R, KIND, true>), grid, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+  else hipLaunchKernelGGL((k_cells_bwd<R, KIND, false>), grid, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
 }
 
 // One stage of an evaluation: 0 colparams, 1 cells_fwd, 2 reduce_M,
@@ -1675,15 +1811,14 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
                            d_fits, d_active);
       break;
     case 1:
-      if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (f32 && L.kind == kGG) launch_fwd<float, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
-      if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, with_grad, gf, bf, st, d_fits, d_active);
+      if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
+      if (f32 && L.kind == kGG) launch_fwd<float, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
+      if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
+      if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
+      if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       break;
     case 2:
-      if (f32) hipLaunchKernelGGL(k_reduce_M<float>, gred, blk, 0, st, d_fits, d_active);
-      else hipLaunchKernelGGL(k_reduce_M<double>, gred, blk, 0, st, d_fits, d_active);
+      hipLaunchKernelGGL(k_reduce_M, gred, blk, 0, st, d_fits, d_active);
       break;
     case 3:
       hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
@@ -1700,14 +1835,11 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       break;
     case 6:
       if (!with_grad) break;
-      if (f32 && L.any_mv)
-        hipLaunchKernelGGL((k_cells_bwd<float, true>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
-      else if (f32)
-        hipLaunchKernelGGL((k_cells_bwd<float, false>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
-      else if (L.any_mv)
-        hipLaunchKernelGGL((k_cells_bwd<double, true>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
-      else
-        hipLaunchKernelGGL((k_cells_bwd<double, false>), gb, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
+      if (f32 && gauss) launch_bwd<float, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
+      if (f32 && L.kind == kGG) launch_bwd<float, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
+      if (!f32 && gauss) launch_bwd<double, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
+      if (!f32 && L.kind == kGG) launch_bwd<double, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
+      if (L.kind == kCount) launch_bwd<double, kCount>(L.any_mv, gb, st, d_fits, d_active, pre);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
@@ -1729,7 +1861,9 @@ __global__ void __launch_bounds__(kBlock) k_expected(const FitDev* fits, double*
   if (!f.mv) {
     if (t < f.N) {
       double mu = 0.0;
-      for (int s = 0; s < f.S; ++s) mu += f.Mp[t * kSP + s] * th[s];
+      if (f.vsum) mu = f.Mp[t * kSP];
+      else
+        for (int s = 0; s < f.S; ++s) mu += f.Mp[t * kSP + s] * th[s];
       out[t] = mu;
     }
     return;

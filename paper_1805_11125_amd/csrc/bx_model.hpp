@@ -42,6 +42,11 @@ struct HostModel {
   std::vector<uint32_t> jent;  // k << 16 | l, counts)
   std::vector<double> jval;
   std::vector<double> jsig;   // [16] (sum_k rho_sk)(sum_l T_sl)
+  // quadrature of the cells: per reco bin the GG bin centre p (ln x_j + ln x_j+1)/2,
+  // the half-width in the quadrature variable and the node constants (FP32 4
+  // nodes, FP64 5 nodes)
+  std::vector<double> qpum, qhw, qrow64;
+  std::vector<float> qrow32;
   GGConst gg;
   Tiles tiles;
 };

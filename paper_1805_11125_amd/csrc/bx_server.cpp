@@ -95,7 +95,8 @@ static int64_t now_ns() {
 }
 
 constexpr int kThetaStride = 40;  // theta[P] and the step number, 5 cache lines
-constexpr int kGroups = 32;       // launch groups: 4 kinds x 2 precisions x 4 forward tile widths
+constexpr int kGroups = 64;       // launch groups: 4 kinds x 2 precisions x (one histogram |
+                                  // several) x 4 forward tile widths
 constexpr int kOutStride = 40;    // nll, grad[P], flags, completion mark
 
 struct Req {
@@ -109,7 +110,7 @@ struct Req {
   void* mem = nullptr;
   DeviceFit df;            // host copy of the slot's FitDev (source of its upload)
   LaunchShape shape{};     // grid needs of this fit (set at admission)
-  int group = 0;           // launch group: (kind, precision, forward tiles per wave)
+  int group = 0;           // launch group: (kind, precision, multivariate, forward tiles per wave)
   bx_fit_result res{};
   bool done = false;
 };
@@ -181,7 +182,9 @@ static void admit(bx_server* s) {
     r->shape = shape_of(df.dev);
     int cgl = 0;
     while ((1 << cgl) < r->shape.CG) ++cgl;
-    r->group = (r->shape.kind * 2 + r->shape.prec) * 4 + cgl;
+    // the sweeps' contraction differs between single-histogram and
+    // multivariate fits, so the two never share a launch
+    r->group = ((r->shape.kind * 2 + r->shape.prec) * 2 + r->shape.any_mv) * 4 + cgl;
     (void)hipMemcpyAsync(s->d_fits + r->slot, &df.dev, sizeof(FitDev), hipMemcpyHostToDevice, s->stream);
     r->res.t_admit_ns = now_ns();
     s->active.push_back(r);

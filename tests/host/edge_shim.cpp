@@ -40,3 +40,46 @@ void edge_f64(int n, const double* ct, const double* k, const double* cR, const 
 // Cell between two encoded edge values.
 float cell_f32(float lo, float hi) { return cell_from<float>(lo, hi); }
 }
+
+// Quadrature cells (bin integrals of the density).  Generalized gamma: the
+// bin [x0, x1] in ln x, column (ct, k, cR, ln k - psi(k)), exponent p; out:
+// value, dR/dk, dR/d ln a.  Gaussian: bin [x0, x1], column (m, 1/sigma); out:
+// value, dR/dm, dR/dsigma.  The value is formed in FP64 from the sums of the
+// cell precision, the derivatives in the cell precision.
+template <class R, int NQ>
+static void quad_gg(int n, const double* lnx0, const double* lnx1, double ct, double k, double cR,
+                    double lnk_psi, double p, double* out) {
+  for (int i = 0; i < n; ++i) {
+    const QRowGG<R, NQ> rw = qrow_gg<R, NQ>(lnx0[i], lnx1[i], p);
+    const double pum = 0.5 * p * (lnx0[i] + lnx1[i]), h = 0.5 * p * (lnx1[i] - lnx0[i]);
+    const CellVal<R> e = gg_cell_quad<R, NQ, true>(pum, h, ct, rw, (R)k, k * cR, (R)lnk_psi, (R)(p * k));
+    out[3 * i] = e.v;
+    out[3 * i + 1] = e.d1;
+    out[3 * i + 2] = e.d2;
+  }
+}
+template <class R, int NQ>
+static void quad_gauss(int n, const double* x0, const double* x1, double m, double inv_sigma, double* out) {
+  for (int i = 0; i < n; ++i) {
+    const CellVal<R> e = gauss_cell_quad<R, NQ, true>(0.5 * (x0[i] + x1[i]), 0.5 * (x1[i] - x0[i]), m, inv_sigma);
+    out[3 * i] = e.v;
+    out[3 * i + 1] = e.d1;
+    out[3 * i + 2] = e.d2;
+  }
+}
+extern "C" {
+void quad_gg_f32(int n, const double* a, const double* b, double ct, double k, double cR, double lk, double p,
+                 double* o) {
+  quad_gg<float, kNQ32>(n, a, b, ct, k, cR, lk, p, o);
+}
+void quad_gg_f64(int n, const double* a, const double* b, double ct, double k, double cR, double lk, double p,
+                 double* o) {
+  quad_gg<double, kNQ64>(n, a, b, ct, k, cR, lk, p, o);
+}
+void quad_gauss_f32(int n, const double* a, const double* b, double m, double is, double* o) {
+  quad_gauss<float, kNQ32>(n, a, b, m, is, o);
+}
+void quad_gauss_f64(int n, const double* a, const double* b, double m, double is, double* o) {
+  quad_gauss<double, kNQ64>(n, a, b, m, is, o);
+}
+}

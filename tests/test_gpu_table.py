@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_util import check_nll_grad, grad_errors
 import synth
 from oracle import model as om
 
@@ -58,12 +59,7 @@ def check(bx, d, x, th, label):
     m = bx.Model(d, x, precision=F64)
     v, g = m.nll_grad(th)
     v0, g0 = oracle.nll_grad(d, x, th)
-    sc = oracle.grad_scale(d, x, th)
-    rel = abs(v - v0) / abs(v0)
-    gerr = np.abs(g - g0) / sc
-    print(f"{label}: NLL {v:.12g} oracle {v0:.12g} rel={rel:.2e}; grad max err/scale={gerr.max():.2e}")
-    assert rel <= 1e-9, (v, v0)
-    assert np.all(gerr <= 1e-6), gerr
+    check_nll_grad(label, d, x, th, v, g, v0, g0)
     assert m.nll(th) == v
     return m
 
