@@ -637,6 +637,19 @@ static bx_status enqueue_eval(bx_model* m, bool grad, bool host, hipStream_t st)
   return BX_OK;
 }
 
+// Work on stream st that uses the model's workspace is ordered after the
+// work the previous call enqueued on another stream (an autograd evaluation on
+// torch's stream followed by a host-path evaluation on the model's, say):
+// record an event there and make st wait for it.
+static bx_status order_on(bx_model* m, hipStream_t st) {
+  if (m->last_stream && m->last_stream != st) {
+    BX_HIP(hipEventRecord(m->ws_event, m->last_stream), "stream ordering");
+    BX_HIP(hipStreamWaitEvent(st, m->ws_event, 0), "stream ordering");
+  }
+  m->last_stream = st;
+  return BX_OK;
+}
+
 namespace bx {
 // Evaluate at host theta; fills nll (and grad).  Shared with the plain fitter.
 bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad) {
@@ -654,7 +667,9 @@ bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad
   const double seq = (double)(++m->seq);
   hp[P] = seq;
   flush_lines(hp, P + 1);  // theta in memory before the launch
-  bx_status s = enqueue_eval(m, grad != nullptr, true, m->stream);
+  bx_status s = order_on(m, m->stream);
+  if (s != BX_OK) return s;
+  s = enqueue_eval(m, grad != nullptr, true, m->stream);
   if (s != BX_OK) return s;
   // The last kernel writes the sequence number after the results (with a
   // system-scope fence): spin on it, and ask the stream now and then so that
@@ -730,6 +745,7 @@ bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* h
     m->own_stream = true;
   }
   if (hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(BX_E_DEVICE);
+  if (hipEventCreateWithFlags(&m->ws_event, hipEventDisableTiming) != hipSuccess) return fail(BX_E_DEVICE);
   const size_t bytes = device_fit_bytes(m->h);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) {
@@ -790,6 +806,8 @@ bx_status bx_model_set_data(bx_model* m, const bx_data* data) {
   }
   bx_status s = set_host_data(&m->h, data);
   if (s != BX_OK) return s;
+  s = order_on(m, m->stream);
+  if (s != BX_OK) return s;
   s = upload_data(m->h, m->df, m->stream);
   if (s != BX_OK) return s;
   BX_HIP(hipStreamSynchronize(m->stream), "data upload");
@@ -803,7 +821,9 @@ bx_status bx_model_free(bx_model* m) {
     set_error("model in use by a server fit");
     return BX_E_BUSY;
   }
+  if (m->last_stream) (void)hipStreamSynchronize(m->last_stream);
   if (m->stream) (void)hipStreamSynchronize(m->stream);
+  if (m->ws_event) (void)hipEventDestroy(m->ws_event);
   if (m->g_eval) (void)hipGraphExecDestroy(m->g_eval);
   if (m->g_grad) (void)hipGraphExecDestroy(m->g_grad);
   if (m->g_grad_dev) (void)hipGraphExecDestroy(m->g_grad_dev);
@@ -839,8 +859,10 @@ bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, voi
   if (!m || !d_theta || !d_out) return inval("NULL argument");
   hipStream_t st = stream ? (hipStream_t)stream : m->stream;
   const int P = m->h.P;
+  bx_status s = order_on(m, st);
+  if (s != BX_OK) return s;
   BX_HIP(hipMemcpyAsync(m->df.d_theta, d_theta, P * sizeof(double), hipMemcpyDeviceToDevice, st), "theta copy");
-  bx_status s = enqueue_eval(m, true, false, st);
+  s = enqueue_eval(m, true, false, st);
   if (s != BX_OK) return s;
   BX_HIP(hipMemcpyAsync(d_out, m->df.d_out, (1 + P) * sizeof(double), hipMemcpyDeviceToDevice, st), "result copy");
   return BX_OK;

@@ -1442,8 +1442,12 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       nll += rad_nll;
       flags |= (int)rad_fl;
     }
+    // a zero-width Gaussian column leaves the NLL defined but not its
+    // gradient: with the gradient requested it is a domain error like the
+    // others (+inf in out[0], which is all the device-pointer entry point hands
+    // back)
     if (!with_grad) flags &= ~kZeroWidth;
-    const double v0 = (flags & ~kZeroWidth) ? INFINITY : nll;
+    const double v0 = flags ? INFINITY : nll;
     out[0] = v0;
     out[1 + P] = (double)flags;
 #pragma unroll

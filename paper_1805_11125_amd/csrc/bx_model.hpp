@@ -104,6 +104,11 @@ struct bx_model {
   int* d_active = nullptr;       // {0}
   hipStream_t stream = nullptr;  // launches
   bool own_stream = false;
+  // The evaluation workspace (theta, column parameters, partials, results) is
+  // shared by every entry point; a call on another stream than the previous
+  // one waits for the work already enqueued there (order_on).
+  hipStream_t last_stream = nullptr;
+  hipEvent_t ws_event = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
   hipGraphExec_t g_eval = nullptr, g_grad = nullptr;  // host-buffer path (d_fit_h)
   hipGraphExec_t g_grad_dev = nullptr;                // device-buffer path (d_fit)

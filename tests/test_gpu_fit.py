@@ -97,6 +97,30 @@ def test_autograd_function(bx):
     np.testing.assert_array_equal(t.grad.cpu().numpy(), 2.5 * g)
 
 
+def test_autograd_then_host_path_are_ordered(bx):
+    # an evaluation enqueued on torch's stream (autograd) and a host-path
+    # evaluation at another point issued right after it share the model's
+    # workspace: each must equal its isolated result bit for bit
+    import torch
+    d, x = synth.load("c2")
+    m = bx.Model(d, x, precision=F32)
+    th_a = d.theta_true * 1.01
+    th_b = d.theta_true * (1 + 0.01 * np.random.default_rng(4).standard_normal(d.P))
+    va, ga = m.nll_grad(th_a)
+    vb, gb = m.nll_grad(th_b)
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        with torch.cuda.stream(side):
+            t = torch.tensor(th_a, dtype=torch.float64, device="cuda", requires_grad=True)
+            loss = bx.NLLFunction.apply(m, t)
+        v2, g2 = m.nll_grad(th_b)          # no synchronisation in between
+        with torch.cuda.stream(side):
+            loss.backward()
+        torch.cuda.synchronize()
+        assert loss.item() == va and np.array_equal(t.grad.cpu().numpy(), ga)
+        assert v2 == vb and np.array_equal(g2, gb)
+
+
 def _toys(n, first=0):
     base, per_species, theta = synth.catalogue()
     out = []

@@ -176,6 +176,12 @@ def test_zero_width_gauss_eval_and_grad_domain(bx):
         assert abs(v - v0) <= 1e-9 * abs(v0)
     with pytest.raises(bx.DomainError):
         m.nll_grad(th)
+    # the device-pointer entry point (autograd) reports it as NLL = +inf
+    import torch
+    t = torch.tensor(th, dtype=torch.float64, device="cuda")
+    out = torch.empty(d.P + 1, dtype=torch.float64, device="cuda")
+    m.nll_grad_dev(t.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert math.isinf(out[0].item()) and out[0].item() > 0
 
 
 def test_domain_errors(bx):

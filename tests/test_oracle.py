@@ -825,3 +825,52 @@ def test_joint_gradient_vs_richardson():
             t[q] = v
             return om.nll(d, x, t)
         assert g[q] == pytest.approx(_richardson(f, th[q], 1e-3 * abs(th[q])), rel=1e-7, abs=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# The gradient tolerance scale, sum_b |(1 - n_b/mu_b) dmu_b/dq| over every bin
+# of every term, against a per-bin loop over Richardson differences of the
+# expected counts (nothing of oracle.grad_scale's own contraction is reused).
+# ---------------------------------------------------------------------------
+def _bruteforce_scale(d, data, th):
+    f0 = om.forward(d, th)
+    obs = om.observed(d, data)
+    keys = list(f0.mu)
+    mu0 = {k: np.asarray(f0.mu[k], float).ravel() for k in keys}
+    n = {k: np.asarray(obs[k], float).ravel() for k in keys}
+    out = []
+    for q in range(d.P):
+        h = 1e-4 * max(abs(th[q]), 1e-3)
+
+        def mu_at(v, key):
+            t = th.copy()
+            t[q] = v
+            return np.asarray(om.forward(d, t).mu[key], float).ravel()
+
+        total = 0.0
+        for key in keys:
+            dmu = _richardson(lambda v: mu_at(v, key), th[q], h)
+            for b in range(len(mu0[key])):
+                w = 1.0 - n[key][b] / mu0[key][b] if n[key][b] > 0 else 1.0
+                total += abs(w) * abs(dmu[b])
+        out.append(total)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("maker", ["gauss", "gg_pileup", "mv"])
+def test_grad_scale_is_the_sum_of_absolute_summands(maker):
+    if maker == "gauss":
+        d = tiny_gauss(T=10, N=9, S=2)
+    elif maker == "gg_pileup":
+        d = tiny_gg(T=12, N=10)
+        d.pu_g, d.pu_frac = np.exp(-np.arange(4) / 2.0), 0.05
+    else:
+        d = synth.config3a()
+    th = d.theta_true * (1 + 0.02 * np.random.default_rng(11).standard_normal(d.P))
+    data = synth.load("c3a")[1] if d.multivariate else poisson_data(d, d.theta_true)
+    got = oracle.grad_scale(d, data, th)
+    want = _bruteforce_scale(d, data, th)
+    np.testing.assert_allclose(got, want, rtol=1e-6)
+    # it bounds the gradient, and the looser scale bounds it
+    assert np.all(np.abs(oracle.grad(d, data, th)) <= got * (1 + 1e-12))
+    assert np.all(got <= oracle.grad_scale_abs(d, data, th))
