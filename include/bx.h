@@ -174,6 +174,22 @@ bx_status bx_nll_grad(bx_model* m, const double* theta, double* nll, double* gra
  * Asynchronous; the status describes the enqueue only. */
 bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as bx_nll_grad_dev, with the same results bit for bit, whose
+ * per-evaluation workspace (about 2 MB for a 3000 x 900 single-histogram
+ * model, 3.5 MB multivariate) comes from one 16 MiB array in device memory
+ * that the library holds on each GPU it runs on until the process ends,
+ * instead of the model's own workspace.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); the caller passes the
+ * inputs and outputs.  Must run on the model's device (BX_E_INVAL otherwise);
+ * a model whose workspace exceeds the array is rejected with BX_E_INVAL.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and must be
+ * serialised by the caller.  Asynchronous on `stream` (NULL = the model's);
+ * the status describes the enqueue only. */
+bx_status bx_nll_grad_dev_noalloc(bx_model* m, const double* d_theta, double* d_out, void* stream);
+
 /* Expected counts of every likelihood term at theta, for the full reco range:
  * out = [mu_energy[N] | mu_tagged[N] | nu_radial[n_rad] | lambda_ps[N][n_ps]]
  * (single histogram: mu[N] only).  bx_model_expected_size gives the length. */

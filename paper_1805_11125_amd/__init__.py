@@ -235,6 +235,12 @@ class Model:
         check(self._lib.bx_nll_grad_dev(self._h, C.c_void_p(theta_dev), C.c_void_p(out_dev),
                                         C.c_void_p(stream) if stream else None))
 
+    def nll_grad_dev_noalloc(self, theta_dev, out_dev, stream=None):
+        """As nll_grad_dev, with the workspace in the library's fixed device
+        array (bx_nll_grad_dev_noalloc): no device memory is allocated."""
+        check(self._lib.bx_nll_grad_dev_noalloc(self._h, C.c_void_p(theta_dev), C.c_void_p(out_dev),
+                                                C.c_void_p(stream) if stream else None))
+
     def fit(self, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, max_eval=0):
         o, keep = _fit_opts(self.P, x0, float_mask, lo, hi, edm_tol, max_iter, max_eval=max_eval)
         r = _abi.bx_fit_result()

@@ -65,6 +65,7 @@ SIGNATURES = {
     "bx_nll_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "bx_nll_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bx_nll_grad_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bx_nll_grad_dev_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bx_model_expected_size": (C.c_int64, [C.c_void_p]),
     "bx_model_expected": (C.c_int, [C.c_void_p, _dp, _dp]),
     "bx_model_stage_times": (C.c_int, [C.c_void_p, _dp, C.c_int32, _dp]),

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -865,6 +866,75 @@ bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, voi
   s = enqueue_eval(m, true, false, st);
   if (s != BX_OK) return s;
   BX_HIP(hipMemcpyAsync(d_out, m->df.d_out, (1 + P) * sizeof(double), hipMemcpyDeviceToDevice, st), "result copy");
+  return BX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation.  The per-evaluation workspace of
+// bx_nll_grad_dev_noalloc (column parameters, forward partials, M, M', the
+// adjoint weights, the per-block partials, theta and the results, and the
+// fit's descriptor) is carved from one file-scope device array instead of the
+// model's own workspace; every kernel writes what it later reads, so nothing
+// in it needs clearing between calls.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a stand-in, not a
+// device address), only the address hipGetSymbolAddress returns for the
+// current device, looked up once per device on the first call there.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)16 << 20;  // 16 MiB per device
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+bx_status scratch_of_device(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index beyond the scratch table");
+    return BX_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bx_status bx_nll_grad_dev_noalloc(bx_model* m, const double* d_theta, double* d_out, void* stream) {
+  if (!m || !d_theta || !d_out) return inval("NULL argument");
+  int dev = -1;
+  BX_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != m->device) return inval("bx_nll_grad_dev_noalloc: the model lives on another device than the current one");
+  const size_t ws = (device_fit_bytes(m->h, true) + 255) & ~(size_t)255;  // inputs stay the model's
+  const size_t need = ws + ((sizeof(FitDev) + 255) & ~(size_t)255);
+  if (need > kScratchBytes) {
+    set_error("bx_nll_grad_dev_noalloc: the model's workspace (" + std::to_string(need) +
+              " bytes) exceeds the scratch array (" + std::to_string(kScratchBytes) + " bytes)");
+    return BX_E_INVAL;
+  }
+  char* base = nullptr;
+  bx_status s = scratch_of_device(dev, &base);
+  if (s != BX_OK) return s;
+  hipStream_t st = stream ? (hipStream_t)stream : m->stream;
+  DeviceFit df;
+  s = place_fit(m->h, base, &df, st, &m->df.dev);  // carves only: no allocation, no upload
+  if (s != BX_OK) return s;
+  FitDev* d_fd = (FitDev*)(base + ws);
+  const int P = m->h.P;
+  BX_HIP(hipMemcpyAsync(d_fd, &df.dev, sizeof(FitDev), hipMemcpyHostToDevice, st), "descriptor copy");
+  BX_HIP(hipMemcpyAsync(df.d_theta, d_theta, P * sizeof(double), hipMemcpyDeviceToDevice, st), "theta copy");
+  launch_eval(d_fd, nullptr, 1, shape_of(df.dev), true, st);
+  BX_HIP(hipGetLastError(), "launch");
+  BX_HIP(hipMemcpyAsync(d_out, df.d_out, (1 + P) * sizeof(double), hipMemcpyDeviceToDevice, st), "result copy");
   return BX_OK;
 }
 
