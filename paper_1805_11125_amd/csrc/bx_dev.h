@@ -21,6 +21,7 @@ constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG 
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
 constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
 constexpr int kBwdWaves = 4;   // waves per backward block (one reco tile each, times RG)
+constexpr int kFixSplit = 4;   // forward fix-up blocks per reco tile (their shares of Mfix)
 constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up adjoint in its own kernel
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
@@ -104,6 +105,13 @@ struct FitDev {
   int2* tb;             // [n_ct] support of each column tile (cells)
   double* Mpart;        // [n_cg][N][16] (multivariate) or [n_cg][N] (vsum): one partial per
                         // chunk of 16 listed true tiles
+  double* Mfix;         // [kFixSplit][N][16] or [kFixSplit][N]: the forward fix-up sweep's
+                        // shares (cells outside the sweeps' common case), added last
+  int has_fix;          // analytic cells: the fix-up sweeps run (not for the count estimator)
+  unsigned char* fixmask;  // [n_rt][n_ct]: bit q set when the forward sweep left step q of the
+                           // (reco tile, true tile) pair to the fix-up sweeps (listed pairs only)
+  int* fixflag;         // [n_rt + n_ct]: reco tiles, then true tiles, with a step left (cleared
+                        // by k_colparams, set by the forward sweep)
   double* M;            // [N][16] sum of the partials (FP64)
   double* Mp;           // [N][16] after pile-up
   double* H;            // [N][16] dNLL/d(r_s M'_js) / r_s, without the radial part
@@ -126,6 +134,7 @@ struct FitDev {
   int* cpflag;          // [n_cpblk] domain flags of the column parameters
   double* bwdpart;      // [n_bwdblk][kBwdPart] response-gradient partials, then (vsum) the
                         // rate-gradient partials sum_i F^_si u_i, u = R^T w~
+  double* bwdfix;       // [n_ct][kBwdPart] the backward fix-up sweep's partials
   double* out;          // [2 + P]: nll, grad[P], flags
   const double* theta_src;  // pinned host [P + 1]: theta and the caller's sequence number, or null
   double* out_host;         // pinned host [3 + P]: the results, then the sequence number as
@@ -134,7 +143,7 @@ struct FitDev {
 
 // Grid sizes of one batched launch (maxima over the fits in it).
 struct LaunchShape {
-  int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks;
+  int max_T, max_fwd_blocks, max_NS, max_rowblk, max_bwd_blocks, max_rt, max_ct;
   int kind, prec, any_mv, any_rad, any_joint;
   int CG;  // forward tiles per wave (one value per launch)
 };

@@ -422,6 +422,7 @@ void derive_tiles(const HostModel& h, FitDev* f) {
   f->sup_prec = h.prec;
   f->mv = h.mv;
   f->vsum = (!h.mv && h.kind != kTable) ? 1 : 0;
+  f->has_fix = (h.kind == kGG || h.kind == kGauss) ? 1 : 0;
   f->n_rad = h.n_rad;
 }
 
@@ -478,6 +479,10 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->cp = c.take<ColPar>(h.kind == kTable ? 0 : h.T);
   f->tb = c.take<int2>(f->n_ct);
   f->Mpart = c.take<double>((size_t)f->n_cg * h.N * (f->vsum ? 1 : kSP));
+  f->Mfix = c.take<double>((size_t)kFixSplit * h.N * (f->vsum ? 1 : kSP));
+  f->bwdfix = c.take<double>((size_t)f->n_ct * kBwdPart);
+  f->fixmask = c.take<unsigned char>((size_t)f->n_rt * f->n_ct);
+  f->fixflag = c.take<int>((size_t)f->n_rt + f->n_ct);
   f->M = c.take<double>((size_t)h.N * kSP);
   f->Mp = c.take<double>((size_t)h.N * kSP);
   f->H = c.take<double>((size_t)h.N * kSP);
@@ -536,6 +541,8 @@ LaunchShape shape_of(const FitDev& f) {
   L.max_NS = f.N * kSP;
   L.max_rowblk = f.n_rowblk;
   L.max_bwd_blocks = (f.n_ct + 7) / 8 * 8 * f.n_rg;  // true tiles interleaved over the 8 XCDs
+  L.max_rt = f.n_rt;
+  L.max_ct = f.n_ct;
   L.kind = f.kind;
   L.prec = f.prec;
   L.any_mv = f.mv;

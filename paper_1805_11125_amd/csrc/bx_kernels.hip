@@ -272,6 +272,10 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   int2* const tbo = f.tb;
   int* const cpflag = f.cpflag;
   const int T = f.T;
+  int* const fixflag = f.fixflag;
+  const int nflag = f.has_fix ? f.n_rt + f.n_ct : 0, nthr = f.n_cpblk * kCpBlock;
+  // this evaluation's fix-up flags start clear (the forward sweep sets them)
+  for (int e = i; e < nflag; e += nthr) fixflag[e] = 0;
   // theta straight from pinned host memory when the caller passed it there,
   // with system-scope loads (a plain load may hit a line of the previous
   // evaluation's theta still held in the GPU caches); block 0 leaves a device
@@ -406,21 +410,42 @@ struct ColPre {
   GColPar* cp;    // the column's parameters (FP64 constants of the CDF at the edges)
 };
 
-// The CDF at a reco edge (GG, Gaussian), in FP64 whatever the cell precision:
-// it serves only bins too wide for the quadrature (or a GG bin from x <= 0,
-// whose cell is the single value F(x_1)), where FP32 would leave the
-// per-column rounding of its constants in the cell.
-template <int KIND, bool D>
-__device__ __forceinline__ EdgeVal<double> edge64(GColPar* cp, double xe) {
+// The CDF at a reco edge (GG, Gaussian) and its two column-parameter
+// derivatives, for bins too wide for the quadrature (or a GG bin from x <= 0,
+// whose cell is the single value F(x_1)).  The value is formed in FP64 (the
+// value alone: no derivative carried through the series), the derivatives in
+// the cell precision: an FP32 value would leave the per-column rounding of its
+// constants in the cell, which the gradient amplifies; FP32 derivatives do not
+// matter there.
+template <class R, int KIND, bool D>
+__device__ __forceinline__ EdgeVal<double> edge_mixed(const ColPre<R>& c, double xe) {
+  EdgeVal<double> o;
+  GColPar* cp = c.cp;
   if constexpr (KIND == kGauss) {
-    return gauss_edge<double, D>(xe, cp->c0, cp->c1);
+    o.v = gauss_edge<double, false>(xe, cp->c0, cp->c1).v;
+    if (D) {
+      const EdgeVal<R> e = gauss_edge<R, true>(xe, c.c0, c.c1);
+      o.d1 = e.d1;
+      o.d2 = e.d2;
+    }
   } else {
     GGCol<double> g;
     g.ct = cp->c0;
     g.k = cp->f64[0]; g.ik = cp->f64[1]; g.skh = cp->f64[2]; g.cR = cp->f64[3]; g.ce = cp->f64[4];
     g.dlngs = cp->f64[5]; g.lnk_psi = cp->f64[6]; g.p = cp->f64[7];
-    return gg_edge<double, D>(xe, g);
+    o.v = gg_edge<double, false>(xe, g).v;
+    if (D) {
+      GGCol<R> h;
+      h.ct = c.c0;
+      h.k = c.s[0]; h.ik = c.s[1]; h.skh = c.s[2]; h.cR = c.s[3]; h.ce = c.s[4];
+      h.dlngs = c.s[5]; h.lnk_psi = c.s[6]; h.p = c.s[7];
+      const EdgeVal<R> e = gg_edge<R, true>(xe, h);
+      o.d1 = e.d1;
+      o.d2 = e.d2;
+    }
   }
+  if (!D) o.d1 = o.d2 = 0.0;
+  return o;
 }
 
 // Quadrature constants of a lane's reco bin: GG the bin centre in p ln x, its
@@ -463,48 +488,86 @@ __device__ __forceinline__ RowQ<R> load_rowq(const FitDev& f, int j) {
 // The cell R_ji of the lane's reco bin j for column c, and with D its
 // derivatives in the column parameters (Gaussian: m, sigma; GG: k, ln a;
 // count: m, r).  Analytic responses integrate the density over the bin by
-// Gauss-Legendre quadrature, with a composite rule of up to kMaxSub intervals
-// when the bin is wide against the column (quad_intervals); a bin wider than
-// that (or a GG bin from x <= 0) is the difference of the CDF at its edges,
-// the upper one from the next lane of the row (DPP row_shl:1).  Every lane of
-// a row evaluates its edge when any lane of the row needs one.  The count
-// estimator's cell is its pmf at the lane's count.  ok = false (no such bin
-// or column) gives zeros.  Called by all lanes of the wave.
+// Gauss-Legendre quadrature.  The sweeps take the common case (cell_lean):
+// every lane of the wave a single quadrature interval, all but about 0.4 % of
+// the wave steps of the 3000 x 900 sweep; the other steps are
+// left to the fix-up sweeps (k_cells_fwd_fix, k_cells_bwd_fix), which take
+// every case (cell_general): a composite rule of up to kMaxSub intervals when
+// the bin is wide against the column (quad_intervals), and a bin wider than
+// that (or a GG bin from x <= 0) as the difference of the CDF at its edges,
+// the upper one from the next lane of the row (DPP row_shl:1).  Kept out of
+// the main sweeps, the general code no longer sets their register allocation
+// (with it inlined they ran several times slower).  The count estimator's
+// cell is its pmf at the lane's count (always the lean case).  ok = false (no
+// such bin or column) gives zeros.  Both are called by all lanes of the wave.
+template <class R, int KIND>
+__device__ __forceinline__ bool lean_lane(const ColPre<R>& c, const RowQ<R>& rq, bool ok) {
+  if constexpr (KIND == kGG) {
+    const R crit = (R)1.4142135623730950488 * c.s[2] * (R)rq.b;  // sqrt(k) h
+    return !ok || crit <= (R)kQuadMax;
+  } else if constexpr (KIND == kGauss) {
+    return !ok || (c.c1 > 0.0 && rq.b * c.c1 <= kQuadMax);
+  }
+  return true;
+}
+
 template <class R, int KIND, bool D>
-__device__ __forceinline__ CellVal<R> cell_eval(const ColPre<R>& c, const RowQ<R>& rq, double xe, double lnf,
+__device__ __forceinline__ CellVal<R> cell_lean(const ColPre<R>& c, const RowQ<R>& rq, double xe, double lnf,
                                                 bool ok) {
   CellVal<R> o;
-  o.v = 0.0;
-  o.d1 = o.d2 = (R)0;
   if constexpr (KIND == kCount) {
     const EdgeVal<R> e = count_cell<D>(xe, lnf, c.s);
     o.v = e.v;
     o.d1 = e.d1;
     o.d2 = e.d2;
+  } else if constexpr (KIND == kGG) {
+    o = gg_cell_lean<R, RowQ<R>::NQ, D>((R)(rq.a - c.c0), rq.b * (c.c1 * gl_norm<R, RowQ<R>::NQ>()), rq.g,
+                                        c.s[0] * (R)kLog2e, c.s[6], c.s[7] * c.s[0]);
   } else {
-    // inverse width of the column in the quadrature variable: GG sqrt(k) in
-    // t = ln(y/k); Gaussian 1/sigma (none for a zero width)
-    const double iw = KIND == kGG ? 1.4142135623730950488 * (double)c.s[2] : (c.c1 > 0.0 ? c.c1 : NAN);
-    const int ns = ok ? quad_intervals(rq.b, iw) : 1;  // lanes without a cell side with quadrature
-    const unsigned long long eb = __ballot(ns == 0);
-    const bool row_edge = ((eb >> (threadIdx.x & 48)) & 0xffffull) != 0;  // row-uniform
-    if (ns > 0) {
-      if constexpr (KIND == kGG)
-        o = gg_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, rq.g, c.s[0], c.c1, c.s[6], c.s[7] * c.s[0], ns);
-      else
-        o = gauss_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, c.c1, ns);
-    }
-    if (row_edge) {
-      const EdgeVal<double> e = edge64<KIND, D>(c.cp, xe);
-      const double vh = dpp_from_next(e.v);
-      const double d1h = D ? dpp_from_next(e.d1) : 0.0;
-      const double d2h = D ? dpp_from_next(e.d2) : 0.0;
-      if (ns == 0) {
-        o.v = cell_from(e.v, vh);
-        if (D) {
-          o.d1 = (R)(d1h - e.d1);
-          o.d2 = (R)(d2h - e.d2);
-        }
+    o = gauss_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, c.c1);
+  }
+  if (!ok) {
+    o.v = 0.0;
+    o.d1 = o.d2 = (R)0;
+  }
+  return o;
+}
+
+template <class R, int KIND, bool D>
+__device__ __forceinline__ CellVal<R> cell_general(const ColPre<R>& c, const RowQ<R>& rq, double xe, bool ok) {
+  CellVal<R> o;
+  o.v = 0.0;
+  o.d1 = o.d2 = (R)0;
+  // inverse width of the column in the quadrature variable: GG sqrt(k) in
+  // t = ln(y/k); Gaussian 1/sigma (none for a zero width)
+  const double iw = KIND == kGG ? 1.4142135623730950488 * (double)c.s[2] : (c.c1 > 0.0 ? c.c1 : NAN);
+  const int ns = ok ? quad_intervals(rq.b, iw) : 1;  // lanes without a cell side with quadrature
+  const unsigned long long eb = __ballot(ns == 0);
+  const int lane = threadIdx.x & 63;
+  const bool row_edge = ((eb >> (lane & 48)) & 0xffffull) != 0;  // row-uniform
+  // the edge values the row needs: the lower edge of each CDF-difference cell
+  // (the lane's own) and its upper edge (the next lane's); the FP64 CDF runs
+  // a series or continued fraction of up to ~100 terms, so the other lanes
+  // leave it alone
+  const bool need = ((eb >> lane) & 1) || ((lane & 15) > 0 && ((eb >> (lane - 1)) & 1));
+  if (ns > 0) {
+    if constexpr (KIND == kGG)
+      o = gg_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, rq.g, c.s[0], c.c1, c.s[6], c.s[7] * c.s[0], ns);
+    else
+      o = gauss_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, c.c1, ns);
+  }
+  if (row_edge) {
+    EdgeVal<double> e;
+    e.v = e.d1 = e.d2 = 0.0;
+    if (need) e = edge_mixed<R, KIND, D>(c, xe);
+    const double vh = dpp_from_next(e.v);
+    const double d1h = D ? dpp_from_next(e.d1) : 0.0;
+    const double d2h = D ? dpp_from_next(e.d2) : 0.0;
+    if (ns == 0) {
+      o.v = cell_from(e.v, vh);
+      if (D) {
+        o.d1 = (R)(d1h - e.d1);
+        o.d2 = (R)(d2h - e.d2);
       }
     }
   }
@@ -689,6 +752,9 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   GD* const F64 = (GD*)f.F64;
   const int T = f.T, N = f.N, n_cg = f.n_cg;
   double* const Mpart = f.Mpart;
+  unsigned char* const fixrow = f.fixmask + (size_t)rt * f.n_ct;
+  int* const fixflag = f.fixflag;
+  const int n_rt = f.n_rt;
   const int je = min(j0 + jr, N);
   const double xe = ((GD*)f.xe)[je];
   const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;  // count estimator: ln n! of the row
@@ -718,15 +784,30 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
     if (e >= n_here) return acc;  // wave-uniform
     const int ct = mylist[e];
     ColPre<R> cur = fetch(ct * kColTile + g);
+    int left = 0;  // steps left to the fix-up sweeps (bit q)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ColPre<R> nxt;
       if (q < 3) nxt = fetch(ct * kColTile + 4 * (q + 1) + g);
       const int i = ct * kColTile + 4 * q + g;
-      const CellVal<R> ev = cell_eval<R, KIND, false>(cur, rq, xe, lnf, row_ok && i < T);
-      if constexpr (MV) acc = mfma16(ev.v, cur.v, acc);
-      else acc = fma(ev.v, cur.v, acc);
+      const bool ok = row_ok && i < T;
+      if (__all(lean_lane<R, KIND>(cur, rq, ok))) {
+        const CellVal<R> ev = cell_lean<R, KIND, false>(cur, rq, xe, lnf, ok);
+        if constexpr (MV) acc = mfma16(ev.v, cur.v, acc);
+        else acc = fma(ev.v, cur.v, acc);
+      } else {
+        left |= 1 << q;
+      }
       if (q < 3) cur = nxt;
+    }
+    if constexpr (KIND != kCount) {
+      if (lane == 0) {
+        fixrow[ct] = (unsigned char)left;
+        if (left) {  // the fix-up sweeps of this reco tile and this true tile have work
+          atomicOr(fixflag + rt, 1);
+          atomicOr(fixflag + n_rt + ct, 1);
+        }
+      }
     }
     return acc;
   };
@@ -823,6 +904,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
     s += a3;
   }
   for (; c < n; ++c) s += p[c * stride];
+  if (f.has_fix && f.fixflag[(t >> 4) / kRowStep]) {  // the fix-up sweep's shares, last
+    const double* q = f.vsum ? f.Mfix + (t >> 4) : f.Mfix + t;
+    for (int b = 0; b < kFixSplit; ++b) s += q[b * stride];
+  }
   f.M[t] = s;
 }
 
@@ -1263,11 +1348,15 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ct * kColTile + 4 * q + g;
-      const CellVal<R> ev = cell_eval<R, KIND, true>(col[q], rq, xe, lnf, row_ok && i < T);
-      const double Wq = MV ? Wm[q] : w1 * col[q].v;
-      aA[q] = fma(Wq, (double)ev.d1, aA[q]);
-      aB[q] = fma(Wq, (double)ev.d2, aB[q]);
-      if (!MV) aU[q] = fma(w1, ev.v, aU[q]);
+      // the same steps as the forward sweep's; the others are k_cells_bwd_fix's
+      const bool ok = row_ok && i < T;
+      if (__all(lean_lane<R, KIND>(col[q], rq, ok))) {
+        const CellVal<R> ev = cell_lean<R, KIND, true>(col[q], rq, xe, lnf, ok);
+        const double Wq = MV ? Wm[q] : w1 * col[q].v;
+        aA[q] = fma(Wq, (double)ev.d1, aA[q]);
+        aB[q] = fma(Wq, (double)ev.d2, aB[q]);
+        if (!MV) aU[q] = fma(w1, ev.v, aU[q]);
+      }
     }
   }
 #pragma unroll
@@ -1312,6 +1401,296 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
 }
 
 // ---------------------------------------------------------------------------
+// Fix-up sweeps: the wave steps the sweeps above leave (some lane of the wave
+// not a single quadrature interval), with the general cell: composite
+// quadrature, or the CDF at the bin's edges.  The forward sweep records the
+// steps it leaves in fixmask (bit q of the (reco tile, true tile) byte); the
+// backward sweep leaves the same ones, by the same test on the same operands.
+// An entry is one such step.  Each fix-up block lists the entries of its tile
+// in a fixed order, its waves take every NW-th entry (the forward spreads a
+// reco tile over kFixSplit blocks, which take turns), and the sums over the
+// waves and blocks are added in a fixed order, so these partials do not
+// depend on the launch either.  In the 3000 x 900 generalized-gamma sweep
+// they are about 0.4 % of the wave steps: the reco bin from x <= 0 (its cell
+// the CDF at x_1) and wide low-energy bins against narrow columns.
+
+constexpr int kFixWaves = 8;  // waves per fix-up block
+
+// Compacts the entries with want = true of one chunk of NW * 64 candidates
+// (candidate c at thread c) into list[], in candidate order; returns their
+// count.  Called by the whole block.
+template <int NW>
+__device__ __forceinline__ int fix_compact(bool want, int value, int* list, int* wcount) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned long long m = __ballot(want);
+  if (lane == 0) wcount[wv] = __popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < NW; ++w) {
+    off += w < wv ? wcount[w] : 0;
+    tot += wcount[w];
+  }
+  if (want) list[off + __popcll(m & ((1ull << lane) - 1ull))] = value;
+  __syncthreads();
+  return tot;
+}
+
+// Column i's constants as the sweeps hold them (i >= T: those of column T - 1
+// with a zero contraction weight; the cell is masked by the caller).
+// v: forward MV F^[i, jr]; otherwise the single-histogram v_i, and (backward
+// MV) zero.
+template <class R, int KIND>
+__device__ __forceinline__ ColPre<R> fix_col(const FitDev& f, int i, double vmv, bool mv) {
+  GColPar& cpi = ((GColPar*)f.cp)[i < f.T ? i : f.T - 1];
+  ColPre<R> c;
+  c.cp = &cpi;
+  c.c0 = cpi.c0;
+  c.c1 = KIND == kGauss ? cpi.c1 : cpi.c1 * cpi.f64[3];
+  if (KIND != kGauss) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c.s[u] = sizeof(R) == 4 ? (R)cpi.f32[u] : (R)cpi.f64[u];
+  }
+  c.v = i >= f.T ? 0.0 : mv ? vmv : cpi.v;
+  return c;
+}
+
+// Block (reco tile rt, share b < kFixSplit).  Candidates: (true tile, step)
+// pairs in order; writes share b of rt's rows of Mfix (zeros where nothing is
+// left).
+template <class R, int KIND, bool MV>
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* fits,
+                                                                                 const int* active) {
+  constexpr int NW = kFixWaves, NTH = NW * 64;
+  typedef typename std::conditional<MV, v4d, double>::type V;
+  constexpr int NR = MV ? 4 : 1;
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) const unsigned char GU;
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int rt = blockIdx.x / kFixSplit, sh = blockIdx.x % kFixSplit;
+  // block-uniform; nothing left in this reco tile: its shares of Mfix are not read
+  if (rt >= f.n_rt || f.vsum == (int)MV || ((GI*)f.fixflag)[rt] == 0) return;
+  __shared__ int list[NTH], wcount[NW];
+  __shared__ double part[NW][NR][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int T = f.T, N = f.N, n_ct = f.n_ct, j0 = rt * kRowStep;
+  GD* const F64 = (GD*)f.F64;
+  GI* const tbp = (GI*)f.tb;
+  GU* const maskrow = (GU*)f.fixmask + (size_t)rt * n_ct;
+  const bool row_ok = (jr < kRowStep) && (j0 + jr < N);
+  const double xe = ((GD*)f.xe)[min(j0 + jr, N)];
+  const RowQ<R> rq = load_rowq<R, KIND>(f, min(j0 + jr, N - 1));
+  V acc = {};
+  for (int c0 = 0; c0 < 4 * n_ct; c0 += NTH) {
+    const int cand = c0 + (int)threadIdx.x, ct = cand >> 2;
+    bool want = false;
+    if (ct < n_ct) {
+      const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];
+      // a tile the forward sweep listed for this reco tile (its byte is current)
+      if (by >= bx && !(by < j0 || bx > j0 + kRowStep - 1)) want = (maskrow[ct] >> (cand & 3)) & 1;
+    }
+    const int n = fix_compact<NW>(want, cand, list, wcount);
+    for (int e = sh * NW + wv; e < n; e += kFixSplit * NW) {
+      const int ent = list[e];
+      const int i = (ent >> 2) * kColTile + 4 * (ent & 3) + g;
+      const ColPre<R> c = fix_col<R, KIND>(f, i, MV && i < T ? F64[i * kSP + jr] : 0.0, MV);
+      const CellVal<R> ev = cell_general<R, KIND, false>(c, rq, xe, row_ok && i < T);
+      if constexpr (MV) acc = mfma16(ev.v, c.v, acc);
+      else acc = fma(ev.v, c.v, acc);
+    }
+    __syncthreads();  // list[] is rewritten by the next chunk
+  }
+  if constexpr (MV) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
+  } else {
+    part[wv][0][lane] = acc;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  if constexpr (MV) {
+    double* const out = f.Mfix + (size_t)sh * N * kSP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double x = part[0][r][lane];
+      for (int w = 1; w < NW; ++w) x += part[w][r][lane];
+      const int row = g + 4 * r;  // FP64 MFMA result layout: row l/16 + 4r, column l%16
+      if (row < kRowStep && j0 + row < N) out[(size_t)(j0 + row) * kSP + jr] = x;
+    }
+  } else {
+    double x = part[0][0][lane];
+    for (int w = 1; w < NW; ++w) x += part[w][0][lane];
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    if (g == 0 && row_ok) f.Mfix[(size_t)sh * N + j0 + jr] = x;
+  }
+}
+
+// Orders one wave's LDS accesses (a wave's LDS operations complete in
+// order; the fences keep the compiler from moving accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Single histogram: w~_j = (P^T w)_j for the rows j = r0 + jr of one reco
+// tile, by one wave, with the arithmetic of the backward sweep's prologue and
+// k_adjoint1 (four fused chains over the taps k = part (mod 4), added
+// pairwise), so the fix-up weights carry the same bits.  Lane (jr, g) runs
+// chain g of row jr from the rows staged in the wave's hs[]; gl[] holds the
+// K > 1 taps.  Returns w~ of the lane's row (0 past the end).
+__device__ __forceinline__ double wtilde_tile(const FitDev& f, int r0, int K, double* hs, const double* gl) {
+  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int N = f.N, nrow = min(kRowStep + K - 1, N - r0);
+  const double* const H = f.H;
+  for (int e = lane; e < nrow; e += 64) hs[e] = H[(size_t)(r0 + e) * kSP];
+  wave_lds_sync();
+  const int j = r0 + jr;
+  const bool row_ok = jr < kRowStep && j < N;
+  double acc = 0.0;
+  if (row_ok) {
+    const int kmax = min(K - 1, N - 1 - j);
+    for (int k = g; k <= kmax; k += 4) acc = fma(gl[k], hs[jr + k], acc);
+  }
+  const double p0 = __shfl(acc, jr, 64), p1 = __shfl(acc, jr + 16, 64);
+  const double p2 = __shfl(acc, jr + 32, 64), p3 = __shfl(acc, jr + 48, 64);
+  const double pp = pu_p(f);
+  const double h = row_ok ? fma(pp, (p0 + p1) + (p2 + p3), (1.0 - pp) * hs[jr]) : 0.0;
+  wave_lds_sync();  // hs[] is rewritten by the wave's next entry
+  return h;
+}
+
+// Block = true tile ct.  Candidates: (reco tile of ct's support, step) pairs
+// in order; a wave forms its entry's weights as the backward sweep does and
+// evaluates the step.  Writes bwdfix[ct] (zeros where nothing is left).
+template <class R, int KIND, bool MV>
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits,
+                                                                                const int* active, int pre) {
+  constexpr int NW = kFixWaves, NTH = NW * 64;
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) const unsigned char GU;
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int ct = blockIdx.x;
+  // block-uniform; nothing left in this true tile: its partials are not read
+  if (ct >= f.n_ct || f.mv != (int)MV || ((GI*)f.fixflag)[f.n_rt + ct] == 0) return;
+  __shared__ int list[NTH], wcount[NW];
+  __shared__ double colA[NW][16], colB[NW][16], colU[NW][16];
+  __shared__ double rsum[16][kSP];
+  __shared__ double gl[kMaxK], hsw[NW][kRowStep + kMaxK - 1];  // single histogram's w~ (pile-up)
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
+  const int T = f.T, N = f.N, S = f.S, n_ct = f.n_ct;
+  GColPar* const cpar = (GColPar*)f.cp;
+  GD* const F64 = (GD*)f.F64;
+  GU* const mask = (GU*)f.fixmask;
+  double* const out = f.bwdfix + (size_t)ct * kBwdPart;
+  const int bx = ((GI*)f.tb)[2 * ct], by = ((GI*)f.tb)[2 * ct + 1];  // support [bx, by]
+  const int rt_a = by >= bx ? max(bx, 0) / kRowStep : 0;
+  const int rt_b = by >= bx ? min(by / kRowStep, f.n_rt - 1) : -1;
+  double fa[4] = {0, 0, 0, 0}, thv[4] = {0, 0, 0, 0};
+  if (MV) {  // F operands of the weights (lane: column lane%16, species 4 kb + lane/16)
+    const int i = ct * kColTile + jr;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const int s = 4 * kb + g;
+      fa[kb] = (i < T && s < S) ? F64[(size_t)i * kSP + s] : 0.0;
+      thv[kb] = s < S ? ((GD*)f.theta)[s] : 0.0;
+    }
+  }
+  const int K = pu_len(f);
+  const bool wt = !MV && !pre && K > 1;  // w~ formed here from H and the taps
+  if (wt) {
+    for (int e = threadIdx.x; e < K; e += NTH) gl[e] = ((GD*)f.ghat)[e];
+    __syncthreads();
+  }
+  double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
+  const int ncand = 4 * (rt_b - rt_a + 1);
+  for (int c0 = 0; c0 < ncand; c0 += NTH) {
+    const int cand = c0 + (int)threadIdx.x, rt = rt_a + (cand >> 2);
+    const bool want = cand < ncand && ((mask[(size_t)rt * n_ct + ct] >> (cand & 3)) & 1);
+    const int n = fix_compact<NW>(want, cand, list, wcount);
+    for (int e = wv; e < n; e += NW) {
+      const int ent = list[e], qe = ent & 3;
+      const int j = (rt_a + (ent >> 2)) * kRowStep + jr;
+      const bool row_ok = (jr < kRowStep) && (j < N);
+      const double xe = ((GD*)f.xe)[min(j, N)];
+      const RowQ<R> rq = load_rowq<R, KIND>(f, min(j, N - 1));
+      const int i = ct * kColTile + 4 * qe + g;
+      const ColPre<R> c = fix_col<R, KIND>(f, i, 0.0, MV);
+      double Wq;
+      double w1 = 0.0;
+      if (MV) {  // W for the 16 columns of the tile (wave-uniform), then the lane's column 4 qe + g
+        v4d Wm = {0, 0, 0, 0};
+        GD* hr = (GD*)f.Ht + (size_t)min(j, N - 1) * kSP + g;
+        const double hb0 = (row_ok && g < S) ? hr[0] : 0.0;
+        const double hb1 = (row_ok && 4 + g < S) ? hr[4] : 0.0;
+        const double hb2 = (row_ok && 8 + g < S) ? hr[8] : 0.0;
+        const double hb3 = (row_ok && 12 + g < S) ? hr[12] : 0.0;
+        Wm = mfma16(fa[0], hb0 * thv[0], Wm);
+        Wm = mfma16(fa[1], hb1 * thv[1], Wm);
+        Wm = mfma16(fa[2], hb2 * thv[2], Wm);
+        Wm = mfma16(fa[3], hb3 * thv[3], Wm);
+        Wq = qe == 0 ? Wm[0] : qe == 1 ? Wm[1] : qe == 2 ? Wm[2] : Wm[3];
+      } else {
+        if (wt) w1 = wtilde_tile(f, j - jr, K, hsw[wv], gl);  // the whole wave
+        else if (row_ok) w1 = ((GD*)(pre ? f.Ht : f.H))[(size_t)j * kSP];
+        Wq = w1 * c.v;
+      }
+      const CellVal<R> ev = cell_general<R, KIND, true>(c, rq, xe, row_ok && i < T);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q != qe) continue;  // wave-uniform
+        aA[q] = fma(Wq, (double)ev.d1, aA[q]);
+        aB[q] = fma(Wq, (double)ev.d2, aB[q]);
+        if (!MV) aU[q] = fma(w1, ev.v, aU[q]);
+      }
+    }
+    __syncthreads();  // list[] is rewritten by the next chunk
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double A = sum16(aA[q]), B = sum16(aB[q]);
+    const double U = MV ? 0.0 : sum16(aU[q]);
+    if (jr == 0) {
+      colA[wv][4 * q + g] = A;
+      colB[wv][4 * q + g] = B;
+      colU[wv][4 * q + g] = U;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // column totals (fixed order over the waves), times the chain factors
+    const int c16 = threadIdx.x & 15, qp = threadIdx.x >> 4;
+    const int icol = ct * kColTile + c16;
+    double A = colA[0][c16], B = colB[0][c16];
+    for (int w = 1; w < NW; ++w) {
+      A += colA[w][c16];
+      B += colB[w][c16];
+    }
+    double v = (icol < T && qp < f.nresp) ? A * cpar[icol].J[0][qp] + B * cpar[icol].J[1][qp] : 0.0;
+    v = sum16(v);
+    if (c16 == 0) out[qp] = v;
+  }
+  if (!MV) {  // rate partials sum_i F^_si u_i over the tile's 16 columns
+    for (int t = threadIdx.x; t < 256; t += NTH) {
+      const int s = t & 15, c = t >> 4;
+      const int i = ct * kColTile + c;
+      double u = colU[0][c];
+      for (int w = 1; w < NW; ++w) u += colU[w][c];
+      rsum[c][s] = (i < T && s < S) ? F64[(size_t)i * kSP + s] * u : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < kSP) {
+      double a = 0.0;
+      for (int cc = 0; cc < 16; ++cc) a += rsum[cc][threadIdx.x];
+      out[4 + threadIdx.x] = a;
+    }
+  } else if (threadIdx.x < kSP) {
+    out[4 + threadIdx.x] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fixed-order sums of the per-block partials into out[] (NT threads).  The
 // order depends only on NT and the partial counts, so the eval-only launch and
 // the backward kernel's last block give identical bits.
@@ -1338,7 +1717,8 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   // every field used is read into registers before the first store (a store
   // through a generic pointer could alias f and force reloads after it)
   const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N, S = f.S, P = f.P;
-  const int nresp = f.nresp, pu_float = f.pu_float, vsum = f.vsum;
+  const int nresp = f.nresp, pu_float = f.pu_float, vsum = f.vsum, has_fix = f.has_fix, n_ct = f.n_ct;
+  const int n_rt = f.n_rt;
   const bool tab = f.kind == kTable && f.nresp > 0;
   const bool jt = f.mv && f.joint;
   const bool rad = f.mv && f.n_rad > 0 && !f.joint;
@@ -1348,6 +1728,8 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   GD* const tpart = (GD*)f.tpart;
   GI* const cpflag = (GI*)f.cpflag;
   GD* const bwdpart = (GD*)f.bwdpart;
+  GD* const bwdfix = (GD*)f.bwdfix;
+  GI* const fixflag = (GI*)f.fixflag;
   GD* const gpart = (GD*)f.gpart;
   GD* const jnll = (GD*)f.jnll;
   GI* const jflag = (GI*)f.jflag;
@@ -1368,9 +1750,14 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     if (tab && with_grad) acc[6] += tpart[b];
   }
   for (int b = t; b < n_cpblk; b += NT) fl |= cpflag[b];
-  if (with_grad)
+  if (with_grad) {
     for (int b = t; b < n_bwdblk; b += NT)
       for (int q = 0; q < 4; ++q) acc[1 + q] += bwdpart[(size_t)b * kBwdPart + q];
+    if (has_fix)  // then the backward fix-up sweep's partials (true tiles with steps left)
+      for (int b = t; b < n_ct; b += NT)
+        if (fixflag[n_rt + b])
+          for (int q = 0; q < 4; ++q) acc[1 + q] += bwdfix[(size_t)b * kBwdPart + q];
+  }
   if (jt)  // joint term: one partial per reco row
     for (int b = t; b < N; b += NT) {
       acc[0] += jnll[b];
@@ -1382,8 +1769,12 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   // (vsum: from the backward sweep's partials sum_i F^_si u_i)
   double gr = 0.0;
   if (vsum) {
-    if (with_grad)
+    if (with_grad) {
       for (int b = t >> 4; b < n_bwdblk; b += NT / 16) gr += bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
+      if (has_fix)
+        for (int b = t >> 4; b < n_ct; b += NT / 16)
+          if (fixflag[n_rt + b]) gr += bwdfix[(size_t)b * kBwdPart + 4 + (t & 15)];
+    }
   } else {
     for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
   }
@@ -1708,7 +2099,7 @@ __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int re
     for (int q = 0; q < 4; ++q) {
       ColPre<R> cc = c[q];
       cc.c0 += eps * r;
-      const CellVal<R> ev = cell_eval<R, KIND, true>(cc, rq, xe + eps * r, lnf, ok);
+      const CellVal<R> ev = cell_lean<R, KIND, true>(cc, rq, xe + eps * r, lnf, ok);
       acc += ev.v + (double)(ev.d1 + ev.d2);
     }
   }
@@ -1760,6 +2151,15 @@ static void launch_fwd(int cg, bool mv, dim3 grid, dim3 blk, hipStream_t st, con
   else launch_fwd_m<R, KIND, false>(cg, grid, blk, st, d_fits, d_active);
 }
 template <class R, int KIND>
+static void launch_fix(bool fwd, bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active,
+                       int pre) {
+  const dim3 b(kFixWaves * 64);
+  if (fwd && mv) hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active);
+  if (fwd && !mv) hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active);
+  if (!fwd && mv) hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active, pre);
+  if (!fwd && !mv) hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active, pre);
+}
+template <class R, int KIND>
 static void launch_bwd(bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active, int pre) {
   if (mv) hipLaunchKernelGGL((k_cells_bwd<R, KIND, true>), grid, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
   else hipLaunchKernelGGL((k_cells_bwd<R, KIND, false>), grid, dim3(kBwdWaves * 64), 0, st, d_fits, d_active, pre);
@@ -1781,6 +2181,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
   const dim3 blk(kBlock);
   const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), grow(L.max_rowblk, n);
   const dim3 gred((L.max_NS + kBlock - 1) / kBlock, n), bf(kFwdWaves * 64);
+  const dim3 gfx(L.max_rt * kFixSplit, n), gbx(L.max_ct, n);  // fix-up sweeps (per reco / true tile)
   const bool f32 = L.prec == kF32, gauss = L.kind == kGauss;
   // batches form a single histogram's pile-up adjoint once per fit
   const int pre = n >= kPreAdjFits ? 1 : 0;
@@ -1820,6 +2221,11 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
+      // then the steps the sweep left
+      if (f32 && gauss) launch_fix<float, kGauss>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
+      if (f32 && L.kind == kGG) launch_fix<float, kGG>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
+      if (!f32 && gauss) launch_fix<double, kGauss>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
+      if (!f32 && L.kind == kGG) launch_fix<double, kGG>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
       break;
     case 2:
       hipLaunchKernelGGL(k_reduce_M, gred, blk, 0, st, d_fits, d_active);
@@ -1844,6 +2250,10 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       if (!f32 && gauss) launch_bwd<double, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (!f32 && L.kind == kGG) launch_bwd<double, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (L.kind == kCount) launch_bwd<double, kCount>(L.any_mv, gb, st, d_fits, d_active, pre);
+      if (f32 && gauss) launch_fix<float, kGauss>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
+      if (f32 && L.kind == kGG) launch_fix<float, kGG>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
+      if (!f32 && gauss) launch_fix<double, kGauss>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
+      if (!f32 && L.kind == kGG) launch_fix<double, kGG>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);

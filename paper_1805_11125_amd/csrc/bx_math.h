@@ -664,6 +664,64 @@ BX_HD CellVal<R> gg_cell_quad(double pum, double h, double ct, const QRowGG<R, N
   return o;
 }
 
+// The common case of gg_cell_quad, written for speed: one interval, the node
+// exponentials e^{-k phi} as 2^{-kl phi} with kl = k log2(e), and the FP64
+// scale sc = h kcr_n (kcr_n = k cR times the weight normalisation, a column
+// constant).  FP32: phi(t) from its series for |t| < 1.25, else as
+// (e^t - 1) - t with e^t = 2^{t log2(e)}, which loses nothing there (e^t - 1
+// and phi are both bounded away from zero) beyond what the FP32 rounding of t
+// itself already costs.  Same quantities as gg_cell_quad.
+template <class R>
+BX_HD R exp2_fast(R x);
+template <>
+BX_HD float exp2_fast<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_exp2f(x);
+#else
+  return exp2f(x);
+#endif
+}
+template <>
+BX_HD double exp2_fast<double>(double x) { return exp2(x); }
+
+template <class R, int NQ, bool D>
+BX_HD CellVal<R> gg_cell_lean(R t, double sc, const QRowGG<R, NQ>& rw, R kl, R lnk_psi, R pk) {
+  R um;
+  R phm;
+  if constexpr (sizeof(R) == 4) {
+    if (fabsf(t) < 1.25f) {
+      phm = phi_series(t);
+      um = phm + t;
+    } else {
+      um = exp2_fast<float>(t * (float)kLog2e) - 1.0f;
+      phm = um - t;
+    }
+  } else {
+    phm = phi_full(t, &um);
+  }
+  const R epm = (R)1 + um;
+  R s0 = (R)0, s1 = (R)0, s2 = (R)0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const R ph = fma(epm, rw.fd[q], fma(um, rw.d[q], phm));
+    const R wE = (R)GaussLegendre<NQ>::w[q] * exp2_fast<R>(-kl * ph);
+    s0 += wE;
+    if (D) {
+      s1 = fma(wE, t + rw.d[q], s1);
+      s2 = fma(wE, fma(epm, rw.ed[q], um), s2);
+    }
+  }
+  CellVal<R> o;
+  o.v = sc * (double)s0;
+  o.d1 = o.d2 = (R)0;
+  if (D) {
+    const R c = (R)sc;
+    o.d1 = c * fma(lnk_psi, s0, s1);
+    o.d2 = c * pk * s2;
+  }
+  return o;
+}
+
 // Gaussian cell R = int phi(z) dz over [zm - hs, zm + hs], zm = (x_mid - m)/sigma,
 // hs = (half bin width)/sigma, and its derivatives
 //   dR/dm     = int phi(z) z dz / sigma,
@@ -705,7 +763,7 @@ BX_HD CellVal<R> gauss_cell_quad(double xm, double hx, double m, double inv_sigm
 // quadrature variable) against the column's inverse width iw: 1 while
 // h iw <= kQuadMax, up to kMaxSub intervals of half-width <= kQuadMax / iw,
 // 0 beyond (the bin is then taken as a CDF difference).
-constexpr int kMaxSub = 8;
+constexpr int kMaxSub = 16;
 BX_HD int quad_intervals(double h, double iw) {
   const double c = h * iw;
   if (!(c <= kQuadMax * kMaxSub)) return 0;  // also h = +inf (a GG bin from x <= 0) or NaN

@@ -236,6 +236,8 @@ static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) 
       L.max_NS = std::max(L.max_NS, l.max_NS);
       L.max_rowblk = std::max(L.max_rowblk, l.max_rowblk);
       L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
+      L.max_rt = std::max(L.max_rt, l.max_rt);
+      L.max_ct = std::max(L.max_ct, l.max_ct);
       L.any_mv |= l.any_mv;
       L.any_rad |= l.any_rad;
       L.any_joint |= l.any_joint;
