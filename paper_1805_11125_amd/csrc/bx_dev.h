@@ -21,7 +21,7 @@ constexpr int kFwdWaves = 16;  // waves per forward block (one reco tile, 16 CG 
 constexpr int kMaxK = 256;     // longest random-trigger spectrum
 constexpr int kMaxRG = 4;      // reco tiles per backward wave (LDS staging bound)
 constexpr int kBwdWaves = 4;   // waves per backward block (one reco tile each, times RG)
-constexpr int kFixSplit = 4;   // forward fix-up blocks per reco tile (their shares of Mfix)
+constexpr int kFixSplit = 8;   // forward fix-up blocks per reco tile (their shares of Mfix)
 constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up adjoint in its own kernel
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
@@ -108,8 +108,11 @@ struct FitDev {
   double* Mfix;         // [kFixSplit][N][16] or [kFixSplit][N]: the forward fix-up sweep's
                         // shares (cells outside the sweeps' common case), added last
   int has_fix;          // analytic cells: the fix-up sweeps run (not for the count estimator)
-  unsigned char* fixmask;  // [n_rt][n_ct]: bit q set when the forward sweep left step q of the
-                           // (reco tile, true tile) pair to the fix-up sweeps (listed pairs only)
+  double* fixq;         // [n_ct][4]: per wave step (true tile, q), the largest column factor of
+                        // the one-interval test (GG sqrt(k) in the cell precision, Gauss 1/sigma;
+                        // +inf for a column without a width), written by k_colparams
+  const double* fixp;   // [n_rt]: per reco tile, the largest half-width of its bins in the
+                        // column's variable (model constant; +inf for the GG bin from x <= 0)
   int* fixflag;         // [n_rt + n_ct]: reco tiles, then true tiles, with a step left (cleared
                         // by k_colparams, set by the forward sweep)
   double* M;            // [N][16] sum of the partials (FP64)

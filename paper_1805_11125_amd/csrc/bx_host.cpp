@@ -347,6 +347,12 @@ bx_status make_host_model(const bx_model_desc* d, const bx_data* x, HostModel* h
       m.qhw[j] = 0.5 * (m.xraw[j + 1] - m.xraw[j]);
     }
   }
+  m.fixp.assign((m.N + kRowStep - 1) / kRowStep, 0.0);
+  for (int j = 0; j < m.N; ++j) {
+    double b = (m.kind == kGG && m.prec == kF32) ? (double)(float)m.qhw[j] : m.qhw[j];
+    if (b != b) b = INFINITY;
+    m.fixp[j / kRowStep] = std::max(m.fixp[j / kRowStep], b);
+  }
   // spectra: unit rows (FP64), times exposure, species padded to 16
   m.F64.assign((size_t)m.T * kSP, 0.0);
   m.F32.assign((size_t)m.T * kSP, 0.f);
@@ -440,6 +446,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->n_e = shared->n_e; f->n_t = shared->n_t; f->n_r = shared->n_r; f->n_p = shared->n_p;
     f->jrow = shared->jrow; f->jent = shared->jent; f->jval = shared->jval; f->jsig = shared->jsig;
     f->qpum = shared->qpum; f->qhw = shared->qhw; f->qrow32 = shared->qrow32; f->qrow64 = shared->qrow64;
+    f->fixp = shared->fixp;
   } else {
     f->xraw = c.take<double>(h.N + 1);
     f->xe = c.take<double>(h.N + 1);
@@ -464,6 +471,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
     f->qhw = c.take<double>(h.N);
     f->qrow32 = c.take<float>((size_t)h.N * 3 * kNQ32);
     f->qrow64 = c.take<double>((size_t)h.N * 3 * kNQ64);
+    f->fixp = c.take<double>(f->n_rt);
   }
   if (h.kind == kTable) {
     if (shared) {
@@ -481,7 +489,7 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->Mpart = c.take<double>((size_t)f->n_cg * h.N * (f->vsum ? 1 : kSP));
   f->Mfix = c.take<double>((size_t)kFixSplit * h.N * (f->vsum ? 1 : kSP));
   f->bwdfix = c.take<double>((size_t)f->n_ct * kBwdPart);
-  f->fixmask = c.take<unsigned char>((size_t)f->n_rt * f->n_ct);
+  f->fixq = c.take<double>((size_t)4 * f->n_ct);
   f->fixflag = c.take<int>((size_t)f->n_rt + f->n_ct);
   f->M = c.take<double>((size_t)h.N * kSP);
   f->Mp = c.take<double>((size_t)h.N * kSP);
@@ -609,6 +617,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   if (h.joint) BX_HIP(up(f.jsig, h.jsig, st), "upload");
   BX_HIP(up(f.qpum, h.qpum, st), "upload");
   BX_HIP(up(f.qhw, h.qhw, st), "upload");
+  BX_HIP(up(f.fixp, h.fixp, st), "upload");
   BX_HIP(up(f.qrow32, h.qrow32, st), "upload");
   BX_HIP(up(f.qrow64, h.qrow64, st), "upload");
   if (h.kind == kTable) BX_HIP(up(f.grid, h.grid, st), "upload");

@@ -273,6 +273,9 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   int* const cpflag = f.cpflag;
   const int T = f.T;
   int* const fixflag = f.fixflag;
+  double* const fixq = f.fixq;
+  const int n_ct = f.has_fix ? f.n_ct : 0;
+  double qv = 0.0;
   const int nflag = f.has_fix ? f.n_rt + f.n_ct : 0, nthr = f.n_cpblk * kCpBlock;
   // this evaluation's fix-up flags start clear (the forward sweep sets them)
   for (int e = i; e < nflag; e += nthr) fixflag[e] = 0;
@@ -388,7 +391,22 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
     if (bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
     c.jlo = jlo; c.jhi = jhi; c.bad = bad; c.pad = 0;
     cpo[i] = c;
+    // the column's factor of the sweeps' one-interval test, as the cells
+    // form it (step_lean)
+    if (f.kind == kGauss) {
+      qv = c.c1 > 0.0 ? c.c1 : INFINITY;
+    } else if (f.prec == kF32) {
+      const float w = 1.4142135623730950488f * c.f32[2];
+      qv = w == w ? (double)w : INFINITY;
+    } else {
+      const double w = 1.4142135623730950488 * c.f64[2];
+      qv = w == w ? w : INFINITY;
+    }
   }
+  // largest over the four columns of each wave step (columns past T: none)
+  qv = fmax(qv, __shfl_xor(qv, 1, 4));
+  qv = fmax(qv, __shfl_xor(qv, 2, 4));
+  if ((i & 3) == 0 && (i >> 2) < 4 * n_ct) fixq[i >> 2] = qv;
   // support of each 16-column tile, domain flags of the block
   for (int m = 8; m >= 1; m >>= 1) {
     jlo = min(jlo, __shfl_xor(jlo, m, 16));
@@ -489,8 +507,8 @@ __device__ __forceinline__ RowQ<R> load_rowq(const FitDev& f, int j) {
 // derivatives in the column parameters (Gaussian: m, sigma; GG: k, ln a;
 // count: m, r).  Analytic responses integrate the density over the bin by
 // Gauss-Legendre quadrature.  The sweeps take the common case (cell_lean):
-// every lane of the wave a single quadrature interval, all but about 0.4 % of
-// the wave steps of the 3000 x 900 sweep; the other steps are
+// every lane of the wave a single quadrature interval (step_lean), all but
+// about 0.4 % of the wave steps of the 3000 x 900 sweep; the other steps are
 // left to the fix-up sweeps (k_cells_fwd_fix, k_cells_bwd_fix), which take
 // every case (cell_general): a composite rule of up to kMaxSub intervals when
 // the bin is wide against the column (quad_intervals), and a bin wider than
@@ -500,14 +518,15 @@ __device__ __forceinline__ RowQ<R> load_rowq(const FitDev& f, int j) {
 // (with it inlined they ran several times slower).  The count estimator's
 // cell is its pmf at the lane's count (always the lean case).  ok = false (no
 // such bin or column) gives zeros.  Both are called by all lanes of the wave.
+// The one-interval test of a wave step (reco tile, true tile, q): every lane's
+// bin half-width times its column's inverse width at most kQuadMax, taken as
+// the product of the step's largest factors (p of the reco tile, q of the
+// four columns), in the precision the cells form it (GG: R; Gauss: FP64).
+// Rounding is monotonic, so this is exactly the test over all the lanes.
 template <class R, int KIND>
-__device__ __forceinline__ bool lean_lane(const ColPre<R>& c, const RowQ<R>& rq, bool ok) {
-  if constexpr (KIND == kGG) {
-    const R crit = (R)1.4142135623730950488 * c.s[2] * (R)rq.b;  // sqrt(k) h
-    return !ok || crit <= (R)kQuadMax;
-  } else if constexpr (KIND == kGauss) {
-    return !ok || (c.c1 > 0.0 && rq.b * c.c1 <= kQuadMax);
-  }
+__device__ __forceinline__ bool step_lean(double q, double p) {
+  if constexpr (KIND == kGG) return (R)q * (R)p <= (R)kQuadMax;
+  else if constexpr (KIND == kGauss) return q * p <= kQuadMax;
   return true;
 }
 
@@ -752,9 +771,10 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   GD* const F64 = (GD*)f.F64;
   const int T = f.T, N = f.N, n_cg = f.n_cg;
   double* const Mpart = f.Mpart;
-  unsigned char* const fixrow = f.fixmask + (size_t)rt * f.n_ct;
   int* const fixflag = f.fixflag;
+  GD* const fixq = (GD*)f.fixq;
   const int n_rt = f.n_rt;
+  const double pmax = KIND == kCount ? 0.0 : ((GD*)f.fixp)[rt];
   const int je = min(j0 + jr, N);
   const double xe = ((GD*)f.xe)[je];
   const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;  // count estimator: ln n! of the row
@@ -791,7 +811,7 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
       if (q < 3) nxt = fetch(ct * kColTile + 4 * (q + 1) + g);
       const int i = ct * kColTile + 4 * q + g;
       const bool ok = row_ok && i < T;
-      if (__all(lean_lane<R, KIND>(cur, rq, ok))) {
+      if (KIND == kCount || step_lean<R, KIND>(fixq[ct * 4 + q], pmax)) {  // wave-uniform
         const CellVal<R> ev = cell_lean<R, KIND, false>(cur, rq, xe, lnf, ok);
         if constexpr (MV) acc = mfma16(ev.v, cur.v, acc);
         else acc = fma(ev.v, cur.v, acc);
@@ -801,12 +821,9 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
       if (q < 3) cur = nxt;
     }
     if constexpr (KIND != kCount) {
-      if (lane == 0) {
-        fixrow[ct] = (unsigned char)left;
-        if (left) {  // the fix-up sweeps of this reco tile and this true tile have work
-          atomicOr(fixflag + rt, 1);
-          atomicOr(fixflag + n_rt + ct, 1);
-        }
+      if (lane == 0 && left) {  // the fix-up sweeps of this reco tile and this true tile have work
+        atomicOr(fixflag + rt, 1);
+        atomicOr(fixflag + n_rt + ct, 1);
       }
     }
     return acc;
@@ -879,36 +896,39 @@ __device__ __forceinline__ double pu_p(const FitDev& f) {
 // M[j, s] = sum over the forward chunks of the partials, FP64, fixed order.
 // A single histogram (vsum) has one partial per row: mu0_j goes to M[j, 0]
 // and the other species columns are zero.
-__global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= f.N * kSP) return;
+// M[j, s] (single histogram: s = 0) as the sum of the forward sweep's chunk
+// partials and then, for a reco tile with steps left, the fix-up sweep's
+// shares, in a fixed order.
+__device__ __forceinline__ double m_sum(const FitDev& f, int j, int s) {
+  typedef __attribute__((address_space(1))) const double GD;
   const int n = f.n_cg;
-  size_t stride = (size_t)f.N * kSP;
-  const double* p = f.Mpart + t;
-  if (f.vsum) {
-    if ((t & 15) != 0) {
-      f.M[t] = 0.0;
-      return;
-    }
-    stride = (size_t)f.N;
-    p = f.Mpart + (t >> 4);
-  }
-  double s = 0.0;
+  const size_t stride = f.vsum ? (size_t)f.N : (size_t)f.N * kSP;
+  const size_t off = f.vsum ? (size_t)j : (size_t)j * kSP + s;
+  GD* const p = (GD*)f.Mpart + off;
+  double a = 0.0;
   int c = 0;
   for (; c + 4 <= n; c += 4) {  // four independent loads in flight
     const double a0 = p[c * stride], a1 = p[(c + 1) * stride], a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
-    s += a0;
-    s += a1;
-    s += a2;
-    s += a3;
+    a += a0;
+    a += a1;
+    a += a2;
+    a += a3;
   }
-  for (; c < n; ++c) s += p[c * stride];
-  if (f.has_fix && f.fixflag[(t >> 4) / kRowStep]) {  // the fix-up sweep's shares, last
-    const double* q = f.vsum ? f.Mfix + (t >> 4) : f.Mfix + t;
-    for (int b = 0; b < kFixSplit; ++b) s += q[b * stride];
+  for (; c < n; ++c) a += p[c * stride];
+  if (f.has_fix && ((const __attribute__((address_space(1))) int*)f.fixflag)[j / kRowStep]) {
+    GD* const q = (GD*)f.Mfix + off;
+    for (int b = 0; b < kFixSplit; ++b) a += q[b * stride];
   }
-  f.M[t] = s;
+  return a;
+}
+
+// Several species histograms: M from the partials (a single histogram's M
+// column is summed by k_rowterms as it stages the rows).
+__global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= f.N * kSP || f.vsum) return;
+  f.M[t] = m_sum(f, t >> 4, t & 15);
 }
 
 // 16 rows x 16 species per block.
@@ -951,8 +971,15 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
   const int j0 = blockIdx.x * 16;
   const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, N);
-  // M rows [r0, r1) staged in LDS for the pile-up sums
-  for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = Mg[(size_t)r0 * kSP + e];
+  // M rows [r0, r1) staged in LDS for the pile-up sums (a single histogram's
+  // column summed here from the forward partials)
+  if (vsum) {
+    for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock)
+      if (e & 15) Ml[e >> 4][e & 15] = 0.0;
+    for (int e = threadIdx.x; e < r1 - r0; e += kBlock) Ml[e][0] = m_sum(f, r0 + e, 0);
+  } else {
+    for (int e = threadIdx.x; e < (r1 - r0) * kSP; e += kBlock) Ml[e >> 4][e & 15] = Mg[(size_t)r0 * kSP + e];
+  }
   __syncthreads();
   const int j = j0 + rl;
   const bool jok = j < N;
@@ -1326,11 +1353,15 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
     __syncthreads();
   }
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
+  double qf[4] = {0, 0, 0, 0};  // the step test's column factors
+  if (KIND != kCount)
+    for (int q = 0; q < 4; ++q) qf[q] = ((GD*)f.fixq)[ct * 4 + q];
   for (int rt = rt0; rt < rt_end; ++rt) {
     const int j = rt * kRowStep + jr;
     const bool row_ok = (jr < kRowStep) && (j < N);
     const double xe = ((GD*)f.xe)[min(j, N)];
     const double lnf = KIND == kCount ? lgamma(xe + 1.0) : 0.0;
+    const double pmax = KIND == kCount ? 0.0 : ((GD*)f.fixp)[rt];
     const RowQ<R> rq = load_rowq<R, KIND>(f, min(j, N - 1));
     const double w1 = (row_ok && !MV) ? (pre ? ((GD*)f.Ht)[(size_t)j * kSP] : htl[j - r0]) : 0.0;
     v4d Wm = {0, 0, 0, 0};
@@ -1350,7 +1381,7 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
       const int i = ct * kColTile + 4 * q + g;
       // the same steps as the forward sweep's; the others are k_cells_bwd_fix's
       const bool ok = row_ok && i < T;
-      if (__all(lean_lane<R, KIND>(col[q], rq, ok))) {
+      if (KIND == kCount || step_lean<R, KIND>(qf[q], pmax)) {  // wave-uniform
         const CellVal<R> ev = cell_lean<R, KIND, true>(col[q], rq, xe, lnf, ok);
         const double Wq = MV ? Wm[q] : w1 * col[q].v;
         aA[q] = fma(Wq, (double)ev.d1, aA[q]);
@@ -1401,16 +1432,19 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
 }
 
 // ---------------------------------------------------------------------------
-// Fix-up sweeps: the wave steps the sweeps above leave (some lane of the wave
-// not a single quadrature interval), with the general cell: composite
-// quadrature, or the CDF at the bin's edges.  The forward sweep records the
-// steps it leaves in fixmask (bit q of the (reco tile, true tile) byte); the
-// backward sweep leaves the same ones, by the same test on the same operands.
-// An entry is one such step.  Each fix-up block lists the entries of its tile
-// in a fixed order, its waves take every NW-th entry (the forward spreads a
-// reco tile over kFixSplit blocks, which take turns), and the sums over the
-// waves and blocks are added in a fixed order, so these partials do not
-// depend on the launch either.  In the 3000 x 900 generalized-gamma sweep
+// Fix-up sweeps: the wave steps the sweeps above leave (step_lean false: some
+// lane of the wave not a single quadrature interval), with the general cell:
+// composite quadrature, or the CDF at the bin's edges.  An entry is one such
+// step; the fix-up sweeps find them by the same test on the same operands
+// (k_colparams' column factors and the row tiles' half-widths).  Launched
+// after the main sweep (use_flags), a block first reads the flag the forward
+// sweep set for its tile and leaves at once when nothing is left there (a
+// graph branch beside the main sweep was measured to cost as much in
+// cross-queue synchronisation as it hid).  Each block lists
+// the entries of its tile in a fixed order, its waves take every NW-th entry
+// (the forward spreads a reco tile over kFixSplit blocks, which take turns),
+// and the sums over the waves and blocks are added in a fixed order, so these
+// partials do not depend on the launch either.  In the 3000 x 900 generalized-gamma sweep
 // they are about 0.4 % of the wave steps: the reco bin from x <= 0 (its cell
 // the CDF at x_1) and wide low-energy bins against narrow columns.
 
@@ -1458,71 +1492,77 @@ __device__ __forceinline__ ColPre<R> fix_col(const FitDev& f, int i, double vmv,
 // pairs in order; writes share b of rt's rows of Mfix (zeros where nothing is
 // left).
 template <class R, int KIND, bool MV>
-__global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* fits,
-                                                                                 const int* active) {
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* fits, const int* active,
+                                                                   int use_flags, int nsplit) {
   constexpr int NW = kFixWaves, NTH = NW * 64;
   typedef typename std::conditional<MV, v4d, double>::type V;
   constexpr int NR = MV ? 4 : 1;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  typedef __attribute__((address_space(1))) const unsigned char GU;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  const int rt = blockIdx.x / kFixSplit, sh = blockIdx.x % kFixSplit;
+  const int rt = blockIdx.x / nsplit, sh = blockIdx.x % nsplit;
   // block-uniform; nothing left in this reco tile: its shares of Mfix are not read
-  if (rt >= f.n_rt || f.vsum == (int)MV || ((GI*)f.fixflag)[rt] == 0) return;
+  if (rt >= f.n_rt || f.vsum == (int)MV || (use_flags && ((GI*)f.fixflag)[rt] == 0)) return;
   __shared__ int list[NTH], wcount[NW];
   __shared__ double part[NW][NR][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int T = f.T, N = f.N, n_ct = f.n_ct, j0 = rt * kRowStep;
   GD* const F64 = (GD*)f.F64;
   GI* const tbp = (GI*)f.tb;
-  GU* const maskrow = (GU*)f.fixmask + (size_t)rt * n_ct;
+  GD* const fixq = (GD*)f.fixq;
+  const double pmax = ((GD*)f.fixp)[rt];
   const bool row_ok = (jr < kRowStep) && (j0 + jr < N);
   const double xe = ((GD*)f.xe)[min(j0 + jr, N)];
   const RowQ<R> rq = load_rowq<R, KIND>(f, min(j0 + jr, N - 1));
-  V acc = {};
-  for (int c0 = 0; c0 < 4 * n_ct; c0 += NTH) {
-    const int cand = c0 + (int)threadIdx.x, ct = cand >> 2;
-    bool want = false;
-    if (ct < n_ct) {
-      const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];
-      // a tile the forward sweep listed for this reco tile (its byte is current)
-      if (by >= bx && !(by < j0 || bx > j0 + kRowStep - 1)) want = (maskrow[ct] >> (cand & 3)) & 1;
+  // logical share ls takes the entries e = ls NW + wv (mod kFixSplit NW),
+  // whatever the number of blocks that run the shares (same sums either way)
+  for (int ls = sh; ls < kFixSplit; ls += nsplit) {
+    V acc = {};
+    for (int c0 = 0; c0 < 4 * n_ct; c0 += NTH) {
+      const int cand = c0 + (int)threadIdx.x, ct = cand >> 2;
+      bool want = false;
+      if (ct < n_ct) {
+        const int bx = tbp[2 * ct], by = tbp[2 * ct + 1];
+        // a tile the forward sweep lists for this reco tile, and a step it leaves
+        if (by >= bx && !(by < j0 || bx > j0 + kRowStep - 1)) want = !step_lean<R, KIND>(fixq[cand], pmax);
+      }
+      const int n = fix_compact<NW>(want, cand, list, wcount);
+      for (int e = ls * NW + wv; e < n; e += kFixSplit * NW) {
+        const int ent = list[e];
+        const int i = (ent >> 2) * kColTile + 4 * (ent & 3) + g;
+        const ColPre<R> c = fix_col<R, KIND>(f, i, MV && i < T ? F64[i * kSP + jr] : 0.0, MV);
+        const CellVal<R> ev = cell_general<R, KIND, false>(c, rq, xe, row_ok && i < T);
+        if constexpr (MV) acc = mfma16(ev.v, c.v, acc);
+        else acc = fma(ev.v, c.v, acc);
+      }
+      __syncthreads();  // list[] is rewritten by the next chunk
     }
-    const int n = fix_compact<NW>(want, cand, list, wcount);
-    for (int e = sh * NW + wv; e < n; e += kFixSplit * NW) {
-      const int ent = list[e];
-      const int i = (ent >> 2) * kColTile + 4 * (ent & 3) + g;
-      const ColPre<R> c = fix_col<R, KIND>(f, i, MV && i < T ? F64[i * kSP + jr] : 0.0, MV);
-      const CellVal<R> ev = cell_general<R, KIND, false>(c, rq, xe, row_ok && i < T);
-      if constexpr (MV) acc = mfma16(ev.v, c.v, acc);
-      else acc = fma(ev.v, c.v, acc);
-    }
-    __syncthreads();  // list[] is rewritten by the next chunk
-  }
-  if constexpr (MV) {
+    if constexpr (MV) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
-  } else {
-    part[wv][0][lane] = acc;
-  }
-  __syncthreads();
-  if (wv != 0) return;
-  if constexpr (MV) {
-    double* const out = f.Mfix + (size_t)sh * N * kSP;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double x = part[0][r][lane];
-      for (int w = 1; w < NW; ++w) x += part[w][r][lane];
-      const int row = g + 4 * r;  // FP64 MFMA result layout: row l/16 + 4r, column l%16
-      if (row < kRowStep && j0 + row < N) out[(size_t)(j0 + row) * kSP + jr] = x;
+      for (int r = 0; r < 4; ++r) part[wv][r][lane] = acc[r];
+    } else {
+      part[wv][0][lane] = acc;
     }
-  } else {
-    double x = part[0][0][lane];
-    for (int w = 1; w < NW; ++w) x += part[w][0][lane];
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-    if (g == 0 && row_ok) f.Mfix[(size_t)sh * N + j0 + jr] = x;
+    __syncthreads();
+    if (wv == 0) {
+      if constexpr (MV) {
+        double* const out = f.Mfix + (size_t)ls * N * kSP;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double x = part[0][r][lane];
+          for (int w = 1; w < NW; ++w) x += part[w][r][lane];
+          const int row = g + 4 * r;  // FP64 MFMA result layout: row l/16 + 4r, column l%16
+          if (row < kRowStep && j0 + row < N) out[(size_t)(j0 + row) * kSP + jr] = x;
+        }
+      } else {
+        double x = part[0][0][lane];
+        for (int w = 1; w < NW; ++w) x += part[w][0][lane];
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        if (g == 0 && row_ok) f.Mfix[(size_t)ls * N + j0 + jr] = x;
+      }
+    }
+    __syncthreads();  // part[] is rewritten by the next share
   }
 }
 
@@ -1565,16 +1605,15 @@ __device__ __forceinline__ double wtilde_tile(const FitDev& f, int r0, int K, do
 // in order; a wave forms its entry's weights as the backward sweep does and
 // evaluates the step.  Writes bwdfix[ct] (zeros where nothing is left).
 template <class R, int KIND, bool MV>
-__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits,
-                                                                                const int* active, int pre) {
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
+                                                                   int use_flags) {
   constexpr int NW = kFixWaves, NTH = NW * 64;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  typedef __attribute__((address_space(1))) const unsigned char GU;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
   const int ct = blockIdx.x;
   // block-uniform; nothing left in this true tile: its partials are not read
-  if (ct >= f.n_ct || f.mv != (int)MV || ((GI*)f.fixflag)[f.n_rt + ct] == 0) return;
+  if (ct >= f.n_ct || f.mv != (int)MV || (use_flags && ((GI*)f.fixflag)[f.n_rt + ct] == 0)) return;
   __shared__ int list[NTH], wcount[NW];
   __shared__ double colA[NW][16], colB[NW][16], colU[NW][16];
   __shared__ double rsum[16][kSP];
@@ -1583,7 +1622,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   const int T = f.T, N = f.N, S = f.S, n_ct = f.n_ct;
   GColPar* const cpar = (GColPar*)f.cp;
   GD* const F64 = (GD*)f.F64;
-  GU* const mask = (GU*)f.fixmask;
+  GD* const fixp = (GD*)f.fixp;
   double* const out = f.bwdfix + (size_t)ct * kBwdPart;
   const int bx = ((GI*)f.tb)[2 * ct], by = ((GI*)f.tb)[2 * ct + 1];  // support [bx, by]
   const int rt_a = by >= bx ? max(bx, 0) / kRowStep : 0;
@@ -1608,7 +1647,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   const int ncand = 4 * (rt_b - rt_a + 1);
   for (int c0 = 0; c0 < ncand; c0 += NTH) {
     const int cand = c0 + (int)threadIdx.x, rt = rt_a + (cand >> 2);
-    const bool want = cand < ncand && ((mask[(size_t)rt * n_ct + ct] >> (cand & 3)) & 1);
+    const bool want = cand < ncand && !step_lean<R, KIND>(((GD*)f.fixq)[ct * 4 + (cand & 3)], fixp[rt]);
     const int n = fix_compact<NW>(want, cand, list, wcount);
     for (int e = wv; e < n; e += NW) {
       const int ent = list[e], qe = ent & 3;
@@ -1770,10 +1809,27 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   double gr = 0.0;
   if (vsum) {
     if (with_grad) {
-      for (int b = t >> 4; b < n_bwdblk; b += NT / 16) gr += bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
+      // four interleaved partial sums (loads in flight), added pairwise
+      constexpr int ST = NT / 16;
+      double g4[4] = {0.0, 0.0, 0.0, 0.0};
+      int b = t >> 4;
+      for (; b + 3 * ST < n_bwdblk; b += 4 * ST) {
+        const double x0 = bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
+        const double x1 = bwdpart[(size_t)(b + ST) * kBwdPart + 4 + (t & 15)];
+        const double x2 = bwdpart[(size_t)(b + 2 * ST) * kBwdPart + 4 + (t & 15)];
+        const double x3 = bwdpart[(size_t)(b + 3 * ST) * kBwdPart + 4 + (t & 15)];
+        g4[0] += x0;
+        g4[1] += x1;
+        g4[2] += x2;
+        g4[3] += x3;
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u, b += ST)  // at most three left
+        if (b < n_bwdblk) g4[u] += bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
+      gr = (g4[0] + g4[1]) + (g4[2] + g4[3]);
       if (has_fix)
-        for (int b = t >> 4; b < n_ct; b += NT / 16)
-          if (fixflag[n_rt + b]) gr += bwdfix[(size_t)b * kBwdPart + 4 + (t & 15)];
+        for (int c = t >> 4; c < n_ct; c += ST)
+          if (fixflag[n_rt + c]) gr += bwdfix[(size_t)c * kBwdPart + 4 + (t & 15)];
     }
   } else {
     for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
@@ -2152,12 +2208,26 @@ static void launch_fwd(int cg, bool mv, dim3 grid, dim3 blk, hipStream_t st, con
 }
 template <class R, int KIND>
 static void launch_fix(bool fwd, bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active,
-                       int pre) {
+                       int pre, int use_flags, int nsplit) {
   const dim3 b(kFixWaves * 64);
-  if (fwd && mv) hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active);
-  if (fwd && !mv) hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active);
-  if (!fwd && mv) hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active, pre);
-  if (!fwd && !mv) hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active, pre);
+  if (fwd && mv)
+    hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active, use_flags, nsplit);
+  if (fwd && !mv)
+    hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active, use_flags, nsplit);
+  if (!fwd && mv)
+    hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active, pre, use_flags);
+  if (!fwd && !mv)
+    hipLaunchKernelGGL((k_cells_bwd_fix<R, KIND, false>), grid, b, 0, st, d_fits, d_active, pre, use_flags);
+}
+// The fix-up sweep of stage 1 (fwd) or 6, after the main sweep (use_flags).
+static void launch_fix_stage(const LaunchShape& L, bool fwd, dim3 grid, hipStream_t st, const FitDev* d_fits,
+                             const int* d_active, int pre, int use_flags, int ns) {
+  const bool f32 = L.prec == kF32;
+  if (f32 && L.kind == kGauss) launch_fix<float, kGauss>(fwd, L.any_mv, grid, st, d_fits, d_active, pre, use_flags, ns);
+  if (f32 && L.kind == kGG) launch_fix<float, kGG>(fwd, L.any_mv, grid, st, d_fits, d_active, pre, use_flags, ns);
+  if (!f32 && L.kind == kGauss)
+    launch_fix<double, kGauss>(fwd, L.any_mv, grid, st, d_fits, d_active, pre, use_flags, ns);
+  if (!f32 && L.kind == kGG) launch_fix<double, kGG>(fwd, L.any_mv, grid, st, d_fits, d_active, pre, use_flags, ns);
 }
 template <class R, int KIND>
 static void launch_bwd(bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active, int pre) {
@@ -2181,7 +2251,12 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
   const dim3 blk(kBlock);
   const dim3 gf(L.max_fwd_blocks, n), gb(L.max_bwd_blocks, n), grow(L.max_rowblk, n);
   const dim3 gred((L.max_NS + kBlock - 1) / kBlock, n), bf(kFwdWaves * 64);
-  const dim3 gfx(L.max_rt * kFixSplit, n), gbx(L.max_ct, n);  // fix-up sweeps (per reco / true tile)
+  // forward fix-up blocks per reco tile (each runs kFixSplit / nsplit of its
+  // shares): a single fit spreads its few busy tiles over more waves; a batch
+  // keeps the (mostly idle) grid small
+  const int nsplit = n > 1 ? 2 : kFixSplit;
+  const dim3 gfx(L.max_rt * nsplit, n), gbx(L.max_ct, n);  // fix-up sweeps (per reco / true tile)
+  const bool fixk = L.kind == kGG || L.kind == kGauss;
   const bool f32 = L.prec == kF32, gauss = L.kind == kGauss;
   // batches form a single histogram's pile-up adjoint once per fit
   const int pre = n >= kPreAdjFits ? 1 : 0;
@@ -2221,14 +2296,10 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
-      // then the steps the sweep left
-      if (f32 && gauss) launch_fix<float, kGauss>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
-      if (f32 && L.kind == kGG) launch_fix<float, kGG>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
-      if (!f32 && gauss) launch_fix<double, kGauss>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
-      if (!f32 && L.kind == kGG) launch_fix<double, kGG>(true, L.any_mv, gfx, st, d_fits, d_active, 0);
+      if (fixk) launch_fix_stage(L, true, gfx, st, d_fits, d_active, 0, 1, nsplit);  // then the steps it left
       break;
     case 2:
-      hipLaunchKernelGGL(k_reduce_M, gred, blk, 0, st, d_fits, d_active);
+      if (L.any_mv) hipLaunchKernelGGL(k_reduce_M, gred, blk, 0, st, d_fits, d_active);
       break;
     case 3:
       hipLaunchKernelGGL(k_rowterms, grow, blk, 0, st, d_fits, d_active);
@@ -2250,10 +2321,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       if (!f32 && gauss) launch_bwd<double, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (!f32 && L.kind == kGG) launch_bwd<double, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (L.kind == kCount) launch_bwd<double, kCount>(L.any_mv, gb, st, d_fits, d_active, pre);
-      if (f32 && gauss) launch_fix<float, kGauss>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
-      if (f32 && L.kind == kGG) launch_fix<float, kGG>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
-      if (!f32 && gauss) launch_fix<double, kGauss>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
-      if (!f32 && L.kind == kGG) launch_fix<double, kGG>(false, L.any_mv, gbx, st, d_fits, d_active, pre);
+      if (fixk) launch_fix_stage(L, false, gbx, st, d_fits, d_active, pre, 1, 1);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);

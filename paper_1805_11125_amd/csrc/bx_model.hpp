@@ -47,6 +47,9 @@ struct HostModel {
   // nodes, FP64 5 nodes)
   std::vector<double> qpum, qhw, qrow64;
   std::vector<float> qrow32;
+  // per reco tile: the largest half-width of its bins, as the sweeps' one-
+  // interval test takes it (the cell precision for GG, FP64 for Gauss)
+  std::vector<double> fixp;
   GGConst gg;
   Tiles tiles;
 };
