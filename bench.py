@@ -1,7 +1,9 @@
 """Benchmark: NLL + gradient evaluations per second of the full single fit
 (3000 true x 900 reco bins, 12 species, generalized-gamma response, 2 %
-pile-up, 3e6 events) on one MI355X, plus the batched toy-fit and served-fit
-figures, the roofline of the dominant kernel and the FP64 oracle on the host.
+pile-up, 3e6 events) on one MI355X, with its error against the FP64 oracle,
+plus the batched form of the same evaluation, the other workloads (configs 1,
+3a, 3b and the other response kinds), the batched toy fits, the served fits,
+the roofline of the dominant kernel and the FP64 oracle on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--toys N] [--no-cpu]
 
@@ -29,21 +31,21 @@ WORKLOAD = ("single fit, 3000 true x 900 reco bins (1 keV x 1 p.e.), 12 species,
             "generalized-gamma response (light yield, 3 resolution params, quenching), "
             "2% pile-up (K=128), 3e6 events")
 PEAK_FP32 = 157.3e12   # MI355X published dense FP32 vector FLOP/s
-# Algorithmic operations per CDF edge evaluation on the dominant code path
-# (the uniform expansion of the incomplete gamma, |eta| < 1), counted from the
-# formula: add/mul/transcendental = 1, FMA = 2.  The forward sweep of an
-# NLL+gradient evaluation forms the edge CDF (130) and its two column-
-# parameter derivatives (27), plus the species contraction of its cell, 2 S;
-# the backward sweep then only weights the stored derivative differences by
-# the adjoint (5 per edge: one product, two multiply-adds) and is bound by
-# reading them (one FP32 pair, 8 bytes, per edge).  The edges counted are
-# those the method needs (oracle-counted: each column's [1e-12, 1 - 1e-12]
-# quantile support plus its two bracketing edges), not the ones a kernel
-# happens to evaluate.
-FLOP_FWD_EDGE = 157
-FLOP_BWD_EDGE = 5
-BYTES_BWD_EDGE = 8
 PEAK_HBM = 8.0e12      # MI355X published HBM3E bandwidth, bytes/s
+# Algorithmic operations per cell of Eq. 1 (the response integrated over one
+# reco bin) on the sweeps' path: the one-interval, four-node Gauss-Legendre
+# quadrature of the generalized-gamma density in t = ln(y/k) (FP32), counted
+# from the formula with add/mul/exp2 = 1 and FMA = 2.  Forward: the bin centre
+# in t, the scale, phi(t) by its series (23), four nodes of 8 (phi at the
+# node from the centre's, -k log2(e) phi, 2^x, weight, sum), the FP64 scale
+# and the one FMA of the single-histogram contraction mu0 = R v: 63.  Backward:
+# the same cell with its two column-parameter derivatives (7 more per node,
+# 6 after the nodes) and the adjoint weights (7), without the contraction:
+# 102.  The cells counted are those the method needs (oracle-counted: the
+# cells between each column's [1e-12, 1 - 1e-12] quantile edges and the edges
+# bracketing them), not the ones a kernel happens to evaluate.
+FLOP_FWD_CELL = 63
+FLOP_BWD_CELL = 102
 
 
 def profiled(fname, key, name):
@@ -72,41 +74,85 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--toys", type=int, default=1024, help="batched toy fits to time (0 = skip)")
+    ap.add_argument("--toys", type=int, default=4096, help="batched toy fits to time (0 = skip)")
     ap.add_argument("--plain-toys", type=int, default=64, help="toys fitted on the plain path")
-    ap.add_argument("--qps", type=str, default="30,300", help="serving arrival rates ('' = skip)")
+    ap.add_argument("--edm", type=float, default=1e-8, help="toy fits stop at EDM below this")
+    ap.add_argument("--qps", type=str, default="10,30,100,300,1000", help="serving arrival rates ('' = skip)")
     ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--batch", type=int, default=512,
                     help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-oracle-check", dest="oracle_check", action="store_false",
+                    help="skip the oracle errors of the GPU results")
     ap.add_argument("--no-table", dest="table", action="store_false",
-                    help="skip the tabulated-response, count-estimator and joint-term legs")
+                    help="skip the per-config, tabulated-response, count-estimator and joint-term legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def support_edges():
+def support():
     z = np.load(os.path.join(ROOT, "tests", "golden", "c2_support.npz"))
-    return int(z["edges"])
+    return int(z["cells"]), int(z["edges"])
 
 
-def cpu_baseline(d, x, th, budget_s=12.0):
+def host_info():
+    """CPU model and the cores this process may use (where the oracle ran)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def oracle_errors(d, x, th, v, g):
+    """The GPU result's error against the FP64 oracle at the same point: NLL
+    absolute and relative, and the largest gradient component error over its
+    magnitude scale sum_b |(1 - n_b/mu_b) dmu_b/dq| (the absolute summands of
+    dNLL/dq).  Also returns the oracle's own wall time for the NLL+gradient."""
     import oracle
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.nll_grad(d, x, th)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 5:
-            break
-    return {"value": n / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} FP64 oracle NLL+gradient evaluations of the same workload "
-                      f"(dense scipy incomplete-gamma cells, Richardson dR/dk), one thread"}
+    v0, g0 = oracle.nll_grad(d, x, th)
+    dt = time.perf_counter() - t0
+    sc = oracle.grad_scale(d, x, th)
+    sc = np.maximum(sc, 1e-20 * sc.max())
+    e = np.abs(np.asarray(g) - g0) / sc
+    return {"nll_abs": abs(v - v0), "nll_rel": abs(v - v0) / abs(v0), "grad_max_over_scale": float(e.max()),
+            "grad_scale": "sum_b |(1 - n_b/mu_b) dmu_b/dq|"}, dt
 
 
-def toy_study(bx, synth, n_toys, n_plain):
+def cpu_baseline(timed):
+    """The FP64 oracle's NLL+gradient on the host, one thread: the config-2
+    evaluation timed beside the GPU error check, and configs 1, 3a (median of
+    5 at theta_true and at a perturbed theta) and 3b (one evaluation)."""
+    import oracle
+    import synth
+    per = {}
+    for name, reps in (("c1", 5), ("c3a", 5), ("c3b", 1)):
+        d, x = synth.load(name)
+        ts = []
+        for th in (d.theta_true, d.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d.P))):
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                oracle.nll_grad(d, x, th)
+                ts.append(time.perf_counter() - t0)
+        per[name] = {"median_s": float(np.median(ts)), "evals": len(ts)}
+    if "c2" in timed:
+        per["c2"] = {"median_s": timed["c2"], "evals": 1}
+    v = 1.0 / per["c2"]["median_s"] if "c2" in per else None
+    return {"value": v, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle NLL+gradient (dense scipy incomplete-gamma or ndtr cells, "
+                      "numpy contraction, explicit pile-up, fsum NLL, Richardson response "
+                      "derivatives), one thread: 1 evaluation of the 3000 x 900 workload "
+                      "(value), plus per-config medians",
+            "per_config_s": per, **host_info()}
+
+
+def toy_study(bx, synth, n_toys, n_plain, edm):
     """Batched toy fits through the fit server vs the same toys fitted one
     at a time through the plain path (histograms resident before timing)."""
     base, per_species, theta = synth.catalogue()
@@ -117,14 +163,14 @@ def toy_study(bx, synth, n_toys, n_plain):
         toys.append((bx.Model(d, synth.Data(energy=t.counts), precision=bx.BX_PREC_F32), d, t))
     srv = bx.Server()
     t0 = time.perf_counter()
-    tickets = [srv.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+    tickets = [srv.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=edm, max_iter=500)
                for m, d, t in toys]
     res = [srv.wait(k, sleep=2e-4) for k in tickets]
     el = time.perf_counter() - t0
     srv.close()
     n_plain = min(n_plain, n_toys)
     t1 = time.perf_counter()
-    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-8, max_iter=500)
+    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=edm, max_iter=500)
              for m, d, t in toys[:n_plain]]
     el_p = time.perf_counter() - t1
     same = all(np.array_equal(p.x, r.x) for p, r in zip(plain, res))
@@ -140,7 +186,34 @@ def toy_study(bx, synth, n_toys, n_plain):
             "converged": int((st == bx.BX_CONVERGED).sum()),
             "median_iters": float(np.median([r.n_iter for r in res])),
             "median_evals": float(np.median([r.n_eval for r in res])),
-            "batched_equals_plain_bitwise": bool(same), "edm_tol": 1e-8}
+            "batched_equals_plain_bitwise": bool(same), "edm_tol": edm}
+
+
+def config_leg(bx, synth, name, prec, steps, warmup, copies, check, timed):
+    """Plain-path NLL+gradient evaluations per second of one of the other
+    workloads (config 1: 400 x 200 Gaussian; 3a / 3b: the multivariate
+    likelihood of Eqs. 3-4 on configs 1 and 2), the batched form of the same
+    evaluation, and the result's error against the oracle."""
+    d, x = synth.load(name)
+    th = d.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d.P))
+    m = bx.Model(d, x, precision=prec)
+    for _ in range(warmup):
+        m.nll_grad(th)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        m.nll_grad(th)
+    evals = steps / (time.perf_counter() - t1)
+    v, g = m.nll_grad(th)
+    rec = {"workload": f"{d.T} true x {d.N} reco bins, {d.S} species, {d.kind} response, "
+                       f"{'multivariate' if d.multivariate else 'single histogram'}",
+           "precision": "FP32 cells" if prec == bx.BX_PREC_F32 else "FP64", "evals_per_s": evals}
+    if copies > 0:
+        bt = m.batch_times(th, copies, reps=5)
+        rec["batched"] = {"copies": copies, "evals_per_s": copies / (bt["total"] * 1e-3)}
+    m.close()
+    if check:
+        rec["oracle_error"], timed[name] = oracle_errors(d, x, th, v, g)
+    return rec
 
 
 def table_leg(bx, synth, x, steps, warmup):
@@ -219,10 +292,12 @@ def joint_leg(bx, synth, steps, warmup):
 
 
 def serving(bx, synth, qps_list, n_req):
+    import torch
     """Poisson arrivals mixing config-1 fits (Gaussian, FP64), config-2 fits
     (generalized gamma, FP32) with fresh Poisson data, and NLL+gradient
-    requests; latency = done - submit.  The plain baseline serves the same
-    stream first-in first-out through the plain path on one thread."""
+    requests through the autograd path; latency = done - submit.  The plain
+    baseline serves the same stream first-in first-out through the plain path
+    on one thread."""
     d1, d2 = synth.config1(), synth.config2(pu_g=synth.pileup_spectrum())
     tab1, tab2 = synth.species_table("c1"), synth.species_table("c2")
     out = {}
@@ -239,17 +314,29 @@ def serving(bx, synth, qps_list, n_req):
             jobs.append((r, m, x0, d.float_mask))
         srv = bx.Server()
         t0 = time.perf_counter()
-        tickets = []
-        for r, m, x0, mask in jobs:
+        tickets, ag = [], {}
+        for n_r, (r, m, x0, mask) in enumerate(jobs):
             dt = t0 + r.t_arrival - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
-            kind = bx.BX_EVAL_GRAD if r.kind == "evalgrad" else bx.BX_FIT
-            tickets.append(srv.submit(m, x0, float_mask=mask, edm_tol=1e-8, max_iter=500, kind=kind))
-        res = [srv.wait(k, sleep=2e-4) for k in tickets]
-        span = (max(x.t_done_ns for x in res) - min(x.t_submit_ns for x in res)) * 1e-9
+            if r.kind == "evalgrad":
+                # the autograd path (torch's stream), while the server's fits run
+                s0 = time.perf_counter_ns()
+                th_t = torch.tensor(x0, dtype=torch.float64, device="cuda", requires_grad=True)
+                loss = bx.NLLFunction.apply(m, th_t)
+                loss.backward()
+                th_t.grad.cpu()
+                ag[n_r] = (s0, time.perf_counter_ns())
+                tickets.append(None)
+            else:
+                tickets.append(srv.submit(m, x0, float_mask=mask, edm_tol=1e-8, max_iter=500))
+        res = [srv.wait(k, sleep=2e-4) if k is not None else None for k in tickets]
+        t_sub = [ag[i][0] if x is None else x.t_submit_ns for i, x in enumerate(res)]
+        t_done = [ag[i][1] if x is None else x.t_done_ns for i, x in enumerate(res)]
         srv.close()
-        lat = np.array([x.latency_s for x in res])
+        fits = [x for x in res if x is not None]
+        span = (max(x.t_done_ns for x in fits) - min(x.t_submit_ns for x in fits)) * 1e-9 if fits else 0.0
+        lat = (np.array(t_done) - np.array(t_sub)) * 1e-9
         kinds = np.array([r.kind for r, *_ in jobs])
         # plain FIFO baseline on the same stream
         t_free, plat = 0.0, []
@@ -269,7 +356,8 @@ def serving(bx, synth, qps_list, n_req):
                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                "plain_p50_s": float(np.percentile(plat, 50)), "plain_p99_s": float(np.percentile(plat, 99)),
                "plain_fits_per_s": n_fit / max(t_free, 1e-12),
-               "converged": int(sum(x.status == bx.BX_CONVERGED for x in res))}
+               "converged": int(sum(x.status == bx.BX_CONVERGED for x in fits)),
+               "evalgrad_path": "autograd (NLLFunction on torch's stream)"}
         for k in ("fit1", "fit2", "evalgrad"):
             sel = lat[kinds == k]
             if len(sel):
@@ -313,6 +401,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     evals = a.steps / el
+    v_gpu, g_gpu = m.nll_grad(th)
 
     # device-pointer path (autograd entry point), stream-ordered, no host sync per eval
     thd = torch.tensor(th, dtype=torch.float64, device="cuda")
@@ -322,33 +411,39 @@ def main():
         m.nll_grad_dev(thd.data_ptr(), out.data_ptr(), stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ndev = a.steps
-    for _ in range(ndev):
+    for _ in range(a.steps):
         m.nll_grad_dev(thd.data_ptr(), out.data_ptr(), stream)
     torch.cuda.synchronize()
-    dev_evals = ndev / (time.perf_counter() - t1)
+    dev_evals = a.steps / (time.perf_counter() - t1)
 
+    # the dominant kernel: the backward cell sweep (cells, their two
+    # derivatives and the adjoint weights), main sweep plus its fix-up sweep,
+    # timed with HIP events on the model's stream (each stage launched back
+    # to back on its own)
     st = m.stage_times(th, reps=200)
-    edges = support_edges()
-    fwd_ms, bwd_ms = st["cells_fwd"], st["cells_bwd"]
-    if bwd_ms >= fwd_ms:  # the backward sweep reads the stored differences: HBM-bound
-        kname, kms = "k_cells_bwd", bwd_ms
-        rl = {"bound": "hbm", "achieved": edges * BYTES_BWD_EDGE / (kms * 1e-3) / 1e9,
-              "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
-    else:
-        kname, kms = "k_cells_fwd", fwd_ms
-        rl = {"bound": "alu", "achieved": edges * (FLOP_FWD_EDGE + 2 * d.S) / (kms * 1e-3) / 1e12,
-              "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s"}
-    rl["frac"] = rl["achieved"] / rl["peak"]
-    # measured ceiling: the edge arithmetic alone, same column/edge mix
-    ceil_eps = m.edge_ceiling(th, reps=64)
-    fwd_eps = edges / (fwd_ms * 1e-3)
-    ceiling = {"edges_per_s": ceil_eps, "TFLOP_s": ceil_eps * FLOP_FWD_EDGE / 1e12,
-               "forward_edges_per_s": fwd_eps, "forward_frac_of_ceiling": fwd_eps / ceil_eps,
-               "what": "registers-only evaluation of the edge CDF and its two derivatives in the "
-                       "forward sweep's lane layout, one (true tile, reco tile) of the workload per wave"}
-    traffic = profiled("config2_hbm_counters.md", "traffic_bytes", kname)
-    valu = profiled("config2_valu_counters.md", "valu_issue", kname)
+    cells, edges = support()
+
+    def roofline(bwd_ms, bwd_main_ms, units):
+        ach = units * cells * FLOP_BWD_CELL / (bwd_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": ach * 1e12 / PEAK_FP32, "kernel": "k_cells_bwd + k_cells_bwd_fix",
+                "kernel_ms": bwd_ms, "main_sweep_ms": bwd_main_ms, "cells_per_launch": units * cells,
+                "flop_per_cell": FLOP_BWD_CELL}
+
+    rl = roofline(st["cells_bwd"], st["cells_bwd_main"], 1)
+    rl["traffic"] = profiled("config2_hbm_counters.md", "traffic_bytes", "k_cells_bwd")
+    rl["traffic_unit"] = "HBM bytes per launch of k_cells_bwd (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+    rl["valu_issue_frac"] = profiled("config2_valu_counters.md", "valu_issue", "k_cells_bwd")
+    ceil_cps = m.cell_ceiling(th, reps=64)
+    rl["measured_ceiling"] = {
+        "cells_per_s": ceil_cps, "TFLOP_s": ceil_cps * FLOP_BWD_CELL / 1e12,
+        "backward_cells_per_s": cells / (st["cells_bwd"] * 1e-3),
+        "what": "registers-only evaluation of the backward cell (value and two derivatives) in the "
+                "sweeps' lane layout, one (true tile, reco tile) of the workload per wave"}
+    fwd = {"kernel": "k_cells_fwd + k_cells_fwd_fix", "kernel_ms": st["cells_fwd"],
+           "main_sweep_ms": st["cells_fwd_main"], "flop_per_cell": FLOP_FWD_CELL,
+           "TFLOP_s": cells * FLOP_FWD_CELL / (st["cells_fwd"] * 1e-3) / 1e12}
+    fwd["frac"] = fwd["TFLOP_s"] * 1e12 / PEAK_FP32
     res = {
         "metric": METRIC, "value": evals, "unit": "evals/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 / evals,
@@ -358,41 +453,38 @@ def main():
                    "path": "plain (host theta in, NLL+grad out, per evaluation)"},
         "dev_path_evals_per_s": dev_evals,
         "stage_ms": {k: round(v, 5) for k, v in st.items()},
-        "roofline": {**rl, "kernel": kname, "traffic": traffic,
-                     "traffic_unit": "bytes per launch", "edges_per_launch": edges,
-                     "flop_per_edge": FLOP_FWD_EDGE + 2 * d.S if kname == "k_cells_fwd" else FLOP_BWD_EDGE,
-                     "valu_issue_frac": valu,
-                     "kernel_ms": kms, "measured_ceiling": ceiling},
+        "roofline": rl, "forward_sweep": fwd,
+        "support": {"cells": cells, "edges": edges, "q": 1e-12},
     }
     if a.batch > 0:
         # one launch per stage over `batch` resident copies (HIP events on the
         # model's stream): throughput of the batched form of the same evaluation
         bt = m.batch_times(th, a.batch, reps=10)
-        bk = "cells_bwd" if bt["cells_bwd"] >= bt["cells_fwd"] else "cells_fwd"
-        if bk == "cells_bwd":
-            brl = {"bound": "hbm", "achieved": a.batch * edges * BYTES_BWD_EDGE / (bt[bk] * 1e-3) / 1e9,
-                   "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
-        else:
-            brl = {"bound": "alu", "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                   "achieved": a.batch * edges * (FLOP_FWD_EDGE + 2 * d.S) / (bt[bk] * 1e-3) / 1e12}
-        brl["frac"] = brl["achieved"] / brl["peak"]
-        fwd_tf = a.batch * edges * (FLOP_FWD_EDGE + 2 * d.S) / (bt["cells_fwd"] * 1e-3) / 1e12
-        bwd_gb = a.batch * edges * BYTES_BWD_EDGE / (bt["cells_bwd"] * 1e-3) / 1e9
+        brl = roofline(bt["cells_bwd"], bt["cells_bwd_main"], a.batch)
+        brl["forward_TFLOP_s"] = a.batch * cells * FLOP_FWD_CELL / (bt["cells_fwd"] * 1e-3) / 1e12
+        brl["frac_of_ceiling"] = a.batch * cells / (bt["cells_bwd"] * 1e-3) / ceil_cps
         res["batched_eval"] = {
             "copies": a.batch, "evals_per_s": a.batch / (bt["total"] * 1e-3),
             "us_per_eval": bt["total"] * 1e3 / a.batch,
             "stage_us_per_eval": {k: round(v * 1e3 / a.batch, 4) for k, v in bt.items()},
-            "roofline": {**brl, "kernel": "k_" + bk, "edges_per_launch": a.batch * edges,
-                         "kernel_ms": bt[bk]},
-            "forward_TFLOP_s": fwd_tf, "forward_frac": fwd_tf * 1e12 / PEAK_FP32,
-            "forward_frac_of_ceiling": a.batch * edges / (bt["cells_fwd"] * 1e-3) / ceil_eps,
-            "backward_GB_s": bwd_gb, "backward_frac": bwd_gb * 1e9 / PEAK_HBM}
+            "roofline": brl}
         print(f"batched: {res['batched_eval']}", file=sys.stderr, flush=True)
     m.close()
+    timed = {}
+    if a.oracle_check:
+        res["oracle_error"], timed["c2"] = oracle_errors(d, x, th, v_gpu, g_gpu)
+        print(f"oracle error: {res['oracle_error']}", file=sys.stderr, flush=True)
     if a.table:
-        # the other response kinds and likelihood forms (reported beside the
-        # headline; a failure is recorded, not fatal to the line)
-        legs = (("tabulated_response", lambda: table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)),
+        # the other workloads, response kinds and likelihood forms (reported
+        # beside the headline; a failure is recorded, not fatal to the line)
+        ck = a.oracle_check
+        legs = (("config1", lambda: config_leg(bx, synth, "c1", bx.BX_PREC_F64, min(a.steps, 3000), a.warmup,
+                                                a.batch, ck, timed)),
+                ("config3a", lambda: config_leg(bx, synth, "c3a", bx.BX_PREC_F64, min(a.steps, 3000), a.warmup,
+                                                 a.batch, ck, timed)),
+                ("config3b", lambda: config_leg(bx, synth, "c3b", bx.BX_PREC_F32, min(a.steps, 2000), a.warmup,
+                                                 min(a.batch, 128), ck, timed)),
+                ("tabulated_response", lambda: table_leg(bx, synth, x, min(a.steps, 3000), a.warmup)),
                 ("count_estimator", lambda: count_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))),
                 ("joint_term", lambda: joint_leg(bx, synth, min(a.steps, 500), min(a.warmup, 20))))
         for key, fn in legs:
@@ -402,13 +494,13 @@ def main():
                 res[key] = {"error": f"{type(e).__name__}: {e}"}
             print(f"{key}: {res[key]}", file=sys.stderr, flush=True)
     if a.toys > 0:
-        res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys)
+        res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys, a.edm)
         print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)
     if a.qps:
         res["serving"] = serving(bx, synth, [float(q) for q in a.qps.split(",")], a.requests)
         print(f"serving: {res['serving']}", file=sys.stderr, flush=True)
     if not a.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(d, x, th)
+        res["cpu_baseline"] = cpu_baseline(timed)
     print(json.dumps(res))
 
 

@@ -96,7 +96,7 @@ typedef struct {
    * [0, 1] is a domain error.  0: pu_frac is fixed. */
   int32_t pu_float;
   /* Tabulated response (response = BX_RESP_TABLE): the Monte Carlo
-   * alternative to the analytic response of Eq. 1 (Sec. 4 names both).
+   * alternative to the analytic response of Eq. 1 (Sec. 3 names both).
    * n_grid matrices R_g [N][T] (rtab, row-major, g slowest; R_g[j][i] is the
    * probability that an event deposited in true bin i is reconstructed in
    * reco bin j, >= 0, columns may lose mass) given at the strictly increasing
@@ -135,8 +135,10 @@ typedef struct {
 typedef struct bx_model bx_model;
 typedef struct bx_server bx_server;
 
-/* Build a model: validate, copy every array to device memory, allocate the
- * evaluation workspace.  hip_stream: a hipStream_t the model uses for all of
+/* Sec. 4, workflow steps 1-2: load the configuration, histograms and
+ * exposure, and construct the spectra, the response, the dataset and the
+ * likelihood terms.  Build a model: validate, copy every array to device
+ * memory, allocate the evaluation workspace.  hip_stream: a hipStream_t the model uses for all of
  * its work (borrowed), or NULL for a stream the model owns.
  * Errors: BX_E_INVAL for bad sizes, non-increasing edges, negative spectra or
  * all-zero rows, non-uniform reco bins with pile-up on, a window out of range;
@@ -144,31 +146,42 @@ typedef struct bx_server bx_server;
 bx_status bx_model_build(const bx_model_desc* desc, const bx_data* data, void* hip_stream,
                          bx_model** out);
 
-/* Replace the observed histograms (same shapes).  Stream-ordered copy. */
+/* Sec. 4, workflow step 1 (a new histogram for the same configuration):
+ * replace the observed histograms (same shapes).  Stream-ordered copy. */
 bx_status bx_model_set_data(bx_model* m, const bx_data* data);
 
-/* Release the model and its device memory.  BX_E_BUSY while a server fit uses it. */
+/* Sec. 4, workflow step 7 (the fit is over): release the model and its
+ * device memory.  BX_E_BUSY while a server fit uses it. */
 bx_status bx_model_free(bx_model* m);
 
-/* Number of parameters P = S + (2 Gaussian | 4 GG or count | 1 table with n_grid >= 2
+/* The parameters the minimiser varies (Sec. 4, step 5): the species rates
+ * and the response parameters p_0, p_1, ... of Eq. 1.  Number of parameters
+ * P = S + (2 Gaussian | 4 GG or count | 1 table with n_grid >= 2
  * | 0 one-matrix table) + (1 when the pile-up fraction floats). */
 int32_t bx_model_nparams(const bx_model* m);
 
-/* Sum of ln Gamma(n+1) over every bin in the NLL (FP64, computed at build and
- * on bx_model_set_data).  NLL + lnfact is the full negative log-likelihood. */
+/* The data-only part of the Poisson likelihood terms of Eqs. 3-4: sum of
+ * ln Gamma(n+1) over every bin in the NLL (FP64, computed at build and on
+ * bx_model_set_data).  NLL + lnfact is the full negative log-likelihood. */
 bx_status bx_model_lnfact(const bx_model* m, double* out);
 
-/* NLL at theta[P] (host).  Synchronous.  Domain errors return BX_E_DOMAIN and
+/* Sec. 4, step 6: one evaluation of the likelihood the minimiser requests --
+ * the expected counts of every bin (Eqs. 1-2 folded with the rates) and the
+ * terms of Eqs. 3-4.  NLL at theta[P] (host).  Synchronous.  Domain errors
+ * return BX_E_DOMAIN and
  * *nll = +INFINITY (non-finite theta, sigma^2 < 0, GG mean or variance <= 0,
  * mu < 0 or mu = 0 < n). */
 bx_status bx_nll_eval(bx_model* m, const double* theta, double* nll);
 
-/* NLL and its gradient grad[P] (host).  Synchronous.  Domain errors as for
+/* Eqs. 1-4 and Sec. 4, steps 5-6: the evaluation of bx_nll_eval and the
+ * analytic gradient the minimiser steps along.  NLL and its gradient grad[P]
+ * (host).  Synchronous.  Domain errors as for
  * bx_nll_eval; the gradient is undefined (BX_E_DOMAIN) when some Gaussian
  * width is exactly zero.  On BX_E_DOMAIN grad is left untouched. */
 bx_status bx_nll_grad(bx_model* m, const double* theta, double* nll, double* grad);
 
-/* Device-pointer variant for stream-ordered use (autograd): reads
+/* Eqs. 1-4 and Sec. 4, steps 5-6, for a minimiser that keeps its state on
+ * the device: device-pointer variant for stream-ordered use (autograd): reads
  * d_theta[P], writes d_out[0] = NLL (+INFINITY on a domain error) and
  * d_out[1..P] = gradient.  stream: hipStream_t to run on (NULL = the model's).
  * Asynchronous; the status describes the enqueue only. */
@@ -190,44 +203,49 @@ bx_status bx_nll_grad_dev(bx_model* m, const double* d_theta, double* d_out, voi
  * the status describes the enqueue only. */
 bx_status bx_nll_grad_dev_noalloc(bx_model* m, const double* d_theta, double* d_out, void* stream);
 
-/* Expected counts of every likelihood term at theta, for the full reco range:
+/* Eqs. 1-4: expected counts of every likelihood term at theta (what Sec. 4,
+ * step 6 evaluates per bin), for the full reco range:
  * out = [mu_energy[N] | mu_tagged[N] | nu_radial[n_rad] | lambda_ps[N][n_ps]]
  * (single histogram: mu[N] only).  bx_model_expected_size gives the length. */
 int64_t bx_model_expected_size(const bx_model* m);
 bx_status bx_model_expected(bx_model* m, const double* theta, double* out);
 
-/* Diagnostics: average duration (milliseconds) of each stage of one NLL +
- * gradient evaluation at theta.  After one evaluation at theta, each stage's
- * kernel is launched `reps` times back to back on the model's stream between
- * two HIP events (each launch recomputes that stage's output from the
- * previous stages' results); ms[8] times `reps` whole evaluations launched
- * kernel by kernel (no graph) the same way.  ms[9] = {column parameters,
- * forward cell sweep + species contraction, partial-sum reduction, pile-up +
- * likelihood terms, radial term, pile-up adjoint, backward cell sweep, final
- * sums, whole evaluation}; a stage the model does not have reads ~0.  A
+/* Diagnostics of the evaluation of Sec. 4, step 6 (Eqs. 1-4): average
+ * duration (milliseconds) of each stage of one NLL + gradient evaluation at
+ * theta.  After one evaluation at theta, each stage's kernels are launched
+ * `reps` times back to back on the model's stream between two HIP events
+ * (each launch recomputes that stage's output from the previous stages'
+ * results); ms[8] times `reps` whole evaluations launched kernel by kernel
+ * (no graph) the same way.  ms[11] = {column parameters, forward cell sweep +
+ * species contraction (with its fix-up sweep), partial-sum reduction, pile-up
+ * + likelihood terms, radial term, pile-up adjoint, backward cell sweep (with
+ * its fix-up sweep), final sums, whole evaluation, forward main sweep alone,
+ * backward main sweep alone}; a stage the model does not have reads ~0.  A
  * tabulated response reports its interpolation as the first stage; the
  * joint term's kernel is timed with the radial stage. */
 bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, double* ms);
 
-/* Diagnostics: the same per-stage timing for a batch.  `copies` independent
- * fits of this model (its data, theta) are placed in device memory as the fit
- * server places them and evaluated together, one launch per stage with
- * blockIdx.y selecting the fit; ms[9] as above, per batched launch.  Device
+/* Diagnostics (Sec. 4, step 6, for many fits at once): the same per-stage
+ * timing for a batch.  `copies` independent fits of this model (its data,
+ * theta) are placed in device memory as the fit server places them and
+ * evaluated together, one launch per stage with blockIdx.y selecting the fit;
+ * ms[11] as above, per batched launch.  Device
  * memory for the batch is allocated and freed inside the call (BX_E_NOMEM if
  * it does not fit).  Synchronous on the model's stream. */
 bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies, int32_t reps, double* ms);
 
-/* Diagnostics: the rate (edge evaluations per second) that the edge
- * arithmetic of this model's response reaches on its own (CDF value and its
- * two column-parameter derivatives; the per-cell pmf for the count
- * estimator), measured with the column constants and supports at theta:
- * 256 x 8 workgroups of 4 waves, each wave one (true tile, reco tile) pair
- * of the workload in the forward sweep's lane layout (4 edges per lane),
- * evaluated `reps` times from registers (no tile lists, contraction or
- * memory traffic).  It is the measured ceiling of the cell sweeps.
- * BX_E_INVAL for a tabulated response (no edge function).
+/* Diagnostics of the cells of Eq. 1 (the response integrated over one reco
+ * bin): the rate (cells per second) that the cell arithmetic of this model's
+ * response reaches on its own (the one-interval quadrature of the cell and its
+ * two column-parameter derivatives, as the backward sweep forms them; the
+ * per-cell pmf for the count estimator), measured with the column constants
+ * and supports at theta: 256 x 8 workgroups of 4 waves, each wave one (true
+ * tile, reco tile) pair of the workload in the sweeps' lane layout (4 cells
+ * per lane), evaluated `reps` times from registers (no tile lists,
+ * contraction or memory traffic).  It is the measured ceiling of the cell
+ * sweeps.  BX_E_INVAL for a tabulated response (no cell function).
  * Synchronous on the model's stream. */
-bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, double* edges_per_s);
+bx_status bx_model_cell_ceiling(bx_model* m, const double* theta, int32_t reps, double* cells_per_s);
 
 /* ---- fitting (Sec. 4, steps 5-7) ---- */
 typedef enum { BX_FIT = 0, BX_EVAL_GRAD = 1 } bx_request_kind;
@@ -258,11 +276,13 @@ typedef struct {
   int64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady-clock timestamps */
 } bx_fit_result;
 
-/* Plain path: fit one model on the calling thread (host BFGS, one device
- * evaluation per step). */
+/* Sec. 4, steps 5-7: vary the parameters until the likelihood is optimal
+ * and hand the result back.  Plain path: fit one model on the calling thread
+ * (host BFGS, one device evaluation per step). */
 bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r);
 
-/* Fit server: admits requests while their device memory fits hbm_budget_bytes
+/* Sec. 4, steps 5-7 for many fits at once (toy studies, served requests).
+ * Fit server: admits requests while their device memory fits hbm_budget_bytes
  * (0 = the device's free memory) and max_slots (<= 0: 4096), keeps each admitted
  * fit's parameters, optimiser state and histograms resident, and advances
  * every active fit by one quasi-Newton step per batched evaluation
@@ -270,21 +290,28 @@ bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r);
  * owns a worker thread and its own stream (hip_stream NULL) or borrows one. */
 bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip_stream,
                            bx_server** out);
+/* Sec. 4, step 7 for the server: finish the queued fits, then release the
+ * worker, stream and device memory. */
 bx_status bx_server_destroy(bx_server* s);
 
-/* Queue a request on model m (borrowed until the ticket reaches a terminal
+/* Sec. 4, step 5 (start a minimisation) or step 6 (one evaluation): queue
+ * a request on model m (borrowed until the ticket reaches a terminal
  * state; the model's current data are copied at submission).  o is copied.
  * BX_E_BUSY if the request can never fit the budget. */
 bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_t* ticket);
 
-/* Result of a ticket: BX_PENDING while running; BX_OK with *r filled once
+/* Sec. 4, step 7 (the minimum found, the result handed back): result of a
+ * ticket: BX_PENDING while running; BX_OK with *r filled once
  * terminal (the ticket is then retired); BX_E_NOTFOUND otherwise. */
 bx_status bx_fit_poll(bx_server* s, uint64_t ticket, bx_fit_result* r);
 
-/* Block until every submitted ticket is terminal. */
+/* Sec. 4, step 7 for every queued fit: block until every submitted ticket
+ * is terminal. */
 bx_status bx_server_drain(bx_server* s);
 
-/* Message of the last error on the calling thread (static storage). */
+/* The reason a call above failed (a domain error of Eqs. 1-4, a bad size,
+ * a device error): message of the last error on the calling thread (static
+ * storage). */
 const char* bx_last_error(void);
 
 #ifdef __cplusplus

@@ -458,12 +458,6 @@ def per_species_expected(desc, theta):
     return forward(desc, theta).Mp
 
 
-def support_cells(desc, theta, eps=1e-30):
-    """Number of cells with R[j, i] > eps."""
-    f = forward(desc, theta)
-    return int(np.count_nonzero(f.R > eps))
-
-
 def support_edges(desc, theta, q=1e-12):
     """CDF evaluations one response sweep needs (Eq. 1 integrated over the
     reco bins): for every column, the reco edges whose CDF lies in [q, 1 - q]
@@ -477,6 +471,21 @@ def support_edges(desc, theta, q=1e-12):
         idx = np.flatnonzero(row)
         if idx.size:
             total += int(min(idx[-1] + 1, n_edges - 1) - max(idx[0] - 1, 0) + 1)
+    return total
+
+
+def support_cells(desc, theta, q=1e-12):
+    """Cells one response sweep needs (Eq. 1 integrated over the reco bins):
+    for every column, the cells between the edges that support_edges counts
+    (one fewer than its edges; none for a column without support)."""
+    _, resp = split_theta(desc, theta)
+    tail, _ = edge_tails(desc, column_params(desc, resp))
+    n_edges = tail.shape[1]
+    total = 0
+    for row in tail >= q:
+        idx = np.flatnonzero(row)
+        if idx.size:
+            total += int(min(idx[-1] + 1, n_edges - 1) - max(idx[0] - 1, 0))
     return total
 
 

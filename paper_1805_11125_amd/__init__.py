@@ -201,7 +201,7 @@ class Model:
                 "ps": out[2 * N + nr:].reshape(N, nps)}
 
     STAGES = ["colparams", "cells_fwd", "reduce_M", "rowterms", "radial", "adjoint",
-              "cells_bwd", "final", "total"]
+              "cells_bwd", "final", "total", "cells_fwd_main", "cells_bwd_main"]
 
     def stage_times(self, theta, reps=20):
         """Average ms per evaluation stage (HIP events, each stage's kernel
@@ -209,7 +209,7 @@ class Model:
         "colparams" is the table interpolation; "radial" also holds the
         joint term's kernel."""
         t = _f64(theta)
-        ms = np.zeros(9)
+        ms = np.zeros(len(self.STAGES))
         check(self._lib.bx_model_stage_times(self._h, dptr(t), int(reps), dptr(ms)))
         return dict(zip(self.STAGES, ms))
 
@@ -217,17 +217,17 @@ class Model:
         """Average ms per batched launch of each stage for `copies` fits of
         this model evaluated together (bx_model_batch_times)."""
         t = _f64(theta)
-        ms = np.zeros(9)
+        ms = np.zeros(len(self.STAGES))
         check(self._lib.bx_model_batch_times(self._h, dptr(t), int(copies), int(reps), dptr(ms)))
         return dict(zip(self.STAGES, ms))
 
-    def edge_ceiling(self, theta, reps=64):
-        """Edge evaluations per second the response's edge arithmetic reaches
-        on its own at theta (bx_model_edge_ceiling): the measured ceiling of
-        the cell sweeps."""
+    def cell_ceiling(self, theta, reps=64):
+        """Cells per second the response's backward cell arithmetic (value and
+        two derivatives) reaches on its own at theta (bx_model_cell_ceiling):
+        the measured ceiling of the cell sweeps."""
         t = _f64(theta)
         v = C.c_double()
-        check(self._lib.bx_model_edge_ceiling(self._h, dptr(t), int(reps), C.byref(v)))
+        check(self._lib.bx_model_cell_ceiling(self._h, dptr(t), int(reps), C.byref(v)))
         return v.value
 
     def nll_grad_dev(self, theta_dev, out_dev, stream=None):

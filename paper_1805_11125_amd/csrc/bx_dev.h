@@ -151,6 +151,10 @@ struct LaunchShape {
   int CG;  // forward tiles per wave (one value per launch)
 };
 constexpr int kStages = 8;  // colparams, cells_fwd, reduce_M, rowterms, radial, adjoint, cells_bwd, final
+// launch_stage's extra codes (timing only): the main sweep of stage 1 or 6
+// without its fix-up sweep
+constexpr int kStageFwdMain = 8, kStageBwdMain = 9;
+constexpr int kStageTimes = kStages + 3;  // the stages, a whole evaluation, the two main sweeps
 void launch_stage(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
                   int stage, hipStream_t st);
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
@@ -158,7 +162,7 @@ void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchS
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
 void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
-void launch_edge_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
+void launch_cell_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
                          hipStream_t st);
 
 }  // namespace bx

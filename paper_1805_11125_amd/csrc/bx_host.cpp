@@ -983,17 +983,18 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   // Each stage is timed on its own: `reps` back-to-back launches of its
   // kernel between two events (every stage only rewrites what it produces
   // from the previous stages' results, which the evaluation above left in
-  // place).  ms[8] times `reps` whole evaluations the same way.
+  // place).  ms[8] times `reps` whole evaluations the same way, ms[9] and
+  // ms[10] the forward and backward main sweeps without their fix-up sweeps.
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return hip_fail(hipErrorUnknown, "hipEventCreate");
   const LaunchShape L = shape_of(m->df.dev);
   hipError_t e = hipSuccess;
-  for (int k = 0; k <= kStages && e == hipSuccess; ++k) {
+  for (int k = 0; k < kStageTimes && e == hipSuccess; ++k) {
     e = hipEventRecord(e0, m->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
-      if (k < kStages) launch_stage(m->d_fit, nullptr, 1, L, true, k, m->stream);
-      else launch_eval(m->d_fit, nullptr, 1, L, true, m->stream);
+      if (k == kStages) launch_eval(m->d_fit, nullptr, 1, L, true, m->stream);
+      else launch_stage(m->d_fit, nullptr, 1, L, true, k < kStages ? k : k - 1, m->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, m->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1007,9 +1008,9 @@ bx_status bx_model_stage_times(bx_model* m, const double* theta, int32_t reps, d
   return BX_OK;
 }
 
-bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, double* edges_per_s) {
-  if (!m || !theta || !edges_per_s || reps < 1) return inval("bad argument");
-  if (m->h.kind == kTable) return inval("a tabulated response has no edge function");
+bx_status bx_model_cell_ceiling(bx_model* m, const double* theta, int32_t reps, double* cells_per_s) {
+  if (!m || !theta || !cells_per_s || reps < 1) return inval("bad argument");
+  if (m->h.kind == kTable) return inval("a tabulated response has no cell function");
   double nll;
   bx_status s = model_eval(m, theta, &nll, nullptr);  // column constants and supports at theta
   if (s != BX_OK) return s;
@@ -1020,11 +1021,11 @@ bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, 
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) {
-    launch_edge_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, 4, d_sink, m->stream);  // warm-up
+    launch_cell_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, 4, d_sink, m->stream);  // warm-up
     e = hipEventRecord(e0, m->stream);
   }
   if (e == hipSuccess) {
-    launch_edge_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, reps, d_sink, m->stream);
+    launch_cell_ceiling(m->d_fit, m->h.kind, m->h.prec, blocks, reps, d_sink, m->stream);
     e = hipEventRecord(e1, m->stream);
   }
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1033,8 +1034,8 @@ bx_status bx_model_edge_ceiling(bx_model* m, const double* theta, int32_t reps, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(d_sink);
-  if (e != hipSuccess) return hip_fail(e, "edge ceiling");
-  *edges_per_s = (double)blocks * 256.0 * 4.0 * reps / (t * 1e-3);  // four edges per lane per repetition
+  if (e != hipSuccess) return hip_fail(e, "cell ceiling");
+  *cells_per_s = (double)blocks * 256.0 * 4.0 * reps / (t * 1e-3);  // four cells per lane per repetition
   return BX_OK;
 }
 
@@ -1084,11 +1085,11 @@ bx_status bx_model_batch_times(bx_model* m, const double* theta, int32_t copies,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (int k = 0; k <= kStages && e == hipSuccess; ++k) {
+    for (int k = 0; k < kStageTimes && e == hipSuccess; ++k) {
       e = hipEventRecord(e0, m->stream);
       for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        if (k < kStages) launch_stage(d_fd, nullptr, copies, L, true, k, m->stream);
-        else launch_eval(d_fd, nullptr, copies, L, true, m->stream);
+        if (k == kStages) launch_eval(d_fd, nullptr, copies, L, true, m->stream);
+        else launch_stage(d_fd, nullptr, copies, L, true, k < kStages ? k : k - 1, m->stream);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, m->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);

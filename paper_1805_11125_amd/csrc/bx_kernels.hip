@@ -32,7 +32,7 @@
 //   k_table_gemm  tabulated response, at build: M_g = R_g F^T (FP64 MFMA);
 //   k_table       per evaluation: M and dM/dlam interpolated between grid
 //                 points (replaces k_colparams .. k_reduce_M).
-//   k_mark        a server step's completion mark; k_edge_ceiling the edge
+//   k_mark        a server step's completion mark; k_cell_ceiling the cell
 //                 arithmetic alone, for the measured ceiling.
 //
 // No reduction uses atomics: every sum has a fixed order, so a fit's result
@@ -2124,7 +2124,7 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
 // hoisted); sink is written only if the sum equals `never`, which keeps the
 // results live.
 template <class R, int KIND>
-__global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int reps, double eps, double never,
+__global__ void __launch_bounds__(256) k_cell_ceiling(const FitDev* fits, int reps, double eps, double never,
                                                       double* sink) {
   const FitDev& f = fits[0];
   const unsigned wid = blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -2162,19 +2162,19 @@ __global__ void __launch_bounds__(256) k_edge_ceiling(const FitDev* fits, int re
   if ((double)acc == never) sink[0] = (double)acc;
 }
 
-void launch_edge_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
+void launch_cell_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
                          hipStream_t st) {
   const double eps = 0.0, never = -1.2345e300;
   if (kind == kGG && prec == kF32)
-    hipLaunchKernelGGL((k_edge_ceiling<float, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+    hipLaunchKernelGGL((k_cell_ceiling<float, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
   else if (kind == kGG)
-    hipLaunchKernelGGL((k_edge_ceiling<double, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+    hipLaunchKernelGGL((k_cell_ceiling<double, kGG>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
   else if (kind == kGauss && prec == kF32)
-    hipLaunchKernelGGL((k_edge_ceiling<float, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+    hipLaunchKernelGGL((k_cell_ceiling<float, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
   else if (kind == kGauss)
-    hipLaunchKernelGGL((k_edge_ceiling<double, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+    hipLaunchKernelGGL((k_cell_ceiling<double, kGauss>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
   else if (kind == kCount)
-    hipLaunchKernelGGL((k_edge_ceiling<double, kCount>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
+    hipLaunchKernelGGL((k_cell_ceiling<double, kCount>), dim3(blocks), dim3(256), 0, st, d_fit, reps, eps, never, d_sink);
 }
 
 // Completion mark of a batched step: launched after its last kernel, it
@@ -2291,12 +2291,13 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
                            d_fits, d_active);
       break;
     case 1:
+    case kStageFwdMain:
       if (f32 && gauss) launch_fwd<float, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (f32 && L.kind == kGG) launch_fwd<float, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (!f32 && gauss) launch_fwd<double, kGauss>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (!f32 && L.kind == kGG) launch_fwd<double, kGG>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
       if (L.kind == kCount) launch_fwd<double, kCount>(L.CG, L.any_mv, gf, bf, st, d_fits, d_active);
-      if (fixk) launch_fix_stage(L, true, gfx, st, d_fits, d_active, 0, 1, nsplit);  // then the steps it left
+      if (fixk && stage == 1) launch_fix_stage(L, true, gfx, st, d_fits, d_active, 0, 1, nsplit);  // the steps left
       break;
     case 2:
       if (L.any_mv) hipLaunchKernelGGL(k_reduce_M, gred, blk, 0, st, d_fits, d_active);
@@ -2315,13 +2316,14 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
         hipLaunchKernelGGL(k_adjoint1, dim3((L.max_rowblk + 3) / 4, n), blk, 0, st, d_fits, d_active);
       break;
     case 6:
+    case kStageBwdMain:
       if (!with_grad) break;
       if (f32 && gauss) launch_bwd<float, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (f32 && L.kind == kGG) launch_bwd<float, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (!f32 && gauss) launch_bwd<double, kGauss>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (!f32 && L.kind == kGG) launch_bwd<double, kGG>(L.any_mv, gb, st, d_fits, d_active, pre);
       if (L.kind == kCount) launch_bwd<double, kCount>(L.any_mv, gb, st, d_fits, d_active, pre);
-      if (fixk) launch_fix_stage(L, false, gbx, st, d_fits, d_active, pre, 1, 1);
+      if (fixk && stage == 6) launch_fix_stage(L, false, gbx, st, d_fits, d_active, pre, 1, 1);
       break;
     case 7:
       hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);

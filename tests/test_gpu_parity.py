@@ -213,14 +213,14 @@ def test_repeatable_bitwise(bx):
         assert a[0] == b[0] and np.array_equal(a[1], b[1])
 
 
-def test_edge_ceiling_bounds_the_sweep(bx):
+def test_cell_ceiling_bounds_the_sweep(bx):
     # the edge arithmetic alone (registers only) must run faster than the
     # forward sweep's algorithmic edge rate, which adds tiles, the
     # contraction and the stored differences
     d, x = synth.load("c2")
     m = bx.Model(d, x, precision=F32)
     th = perturbed(d)
-    ceiling = m.edge_ceiling(th, reps=32)
+    ceiling = m.cell_ceiling(th, reps=32)
     st = m.stage_times(th, reps=20)
     edges = int(np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_support.npz"))["edges"])
     rate = edges / (st["cells_fwd"] * 1e-3)
@@ -229,4 +229,4 @@ def test_edge_ceiling_bounds_the_sweep(bx):
     t = synth.table_config(grid_L=(500.0,), true_step=0.05, reco_step=30.0, n_mc=100)
     mt = bx.Model(t, synth.Data(energy=np.ones(t.N)), precision=F64)
     with pytest.raises(bx.BxError):
-        mt.edge_ceiling(t.theta_true)
+        mt.cell_ceiling(t.theta_true)

@@ -491,6 +491,40 @@ def test_support_edges_gauss_quantiles():
     assert oracle.support_edges(d, d.theta_true, q=q) == expect
 
 
+def _quantile_count(d, th, q, cells=False):
+    # GG columns: y = (x/a)^p is Gamma(k, 1); F(x) >= q and 1 - F(x) >= q
+    # hold between the q and 1 - q quantiles, which come from the inverse
+    # incomplete gamma (a route independent of the forward P, Q the oracle
+    # compares against q); add the bracketing edge on each side.
+    cp = om.column_params(d, th[d.S:])
+    x = np.asarray(d.reco_edges, np.float64)
+    total = 0
+    for k, a in zip(cp.k, cp.a):
+        xl = a * special.gammaincinv(k, q) ** (1.0 / cp.p)
+        xh = a * special.gammainccinv(k, q) ** (1.0 / cp.p)
+        idx = np.flatnonzero((x > 0) & (x >= xl) & (x <= xh))
+        if idx.size:
+            total += min(idx[-1] + 1, len(x) - 1) - max(idx[0] - 1, 0) + (0 if cells else 1)
+    return total
+
+
+@pytest.mark.parametrize("T,N", [(60, 45), (200, 120)])
+def test_support_edges_gg_quantiles(T, N):
+    d = tiny_gg(T=T, N=N)
+    th = d.theta_true
+    for q in (1e-12, 1e-6):
+        assert oracle.support_edges(d, th, q=q) == _quantile_count(d, th, q)
+        assert oracle.support_cells(d, th, q=q) == _quantile_count(d, th, q, cells=True)
+
+
+def test_support_cells_gauss_is_edges_minus_columns():
+    d = synth.config1()
+    th = d.theta_true
+    cp = om.column_params(d, th[d.S:])
+    assert np.all(cp.sigma > 0)  # every column has support on this grid
+    assert oracle.support_cells(d, th) == oracle.support_edges(d, th) - d.T
+
+
 # ---------------------------------------------------------------------------
 # Pile-up fraction as a fit parameter (the last entry of theta)
 # ---------------------------------------------------------------------------
