@@ -264,6 +264,16 @@ typedef struct {
   int32_t max_eval;        /* NLL + gradient evaluations (<= 0: 200 + 100 n + 5 n^2,
                               n = varied parameters); reaching it ends the fit with
                               BX_MAXITER at the best point accepted so far */
+  /* Mixed-precision fit: an FP64 model of the same fit (same description but
+   * for the precision, same data; NULL = none).  The fit runs on the model it
+   * was submitted with until EDM < polish_edm (or until its line search can
+   * make no more progress), then evaluates again at that point with `polish`
+   * and goes on from there, with the same Hessian approximation, until
+   * EDM < edm_tol: FP32 cells for the bulk of the iterations, the minimum
+   * and its EDM those of the FP64 model.  BX_E_INVAL if the shapes differ or
+   * polish is not FP64; the server keeps `polish` busy like the model. */
+  bx_model* polish;
+  double polish_edm;       /* <= 0: 1e-8 */
 } bx_fit_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class FitResult:
 
 
 def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, kind=BX_FIT,
-              max_eval=0):
+              max_eval=0, polish=None, polish_edm=0.0):
     keep = []
     x0 = _f64(x0)
     keep.append(x0)
@@ -66,6 +66,9 @@ def _fit_opts(P, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0,
     o.edm_tol = float(edm_tol)
     o.max_iter = int(max_iter)
     o.max_eval = int(max_eval)
+    if polish is not None:  # mixed precision: the FP64 model of the same fit
+        o.polish = polish.handle
+        o.polish_edm = float(polish_edm)
     return o, keep
 
 
@@ -241,8 +244,12 @@ class Model:
         check(self._lib.bx_nll_grad_dev_noalloc(self._h, C.c_void_p(theta_dev), C.c_void_p(out_dev),
                                                 C.c_void_p(stream) if stream else None))
 
-    def fit(self, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, max_eval=0):
-        o, keep = _fit_opts(self.P, x0, float_mask, lo, hi, edm_tol, max_iter, max_eval=max_eval)
+    def fit(self, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0, max_iter=0, max_eval=0,
+            polish=None, polish_edm=0.0):
+        """Fit on the calling thread (bx_fit).  polish: an FP64 Model of the
+        same fit that takes over at EDM < polish_edm (mixed precision)."""
+        o, keep = _fit_opts(self.P, x0, float_mask, lo, hi, edm_tol, max_iter, max_eval=max_eval,
+                            polish=polish, polish_edm=polish_edm)
         r = _abi.bx_fit_result()
         check(self._lib.bx_fit(self._h, C.byref(o), C.byref(r)))
         del keep
@@ -272,8 +279,9 @@ class Server:
         self._P = {}
 
     def submit(self, model: Model, x0, float_mask=None, lo=None, hi=None, edm_tol=0.0,
-               max_iter=0, kind=BX_FIT, max_eval=0):
-        o, keep = _fit_opts(model.P, x0, float_mask, lo, hi, edm_tol, max_iter, kind, max_eval)
+               max_iter=0, kind=BX_FIT, max_eval=0, polish=None, polish_edm=0.0):
+        o, keep = _fit_opts(model.P, x0, float_mask, lo, hi, edm_tol, max_iter, kind, max_eval,
+                            polish=polish, polish_edm=polish_edm)
         t = C.c_uint64()
         check(self._lib.bx_fit_submit(self._h, model.handle, C.byref(o), C.byref(t)))
         self._P[t.value] = model.P

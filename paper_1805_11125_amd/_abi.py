@@ -43,7 +43,7 @@ class bx_data(C.Structure):
 class bx_fit_opts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("x0", _dp), ("float_mask", C.POINTER(C.c_uint8)),
                 ("lo", _dp), ("hi", _dp), ("edm_tol", C.c_double), ("max_iter", C.c_int32),
-                ("max_eval", C.c_int32)]
+                ("max_eval", C.c_int32), ("polish", C.c_void_p), ("polish_edm", C.c_double)]
 
 
 class bx_fit_result(C.Structure):

@@ -32,6 +32,7 @@ struct FitProblem {
   double x0[32], lo[32], hi[32], scale[32];
   double edm_tol = 1e-9;
   double f_noise = 0.0;              // relative rounding noise of the NLL values
+  double final_tol = 1e-9;           // mixed precision: the polishing model's tolerance
 };
 
 // unit: index of a parameter with default bounds [0, 1] (a floated pile-up
@@ -45,6 +46,9 @@ inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb,
   pb->S = S;
   pb->kind = o->kind == BX_EVAL_GRAD ? BX_EVAL_GRAD : BX_FIT;
   pb->edm_tol = o->edm_tol > 0 ? o->edm_tol : 1e-9;
+  pb->final_tol = pb->edm_tol;
+  // mixed precision: the first model stops at the switch tolerance
+  if (o->polish) pb->edm_tol = std::max(pb->edm_tol, o->polish_edm > 0 ? o->polish_edm : 1e-8);
   pb->max_iter = o->max_iter > 0 ? o->max_iter : 500;
   pb->nf = 0;
   for (int q = 0; q < P; ++q) {
@@ -80,15 +84,42 @@ class Bfgs {
   // Point to evaluate next; false when finished.
   bool next(double* x) {
     if (state_ == kDone) return false;
-    memcpy(x, state_ == kInit ? x_ : xt_, sizeof(double) * pb_.P);
+    memcpy(x, state_ == kInit || state_ == kReeval ? x_ : xt_, sizeof(double) * pb_.P);
     return true;
   }
+
+  // Go on from the accepted point with evaluations of another model (the
+  // FP64 model of a mixed-precision fit): the point is evaluated again, then
+  // the iterations continue with the same Hessian approximation until
+  // EDM < edm_tol.  Only after a finished fit that did not run out of budget.
+  bool polish(double edm_tol, double f_noise) {
+    if (state_ != kDone || pb_.kind != BX_FIT || status_ == BX_MAXITER || !std::isfinite(f_)) return false;
+    pb_.edm_tol = edm_tol;
+    pb_.f_noise = f_noise;
+    state_ = kReeval;
+    status_ = BX_FAILED;
+    restarted_ = false;
+    refresh_iter_ = iter_;
+    edm_refresh_ = INFINITY;
+    return true;
+  }
+  int status() const { return status_; }
 
   void feed(double f, const double* g) {
     ++n_eval_;
     const int n = pb_.nf;
     if (state_ != kInit && n_eval_ >= pb_.max_eval) {  // budget spent: keep the accepted point
       finish(BX_MAXITER);
+      return;
+    }
+    if (state_ == kReeval) {  // the accepted point, by the polishing model
+      f_ = f;
+      memcpy(g_, g, sizeof(double) * pb_.P);
+      if (!std::isfinite(f)) {
+        finish(BX_FAILED);
+        return;
+      }
+      start_iteration();
       return;
     }
     if (state_ == kInit) {
@@ -180,7 +211,7 @@ class Bfgs {
   bool done() const { return state_ == kDone; }
 
  private:
-  enum { kInit, kHess, kSearch, kDone };
+  enum { kInit, kHess, kSearch, kDone, kReeval };
   static constexpr double kProbe = 1e-4;  // Hessian probe step (scaled units)
 
   double lo_u(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }

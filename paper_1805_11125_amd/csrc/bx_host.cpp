@@ -668,6 +668,16 @@ static bx_status order_on(bx_model* m, hipStream_t st) {
 }
 
 namespace bx {
+// The polishing model of a mixed-precision fit: FP64, and the same shapes.
+bx_status polish_compatible(const bx_model* m, const bx_model* p) {
+  const HostModel &a = m->h, &b = p->h;
+  if (b.prec != kF64) return inval("the polishing model must be FP64");
+  if (a.T != b.T || a.N != b.N || a.S != b.S || a.P != b.P || a.kind != b.kind || a.mv != b.mv ||
+      a.win_lo != b.win_lo || a.win_hi != b.win_hi || a.pu_float != b.pu_float)
+    return inval("the polishing model's shapes differ from the fit's");
+  return BX_OK;
+}
+
 // Evaluate at host theta; fills nll (and grad).  Shared with the plain fitter.
 bx_status model_eval(bx_model* m, const double* theta, double* nll, double* grad) {
   const int P = m->h.P;
@@ -1114,16 +1124,21 @@ bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r) {
   FitProblem pb;
   bx_status s = fit_problem(P, m->h.S, o, &pb, m->h.pu_float ? P - 1 : -1);
   if (s != BX_OK) return s;
+  if (o->polish && (s = polish_compatible(m, o->polish)) != BX_OK) return s;
   pb.f_noise = nll_noise(m->h);
   memset(r, 0, sizeof *r);
   const auto t0 = std::chrono::steady_clock::now().time_since_epoch();
   r->t_submit_ns = r->t_admit_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t0).count();
   Bfgs opt(pb);
   double x[32], f = 0.0, g[32];
-  while (opt.next(x)) {
-    const bx_status e = model_eval(m, x, &f, g);
-    if (e != BX_OK && e != BX_E_DOMAIN) return e;
-    opt.feed(e == BX_OK ? f : INFINITY, g);
+  // the fit's own model, then (mixed precision) the FP64 model from where it stopped
+  for (bx_model* em = m; em;) {
+    while (opt.next(x)) {
+      const bx_status e = model_eval(em, x, &f, g);
+      if (e != BX_OK && e != BX_E_DOMAIN) return e;
+      opt.feed(e == BX_OK ? f : INFINITY, g);
+    }
+    em = (em == m && o->polish && opt.polish(pb.final_tol, nll_noise(o->polish->h))) ? o->polish : nullptr;
   }
   opt.result(r);
   const auto t1 = std::chrono::steady_clock::now().time_since_epoch();

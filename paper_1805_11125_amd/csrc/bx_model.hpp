@@ -127,3 +127,9 @@ struct bx_model {
   std::atomic<int> users{0};     // server fits referencing this model
   int device = 0;
 };
+
+namespace bx {
+// The polishing model of a mixed-precision fit: FP64 and the same shapes
+// (BX_E_INVAL otherwise).
+bx_status polish_compatible(const bx_model* m, const bx_model* p);
+}  // namespace bx

@@ -113,7 +113,25 @@ struct Req {
   int group = 0;           // launch group: (kind, precision, multivariate, forward tiles per wave)
   bx_fit_result res{};
   bool done = false;
+  // mixed precision: the FP64 model the fit moves to, and its placement in
+  // the same allocation (after the first one's bytes1)
+  bx_model* polish = nullptr;
+  HostModel hp;
+  DeviceFit dfp;
+  LaunchShape shape_p{};
+  int group_p = 0;
+  size_t bytes1 = 0;
+  bool polished = false;
 };
+
+// Launch group of a placed fit: kind, precision, single histogram or several
+// (the sweeps' contraction differs, so the two never share a launch), and the
+// forward tiles per wave.
+static int group_of(const LaunchShape& l) {
+  int cgl = 0;
+  while ((1 << cgl) < l.CG) ++cgl;
+  return ((l.kind * 2 + l.prec) * 2 + l.any_mv) * 4 + cgl;
+}
 
 }  // namespace bx
 
@@ -170,21 +188,26 @@ static void admit(bx_server* s) {
     s->free_slots.pop_back();
     s->used += r->bytes;
     DeviceFit& df = r->df;
-    if (!got || place_fit(r->h, mem, &df, s->stream, &r->model->df.dev) != BX_OK) {
+    bool placed = got && place_fit(r->h, mem, &df, s->stream, &r->model->df.dev) == BX_OK;
+    if (placed && r->polish)
+      placed = place_fit(r->hp, (char*)mem + r->bytes1, &r->dfp, s->stream, &r->polish->df.dev) == BX_OK;
+    if (!placed) {
       r->res.status = BX_FAILED;
       retire(s, r);
       continue;
     }
-    df.dev.theta = s->d_theta + (size_t)r->slot * kThetaStride;
-    df.dev.out = s->d_out + (size_t)r->slot * kOutStride;
-    df.dev.theta_src = s->dh_theta + (size_t)r->slot * kThetaStride;
-    df.dev.out_host = s->dh_out + (size_t)r->slot * kOutStride;
+    for (DeviceFit* d : {&r->df, &r->dfp}) {  // both read theta and write results in the slot's rows
+      d->dev.theta = s->d_theta + (size_t)r->slot * kThetaStride;
+      d->dev.out = s->d_out + (size_t)r->slot * kOutStride;
+      d->dev.theta_src = s->dh_theta + (size_t)r->slot * kThetaStride;
+      d->dev.out_host = s->dh_out + (size_t)r->slot * kOutStride;
+    }
     r->shape = shape_of(df.dev);
-    int cgl = 0;
-    while ((1 << cgl) < r->shape.CG) ++cgl;
-    // the sweeps' contraction differs between single-histogram and
-    // multivariate fits, so the two never share a launch
-    r->group = ((r->shape.kind * 2 + r->shape.prec) * 2 + r->shape.any_mv) * 4 + cgl;
+    r->group = group_of(r->shape);
+    if (r->polish) {
+      r->shape_p = shape_of(r->dfp.dev);
+      r->group_p = group_of(r->shape_p);
+    }
     (void)hipMemcpyAsync(s->d_fits + r->slot, &df.dev, sizeof(FitDev), hipMemcpyHostToDevice, s->stream);
     r->res.t_admit_ns = now_ns();
     s->active.push_back(r);
@@ -199,6 +222,7 @@ static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
   r->res.t_done_ns = now_ns();
   r->done = true;
   r->model->users.fetch_sub(1);
+  if (r->polish) r->polish->users.fetch_sub(1);
   --s->pending;
 }
 
@@ -305,6 +329,16 @@ static void worker_loop(bx_server* s) {
     }
     std::vector<std::shared_ptr<Req>> keep;
     for (auto& r : s->active) {
+      if (r->opt->done() && r->polish && !r->polished &&
+          r->opt->polish(r->pb.final_tol, nll_noise(r->polish->h))) {
+        // mixed precision: on to the FP64 placement, from the same point
+        r->h = r->hp;
+        r->df = r->dfp;
+        r->shape = r->shape_p;
+        r->group = r->group_p;
+        r->polished = true;
+        (void)hipMemcpyAsync(s->d_fits + r->slot, &r->df.dev, sizeof(FitDev), hipMemcpyHostToDevice, s->stream);
+      }
       if (r->opt->done()) {
         r->opt->result(&r->res);
         retire(s, r);
@@ -414,11 +448,17 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   bx_status st = fit_problem(m->h.P, m->h.S, o, &r->pb, m->h.pu_float ? m->h.P - 1 : -1);
   if (st != BX_OK) return st;
   r->pb.f_noise = nll_noise(m->h);
+  if (o->polish && (st = polish_compatible(m, o->polish)) != BX_OK) return st;
   // the fit reads the model's inputs in place (the model stays busy while it
   // is pending) and gets its own workspace, with the batched tile widths
   r->h = shape_only(m->h);
   r->h.tiles = choose_tiles(r->h.T, r->h.N, r->h.kind, r->h.prec, 1);
-  r->bytes = (device_fit_bytes(r->h, true) + 4095) & ~(size_t)4095;
+  r->bytes = r->bytes1 = (device_fit_bytes(r->h, true) + 4095) & ~(size_t)4095;
+  if (o->polish) {  // and a second workspace for the FP64 model's iterations
+    r->hp = shape_only(o->polish->h);
+    r->hp.tiles = choose_tiles(r->hp.T, r->hp.N, r->hp.kind, r->hp.prec, 1);
+    r->bytes += (device_fit_bytes(r->hp, true) + 4095) & ~(size_t)4095;
+  }
   if (r->bytes > s->budget) {
     set_error("request larger than the server's memory budget");
     return BX_E_BUSY;
@@ -426,6 +466,10 @@ bx_status bx_fit_submit(bx_server* s, bx_model* m, const bx_fit_opts* o, uint64_
   r->opt.reset(new Bfgs(r->pb));
   r->model = m;
   m->users.fetch_add(1);
+  if (o->polish) {
+    r->polish = o->polish;
+    r->polish->users.fetch_add(1);
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     r->ticket = s->next_ticket++;

@@ -28,13 +28,21 @@ def fit_fixture(name):
     return np.load(p)
 
 
+# MIX: FP32 cells for the bulk of the iterations, then the FP64 model of the
+# same fit from EDM < 1e-8 (mixed precision); held to the FP64 bounds.
+MIX = 2
+
+
 @pytest.mark.parametrize("name,prec,tol", [("c1", F64, 1e-14), ("c3a", F64, 1e-14), ("c2", F64, 1e-14),
+                                           ("c1", MIX, 1e-14), ("c2", MIX, 1e-14), ("c3a", MIX, 1e-14),
+                                           ("c3b", MIX, 1e-12),
                                            ("c1", F32, 1e-8), ("c2", F32, 1e-8)])
 def test_plain_fit_matches_oracle_minimum(bx, name, prec, tol):
     z = fit_fixture(name)
     d, x = synth.load(name)
-    m = bx.Model(d, x, precision=prec)
-    r = m.fit(z["theta0"], float_mask=z["mask"], edm_tol=tol, max_iter=1000)
+    m = bx.Model(d, x, precision=F64 if prec == F64 else F32)
+    pm = bx.Model(d, x, precision=F64) if prec == MIX else None
+    r = m.fit(z["theta0"], float_mask=z["mask"], edm_tol=tol, max_iter=1000, polish=pm)
     err = np.where(np.isfinite(z["err"]), z["err"], 0.0)
     scale = np.maximum(np.abs(z["theta"]), err)
     dev = np.abs(r.x - z["theta"]) / scale
@@ -43,7 +51,7 @@ def test_plain_fit_matches_oracle_minimum(bx, name, prec, tol):
           f"nll {r.nll:.10g} oracle {float(z['nll']):.10g}; rates max |d|/max(|r|,sigma) "
           f"{dev[:d.S].max():.2e}; response params max |d|/sigma {dsig[d.S:].max():.2e}")
     assert r.status == bx.BX_CONVERGED
-    if prec == F64:
+    if prec in (F64, MIX):
         # fitted rates: |r - r*| <= 1e-6 max(|r*|, sigma*); response parameters within 1e-6 sigma
         assert np.all(dev[: d.S] <= 1e-6), dev
         assert np.all(dsig[d.S:] <= 1e-6), dsig
@@ -185,6 +193,39 @@ def test_batched_fits_equal_plain_and_isolated(bx):
         assert p.n_eval == b.n_eval and p.nll == b.nll and np.array_equal(p.x, b.x)
     assert np.array_equal(alone.x, mixed[1].x) and alone.nll == mixed[1].nll
     print("toy fits:", [(r.status, r.n_iter, r.n_eval, f"{r.edm:.1e}") for r in batched])
+
+
+def test_mixed_precision_fits_batched_equal_plain(bx):
+    # FP32 cells until EDM < 1e-8, then the FP64 model of the same toy: the
+    # server moves each fit to its FP64 placement at that point, and every
+    # result equals the plain path's bit for bit
+    toys = _toys(4, first=20)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+    pol = [bx.Model(d, x, precision=F64) for d, x, _ in toys]
+    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=1e-12, max_iter=500, polish=p)
+             for m, p, (d, x, t) in zip(models, pol, toys)]
+    s = bx.Server()
+    tickets = [s.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=1e-12, max_iter=500, polish=p)
+               for m, p, (d, x, t) in zip(models, pol, toys)]
+    batched = [s.wait(tk) for tk in tickets]
+    s.close()
+    for p, b in zip(plain, batched):
+        assert p.status == bx.BX_CONVERGED and p.edm < 1e-12
+        assert p.n_eval == b.n_eval and p.nll == b.nll and np.array_equal(p.x, b.x)
+    # the FP64 model's point: its own NLL there
+    for m64, r in zip(pol, plain):
+        assert m64.nll(r.x) == r.nll
+    print("mixed toy fits:", [(r.n_iter, r.n_eval, f"{r.edm:.1e}") for r in plain])
+
+
+def test_polish_model_must_match(bx):
+    d, x = synth.load("c1")
+    m = bx.Model(d, x, precision=F32)
+    with pytest.raises(bx.BxError):  # the polishing model is not FP64
+        m.fit(d.theta_true, polish=bx.Model(d, x, precision=F32))
+    d2, x2 = synth.load("c3a")
+    with pytest.raises(bx.BxError):  # other shapes
+        m.fit(d.theta_true, polish=bx.Model(d2, x2, precision=F64))
 
 
 def test_admission_under_small_budget(bx):
