@@ -1,6 +1,6 @@
 """Oracle fits of the frozen datasets (slow: the config-2 fit takes minutes).
 
-    python tests/golden/make_fit_fixtures.py [c1 c2 c3a]
+    python tests/golden/make_fit_fixtures.py [c1 c2 c3a c3b]
 
 Writes fit_<name>.npz with the oracle's minimum (theta, NLL, EDM, parameter
 errors from the inverse Hessian) from the start point theta_true * (1 + 5%
@@ -40,4 +40,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c1", "c3a", "c2"])
+    main(sys.argv[1:] or ["c1", "c3a", "c2", "c3b"])

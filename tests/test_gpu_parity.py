@@ -4,7 +4,7 @@ the same seeded inputs.
 Tolerances: NLL within 1e-9 relative; every gradient component within 1e-6
 of its magnitude scale sum_b |(1 - n_b/mu_b) dmu_b/dq| (the absolute summands
 of dNLL/dq); expected counts per bin within 1e-11 relative (FP64 cells)
-or 3e-5 relative to the term's largest bin (FP32 cells).
+or 1e-6 relative per bin (FP32 cells; 1e-9 absolute below 1e-3 counts).
 """
 import math
 import os
@@ -109,8 +109,56 @@ def test_expected_counts_parity(bx, name, prec):
         got = np.asarray(mu[key]).reshape(arr.shape)
         if prec == F64:
             np.testing.assert_allclose(got, arr, rtol=1e-11, atol=1e-12 * np.abs(arr).max())
-        else:
-            assert np.max(np.abs(got - arr)) <= 3e-5 * np.abs(arr).max(), key
+    if prec == F32:
+        _per_bin_check(mu, ref, f"{name}/F32")
+
+
+# Per-bin parity of the expected counts of every term (Eqs. 1-4) with FP32
+# cells: each bin against its own oracle value.  The cells carry ~1e-7 of
+# relative rounding (FP32 nodes; FP64 scale and sums), and a bin's expected
+# count is a positive sum of cells, so its relative error stays at that
+# level wherever the bin is populated (4.1e-7 at worst, a tagged bin of the
+# 3000 x 900 multivariate model); bins far in the tails of every column
+# (expected counts below 1e-3) are held to an absolute 1e-9 instead.
+PER_BIN_REL = 1e-6
+
+
+def _per_bin_check(mu, ref, label):
+    worst = {}
+    for key, arr in ref.items():
+        got = np.asarray(mu[key]).reshape(arr.shape)
+        big = np.abs(arr) >= 1e-3
+        rel = np.abs(got - arr)[big] / np.abs(arr)[big]
+        small = np.abs(got - arr)[~big]
+        worst[key] = (float(rel.max()) if rel.size else 0.0, float(small.max()) if small.size else 0.0)
+        assert rel.size == 0 or rel.max() <= PER_BIN_REL, (label, key, rel.max())
+        assert small.size == 0 or small.max() <= 1e-9, (label, key, small.max())
+    print(label, {k: f"rel {a:.2e} abs(small) {b:.1e}" for k, (a, b) in worst.items()})
+
+
+@pytest.mark.parametrize("name", ["c3b", "c3a", "c2"])
+def test_expected_counts_per_bin_fp32(bx, name):
+    d, x = synth.load(name)
+    th = perturbed(d, seed=5)
+    m = bx.Model(d, x, precision=F32)
+    mu = m.expected(th)
+    f = om.forward(d, th)
+    full = d.copy()
+    full.win = (0, d.N)
+    _per_bin_check(mu, om.expected(full, f.Mp, f.r), f"{name}/F32")
+
+
+@pytest.mark.parametrize("b", [143, 3, 13])
+def test_expected_counts_per_bin_toys(bx, b):
+    base, per_species, theta = synth.catalogue()
+    t = synth.toy(b, per_species, theta)
+    d = synth.toy_desc(base, t)
+    m = bx.Model(d, synth.Data(energy=t.counts), precision=F32)
+    mu = m.expected(t.theta0)
+    f = om.forward(d, t.theta0)
+    full = d.copy()
+    full.win = (0, d.N)
+    _per_bin_check(mu, om.expected(full, f.Mp, f.r), f"toy{b}/F32")
 
 
 def test_lnfact_matches_oracle(bx):
