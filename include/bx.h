@@ -291,6 +291,22 @@ typedef struct {
  * (host BFGS, one device evaluation per step). */
 bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r);
 
+/* Sec. 4, steps 5-7 for a batch of fits at once (a toy study): fit model
+ * models[i] from opts[i] (as for bx_fit, a polishing model included) for
+ * i < n, with the fits' minimisers on the device.  Each fit is placed once
+ * (inputs shared with its model, its own workspace); one iteration of all of
+ * them -- the evaluation launches of every launch group, then a kernel that
+ * runs each fit's minimiser step (one thread per fit) -- is captured as a HIP
+ * graph and replayed until no fit is running, the host reading the count of
+ * running fits every check_every replays (<= 0: 4).  results[i] equal
+ * bx_fit's bit for bit (the minimiser is the same code, compiled for the
+ * device with the same arithmetic).  The models must be on one device;
+ * their pending work is waited for first.  Synchronous; the batch's device
+ * memory is allocated and freed inside the call (BX_E_NOMEM if it does not
+ * fit). */
+bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* opts, int32_t n, bx_fit_result* results,
+                       int32_t check_every);
+
 /* Sec. 4, steps 5-7 for many fits at once (toy studies, served requests).
  * Fit server: admits requests while their device memory fits hbm_budget_bytes
  * (0 = the device's free memory) and max_slots (<= 0: 4096), keeps each admitted

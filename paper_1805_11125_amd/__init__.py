@@ -317,6 +317,30 @@ class Server:
             pass
 
 
+def fit_batch(models, x0s, float_masks=None, edm_tol=0.0, max_iter=0, max_eval=0, polish=None,
+              polish_edm=0.0, check_every=0):
+    """Fit models[i] from x0s[i] together, with the minimisers on the device
+    and one iteration of all the fits replayed as a HIP graph
+    (bx_fit_batch).  polish: FP64 models of the same fits (mixed precision),
+    or None.  Returns one FitResult per fit, equal to Model.fit's."""
+    n = len(models)
+    if n == 0:
+        return []
+    lib = models[0]._lib
+    arr = (_abi.bx_fit_opts * n)()
+    keep = []
+    for i, m in enumerate(models):
+        o, k = _fit_opts(m.P, x0s[i], None if float_masks is None else float_masks[i], None, None, edm_tol,
+                         max_iter, BX_FIT, max_eval, None if polish is None else polish[i], polish_edm)
+        arr[i] = o
+        keep.append(k)
+    hs = (C.c_void_p * n)(*[m.handle for m in models])
+    res = (_abi.bx_fit_result * n)()
+    check(lib.bx_fit_batch(hs, arr, n, res, int(check_every)))
+    del keep
+    return [FitResult(res[i], models[i].P) for i in range(n)]
+
+
 def _make_nll_function():
     import torch
 

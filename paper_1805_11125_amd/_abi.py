@@ -71,6 +71,8 @@ SIGNATURES = {
     "bx_model_stage_times": (C.c_int, [C.c_void_p, _dp, C.c_int32, _dp]),
     "bx_model_batch_times": (C.c_int, [C.c_void_p, _dp, C.c_int32, C.c_int32, _dp]),
     "bx_model_cell_ceiling": (C.c_int, [C.c_void_p, _dp, C.c_int32, _dp]),
+    "bx_fit_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(bx_fit_opts), C.c_int32,
+                               C.POINTER(bx_fit_result), C.c_int32]),
     "bx_fit": (C.c_int, [C.c_void_p, C.POINTER(bx_fit_opts), C.POINTER(bx_fit_result)]),
     "bx_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "bx_server_destroy": (C.c_int, [C.c_void_p]),

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbx.so")
-SOURCES = ["bx_kernels.hip", "bx_host.cpp", "bx_server.cpp"]
+SOURCES = ["bx_kernels.hip", "bx_host.cpp", "bx_server.cpp", "bx_batch.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-value"]

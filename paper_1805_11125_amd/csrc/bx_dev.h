@@ -108,6 +108,8 @@ struct FitDev {
   double* Mfix;         // [kFixSplit][N][16] or [kFixSplit][N]: the forward fix-up sweep's
                         // shares (cells outside the sweeps' common case), added last
   int has_fix;          // analytic cells: the fix-up sweeps run (not for the count estimator)
+  int skip;             // 1: every kernel leaves this fit alone (a device-minimised fit that
+                        // has finished, or the placement it does not use now)
   double* fixq;         // [n_ct][4]: per wave step (true tile, q), the largest column factor of
                         // the one-interval test (GG sqrt(k) in the cell precision, Gauss 1/sigma;
                         // +inf for a column without a width), written by k_colparams
@@ -160,6 +162,22 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L,
                  bool with_grad, hipStream_t st);
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st);
+
+// One device-minimised fit (bx_fit_batch): its placements in the FitDev
+// array (fit_p: the FP64 polishing placement, or -1), its parameter count,
+// the phase (0: first model, 1: polishing model), the polishing model's
+// tolerance and NLL rounding noise.
+struct FitSlot {
+  int fit, fit_p, P, phase;
+  double final_tol, noise_p;
+};
+// opts: the fits' minimisers (bx::Bfgs[n], device memory).  start: every fit
+// names its first point (theta rows); step: hands each unfinished fit the
+// results of its last evaluation, moves it to its polishing placement when
+// the first model is done, names its next point, and counts the fits still
+// running into *d_count (zeroed in the same launch sequence).
+void launch_fit_start(void* opts, FitSlot* slots, FitDev* fits, int n, hipStream_t st);
+void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
 void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
 void launch_cell_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,

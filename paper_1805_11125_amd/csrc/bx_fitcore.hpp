@@ -14,6 +14,10 @@
 // definite, truncates the step at the box, and backtracks (Armijo, quadratic
 // interpolation).  EDM = g_F^T B_FF^-1 g_F / 2; the fit has converged when it
 // falls below the tolerance.
+//
+// The minimiser is compiled for the host (plain path, fit server) and for the
+// device (the batched fits' minimiser steps, k_fit_step): one code, with
+// floating-point contraction off, so that both give the same bits.
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -21,6 +25,20 @@
 #include <string>
 
 #include "../../include/bx.h"
+
+// HIP in the library (host and device); plain C++ in the minimiser's CPU
+// unit test.
+#ifdef __HIP__
+#include <hip/hip_runtime.h>
+#define BX_FHD __host__ __device__
+#else
+#define BX_FHD
+#endif
+
+#ifdef __clang__
+#pragma float_control(push)
+#pragma clang fp contract(off)
+#endif
 
 namespace bx {
 
@@ -72,19 +90,25 @@ inline bx_status fit_problem(int P, int S, const bx_fit_opts* o, FitProblem* pb,
   return BX_OK;
 }
 
+// element copy (host and device)
+BX_FHD inline void fcopy(double* d, const double* s, int n) {
+  for (int i = 0; i < n; ++i) d[i] = s[i];
+}
+
 class Bfgs {
  public:
-  explicit Bfgs(const FitProblem& pb) : pb_(pb) {
-    memcpy(x_, pb.x0, sizeof x_);
+  BX_FHD Bfgs() = default;
+  BX_FHD explicit Bfgs(const FitProblem& pb) : pb_(pb) {
+    fcopy(x_, pb.x0, 32);
     const int n = pb.nf;
     for (int a = 0; a < n * n; ++a) B_[a] = 0.0;
     for (int a = 0; a < n; ++a) B_[a * n + a] = 1.0;
   }
 
   // Point to evaluate next; false when finished.
-  bool next(double* x) {
+  BX_FHD bool next(double* x) {
     if (state_ == kDone) return false;
-    memcpy(x, state_ == kInit || state_ == kReeval ? x_ : xt_, sizeof(double) * pb_.P);
+    fcopy(x, state_ == kInit || state_ == kReeval ? x_ : xt_, pb_.P);
     return true;
   }
 
@@ -92,7 +116,7 @@ class Bfgs {
   // FP64 model of a mixed-precision fit): the point is evaluated again, then
   // the iterations continue with the same Hessian approximation until
   // EDM < edm_tol.  Only after a finished fit that did not run out of budget.
-  bool polish(double edm_tol, double f_noise) {
+  BX_FHD bool polish(double edm_tol, double f_noise) {
     if (state_ != kDone || pb_.kind != BX_FIT || status_ == BX_MAXITER || !std::isfinite(f_)) return false;
     pb_.edm_tol = edm_tol;
     pb_.f_noise = f_noise;
@@ -103,9 +127,9 @@ class Bfgs {
     edm_refresh_ = INFINITY;
     return true;
   }
-  int status() const { return status_; }
+  BX_FHD int status() const { return status_; }
 
-  void feed(double f, const double* g) {
+  BX_FHD void feed(double f, const double* g) {
     ++n_eval_;
     const int n = pb_.nf;
     if (state_ != kInit && n_eval_ >= pb_.max_eval) {  // budget spent: keep the accepted point
@@ -114,7 +138,7 @@ class Bfgs {
     }
     if (state_ == kReeval) {  // the accepted point, by the polishing model
       f_ = f;
-      memcpy(g_, g, sizeof(double) * pb_.P);
+      fcopy(g_, g, pb_.P);
       if (!std::isfinite(f)) {
         finish(BX_FAILED);
         return;
@@ -124,7 +148,7 @@ class Bfgs {
     }
     if (state_ == kInit) {
       f_ = f;
-      memcpy(g_, g, sizeof(double) * pb_.P);
+      fcopy(g_, g, pb_.P);
       if (!std::isfinite(f) || pb_.kind == BX_EVAL_GRAD || n == 0) {
         edm_ = std::isfinite(f) && n > 0 ? newton_dir(g_, x_, nullptr) : 0.0;
         finish(std::isfinite(f) ? BX_CONVERGED : BX_FAILED);
@@ -197,7 +221,7 @@ class Bfgs {
     set_trial();
   }
 
-  void result(bx_fit_result* r) const {
+  BX_FHD void result(bx_fit_result* r) const {
     r->status = status_;
     r->nll = f_;
     for (int q = 0; q < pb_.P; ++q) {
@@ -208,17 +232,17 @@ class Bfgs {
     r->n_iter = iter_;
     r->n_eval = n_eval_;
   }
-  bool done() const { return state_ == kDone; }
+  BX_FHD bool done() const { return state_ == kDone; }
 
  private:
   enum { kInit, kHess, kSearch, kDone, kReeval };
   static constexpr double kProbe = 1e-4;  // Hessian probe step (scaled units)
 
-  double lo_u(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
-  double hi_u(int a) const { return pb_.hi[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
+  BX_FHD double lo_u(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
+  BX_FHD double hi_u(int a) const { return pb_.hi[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
 
-  void set_probe() {
-    memcpy(xt_, x_, sizeof xt_);
+  BX_FHD void set_probe() {
+    fcopy(xt_, x_, 32);
     const int q = pb_.idx[hq_];
     double v = x_[q] / pb_.scale[q] + hsign_ * kProbe;
     if (v > hi_u(hq_) || v < lo_u(hq_)) {  // stay inside the box
@@ -231,7 +255,7 @@ class Bfgs {
   // Newton direction on the free set at point x with gradient g:
   // B_FF d_F = -g_F (Cholesky, shifted if needed); returns EDM = -g.d/2 and
   // writes d (scaled units, zero on held parameters) when d != nullptr.
-  double newton_dir(const double* g, const double* x, double* d) const {
+  BX_FHD double newton_dir(const double* g, const double* x, double* d) const {
     const int n = pb_.nf;
     int fr[32], m = 0;
     double gu[32];
@@ -247,7 +271,8 @@ class Bfgs {
     double dmax = 0.0;
     for (int i = 0; i < m; ++i) dmax = std::max(dmax, std::fabs(B_[fr[i] * n + fr[i]]));
     if (!(dmax > 0)) dmax = 1.0;
-    double L[32 * 32], shift = 0.0;
+    double* const L = L_;  // the factor (a member: no 8 KB array on a device thread's stack)
+    double shift = 0.0;
     for (int attempt = 0; attempt < 40; ++attempt) {
       bool ok = true;
       for (int j = 0; j < m && ok; ++j) {
@@ -286,7 +311,7 @@ class Bfgs {
     return -0.5 * gd;
   }
 
-  void start_iteration() {
+  BX_FHD void start_iteration() {
     const int n = pb_.nf;
     edm_ = newton_dir(g_, x_, d_);
     if (!(edm_ == edm_)) edm_ = INFINITY;
@@ -321,8 +346,8 @@ class Bfgs {
     set_trial();
   }
 
-  void set_trial() {
-    memcpy(xt_, x_, sizeof xt_);
+  BX_FHD void set_trial() {
+    fcopy(xt_, x_, 32);
     for (int a = 0; a < pb_.nf; ++a) {
       const int q = pb_.idx[a];
       double v = x_[q] / pb_.scale[q] + alpha_ * d_[a];
@@ -331,7 +356,7 @@ class Bfgs {
     }
   }
 
-  void accept(double f, const double* g) {
+  BX_FHD void accept(double f, const double* g) {
     const int n = pb_.nf;
     double s[32], y[32], sy = 0.0, Bs[32], sBs = 0.0;
     for (int a = 0; a < n; ++a) {
@@ -345,8 +370,8 @@ class Bfgs {
       for (int b = 0; b < n; ++b) Bs[a] += B_[a * n + b] * s[b];
       sBs += s[a] * Bs[a];
     }
-    memcpy(x_, xt_, sizeof x_);
-    memcpy(g_, g, sizeof(double) * pb_.P);
+    fcopy(x_, xt_, 32);
+    fcopy(g_, g, pb_.P);
     f_ = f;
     ++iter_;
     restarted_ = false;
@@ -358,7 +383,7 @@ class Bfgs {
     start_iteration();
   }
 
-  void finish(int st) {
+  BX_FHD void finish(int st) {
     status_ = st;
     state_ = kDone;
   }
@@ -369,7 +394,12 @@ class Bfgs {
   bool restarted_ = false;
   double hsign_ = 1.0;
   double x_[32], xt_[32], g_[32], d_[32], B_[32 * 32], Hs_[32 * 32];
+  mutable double L_[32 * 32];  // Cholesky factor of the free block of B
   double f_ = INFINITY, alpha_ = 1.0, slope_ = 0.0, edm_ = INFINITY;
 };
 
 }  // namespace bx
+
+#ifdef __clang__
+#pragma float_control(pop)
+#endif

@@ -45,6 +45,7 @@
 #include <type_traits>
 
 #include "bx_dev.h"
+#include "bx_fitcore.hpp"
 
 namespace bx {
 
@@ -133,6 +134,7 @@ constexpr int kCpLanes = 8;                      // lanes per column (half per e
 constexpr int kCpCountBlock = kCpLanes * kCpBlock;
 __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
   constexpr int NE = kCpLanes / 2;  // test points per end and round
   const int t = threadIdx.x, lane = t & 63, u = lane & (kCpLanes - 1);
@@ -263,6 +265,7 @@ __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev*
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
   const int i = blockIdx.x * kCpBlock + threadIdx.x;
   int jlo = 1 << 30, jhi = -1, bad = 0;
@@ -649,6 +652,7 @@ void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int
 // the domain flags).
 __global__ void __launch_bounds__(kBlock) k_table(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if ((int)blockIdx.x * kBlock >= f.N * kSP) return;  // block-uniform
   __shared__ double sth[kMaxP + 1];
@@ -730,6 +734,7 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   constexpr int NR = MV ? 4 : 1;
   typedef __attribute__((address_space(1))) const double GD;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int rt = blockIdx.x / f.n_fb, fb = blockIdx.x % f.n_fb;
   // block-uniform; a launch holds fits of one contraction kind only (a fit of
   // the other kind is left alone rather than written with the wrong layout)
@@ -926,6 +931,7 @@ __device__ __forceinline__ double m_sum(const FitDev& f, int j, int s) {
 // column is summed by k_rowterms as it stages the rows).
 __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= f.N * kSP || f.vsum) return;
   f.M[t] = m_sum(f, t >> 4, t & 15);
@@ -934,6 +940,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
 // 16 rows x 16 species per block.
 __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) double GDw;
@@ -1105,6 +1112,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
 // Radial term: nu_k = sum_s (1 - t_s) r_s (sum_{j in W} M'_js) rho_sk.
 __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if (!f.mv || f.n_rad <= 0 || f.joint) return;  // block-uniform
   __shared__ double part[16][kSP], partd[16][kSP], partt[16][kSP];
   __shared__ double SW[kSP], SD[kSP], ST[kSP], A[kSP], pgs[kSP], tgs[kSP], wr[128], red[kBlock];
@@ -1182,6 +1190,7 @@ __global__ void __launch_bounds__(kBlock) k_radial(const FitDev* fits, const int
 // H~ = P^T H_tot, H_tot = H + [j in W](1 - t_s) rho.w_s; 16 rows per block.
 __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
   __shared__ double Hl[16 + kMaxK - 1][kSP];
   const int j0 = blockIdx.x * 16;
@@ -1214,6 +1223,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 // backward sweep's own prologue (same bits).
 __global__ void __launch_bounds__(kBlock) k_adjoint1(const FitDev* fits, const int* active) {
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int j0 = blockIdx.x * 64;
   if (f.mv || j0 >= f.N) return;  // block-uniform
   __shared__ double hs[64 + kMaxK - 1], gl[kMaxK];
@@ -1265,6 +1275,7 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int2 cr = bwd_block(f.n_rg);
   const int ct = cr.x, rg = cr.y, bl = ct * f.n_rg + rg;
   if (ct >= f.n_ct || f.mv != (int)MV) return;  // block-uniform (one contraction kind per launch)
@@ -1500,6 +1511,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int rt = blockIdx.x / nsplit, sh = blockIdx.x % nsplit;
   // block-uniform; nothing left in this reco tile: its shares of Mfix are not read
   if (rt >= f.n_rt || f.vsum == (int)MV || (use_flags && ((GI*)f.fixflag)[rt] == 0)) return;
@@ -1611,6 +1623,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   const int ct = blockIdx.x;
   // block-uniform; nothing left in this true tile: its partials are not read
   if (ct >= f.n_ct || f.mv != (int)MV || (use_flags && ((GI*)f.fixflag)[f.n_rt + ct] == 0)) return;
@@ -1921,7 +1934,9 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
 }
 
 __global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
-  final_sums<1024>(fits[active ? active[blockIdx.y] : blockIdx.y], with_grad);
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
+  final_sums<1024>(f, with_grad);
 }
 
 // Joint energy x radius x pulse-shape term (the alternative to the additive
@@ -1948,6 +1963,7 @@ __global__ void __launch_bounds__(kJointBlock) k_joint(const FitDev* fits, const
   typedef __attribute__((address_space(1))) const int GI;
   typedef __attribute__((address_space(1))) const uint32_t GU;
   const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   if (!f.mv || !f.joint || (int)blockIdx.x * kJointRows >= f.N) return;  // block-uniform
   constexpr int NW = kJointBlock / 64;
   // rows of 18 doubles (144 B): lanes reading different radial or pulse-shape
@@ -2381,6 +2397,56 @@ __global__ void __launch_bounds__(kBlock) k_expected(const FitDev* fits, double*
 void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n_ps, hipStream_t st) {
   const int n = max(max(N, n_rad), N * n_ps);
   hipLaunchKernelGGL(k_expected, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d_fit, d_out);
+}
+
+// ---------------------------------------------------------------------------
+// Device-minimised batched fits (Sec. 4, steps 5-6 for many fits at once):
+// the minimiser of every fit runs on the device, one thread per fit, between
+// the evaluation launches of a captured graph, so that an iteration of all
+// the fits needs no host round trip.  The minimiser is the host's own code
+// (bx_fitcore.hpp, contraction off), so a fit takes the same steps as on the
+// plain path.
+__global__ void __launch_bounds__(64) k_fit_start(Bfgs* opts, FitSlot* slots, FitDev* fits, int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  FitDev& f = fits[slots[i].fit];
+  opts[i].next(const_cast<double*>(f.theta));
+}
+
+__global__ void k_zero_count(int* c) { *c = 0; }
+
+__global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, FitDev* fits, int n, int* count) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  Bfgs& o = opts[i];
+  FitSlot& sl = slots[i];
+  if (o.done()) return;
+  FitDev& f = fits[sl.phase ? sl.fit_p : sl.fit];
+  const double* out = f.out;
+  const int fl = (int)out[1 + sl.P];
+  const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
+  o.feed(bad ? INFINITY : out[0], out + 1);
+  if (o.done() && sl.fit_p >= 0 && sl.phase == 0 && o.polish(sl.final_tol, sl.noise_p)) {
+    f.skip = 1;  // on to the polishing placement (same theta and result rows)
+    sl.phase = 1;
+    fits[sl.fit_p].skip = 0;
+  }
+  FitDev& g = fits[sl.phase ? sl.fit_p : sl.fit];
+  if (o.done()) {
+    g.skip = 1;
+    return;
+  }
+  o.next(const_cast<double*>(g.theta));
+  atomicAdd(count, 1);
+}
+
+void launch_fit_start(void* opts, FitSlot* slots, FitDev* fits, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fit_start, dim3((n + 63) / 64), dim3(64), 0, st, (Bfgs*)opts, slots, fits, n);
+}
+
+void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, d_count);
+  hipLaunchKernelGGL(k_fit_step, dim3((n + 63) / 64), dim3(64), 0, st, (Bfgs*)opts, slots, fits, n, d_count);
 }
 
 }  // namespace bx

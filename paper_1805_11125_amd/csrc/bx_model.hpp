@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,31 @@ void derive_tiles(const HostModel& h, FitDev* f);
 bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t st, const FitDev* shared = nullptr);
 bx_status upload_data(const HostModel& h, const DeviceFit& df, hipStream_t st);
 LaunchShape shape_of(const FitDev& f);
+// Launch group of a placed fit: kind, precision, single histogram or several
+// (the sweeps' contraction differs, so the two never share a launch), and the
+// forward tiles per wave.
+constexpr int kGroups = 64;
+inline int group_of(const LaunchShape& l) {
+  int cgl = 0;
+  while ((1 << cgl) < l.CG) ++cgl;
+  return ((l.kind * 2 + l.prec) * 2 + l.any_mv) * 4 + cgl;
+}
+// The grid needs of a launch covering both shapes.
+inline void widen(LaunchShape* L, const LaunchShape& l) {
+  L->kind = l.kind;
+  L->prec = l.prec;
+  L->CG = l.CG;
+  L->max_T = std::max(L->max_T, l.max_T);
+  L->max_fwd_blocks = std::max(L->max_fwd_blocks, l.max_fwd_blocks);
+  L->max_NS = std::max(L->max_NS, l.max_NS);
+  L->max_rowblk = std::max(L->max_rowblk, l.max_rowblk);
+  L->max_bwd_blocks = std::max(L->max_bwd_blocks, l.max_bwd_blocks);
+  L->max_rt = std::max(L->max_rt, l.max_rt);
+  L->max_ct = std::max(L->max_ct, l.max_ct);
+  L->any_mv |= l.any_mv;
+  L->any_rad |= l.any_rad;
+  L->any_joint |= l.any_joint;
+}
 
 }  // namespace bx
 

@@ -95,8 +95,6 @@ static int64_t now_ns() {
 }
 
 constexpr int kThetaStride = 40;  // theta[P] and the step number, 5 cache lines
-constexpr int kGroups = 64;       // launch groups: 4 kinds x 2 precisions x (one histogram |
-                                  // several) x 4 forward tile widths
 constexpr int kOutStride = 40;    // nll, grad[P], flags, completion mark
 
 struct Req {
@@ -124,14 +122,7 @@ struct Req {
   bool polished = false;
 };
 
-// Launch group of a placed fit: kind, precision, single histogram or several
-// (the sweeps' contraction differs, so the two never share a launch), and the
-// forward tiles per wave.
-static int group_of(const LaunchShape& l) {
-  int cgl = 0;
-  while ((1 << cgl) < l.CG) ++cgl;
-  return ((l.kind * 2 + l.prec) * 2 + l.any_mv) * 4 + cgl;
-}
+
 
 }  // namespace bx
 
@@ -251,20 +242,7 @@ static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) 
     int* d_list = s->d_active + (size_t)grp * s->max_slots;
     for (auto& r : act) {
       if (r->group != grp) continue;
-      const LaunchShape& l = r->shape;
-      L.kind = l.kind;
-      L.prec = l.prec;
-      L.CG = l.CG;
-      L.max_T = std::max(L.max_T, l.max_T);
-      L.max_fwd_blocks = std::max(L.max_fwd_blocks, l.max_fwd_blocks);
-      L.max_NS = std::max(L.max_NS, l.max_NS);
-      L.max_rowblk = std::max(L.max_rowblk, l.max_rowblk);
-      L.max_bwd_blocks = std::max(L.max_bwd_blocks, l.max_bwd_blocks);
-      L.max_rt = std::max(L.max_rt, l.max_rt);
-      L.max_ct = std::max(L.max_ct, l.max_ct);
-      L.any_mv |= l.any_mv;
-      L.any_rad |= l.any_rad;
-      L.any_joint |= l.any_joint;
+      widen(&L, r->shape);
       act_list[n++] = r->slot;
     }
     if (!n) continue;

@@ -218,6 +218,46 @@ def test_mixed_precision_fits_batched_equal_plain(bx):
     print("mixed toy fits:", [(r.n_iter, r.n_eval, f"{r.edm:.1e}") for r in plain])
 
 
+def test_device_minimised_batch_equals_plain(bx):
+    # the minimisers on the device, one iteration of all the fits replayed as
+    # a graph: every fit ends exactly as on the plain path (FP32 fits, then
+    # mixed-precision fits that move to their FP64 placement mid-way)
+    toys = _toys(6, first=30)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+    pol = [bx.Model(d, x, precision=F64) for d, x, _ in toys]
+    x0s = [t.theta0 for _, _, t in toys]
+    masks = [d.float_mask for d, _, _ in toys]
+    for polish, tol in ((None, 1e-9), (pol, 1e-12)):
+        plain = [m.fit(x0, float_mask=mk, edm_tol=tol, max_iter=500, polish=None if polish is None else polish[i])
+                 for i, (m, x0, mk) in enumerate(zip(models, x0s, masks))]
+        bat = bx.fit_batch(models, x0s, masks, edm_tol=tol, max_iter=500, polish=polish, check_every=3)
+        for p, b in zip(plain, bat):
+            assert p.status == b.status and p.n_iter == b.n_iter and p.n_eval == b.n_eval
+            assert p.nll == b.nll and p.edm == b.edm and np.array_equal(p.x, b.x) and np.array_equal(p.grad, b.grad)
+        print("device-minimised:", [(b.status, b.n_eval, f"{b.edm:.1e}") for b in bat])
+
+
+def test_device_minimised_batch_of_mixed_kinds(bx):
+    # fits of several launch groups (Gaussian FP64, multivariate, generalized
+    # gamma FP32) in one batch
+    cases = [("c1", F64), ("c3a", F64), ("c2", F32), ("c1", F32)]
+    models, x0s, masks, ref = [], [], [], []
+    for name, prec in cases:
+        d, x = synth.load(name)
+        m = bx.Model(d, x, precision=prec)
+        z = np.random.default_rng(11).standard_normal(d.P)
+        x0 = d.theta_true * (1 + 0.03 * z)
+        mk = d.float_mask if d.float_mask is not None else np.ones(d.P, bool)
+        x0[~mk] = d.theta_true[~mk]
+        models.append(m)
+        x0s.append(x0)
+        masks.append(mk)
+        ref.append(m.fit(x0, float_mask=mk, edm_tol=1e-10, max_iter=500))
+    bat = bx.fit_batch(models, x0s, masks, edm_tol=1e-10, max_iter=500)
+    for (name, _), p, b in zip(cases, ref, bat):
+        assert p.n_eval == b.n_eval and p.nll == b.nll and np.array_equal(p.x, b.x), name
+
+
 def test_polish_model_must_match(bx):
     d, x = synth.load("c1")
     m = bx.Model(d, x, precision=F32)
