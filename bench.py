@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--toys", type=int, default=4096, help="batched toy fits to time (0 = skip)")
     ap.add_argument("--plain-toys", type=int, default=64, help="toys fitted on the plain path")
-    ap.add_argument("--edm", type=float, default=1e-8, help="toy fits stop at EDM below this")
+    ap.add_argument("--edm", type=float, default=1e-12, help="toy fits stop at EDM below this")
     ap.add_argument("--qps", type=str, default="10,30,100,300,1000", help="serving arrival rates ('' = skip)")
     ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--batch", type=int, default=512,
@@ -153,40 +153,58 @@ def cpu_baseline(timed):
 
 
 def toy_study(bx, synth, n_toys, n_plain, edm):
-    """Batched toy fits through the fit server vs the same toys fitted one
-    at a time through the plain path (histograms resident before timing)."""
+    """Toy study (config 4): ragged Poisson pseudo-experiments of the config-2
+    model, each fitted with FP32 cells until EDM < 1e-8 and then with its
+    FP64 model until EDM < edm (mixed precision).  Three ways: the device-
+    minimised batch (every fit's minimiser on the GPU, one iteration of all
+    fits replayed as a HIP graph), the fit server (continuous batching, host
+    minimisers), and the plain path one fit at a time (a sample).  Models and
+    histograms are resident before any timing starts."""
     base, per_species, theta = synth.catalogue()
+    t0 = time.perf_counter()
     toys = []
     for b in range(n_toys):
         t = synth.toy(b, per_species, theta)
         d = synth.toy_desc(base, t)
-        toys.append((bx.Model(d, synth.Data(energy=t.counts), precision=bx.BX_PREC_F32), d, t))
+        x = synth.Data(energy=t.counts)
+        toys.append((bx.Model(d, x, precision=bx.BX_PREC_F32), bx.Model(d, x, precision=bx.BX_PREC_F64), d, t))
+    build_s = time.perf_counter() - t0
+    m32 = [m for m, _, _, _ in toys]
+    m64 = [p for _, p, _, _ in toys]
+    x0s = [t.theta0 for _, _, _, t in toys]
+    masks = [d.float_mask for _, _, d, _ in toys]
+    t1 = time.perf_counter()
+    graph = bx.fit_batch(m32, x0s, masks, edm_tol=edm, max_iter=500, polish=m64)
+    el_g = time.perf_counter() - t1
     srv = bx.Server()
-    t0 = time.perf_counter()
-    tickets = [srv.submit(m, t.theta0, float_mask=d.float_mask, edm_tol=edm, max_iter=500)
-               for m, d, t in toys]
-    res = [srv.wait(k, sleep=2e-4) for k in tickets]
-    el = time.perf_counter() - t0
+    t2 = time.perf_counter()
+    tickets = [srv.submit(m, x0, float_mask=mk, edm_tol=edm, max_iter=500, polish=p)
+               for m, p, x0, mk in zip(m32, m64, x0s, masks)]
+    served = [srv.wait(k, sleep=2e-4) for k in tickets]
+    el_s = time.perf_counter() - t2
     srv.close()
     n_plain = min(n_plain, n_toys)
-    t1 = time.perf_counter()
-    plain = [m.fit(t.theta0, float_mask=d.float_mask, edm_tol=edm, max_iter=500)
-             for m, d, t in toys[:n_plain]]
-    el_p = time.perf_counter() - t1
-    same = all(np.array_equal(p.x, r.x) for p, r in zip(plain, res))
-    for m, _, _ in toys:
+    t3 = time.perf_counter()
+    plain = [m.fit(x0, float_mask=mk, edm_tol=edm, max_iter=500, polish=p)
+             for m, p, x0, mk in list(zip(m32, m64, x0s, masks))[:n_plain]]
+    el_p = time.perf_counter() - t3
+    same_g = all(np.array_equal(p.x, r.x) and p.nll == r.nll for p, r in zip(plain, graph))
+    same_s = all(np.array_equal(g.x, r.x) and g.nll == r.nll for g, r in zip(graph, served))
+    for m, p, _, _ in toys:
         m.close()
-    st = np.array([r.status for r in res])
-    # NLL+gradient evaluations the fits asked for, per second of wall time
-    ev_b = sum(r.n_eval for r in res) / el
-    ev_p = sum(r.n_eval for r in plain) / el_p
-    return {"toys": n_toys, "batched_fits_per_s": n_toys / el, "plain_fits_per_s": n_plain / el_p,
-            "batched_evals_per_s": ev_b, "plain_evals_per_s": ev_p,
-            "plain_sample": n_plain, "speedup": (n_toys / el) / (n_plain / el_p),
+        p.close()
+    st = np.array([r.status for r in graph])
+    n_eval = np.array([r.n_eval for r in graph])
+    return {"toys": n_toys, "edm_tol": edm, "precision": "FP32 cells, FP64 from EDM < 1e-8",
+            "device_minimised_fits_per_s": n_toys / el_g, "server_fits_per_s": n_toys / el_s,
+            "plain_fits_per_s": n_plain / el_p, "plain_sample": n_plain,
+            "speedup_device_vs_plain": (n_toys / el_g) / (n_plain / el_p),
+            "device_minimised_evals_per_s": float(n_eval.sum()) / el_g,
             "converged": int((st == bx.BX_CONVERGED).sum()),
-            "median_iters": float(np.median([r.n_iter for r in res])),
-            "median_evals": float(np.median([r.n_eval for r in res])),
-            "batched_equals_plain_bitwise": bool(same), "edm_tol": edm}
+            "median_iters": float(np.median([r.n_iter for r in graph])),
+            "median_evals": float(np.median(n_eval)), "max_evals": int(n_eval.max()),
+            "device_equals_plain_bitwise": bool(same_g), "server_equals_device_bitwise": bool(same_s),
+            "model_build_s": build_s}
 
 
 def config_leg(bx, synth, name, prec, steps, warmup, copies, check, timed):

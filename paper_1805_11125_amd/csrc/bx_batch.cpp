@@ -3,8 +3,12 @@
 // shared with its model, its own workspace, theta and result rows), and one
 // iteration of all of them -- the evaluation launches of every launch group,
 // then the minimisers' step kernel -- is captured as a HIP graph and replayed
-// until no fit is left running.  The host only checks the count of running
-// fits every few replays.  The minimiser is the plain path's (bx_fitcore.hpp,
+// until no fit is left running.  The host only checks which fits are still
+// running every few replays; when half of the fits in the graph have
+// finished, it captures the iteration again over the running ones (their
+// grids shrink with them, so the long tail of slow fits costs little).  A
+// mixed-precision fit whose first model is done waits (no evaluation) until
+// a capture puts its FP64 placement in the graph in place of the first one.  The minimiser is the plain path's (bx_fitcore.hpp,
 // compiled for the device with the same arithmetic), so every fit ends with
 // the plain path's result bit for bit.
 #include <hip/hip_runtime.h>
@@ -37,13 +41,16 @@ struct Batch {
   FitSlot* d_slots = nullptr;
   Bfgs* d_opts = nullptr;
   int* d_lists = nullptr;       // active lists of the launch groups
-  int* d_count = nullptr;
-  int* h_count = nullptr;       // pinned
+  int* d_count = nullptr;       // running fits, then their states [n]
+  int* h_count = nullptr;       // pinned copy of the same
+  int* d_ready = nullptr;       // [n]: the fit's polishing placement is in the graph
+  std::vector<int> h_ready;
   hipGraphExec_t exec = nullptr;
   ~Batch() {
     if (st) (void)hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
-    for (void* p : {(void*)d_fits, (void*)d_slots, (void*)d_opts, (void*)d_lists, (void*)d_count, (void*)rows, mem})
+    for (void* p : {(void*)d_fits, (void*)d_slots, (void*)d_opts, (void*)d_lists, (void*)d_count, (void*)d_ready,
+                    (void*)rows, mem})
       if (p) (void)hipFree(p);
     if (h_count) (void)hipHostFree(h_count);
     if (st) (void)hipStreamDestroy(st);
@@ -118,8 +125,10 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
       hipMalloc((void**)&b.d_fits, sizeof(FitDev) * npl) != hipSuccess ||
       hipMalloc((void**)&b.d_slots, sizeof(FitSlot) * n) != hipSuccess ||
       hipMalloc((void**)&b.d_opts, sizeof(Bfgs) * n) != hipSuccess ||
-      hipMalloc((void**)&b.d_lists, sizeof(int) * npl) != hipSuccess || hipMalloc((void**)&b.d_count, sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&b.h_count, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      hipMalloc((void**)&b.d_lists, sizeof(int) * npl) != hipSuccess ||
+      hipMalloc((void**)&b.d_count, sizeof(int) * (1 + n)) != hipSuccess ||
+      hipMalloc((void**)&b.d_ready, sizeof(int) * n) != hipSuccess ||
+      hipHostMalloc((void**)&b.h_count, sizeof(int) * (1 + n), hipHostMallocDefault) != hipSuccess) {
     set_error("device memory for the batch could not be allocated");
     return BX_E_NOMEM;
   }
@@ -146,52 +155,85 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
       grp[k] = group_of(shp[k]);
     }
   }
-  // launch groups: each lists its placements (fixed for the whole batch)
-  std::vector<int> lists;
-  struct G {
-    int first, count;
-    LaunchShape L;
-  };
-  std::vector<G> groups;
-  for (int g = 0; g < kGroups; ++g) {
-    G e{(int)lists.size(), 0, LaunchShape{}};
-    for (int k = 0; k < npl; ++k)
-      if (grp[k] == g) {
-        lists.push_back(k);
-        widen(&e.L, shp[k]);
-        ++e.count;
-      }
-    if (e.count) groups.push_back(e);
-  }
   hipError_t e = hipMemcpyAsync(b.d_fits, fd.data(), sizeof(FitDev) * npl, hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipMemcpyAsync(b.d_slots, slot.data(), sizeof(FitSlot) * n, hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipMemcpyAsync(b.d_opts, opt.data(), sizeof(Bfgs) * n, hipMemcpyHostToDevice, b.st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b.d_lists, lists.data(), sizeof(int) * npl, hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipStreamSynchronize(b.st);  // the host arrays above are temporaries
   if (e != hipSuccess) return hip_fail(e, "batch upload");
   for (int i = 0; i < n; ++i) results[i] = bx_fit_result{};
-  // every fit's first point, then one iteration of all of them as a graph
-  launch_fit_start(b.d_opts, b.d_slots, b.d_fits, n, b.st);
-  hipGraph_t graph;
-  e = hipStreamBeginCapture(b.st, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "graph capture");
-  for (const G& g : groups) launch_eval(b.d_fits, b.d_lists + g.first, g.count, g.L, true, b.st);
-  launch_fit_step(b.d_opts, b.d_slots, b.d_fits, n, b.d_count, b.st);
-  e = hipStreamEndCapture(b.st, &graph);
-  if (e != hipSuccess) return hip_fail(e, "graph capture");
-  e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  launch_fit_start(b.d_opts, b.d_slots, b.d_fits, n, b.st);  // every fit's first point
+  // One iteration of the running fits as a graph: each launch group lists
+  // the placement each fit evaluates now (state 1: its first model; 2 or 3:
+  // its polishing model, which a waiting fit moves to at its next step).
+  std::vector<int> lists, state(n, 1), cur;
+  auto capture = [&]() -> bx_status {
+    cur.clear();
+    b.h_ready.assign(n, 0);
+    for (int i = 0; i < n; ++i)
+      if (state[i]) {
+        cur.push_back(i);
+        b.h_ready[i] = state[i] >= 2;
+      }
+    struct G {
+      int first, count;
+      LaunchShape L;
+    };
+    std::vector<G> groups;
+    lists.clear();
+    for (int g = 0; g < kGroups; ++g) {
+      G gr{(int)lists.size(), 0, LaunchShape{}};
+      for (int i : cur) {
+        const int k = state[i] >= 2 ? slot[i].fit_p : i;
+        if (grp[k] == g) {
+          lists.push_back(k);
+          widen(&gr.L, shp[k]);
+          ++gr.count;
+        }
+      }
+      if (gr.count) groups.push_back(gr);
+    }
+    hipError_t er = hipMemcpyAsync(b.d_lists, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, b.st);
+    if (er == hipSuccess) er = hipMemcpyAsync(b.d_ready, b.h_ready.data(), sizeof(int) * n, hipMemcpyHostToDevice, b.st);
+    if (er == hipSuccess) er = hipStreamSynchronize(b.st);  // the host arrays are rewritten by the next capture
+    if (er != hipSuccess) return hip_fail(er, "batch lists");
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    b.exec = nullptr;
+    hipGraph_t graph;
+    er = hipStreamBeginCapture(b.st, hipStreamCaptureModeThreadLocal);
+    if (er != hipSuccess) return hip_fail(er, "graph capture");
+    for (const G& g : groups) launch_eval(b.d_fits, b.d_lists + g.first, g.count, g.L, true, b.st);
+    launch_fit_step(b.d_opts, b.d_slots, b.d_fits, n, b.d_count, b.d_count + 1, b.d_ready, b.st);
+    er = hipStreamEndCapture(b.st, &graph);
+    if (er != hipSuccess) return hip_fail(er, "graph capture");
+    er = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (er != hipSuccess) return hip_fail(er, "graph instantiate");
+    return BX_OK;
+  };
+  bx_status cs = capture();
+  if (cs != BX_OK) return cs;
   // replay until no fit is running (every fit ends within its evaluation
-  // budget, one evaluation per iteration)
+  // budget, one evaluation per iteration, and waits for its polishing
+  // placement for fewer iterations than another fit runs)
   const int64_t t_start = now_ns();
   int steps = 0;
-  for (bool running = true; running && steps <= max_eval + 1;) {
+  for (bool running = true; running && steps <= 2 * max_eval + 4 * K + 8;) {
     for (int k = 0; k < K && e == hipSuccess; ++k, ++steps) e = hipGraphLaunch(b.exec, b.st);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.h_count, b.d_count, sizeof(int), hipMemcpyDeviceToHost, b.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.h_count, b.d_count, sizeof(int) * (1 + n), hipMemcpyDeviceToHost, b.st);
     if (e == hipSuccess) e = hipStreamSynchronize(b.st);
     if (e != hipSuccess) return hip_fail(e, "batch iteration");
-    running = *b.h_count > 0;
+    const int left = *b.h_count;
+    running = left > 0;
+    int waiting = 0;
+    for (int i : cur) waiting += b.h_count[1 + i] == 2;
+    // capture again when half of the graph's fits are done (their grids go),
+    // or when an eighth of them (or all that run) wait for their polishing
+    // placement
+    const int nc = (int)cur.size();
+    if (running && (2 * left <= nc || 8 * waiting >= nc || waiting == left)) {
+      for (int i = 0; i < n; ++i) state[i] = b.h_count[1 + i];
+      if ((cs = capture()) != BX_OK) return cs;
+    }
   }
   e = hipMemcpyAsync(opt.data(), b.d_opts, sizeof(Bfgs) * n, hipMemcpyDeviceToHost, b.st);
   if (e == hipSuccess) e = hipStreamSynchronize(b.st);

@@ -175,9 +175,13 @@ struct FitSlot {
 // names its first point (theta rows); step: hands each unfinished fit the
 // results of its last evaluation, moves it to its polishing placement when
 // the first model is done, names its next point, and counts the fits still
-// running into *d_count (zeroed in the same launch sequence).
+// running into *d_count (zeroed in the same launch sequence) and their state
+// into d_running[n] (0 finished, 1 first model, 2 waiting for its polishing
+// placement, 3 polishing model).  A fit whose first model is done moves on
+// only when d_ready[i] says its polishing placement is in the graph.
 void launch_fit_start(void* opts, FitSlot* slots, FitDev* fits, int n, hipStream_t st);
-void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, hipStream_t st);
+void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, int* d_running,
+                     const int* d_ready, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
 void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
 void launch_cell_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,

@@ -117,7 +117,7 @@ class Bfgs {
   // the iterations continue with the same Hessian approximation until
   // EDM < edm_tol.  Only after a finished fit that did not run out of budget.
   BX_FHD bool polish(double edm_tol, double f_noise) {
-    if (state_ != kDone || pb_.kind != BX_FIT || status_ == BX_MAXITER || !std::isfinite(f_)) return false;
+    if (!can_polish()) return false;
     pb_.edm_tol = edm_tol;
     pb_.f_noise = f_noise;
     state_ = kReeval;
@@ -128,6 +128,10 @@ class Bfgs {
     return true;
   }
   BX_FHD int status() const { return status_; }
+  // polish() would go on (a finished fit that can move to another model)
+  BX_FHD bool can_polish() const {
+    return state_ == kDone && pb_.kind == BX_FIT && status_ != BX_MAXITER && std::isfinite(f_);
+  }
 
   BX_FHD void feed(double f, const double* g) {
     ++n_eval_;
@@ -257,8 +261,9 @@ class Bfgs {
   // writes d (scaled units, zero on held parameters) when d != nullptr.
   BX_FHD double newton_dir(const double* g, const double* x, double* d) const {
     const int n = pb_.nf;
-    int fr[32], m = 0;
-    double gu[32];
+    int* const fr = wi_;  // work arrays are members: on the device they live with the state in LDS
+    double* const gu = wa_;
+    int m = 0;
     for (int a = 0; a < n; ++a) {
       const int q = pb_.idx[a];
       gu[a] = g[q] * pb_.scale[q];
@@ -292,7 +297,8 @@ class Bfgs {
       if (ok) break;
       shift = shift > 0 ? 4.0 * shift : 1e-10 * dmax;
     }
-    double y[32], dd[32];
+    double* const y = wb_;
+    double* const dd = wc_;
     for (int i = 0; i < m; ++i) {  // L y = -g
       double t = -gu[fr[i]];
       for (int k = 0; k < i; ++k) t -= L[i * m + k] * y[k];
@@ -358,7 +364,10 @@ class Bfgs {
 
   BX_FHD void accept(double f, const double* g) {
     const int n = pb_.nf;
-    double s[32], y[32], sy = 0.0, Bs[32], sBs = 0.0;
+    double* const s = wa_;
+    double* const y = wb_;
+    double* const Bs = wc_;
+    double sy = 0.0, sBs = 0.0;
     for (int a = 0; a < n; ++a) {
       const int q = pb_.idx[a];
       s[a] = (xt_[q] - x_[q]) / pb_.scale[q];
@@ -395,6 +404,8 @@ class Bfgs {
   double hsign_ = 1.0;
   double x_[32], xt_[32], g_[32], d_[32], B_[32 * 32], Hs_[32 * 32];
   mutable double L_[32 * 32];  // Cholesky factor of the free block of B
+  mutable double wa_[32], wb_[32], wc_[32];  // work vectors of newton_dir and accept
+  mutable int wi_[32];
   double f_ = INFINITY, alpha_ = 1.0, slope_ = 0.0, edm_ = INFINITY;
 };
 

@@ -2415,38 +2415,81 @@ __global__ void __launch_bounds__(64) k_fit_start(Bfgs* opts, FitSlot* slots, Fi
 
 __global__ void k_zero_count(int* c) { *c = 0; }
 
-__global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, FitDev* fits, int n, int* count) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
+// running[i]: 0 finished, 1 on its first model, 2 waiting for its polishing
+// placement to join the graph, 3 on the polishing model.  ready[i]: the
+// polishing placement is in the graph now.  One block (one wave) per fit:
+// the minimiser state is staged in LDS by the whole wave, one lane runs the
+// step on it (its Cholesky and BFGS updates then read LDS, not scattered
+// global memory), and the wave writes it back.
+__global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, FitDev* fits, int n, int* count,
+                                                 int* running, const int* ready) {
+  const int i = blockIdx.x;
   if (i >= n) return;
-  Bfgs& o = opts[i];
-  FitSlot& sl = slots[i];
-  if (o.done()) return;
-  FitDev& f = fits[sl.phase ? sl.fit_p : sl.fit];
-  const double* out = f.out;
-  const int fl = (int)out[1 + sl.P];
-  const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
-  o.feed(bad ? INFINITY : out[0], out + 1);
-  if (o.done() && sl.fit_p >= 0 && sl.phase == 0 && o.polish(sl.final_tol, sl.noise_p)) {
-    f.skip = 1;  // on to the polishing placement (same theta and result rows)
-    sl.phase = 1;
-    fits[sl.fit_p].skip = 0;
+  constexpr int kWords = (int)(sizeof(Bfgs) / sizeof(double));
+  static_assert(sizeof(Bfgs) % sizeof(double) == 0, "minimiser state in whole words");
+  __shared__ int go;
+  __shared__ __align__(16) double sw[kWords];  // the fit's minimiser (raw words: no constructor runs)
+  Bfgs& sb = *reinterpret_cast<Bfgs*>(sw);
+  if (threadIdx.x == 0) {
+    const Bfgs& o = opts[i];
+    const FitSlot& sl = slots[i];
+    go = !o.done() || (sl.fit_p >= 0 && sl.phase == 0 && o.can_polish());
+    if (!go) running[i] = 0;
   }
-  FitDev& g = fits[sl.phase ? sl.fit_p : sl.fit];
-  if (o.done()) {
-    g.skip = 1;
-    return;
+  __syncthreads();
+  if (!go) return;  // block-uniform: a finished fit
+  double* const gw = reinterpret_cast<double*>(opts + i);
+  for (int w = threadIdx.x; w < kWords; w += 64) sw[w] = gw[w];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Bfgs& o = sb;
+    FitSlot& sl = slots[i];
+    running[i] = 0;
+    const bool waiting = o.done();  // only a fit about to move to its polishing model gets here done
+    if (!waiting) {  // the results of the last evaluation
+      const FitDev& f = fits[sl.phase ? sl.fit_p : sl.fit];
+      const double* out = f.out;
+      const int fl = (int)out[1 + sl.P];
+      const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
+      o.feed(bad ? INFINITY : out[0], out + 1);
+    }
+    bool held = false;
+    if (o.done() && sl.fit_p >= 0 && sl.phase == 0 && o.can_polish()) {
+      fits[sl.fit].skip = 1;
+      if (!ready[i]) {  // wait (no evaluation) until the host adds the FP64 placement
+        running[i] = 2;
+        atomicAdd(count, 1);
+        held = true;
+      } else {
+        o.polish(sl.final_tol, sl.noise_p);  // on to the polishing placement (same theta and result rows)
+        sl.phase = 1;
+        fits[sl.fit_p].skip = 0;
+      }
+    }
+    if (!held) {
+      FitDev& g = fits[sl.phase ? sl.fit_p : sl.fit];
+      if (o.done()) {
+        g.skip = 1;
+      } else {
+        o.next(const_cast<double*>(g.theta));
+        running[i] = 1 + 2 * sl.phase;
+        atomicAdd(count, 1);
+      }
+    }
   }
-  o.next(const_cast<double*>(g.theta));
-  atomicAdd(count, 1);
+  __syncthreads();
+  for (int w = threadIdx.x; w < kWords; w += 64) gw[w] = sw[w];
 }
 
 void launch_fit_start(void* opts, FitSlot* slots, FitDev* fits, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_fit_start, dim3((n + 63) / 64), dim3(64), 0, st, (Bfgs*)opts, slots, fits, n);
 }
 
-void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, hipStream_t st) {
+void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, int* d_running,
+                     const int* d_ready, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, d_count);
-  hipLaunchKernelGGL(k_fit_step, dim3((n + 63) / 64), dim3(64), 0, st, (Bfgs*)opts, slots, fits, n, d_count);
+  hipLaunchKernelGGL(k_fit_step, dim3(n), dim3(64), 0, st, (Bfgs*)opts, slots, fits, n, d_count, d_running,
+                     d_ready);
 }
 
 }  // namespace bx
