@@ -1,18 +1,22 @@
 """Tile autotuner for the cell sweeps.
 
-For each shape class it builds a representative model, times every candidate
-number of true tiles per forward wave (CG) on the device, once for a fit
-evaluated alone (whole-evaluation time of the back-to-back stage launches,
+For each shape class it builds a representative model and times every
+candidate pair of true tiles per forward wave (CG) and reco tiles per
+backward wave (RG) on the device, once for a fit evaluated alone
+(whole-evaluation time of the back-to-back stage launches,
 `bx_model_stage_times`) and once for a batch of resident fits
-(`bx_model_batch_times`, time per fit), and writes the table the library
+(`bx_model_batch_times`, time per fit).  It writes the table the library
 reads at model build and at admission to the fit server (BX_TUNE_CACHE):
 
     kind prec Tmin Tmax Nmin Nmax batched CG RG
 
 CG changes no result bit (the forward partials are summed in a fixed tree),
-so the two modes may differ; RG (reco tiles per backward wave) groups the
-backward partials, so it is kept at 1 in both modes and a fit gives the same
-bits alone and in the server.
+so the two modes take their own best CG.  RG groups the backward partials, so
+both modes share one RG (a fit gives the same bits alone and in a batch): the
+one whose best times, alone and batched, are together the least above the
+best of each mode.  The block sizes (waves per forward and backward
+workgroup, fits per workgroup = 1) are compile-time constants of the kernels,
+chosen by the measurements recorded with them.
 
     python -m paper_1805_11125_amd.tune --out paper_1805_11125_amd/tiles_mi355x.txt
 """
@@ -22,11 +26,12 @@ import sys
 
 import numpy as np
 
-CANDIDATES = (1, 2, 4, 8)
+CANDIDATES = (1, 2, 4, 8)      # CG
+RG_CANDIDATES = (1, 2, 4)      # RG
 
 
-def _time(bx, desc, data, prec, theta, cg, copies):
-    os.environ["BX_TILES"] = f"{cg},1"
+def _time(bx, desc, data, prec, theta, cg, rg, copies):
+    os.environ["BX_TILES"] = f"{cg},{rg}"
     try:
         m = bx.Model(desc, data, precision=prec)
         single = m.stage_times(theta, reps=100)["total"]
@@ -43,13 +48,21 @@ def tune(classes, copies=128, log=print):
     import paper_1805_11125_amd as bx
     lines = []
     for kind, prec, tmin, tmax, nmin, nmax, desc, data, theta in classes:
-        res = {cg: _time(bx, desc, data, prec, theta, cg, copies) for cg in CANDIDATES}
+        res = {(cg, rg): _time(bx, desc, data, prec, theta, cg, rg, copies)
+               for rg in RG_CANDIDATES for cg in CANDIDATES}
+        best_mode = [min(v[mode] for v in res.values()) for mode in (0, 1)]
+
+        def cost(rg):  # relative excess over each mode's best, at the best CG for this RG
+            return sum(min(res[(cg, rg)][mode] for cg in CANDIDATES) / best_mode[mode] for mode in (0, 1))
+
+        rg = min(RG_CANDIDATES, key=cost)
         for batched in (0, 1):
-            best = min(CANDIDATES, key=lambda cg: res[cg][batched])
-            lines.append(f"{kind} {prec} {tmin} {tmax} {nmin} {nmax} {batched} {best} 1")
+            cg = min(CANDIDATES, key=lambda c: res[(c, rg)][batched])
+            lines.append(f"{kind} {prec} {tmin} {tmax} {nmin} {nmax} {batched} {cg} {rg}")
             log(f"class kind={kind} prec={prec} T=[{tmin},{tmax}] N=[{nmin},{nmax}] "
                 f"{'batched' if batched else 'single'}: " +
-                " ".join(f"CG{cg}={res[cg][batched] * 1e3:.2f}us" for cg in CANDIDATES) + f" -> CG {best}")
+                " ".join(f"CG{c}/RG{r}={res[(c, r)][batched] * 1e3:.2f}us" for r in RG_CANDIDATES
+                         for c in CANDIDATES) + f" -> CG {cg} RG {rg}")
     return lines
 
 
