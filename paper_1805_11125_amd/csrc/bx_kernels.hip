@@ -81,8 +81,22 @@ template <> struct Pair<double> { typedef double2 T; };
 // its own L2.  The backward sweep gives true tile ct to XCD ct % 8 with all
 // of its blocks: the tile's column parameters are fetched into one L2, and
 // neighbouring tiles (similar work) are spread over all eight.
-__device__ __forceinline__ int2 bwd_block(int n_rg) {
-  const int b = blockIdx.x, q = b >> 3;
+// (block, fit) of this workgroup.  A batch (gridDim.y = fits, a multiple of
+// 8) is remapped so that every block of a fit runs on one XCD: the hardware
+// deals workgroups to the 8 XCDs round-robin by linear id, and each XCD has
+// its own L2, so a fit's column constants, row tables and partials are then
+// fetched into one L2 instead of eight.  A single fit keeps the grid as is
+// (spread over every XCD).
+__device__ __forceinline__ int2 fit_block() {
+  const int X = gridDim.x, n = gridDim.y;
+  if (n < 8 || (n & 7)) return make_int2(blockIdx.x, blockIdx.y);
+  const int L = blockIdx.x + blockIdx.y * X;  // linear workgroup id
+  const int s = L >> 3;                       // slot on XCD L % 8
+  return make_int2(s % X, 8 * (s / X) + (L & 7));
+}
+
+__device__ __forceinline__ int2 bwd_block(int b, int n_rg) {
+  const int q = b >> 3;
   return make_int2((b & 7) + 8 * (q / n_rg), q % n_rg);  // (ct, rg)
 }
 
@@ -264,10 +278,11 @@ __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev*
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  if ((int)blockIdx.x >= f.n_cpblk) return;  // block-uniform
-  const int i = blockIdx.x * kCpBlock + threadIdx.x;
+  if (fb2.x >= f.n_cpblk) return;  // block-uniform
+  const int i = fb2.x * kCpBlock + threadIdx.x;
   int jlo = 1 << 30, jhi = -1, bad = 0;
   // output pointers and T read before the first store (a store through a
   // generic pointer could alias f and force reloads after it)
@@ -293,7 +308,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
     if ((int)threadIdx.x <= f.P) {
       const double v = __hip_atomic_load(f.theta_src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       sth[threadIdx.x] = v;
-      if (blockIdx.x == 0) const_cast<double*>(f.theta)[threadIdx.x] = v;
+      if (fb2.x == 0) const_cast<double*>(f.theta)[threadIdx.x] = v;
     }
     __syncthreads();
     th = sth;
@@ -417,7 +432,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   }
   if ((threadIdx.x & 15) == 0 && i < T) tbo[i >> 4] = make_int2(jlo, jhi);
   for (int m = 32; m >= 1; m >>= 1) bad |= __shfl_xor(bad, m, 64);
-  if (threadIdx.x == 0) cpflag[blockIdx.x] = bad;
+  if (threadIdx.x == 0) cpflag[fb2.x] = bad;
 }
 
 // A column's constants as one lane holds them in the sweeps.
@@ -733,9 +748,10 @@ __global__ void __launch_bounds__(kFwdWaves * 64) k_cells_fwd(const FitDev* fits
   typedef typename std::conditional<MV, v4d, double>::type V;
   constexpr int NR = MV ? 4 : 1;
   typedef __attribute__((address_space(1))) const double GD;
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int rt = blockIdx.x / f.n_fb, fb = blockIdx.x % f.n_fb;
+  const int rt = fb2.x / f.n_fb, fb = fb2.x % f.n_fb;
   // block-uniform; a launch holds fits of one contraction kind only (a fit of
   // the other kind is left alone rather than written with the wrong layout)
   if (rt >= f.n_rt || f.vsum == (int)MV) return;
@@ -939,9 +955,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
 
 // 16 rows x 16 species per block.
 __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  if ((int)blockIdx.x >= f.n_rowblk) return;  // block-uniform
+  if (fb2.x >= f.n_rowblk) return;  // block-uniform
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) double GDw;
   typedef __attribute__((address_space(1))) int GIw;
@@ -976,7 +993,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   __shared__ int redf[kBlock];
   __shared__ double wps[16][64];
   const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
-  const int j0 = blockIdx.x * 16;
+  const int j0 = fb2.x * 16;
   const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, N);
   // M rows [r0, r1) staged in LDS for the pile-up sums (a single histogram's
   // column summed here from the forward partials)
@@ -1076,8 +1093,8 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    nllpart[blockIdx.x] = red[0];
-    flagpart[blockIdx.x] = redf[0];
+    nllpart[fb2.x] = red[0];
+    flagpart[fb2.x] = redf[0];
   }
   __syncthreads();
   red[threadIdx.x] = (jok && s < S) ? h * m : 0.0;
@@ -1085,7 +1102,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   if (threadIdx.x < 16) {
     double a = 0.0;
     for (int r = 0; r < 16; ++r) a += red[r * 16 + threadIdx.x];
-    gpart[blockIdx.x * kSP + threadIdx.x] = a;
+    gpart[fb2.x * kSP + threadIdx.x] = a;
   }
   if (pu_float) {  // block-uniform: dNLL/dp without the radial part, sum_js H_js r_s dM'_js/dp
     __syncthreads();
@@ -1095,7 +1112,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) ppart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) ppart[fb2.x] = red[0];
   }
   if (tab) {  // block-uniform: dNLL/dlam without the radial part, sum_js H_js r_s dM'_js/dlam
     __syncthreads();
@@ -1105,7 +1122,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) tpart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) tpart[fb2.x] = red[0];
   }
 }
 
@@ -1222,9 +1239,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const FitDev* fits, const in
 // same order and with the same explicit fused multiply-adds as in the
 // backward sweep's own prologue (same bits).
 __global__ void __launch_bounds__(kBlock) k_adjoint1(const FitDev* fits, const int* active) {
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int j0 = blockIdx.x * 64;
+  const int j0 = fb2.x * 64;
   if (f.mv || j0 >= f.N) return;  // block-uniform
   __shared__ double hs[64 + kMaxK - 1], gl[kMaxK];
   const int K = pu_len(f);
@@ -1274,9 +1292,10 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
   constexpr int kRows = kBwdWaves * kMaxRG * kRowStep;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int2 cr = bwd_block(f.n_rg);
+  const int2 cr = bwd_block(fb2.x, f.n_rg);
   const int ct = cr.x, rg = cr.y, bl = ct * f.n_rg + rg;
   if (ct >= f.n_ct || f.mv != (int)MV) return;  // block-uniform (one contraction kind per launch)
   __shared__ double colA[kBwdWaves][16], colB[kBwdWaves][16], colU[kBwdWaves][16];
@@ -1510,9 +1529,10 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
   constexpr int NR = MV ? 4 : 1;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int rt = blockIdx.x / nsplit, sh = blockIdx.x % nsplit;
+  const int rt = fb2.x / nsplit, sh = fb2.x % nsplit;
   // block-uniform; nothing left in this reco tile: its shares of Mfix are not read
   if (rt >= f.n_rt || f.vsum == (int)MV || (use_flags && ((GI*)f.fixflag)[rt] == 0)) return;
   __shared__ int list[NTH], wcount[NW];
@@ -1622,9 +1642,10 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   constexpr int NW = kFixWaves, NTH = NW * 64;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
   if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int ct = blockIdx.x;
+  const int ct = fb2.x;
   // block-uniform; nothing left in this true tile: its partials are not read
   if (ct >= f.n_ct || f.mv != (int)MV || (use_flags && ((GI*)f.fixflag)[f.n_rt + ct] == 0)) return;
   __shared__ int list[NTH], wcount[NW];
