@@ -122,10 +122,10 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
       if (m && m->last_stream && hipStreamSynchronize(m->last_stream) != hipSuccess)
         return hip_fail(hipErrorUnknown, "model stream");
   if (hipMalloc(&b.mem, bytes) != hipSuccess || hipMalloc((void**)&b.rows, sizeof(double) * 2 * kRow * n) != hipSuccess ||
-      hipMalloc((void**)&b.d_fits, sizeof(FitDev) * npl) != hipSuccess ||
+      hipMalloc((void**)&b.d_fits, sizeof(FitDev) * (npl + 1)) != hipSuccess ||
       hipMalloc((void**)&b.d_slots, sizeof(FitSlot) * n) != hipSuccess ||
       hipMalloc((void**)&b.d_opts, sizeof(Bfgs) * n) != hipSuccess ||
-      hipMalloc((void**)&b.d_lists, sizeof(int) * npl) != hipSuccess ||
+      hipMalloc((void**)&b.d_lists, sizeof(int) * (npl + 8 * kGroups)) != hipSuccess ||
       hipMalloc((void**)&b.d_count, sizeof(int) * (1 + n)) != hipSuccess ||
       hipMalloc((void**)&b.d_ready, sizeof(int) * n) != hipSuccess ||
       hipHostMalloc((void**)&b.h_count, sizeof(int) * (1 + n), hipHostMallocDefault) != hipSuccess) {
@@ -133,7 +133,7 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
     return BX_E_NOMEM;
   }
   // placements: theta and result rows per fit, shared by its two placements
-  std::vector<FitDev> fd(npl);
+  std::vector<FitDev> fd(npl + 1);  // + one that never runs: the padding of the launch lists
   std::vector<int> grp(npl);
   std::vector<LaunchShape> shp(npl);
   for (int i = 0; i < n; ++i) {
@@ -155,7 +155,9 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
       grp[k] = group_of(shp[k]);
     }
   }
-  hipError_t e = hipMemcpyAsync(b.d_fits, fd.data(), sizeof(FitDev) * npl, hipMemcpyHostToDevice, b.st);
+  fd[npl] = fd[0];
+  fd[npl].skip = 1;
+  hipError_t e = hipMemcpyAsync(b.d_fits, fd.data(), sizeof(FitDev) * (npl + 1), hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipMemcpyAsync(b.d_slots, slot.data(), sizeof(FitSlot) * n, hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipMemcpyAsync(b.d_opts, opt.data(), sizeof(Bfgs) * n, hipMemcpyHostToDevice, b.st);
   if (e == hipSuccess) e = hipStreamSynchronize(b.st);  // the host arrays above are temporaries
@@ -189,6 +191,12 @@ extern "C" bx_status bx_fit_batch(bx_model* const* models, const bx_fit_opts* op
           widen(&gr.L, shp[k]);
           ++gr.count;
         }
+      }
+      // a multiple of 8 fits: the kernels then keep each fit's blocks on one
+      // XCD (a group of a few fits stays spread over all of them)
+      while (gr.count >= 64 && (gr.count & 7)) {
+        lists.push_back(npl);
+        ++gr.count;
       }
       if (gr.count) groups.push_back(gr);
     }
