@@ -133,8 +133,8 @@ struct bx_server {
   int max_slots = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  FitDev* d_fits = nullptr;       // [max_slots]
-  int* d_active = nullptr;        // [kGroups][max_slots] active lists, one region per launch group
+  FitDev* d_fits = nullptr;       // [max_slots + 1]: the last one never runs (list padding)
+  int* d_active = nullptr;        // [kGroups][max_slots + 8] active lists, one region per launch group
   double* d_theta = nullptr;      // [max_slots][kThetaStride] device copies of theta
   double* d_out = nullptr;        // [max_slots][kOutStride]
   // pinned, coherent: theta and the step number written by the host and read
@@ -238,14 +238,17 @@ static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) 
   for (int grp = 0; grp < kGroups; ++grp) {
     int n = 0;
     LaunchShape L{};
-    int* act_list = s->h_active + (size_t)grp * s->max_slots;  // each group stages its own list
-    int* d_list = s->d_active + (size_t)grp * s->max_slots;
+    int* act_list = s->h_active + (size_t)grp * (s->max_slots + 8);  // each group stages its own list
+    int* d_list = s->d_active + (size_t)grp * (s->max_slots + 8);
     for (auto& r : act) {
       if (r->group != grp) continue;
       widen(&L, r->shape);
       act_list[n++] = r->slot;
     }
     if (!n) continue;
+    // a multiple of 8 fits (the slot past the last never runs): the kernels
+    // then keep each fit's blocks on one XCD
+    while (n >= 64 && (n & 7)) act_list[n++] = s->max_slots;
     (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
     launch_eval(s->d_fits, d_list, n, L, true, s->stream);
   }
@@ -362,13 +365,14 @@ bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip
     s->own_stream = true;
   }
   const size_t M = s->max_slots;
-  if (hipMalloc(&s->d_fits, sizeof(FitDev) * M) != hipSuccess || hipMalloc(&s->d_active, sizeof(int) * kGroups * M) != hipSuccess ||
+  if (hipMalloc(&s->d_fits, sizeof(FitDev) * (M + 1)) != hipSuccess ||
+      hipMalloc(&s->d_active, sizeof(int) * kGroups * (M + 8)) != hipSuccess ||
       hipMalloc(&s->d_theta, sizeof(double) * kThetaStride * M) != hipSuccess ||
       hipMalloc(&s->d_out, sizeof(double) * kOutStride * M) != hipSuccess ||
       hipHostMalloc((void**)&s->h_theta, sizeof(double) * kThetaStride * M, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutStride * M, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void**)&s->h_mark, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_active, sizeof(int) * kGroups * M, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_active, sizeof(int) * kGroups * (M + 8), hipHostMallocDefault) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->dh_theta, s->h_theta, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->dh_out, s->h_out, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->dh_mark, s->h_mark, 0) != hipSuccess) {
@@ -384,6 +388,15 @@ bx_status bx_server_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip
   flush_lines(s->h_out, kOutStride * (int)M);
   flush_lines(s->h_mark, 512);
   for (int i = (int)M - 1; i >= 0; --i) s->free_slots.push_back(i);
+  {  // the padding entry of the launch lists: a fit that never runs
+    FitDev pad{};
+    pad.skip = 1;
+    if (hipMemcpy(s->d_fits + M, &pad, sizeof pad, hipMemcpyHostToDevice) != hipSuccess) {
+      bx_server_destroy(s);
+      set_error("server allocation failed");
+      return BX_E_DEVICE;
+    }
+  }
   const unsigned hc = std::thread::hardware_concurrency();
   s->pool.reset(new StepPool((int)std::min(7u, hc > 1 ? hc - 1 : 0u)));
   s->worker = std::thread(worker_loop, s);
