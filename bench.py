@@ -78,7 +78,9 @@ def parse():
     ap.add_argument("--plain-toys", type=int, default=64, help="toys fitted on the plain path")
     ap.add_argument("--edm", type=float, default=1e-12, help="toy fits stop at EDM below this")
     ap.add_argument("--qps", type=str, default="10,30,100,300,1000", help="serving arrival rates ('' = skip)")
-    ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="cap on each rate's arrival window: min(requests, rate x this) requests")
     ap.add_argument("--batch", type=int, default=512,
                     help="resident copies of the fit for the batched-launch timing (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -309,7 +311,7 @@ def joint_leg(bx, synth, steps, warmup):
                              "bins_per_s": nb / (jms * 1e-3) if jms > 0 else None}}
 
 
-def serving(bx, synth, qps_list, n_req):
+def serving(bx, synth, qps_list, n_max, window_s):
     import torch
     """Poisson arrivals mixing config-1 fits (Gaussian, FP64), config-2 fits
     (generalized gamma, FP32) with fresh Poisson data, and NLL+gradient
@@ -320,6 +322,7 @@ def serving(bx, synth, qps_list, n_req):
     tab1, tab2 = synth.species_table("c1"), synth.species_table("c2")
     out = {}
     for qps in qps_list:
+        n_req = int(min(n_max, max(100, round(qps * window_s))))
         reqs, rng = synth.request_stream(qps, n_req)
         jobs = []
         for r in reqs:
@@ -515,7 +518,8 @@ def main():
         res["toy_study"] = toy_study(bx, synth, a.toys, a.plain_toys, a.edm)
         print(f"toys: {res['toy_study']}", file=sys.stderr, flush=True)
     if a.qps:
-        res["serving"] = serving(bx, synth, [float(q) for q in a.qps.split(",")], a.requests)
+        res["serving"] = serving(bx, synth, [float(q) for q in a.qps.split(",")], a.requests,
+                                 a.serve_seconds)
         print(f"serving: {res['serving']}", file=sys.stderr, flush=True)
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(timed)

@@ -26,6 +26,10 @@ constexpr int kPreAdjFits = 8; // launches of this many fits form the pile-up ad
 constexpr int kMaxCG = 8;      // true tiles per forward wave
 constexpr int kMaxP = 32;      // parameters (16 rates + response parameters)
 constexpr int kBwdPart = 4 + kSP;  // backward partials per block: response parameters, then rates
+constexpr int kFinBlocks = 16;  // blocks of the final sums (each a share of every partial)
+constexpr int kFinThreads = 256;
+constexpr int kFinRow = 8 + kSP;  // per final-sums block: NLL, 4 response-parameter gradients,
+                                  // pile-up fraction, table coordinate, flags; then the rates
 
 enum : int { kGauss = 0, kGG = 1, kTable = 2, kCount = 3 };
 constexpr int kMaxGrid = 64;   // grid points of a tabulated response
@@ -140,6 +144,9 @@ struct FitDev {
   double* bwdpart;      // [n_bwdblk][kBwdPart] response-gradient partials, then (vsum) the
                         // rate-gradient partials sum_i F^_si u_i, u = R^T w~
   double* bwdfix;       // [n_ct][kBwdPart] the backward fix-up sweep's partials
+  double* fpart;        // [kFinBlocks][kFinRow] the final-sums blocks' rows
+  int* fcount;          // final-sums blocks done (zeroed by the first kernel of an evaluation
+                        // and by the block that adds the rows)
   double* out;          // [2 + P]: nll, grad[P], flags
   const double* theta_src;  // pinned host [P + 1]: theta and the caller's sequence number, or null
   double* out_host;         // pinned host [3 + P]: the results, then the sequence number as

@@ -489,6 +489,8 @@ static size_t carve(const HostModel& h, char* base, FitDev* f, double** theta, d
   f->Mpart = c.take<double>((size_t)f->n_cg * h.N * (f->vsum ? 1 : kSP));
   f->Mfix = c.take<double>((size_t)kFixSplit * h.N * (f->vsum ? 1 : kSP));
   f->bwdfix = c.take<double>((size_t)f->n_ct * kBwdPart);
+  f->fpart = c.take<double>((size_t)kFinBlocks * kFinRow);
+  f->fcount = c.take<int>(1);
   f->fixq = c.take<double>((size_t)4 * f->n_ct);
   f->fixflag = c.take<int>((size_t)f->n_rt + f->n_ct);
   f->M = c.take<double>((size_t)h.N * kSP);

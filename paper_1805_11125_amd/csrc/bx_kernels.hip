@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev*
   const int i = blockIdx.x * kCpBlock + col;
   __shared__ double sth[kMaxP + 1];
   __shared__ int slo[kCpBlock], shi[kCpBlock], sbad[kCpBlock];
+  if (blockIdx.x == 0 && t == 0) *f.fcount = 0;  // this evaluation's final sums start their count
   // theta as in k_colparams (pinned host source, device copy by block 0)
   const double* th = f.theta;
   if (f.theta_src) {
@@ -230,7 +231,15 @@ __global__ void __launch_bounds__(kCpCountBlock) k_colparams_count(const FitDev*
   if (u == 0 && valid) {
     ColPar& c = f.cp[i];  // fields stored as formed
     double v = 0.0;
-    for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
+    {  // the spectra row (zero-padded to kSP species) loaded whole, then summed in species order
+      const int S = f.S;
+      double fr[kSP];
+#pragma unroll
+      for (int s = 0; s < kSP; ++s) fr[s] = f.F64[i * kSP + s];
+#pragma unroll
+      for (int s = 0; s < kSP; ++s)
+        if (s < S) v += th[s] * fr[s];
+    }
     c.v = v;
     for (int q = 0; q < kMaxResp; ++q) c.J[0][q] = c.J[1][q] = 0.0;
     for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
@@ -291,18 +300,30 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   int* const cpflag = f.cpflag;
   const int T = f.T;
   int* const fixflag = f.fixflag;
+  int* const fcount = f.fcount;
   double* const fixq = f.fixq;
   const int n_ct = f.has_fix ? f.n_ct : 0;
   double qv = 0.0;
   const int nflag = f.has_fix ? f.n_rt + f.n_ct : 0, nthr = f.n_cpblk * kCpBlock;
-  // this evaluation's fix-up flags start clear (the forward sweep sets them)
+  // this evaluation's fix-up flags start clear (the forward sweep sets them),
+  // and so does its final sums' count
   for (int e = i; e < nflag; e += nthr) fixflag[e] = 0;
+  if (i == 0) *fcount = 0;
   // theta straight from pinned host memory when the caller passed it there,
   // with system-scope loads (a plain load may hit a line of the previous
   // evaluation's theta still held in the GPU caches); block 0 leaves a device
   // copy for the later kernels, with the caller's sequence number after it
   // (the completion mark of k_final)
   __shared__ double sth[kMaxP + 1];
+  // the column's inputs that do not depend on theta (the spectra row,
+  // zero-padded to kSP species, its energy and light yield factor), in flight
+  // while theta arrives
+  const int ic = min(i, T - 1);
+  double fr[kSP];
+#pragma unroll
+  for (int s = 0; s < kSP; ++s) fr[s] = f.F64[ic * kSP + s];
+  const double E = f.Ec[ic];
+  const double Qt = f.kind == kGG ? f.Qt[ic] : 0.0;
   const double* th = f.theta;
   if (f.theta_src) {
     if ((int)threadIdx.x <= f.P) {
@@ -316,11 +337,15 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
   if (i < f.T) {
     ColPar c;
     double v = 0.0;
-    for (int s = 0; s < f.S; ++s) v += th[s] * f.F64[i * kSP + s];
+    {  // summed in species order
+      const int S = f.S;
+#pragma unroll
+      for (int s = 0; s < kSP; ++s)
+        if (s < S) v += th[s] * fr[s];
+    }
     c.v = v;
     for (int q = 0; q < kMaxResp; ++q) c.J[0][q] = c.J[1][q] = 0.0;
     for (int q = 0; q < 8; ++q) { c.f32[q] = 0.f; c.f64[q] = 0.0; }
-    const double E = f.Ec[i];
     bool okth = true;
     for (int q = 0; q < f.P; ++q) okth = okth && isfinite(th[q]);
     if (f.pu_float && !(th[f.P - 1] >= 0.0 && th[f.P - 1] <= 1.0)) okth = false;
@@ -343,7 +368,7 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
       jlo = r.x; jhi = r.y;
     } else {
       const double L = th[f.S], v0 = th[f.S + 1], v1 = th[f.S + 2], v2 = th[f.S + 3];
-      const double m = L * f.Qt[i] * E;
+      const double m = L * Qt * E;
       const double s2 = v0 + v1 * m + v2 * m * m;
       if (!(m > 0.0) || !(s2 > 0.0)) {
         bad |= kBadGG;
@@ -699,7 +724,10 @@ __global__ void __launch_bounds__(kBlock) k_table(const FitDev* fits, const int*
     sw = w;
     sdl = dl;
     sbad = bad;
-    if (blockIdx.x == 0) f.cpflag[0] = bad;
+    if (blockIdx.x == 0) {
+      f.cpflag[0] = bad;
+      *f.fcount = 0;  // this evaluation's final sums start their count
+    }
   }
   __syncthreads();
   if (t >= f.N * kSP) return;
@@ -926,19 +954,26 @@ __device__ __forceinline__ double m_sum(const FitDev& f, int j, int s) {
   const size_t stride = f.vsum ? (size_t)f.N : (size_t)f.N * kSP;
   const size_t off = f.vsum ? (size_t)j : (size_t)j * kSP + s;
   GD* const p = (GD*)f.Mpart + off;
+  // the first U partials, the tile's fix-up flag and its shares are loaded
+  // together (the shares whatever the flag: a tile without steps left holds
+  // stale values there, which are then not added)
+  constexpr int U = 16;
+  const bool fx = f.has_fix != 0;
+  double v[U], w[kFixSplit];
+#pragma unroll
+  for (int c = 0; c < U; ++c) v[c] = c < n ? p[c * stride] : 0.0;
+  const int fl = fx ? ((const __attribute__((address_space(1))) int*)f.fixflag)[j / kRowStep] : 0;
+  GD* const q = (GD*)f.Mfix + off;
+#pragma unroll
+  for (int b = 0; b < kFixSplit; ++b) w[b] = fx ? q[b * stride] : 0.0;
   double a = 0.0;
-  int c = 0;
-  for (; c + 4 <= n; c += 4) {  // four independent loads in flight
-    const double a0 = p[c * stride], a1 = p[(c + 1) * stride], a2 = p[(c + 2) * stride], a3 = p[(c + 3) * stride];
-    a += a0;
-    a += a1;
-    a += a2;
-    a += a3;
-  }
-  for (; c < n; ++c) a += p[c * stride];
-  if (f.has_fix && ((const __attribute__((address_space(1))) int*)f.fixflag)[j / kRowStep]) {
-    GD* const q = (GD*)f.Mfix + off;
-    for (int b = 0; b < kFixSplit; ++b) a += q[b * stride];
+#pragma unroll
+  for (int c = 0; c < U; ++c)
+    if (c < n) a += v[c];
+  for (int c = U; c < n; ++c) a += p[c * stride];
+  if (fl) {
+#pragma unroll
+    for (int b = 0; b < kFixSplit; ++b) a += w[b];
   }
   return a;
 }
@@ -951,6 +986,24 @@ __global__ void __launch_bounds__(kBlock) k_reduce_M(const FitDev* fits, const i
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= f.N * kSP || f.vsum) return;
   f.M[t] = m_sum(f, t >> 4, t & 15);
+}
+
+// (g * M)_j = sum_k g_k M_(j-k) over the taps k <= kmax, with row j - k of
+// M staged at Ml[jl - k] and the taps at gl[]: four chains over k (mod 4),
+// added pairwise.
+__device__ __forceinline__ double pu_conv(const double* gl, const double (*Ml)[kSP], int jl, int s, int kmax) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 3 <= kmax; k += 4) {
+    a0 = fma(gl[k], Ml[jl - k][s], a0);
+    a1 = fma(gl[k + 1], Ml[jl - k - 1][s], a1);
+    a2 = fma(gl[k + 2], Ml[jl - k - 2][s], a2);
+    a3 = fma(gl[k + 3], Ml[jl - k - 3][s], a3);
+  }
+  if (k <= kmax) a0 = fma(gl[k], Ml[jl - k][s], a0);
+  if (k + 1 <= kmax) a1 = fma(gl[k + 1], Ml[jl - k - 1][s], a1);
+  if (k + 2 <= kmax) a2 = fma(gl[k + 2], Ml[jl - k - 2][s], a2);
+  return (a0 + a1) + (a2 + a3);
 }
 
 // 16 rows x 16 species per block.
@@ -992,9 +1045,11 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   __shared__ double red[kBlock];
   __shared__ int redf[kBlock];
   __shared__ double wps[16][64];
+  __shared__ double gl[kMaxK];
   const int rl = threadIdx.x >> 4, s = threadIdx.x & 15;
   const int j0 = fb2.x * 16;
   const int r0 = max(j0 - (K - 1), 0), r1 = min(j0 + 16, N);
+  for (int e = threadIdx.x; e < K; e += kBlock) gl[e] = ghat[e];
   // M rows [r0, r1) staged in LDS for the pile-up sums (a single histogram's
   // column summed here from the forward partials)
   if (vsum) {
@@ -1011,9 +1066,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
   if (jok) {
     m = Ml[j - r0][s];
     if (K > 1) {
-      double acc = 0.0;
-      const int kmax = min(j, K - 1);
-      for (int k = 0; k <= kmax; ++k) acc += ghat[k] * Ml[j - k - r0][s];
+      const double acc = pu_conv(gl, Ml, j - r0, s, min(j, K - 1));
       dmp = acc - m;
       m = (1.0 - pp) * m + pp * acc;
     }
@@ -1031,9 +1084,7 @@ __global__ void __launch_bounds__(kBlock) k_rowterms(const FitDev* fits, const i
     if (jok) {
       dmt = Ml[j - r0][s];
       if (K > 1) {
-        double acc = 0.0;
-        const int kmax = min(j, K - 1);
-        for (int k = 0; k <= kmax; ++k) acc += ghat[k] * Ml[j - k - r0][s];
+        const double acc = pu_conv(gl, Ml, j - r0, s, min(j, K - 1));
         dmt = (1.0 - pp) * dmt + pp * acc;
       }
       Dtp[j * kSP + s] = dmt;
@@ -1764,9 +1815,17 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order sums of the per-block partials into out[] (NT threads).  The
-// order depends only on NT and the partial counts, so the eval-only launch and
-// the backward kernel's last block give identical bits.
+// Fixed-order sums of the per-block partials into out[].  The partials are
+// split into kFinBlocks logical blocks of kFinThreads threads, each summing a
+// fixed share of every kind of partial into a row (wave sums in lane order,
+// the block's waves in order); the rows are then added in block order.  A
+// launch of few fits runs one workgroup per logical block (spread over many
+// CUs, the partials stream in at the rate of many CUs, where one workgroup
+// would wait on its own few outstanding loads), and the workgroup that
+// finishes last (a device-scope counter) adds the rows from fpart; a launch
+// of many fits runs one 1024-thread workgroup per fit, four logical blocks
+// at a time, with the rows in LDS.  The arithmetic, and so every bit, is the
+// same either way, and the same for the eval-only launch.
 __device__ __forceinline__ double sum64(double x) {
   for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
@@ -1776,17 +1835,23 @@ __device__ __forceinline__ int or64(int x) {
   return x;
 }
 
-template <int NT>
-__device__ void final_sums(const FitDev& f, int with_grad) {
-  constexpr int NW = NT / 64;
+template <int PT>  // threads per workgroup: kFinThreads (kFinBlocks workgroups per fit) or 1024 (one)
+__global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* active, int with_grad) {
+  constexpr int NT = kFinThreads, NB = kFinBlocks, G = NT * NB;
+  constexpr int PW = PT / 64, LPB = PT / NT, NPASS = PT == NT ? 1 : NB / LPB;
+  static_assert(PT == NT || (PT % NT == 0 && NB % (PT / NT) == 0), "logical blocks per workgroup");
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
   typedef __attribute__((address_space(1))) double GDw;
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
   // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient,
   // table-coordinate gradient
   constexpr int NA = 7;
-  __shared__ double wred[NW][NA + kSP];
-  __shared__ int wflag[NW];
+  __shared__ double wred[PW][NA + kSP];
+  __shared__ int wflag[PW];
+  __shared__ double rowl[PT == NT ? 1 : NB][kFinRow];
+  __shared__ int slast;
   // every field used is read into registers before the first store (a store
   // through a generic pointer could alias f and force reloads after it)
   const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N, S = f.S, P = f.P;
@@ -1811,69 +1876,13 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
   GD* const jg = (GD*)f.jg;
   GD* const rad_out = (GD*)f.rad_out;
   GDw* const out = (GDw*)f.out;
+  double* const fpart = f.fpart;
+  int* const fcount = f.fcount;
   double* const out_host = f.out_host;
   const double* const theta = f.theta;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  double acc[NA] = {0, 0, 0, 0, 0, 0, 0};
-  int fl = 0;
-  for (int b = t; b < n_rowblk; b += NT) {
-    acc[0] += nllpart[b];
-    fl |= flagpart[b];
-    if (pu_float && with_grad) acc[5] += ppart[b];
-    if (tab && with_grad) acc[6] += tpart[b];
-  }
-  for (int b = t; b < n_cpblk; b += NT) fl |= cpflag[b];
-  if (with_grad) {
-    for (int b = t; b < n_bwdblk; b += NT)
-      for (int q = 0; q < 4; ++q) acc[1 + q] += bwdpart[(size_t)b * kBwdPart + q];
-    if (has_fix)  // then the backward fix-up sweep's partials (true tiles with steps left)
-      for (int b = t; b < n_ct; b += NT)
-        if (fixflag[n_rt + b])
-          for (int q = 0; q < 4; ++q) acc[1 + q] += bwdfix[(size_t)b * kBwdPart + q];
-  }
-  if (jt)  // joint term: one partial per reco row
-    for (int b = t; b < N; b += NT) {
-      acc[0] += jnll[b];
-      fl |= jflag[b];
-      if (pu_float && with_grad) acc[5] += jpp[b];
-      if (tab && with_grad) acc[6] += jtp[b];
-    }
-  // rate gradient: species s = t % 16, row blocks b = t / 16 + (NT / 16) n
-  // (vsum: from the backward sweep's partials sum_i F^_si u_i)
-  double gr = 0.0;
-  if (vsum) {
-    if (with_grad) {
-      // four interleaved partial sums (loads in flight), added pairwise
-      constexpr int ST = NT / 16;
-      double g4[4] = {0.0, 0.0, 0.0, 0.0};
-      int b = t >> 4;
-      for (; b + 3 * ST < n_bwdblk; b += 4 * ST) {
-        const double x0 = bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
-        const double x1 = bwdpart[(size_t)(b + ST) * kBwdPart + 4 + (t & 15)];
-        const double x2 = bwdpart[(size_t)(b + 2 * ST) * kBwdPart + 4 + (t & 15)];
-        const double x3 = bwdpart[(size_t)(b + 3 * ST) * kBwdPart + 4 + (t & 15)];
-        g4[0] += x0;
-        g4[1] += x1;
-        g4[2] += x2;
-        g4[3] += x3;
-      }
-#pragma unroll
-      for (int u = 0; u < 3; ++u, b += ST)  // at most three left
-        if (b < n_bwdblk) g4[u] += bwdpart[(size_t)b * kBwdPart + 4 + (t & 15)];
-      gr = (g4[0] + g4[1]) + (g4[2] + g4[3]);
-      if (has_fix)
-        for (int c = t >> 4; c < n_ct; c += ST)
-          if (fixflag[n_rt + c]) gr += bwdfix[(size_t)c * kBwdPart + 4 + (t & 15)];
-    }
-  } else {
-    for (int b = t >> 4; b < n_rowblk; b += NT / 16) gr += gpart[b * kSP + (t & 15)];
-  }
-  if (jt && with_grad)
-    for (int b = t >> 4; b < N; b += NT / 16) gr += jg[b * kSP + (t & 15)];
-  gr += __shfl_xor(gr, 16, 64);
-  gr += __shfl_xor(gr, 32, 64);
   // the radial term's parts (one block wrote them) and the caller's sequence
-  // number, loaded now so that their latency overlaps the sums
+  // number, for the block that adds the rows, in flight with the first round
   double rad_g = 0.0, rad_nll = 0.0, rad_fl = 0.0, rad_p = 0.0, rad_t = 0.0, seq = 0.0;
   if (rad) {
     if (t < S) rad_g = rad_out[2 + 16 + t];
@@ -1885,33 +1894,160 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
     }
   }
   if (out_host && t == 0) seq = theta[P];
+  // The partials, in rounds: every load of a round is issued before any of
+  // its values is added, so a round costs one memory round trip (the 3000 x
+  // 900 fit needs one).  Thread gt of the G threads takes, per round, the
+  // row, cell-parameter and true-tile partials b = gt + G r, UQ backward
+  // blocks' response parts and, for species s = gt % 16, UR blocks' rate
+  // parts (or the row blocks' species sums) and UX true tiles' fix-up rate
+  // parts.  Sums within a round are pairwise in a fixed order, rounds are
+  // added in order.
+  constexpr int ST = G / 16, UQ = 2, UR = 4, UX = 2;
+  const bool wg = with_grad != 0;
+  const bool fixg = has_fix && wg;
+  const int nA = max(max(n_rowblk, n_cpblk), max(jt ? N : 0, fixg ? n_ct : 0));
+  const int nQ = wg ? n_bwdblk : 0;
+  const int nR = vsum ? (wg ? n_bwdblk : 0) : n_rowblk;
+  const int nX = vsum && fixg ? n_ct : 0;
+  const int rounds = max(max((nA + G - 1) / G, (nQ + UQ * G - 1) / (UQ * G)),
+                         max((nR + UR * ST - 1) / (UR * ST), (nX + UX * ST - 1) / (UX * ST)));
+  for (int pass = 0; pass < NPASS; ++pass) {
+    // logical block lb, its thread gt
+    const int lb = PT == NT ? (int)blockIdx.x : pass * LPB + t / NT;
+    const int gt = lb * NT + (t & (NT - 1));
+    const int sp = gt & 15, tb = gt >> 4;
+    double acc[NA] = {0, 0, 0, 0, 0, 0, 0};
+    int fl = 0;
+    double gr = 0.0;
+    for (int r = 0; r < rounds; ++r) {
+      const int b = gt + G * r;
+      const bool inR = b < n_rowblk, inF = fixg && b < n_ct, inJ = jt && b < N;
+      const double x0 = inR ? nllpart[b] : 0.0;
+      const int xf = inR ? flagpart[b] : 0;
+      const double x5 = inR && pu_float && wg ? ppart[b] : 0.0;
+      const double x6 = inR && tab && wg ? tpart[b] : 0.0;
+      const int xc = b < n_cpblk ? cpflag[b] : 0;
+      const int ff = inF ? fixflag[n_rt + b] : 0;
+      double fq[4], qv[UQ][4], rv[UR], xv[UX];
+      int xff[UX];
 #pragma unroll
-  for (int q = 0; q < NA; ++q) acc[q] = sum64(acc[q]);
-  fl = or64(fl);
-  if (lane == 0) {
-    for (int q = 0; q < NA; ++q) wred[w][q] = acc[q];
-    wflag[w] = fl;
+      for (int q = 0; q < 4; ++q) fq[q] = inF ? bwdfix[(size_t)b * kBwdPart + q] : 0.0;
+      const double y0 = inJ ? jnll[b] : 0.0;
+      const int yf = inJ ? jflag[b] : 0;
+      const double y5 = inJ && pu_float && wg ? jpp[b] : 0.0;
+      const double y6 = inJ && tab && wg ? jtp[b] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UQ; ++u) {
+        const int bb = gt + G * (UQ * r + u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) qv[u][q] = bb < nQ ? bwdpart[(size_t)bb * kBwdPart + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const int bb = tb + ST * (UR * r + u);
+        rv[u] = bb >= nR ? 0.0 : vsum ? bwdpart[(size_t)bb * kBwdPart + 4 + sp] : gpart[bb * kSP + sp];
+      }
+#pragma unroll
+      for (int u = 0; u < UX; ++u) {
+        const int c = tb + ST * (UX * r + u);
+        xff[u] = c < nX ? fixflag[n_rt + c] : 0;
+        xv[u] = c < nX ? bwdfix[(size_t)c * kBwdPart + 4 + sp] : 0.0;
+      }
+      // the sums (true tiles without fix-up steps left hold stale partials: not added)
+      acc[0] += x0 + y0;
+      fl |= xf | xc | yf;
+      acc[5] += x5 + y5;
+      acc[6] += x6 + y6;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = qv[0][q];
+#pragma unroll
+        for (int u = 1; u < UQ; ++u) v += qv[u][q];
+        acc[1 + q] += v + (ff ? fq[q] : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < UX; ++u)
+        if (!xff[u]) xv[u] = 0.0;
+#pragma unroll
+      for (int h = 1; h < UR; h *= 2)
+#pragma unroll
+        for (int u = 0; u + h < UR; u += 2 * h) rv[u] += rv[u + h];
+#pragma unroll
+      for (int h = 1; h < UX; h *= 2)
+#pragma unroll
+        for (int u = 0; u + h < UX; u += 2 * h) xv[u] += xv[u + h];
+      gr += rv[0] + xv[0];
+    }
+    if (jt && wg)  // the joint term's species sums, one per reco row
+      for (int b = tb; b < N; b += ST) gr += jg[b * kSP + sp];
+    gr += __shfl_xor(gr, 16, 64);
+    gr += __shfl_xor(gr, 32, 64);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = sum64(acc[q]);
+    fl = or64(fl);
+    if (lane == 0) {
+      for (int q = 0; q < NA; ++q) wred[w][q] = acc[q];
+      wflag[w] = fl;
+    }
+    if (lane < kSP) wred[w][NA + lane] = gr;
+    __syncthreads();
+    // the first wave of each logical block forms its row (lane c: column c,
+    // summed over the block's waves in order; column NA holds the flags)
+    if ((w & (NT / 64 - 1)) == 0) {
+      const int w0 = w;
+      double v = 0.0;
+      if (lane < kFinRow && lane != NA) {
+        const int col = lane < NA ? lane : lane - 1;
+        v = wred[w0][col];
+        for (int u = 1; u < NT / 64; ++u) v += wred[w0 + u][col];
+      }
+      int fw = 0;
+      for (int u = 0; u < NT / 64; ++u) fw |= wflag[w0 + u];
+      if (lane == NA) v = (double)fw;
+      if (PT == NT) {  // to fpart, device-wide before the count
+        if (lane < kFinRow) fpart[lb * kFinRow + lane] = v;
+        __threadfence();
+        if (lane == 0) slast = atomicAdd(fcount, 1) == NB - 1;
+      } else if (lane < kFinRow) {
+        rowl[lb][lane] = v;
+      }
+    }
+    __syncthreads();  // wred[] is rewritten by the next pass
   }
-  if (lane < kSP) wred[w][NA + lane] = gr;
-  __syncthreads();
+  if (PT == NT && !slast) return;  // block-uniform
+  if (w != 0) return;
+  // the workgroup that adds the rows, in block order
+  if (PT == NT) __threadfence();
+  double v = 0.0;
+  int fv = 0;
+  if (lane < kFinRow) {
+    GD* const rows = (GD*)fpart;
+    double x[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) x[u] = PT == NT ? rows[u * kFinRow + lane] : rowl[u][lane];
+    if (lane == NA) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) fv |= (int)x[u];
+    } else {
+      v = x[0];
+#pragma unroll
+      for (int u = 1; u < NB; ++u) v += x[u];
+    }
+  }
+  if (PT == NT && lane == 0) *fcount = 0;  // for the next launch (the stage timer repeats this kernel alone)
+  double tot[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) tot[q] = __shfl(v, q, 64);
+  int flags = __shfl(fv, NA, 64);
+  const double gs = __shfl(v, (NA + 1 + lane) & 63, 64);  // the rate gradient of species `lane`
   // results go to f.out and, when set, straight into the caller's pinned
   // host buffer as well (no separate copy node)
-  if (t < S) {
-    double a = wred[0][NA + t];
-    for (int v = 1; v < NW; ++v) a += wred[v][NA + t];
-    if (rad) a += rad_g;
-    out[1 + t] = a;
-    if (out_host) out_host[1 + t] = a;
+  if (lane < S) {
+    const double a = rad ? gs + rad_g : gs;
+    out[1 + lane] = a;
+    if (out_host) out_host[1 + lane] = a;
   }
-  if (t == 0) {
-    double tot[NA];
-    int flags = wflag[0];
-    for (int q = 0; q < NA; ++q) tot[q] = wred[0][q];
-#pragma unroll 1  // one wave's row at a time (a full unroll spills)
-    for (int v = 1; v < NW; ++v) {
-      for (int q = 0; q < NA; ++q) tot[q] += wred[v][q];
-      flags |= wflag[v];
-    }
+  if (lane == 0) {
     double pg = tot[5];  // dNLL/dp: row terms, then the radial term
     if (rad) pg += rad_p;
     if (tab) {  // the table coordinate takes the response gradient's place
@@ -1944,20 +2080,22 @@ __device__ void final_sums(const FitDev& f, int with_grad) {
       if (pu_float) out_host[P] = with_grad ? pg : 0.0;
     }
   }
-  if (out_host) {  // then the completion mark the caller spins on
+  if (out_host) {  // then the completion mark the caller spins on (all writers are in this wave)
     __threadfence_system();
-    __syncthreads();
-    if (t == 0) {
+    if (lane == 0) {
       out_host[2 + P] = seq;
       __threadfence_system();
     }
   }
 }
 
-__global__ void __launch_bounds__(1024) k_final(const FitDev* fits, const int* active, int with_grad) {
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  final_sums<1024>(f, with_grad);
+// Few fits: kFinBlocks workgroups each; many: one 1024-thread workgroup each.
+static void launch_final(const FitDev* d_fits, const int* d_active, int n, bool with_grad, hipStream_t st) {
+  if (n < 8)
+    hipLaunchKernelGGL(k_final<kFinThreads>, dim3(kFinBlocks, n), dim3(kFinThreads), 0, st, d_fits, d_active,
+                       with_grad ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_final<1024>, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
 }
 
 // Joint energy x radius x pulse-shape term (the alternative to the additive
@@ -2311,7 +2449,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
           launch_joint(L, n, with_grad, st, d_fits, d_active);
         break;
       case 7:
-        hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+        launch_final(d_fits, d_active, n, with_grad, st);
         break;
       default:
         break;
@@ -2363,7 +2501,7 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
       if (fixk && stage == 6) launch_fix_stage(L, false, gbx, st, d_fits, d_active, pre, 1, 1);
       break;
     case 7:
-      hipLaunchKernelGGL(k_final, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+      launch_final(d_fits, d_active, n, with_grad, st);
       break;
   }
 }
