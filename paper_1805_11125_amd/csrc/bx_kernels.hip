@@ -1426,10 +1426,16 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
       __syncthreads();
     }
     const double pp = pu_p(f);
+    // a true tile with fix-up steps left leaves w~ of its rows for
+    // k_cells_bwd_fix (the adjoint H~ is otherwise unused without pre; tiles
+    // that share rows write the same bits)
+    const bool keep = K > 1 && f.has_fix && ((GI*)f.fixflag)[f.n_rt + ct];
+    double* const Ht = f.Ht;
     for (int e = threadIdx.x; e < nr; e += NT) {
       double h = hst[e];
       if (K > 1) h = fma(pp, (pq[e][0] + pq[e][1]) + (pq[e][2] + pq[e][3]), (1.0 - pp) * h);
       htl[e] = h;
+      if (keep) Ht[(size_t)(r0 + e) * kSP] = h;
     }
     __syncthreads();
   }
@@ -1649,43 +1655,9 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
   }
 }
 
-// Orders one wave's LDS accesses (a wave's LDS operations complete in
-// order; the fences keep the compiler from moving accesses across).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Single histogram: w~_j = (P^T w)_j for the rows j = r0 + jr of one reco
-// tile, by one wave, with the arithmetic of the backward sweep's prologue and
-// k_adjoint1 (four fused chains over the taps k = part (mod 4), added
-// pairwise), so the fix-up weights carry the same bits.  Lane (jr, g) runs
-// chain g of row jr from the rows staged in the wave's hs[]; gl[] holds the
-// K > 1 taps.  Returns w~ of the lane's row (0 past the end).
-__device__ __forceinline__ double wtilde_tile(const FitDev& f, int r0, int K, double* hs, const double* gl) {
-  const int lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
-  const int N = f.N, nrow = min(kRowStep + K - 1, N - r0);
-  const double* const H = f.H;
-  for (int e = lane; e < nrow; e += 64) hs[e] = H[(size_t)(r0 + e) * kSP];
-  wave_lds_sync();
-  const int j = r0 + jr;
-  const bool row_ok = jr < kRowStep && j < N;
-  double acc = 0.0;
-  if (row_ok) {
-    const int kmax = min(K - 1, N - 1 - j);
-    for (int k = g; k <= kmax; k += 4) acc = fma(gl[k], hs[jr + k], acc);
-  }
-  const double p0 = __shfl(acc, jr, 64), p1 = __shfl(acc, jr + 16, 64);
-  const double p2 = __shfl(acc, jr + 32, 64), p3 = __shfl(acc, jr + 48, 64);
-  const double pp = pu_p(f);
-  const double h = row_ok ? fma(pp, (p0 + p1) + (p2 + p3), (1.0 - pp) * hs[jr]) : 0.0;
-  wave_lds_sync();  // hs[] is rewritten by the wave's next entry
-  return h;
-}
-
 // Block = true tile ct.  Candidates: (reco tile of ct's support, step) pairs
-// in order; a wave forms its entry's weights as the backward sweep does and
+// in order; a wave forms its entry's weights as the backward sweep does (a
+// single histogram's w~ with pile-up as k_cells_bwd left it in H~) and
 // evaluates the step.  Writes bwdfix[ct] (zeros where nothing is left).
 template <class R, int KIND, bool MV>
 __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
@@ -1702,7 +1674,6 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   __shared__ int list[NTH], wcount[NW];
   __shared__ double colA[NW][16], colB[NW][16], colU[NW][16];
   __shared__ double rsum[16][kSP];
-  __shared__ double gl[kMaxK], hsw[NW][kRowStep + kMaxK - 1];  // single histogram's w~ (pile-up)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, jr = lane & 15, g = lane >> 4;
   const int T = f.T, N = f.N, S = f.S, n_ct = f.n_ct;
   GColPar* const cpar = (GColPar*)f.cp;
@@ -1722,11 +1693,20 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
       thv[kb] = s < S ? ((GD*)f.theta)[s] : 0.0;
     }
   }
-  const int K = pu_len(f);
-  const bool wt = !MV && !pre && K > 1;  // w~ formed here from H and the taps
-  if (wt) {
-    for (int e = threadIdx.x; e < K; e += NTH) gl[e] = ((GD*)f.ghat)[e];
-    __syncthreads();
+  // w~ (single histogram): H~ with pile-up (k_adjoint1 or k_cells_bwd wrote it), else H
+  GD* const wsrc = (GD*)(pre || pu_len(f) > 1 ? f.Ht : f.H);
+  // the tail's factors, in flight with the entries: chain factors (threads
+  // < 64: column c16, parameter qp) and spectra (column t / 16, species t % 16)
+  const int c16 = threadIdx.x & 15, qp = (threadIdx.x >> 4) & 3;
+  const int icol = ct * kColTile + c16;
+  double J0 = 0.0, J1 = 0.0, Fs = 0.0;
+  if (threadIdx.x < 64 && icol < T && qp < f.nresp) {
+    J0 = cpar[icol].J[0][qp];
+    J1 = cpar[icol].J[1][qp];
+  }
+  if (!MV && threadIdx.x < 256) {
+    const int s = threadIdx.x & 15, i = ct * kColTile + (threadIdx.x >> 4);
+    Fs = (i < T && s < S) ? F64[(size_t)i * kSP + s] : 0.0;
   }
   double aA[4] = {0, 0, 0, 0}, aB[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
   const int ncand = 4 * (rt_b - rt_a + 1);
@@ -1757,8 +1737,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
         Wm = mfma16(fa[3], hb3 * thv[3], Wm);
         Wq = qe == 0 ? Wm[0] : qe == 1 ? Wm[1] : qe == 2 ? Wm[2] : Wm[3];
       } else {
-        if (wt) w1 = wtilde_tile(f, j - jr, K, hsw[wv], gl);  // the whole wave
-        else if (row_ok) w1 = ((GD*)(pre ? f.Ht : f.H))[(size_t)j * kSP];
+        if (row_ok) w1 = wsrc[(size_t)j * kSP];
         Wq = w1 * c.v;
       }
       const CellVal<R> ev = cell_general<R, KIND, true>(c, rq, xe, row_ok && i < T);
@@ -1784,24 +1763,23 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   }
   __syncthreads();
   if (threadIdx.x < 64) {  // column totals (fixed order over the waves), times the chain factors
-    const int c16 = threadIdx.x & 15, qp = threadIdx.x >> 4;
-    const int icol = ct * kColTile + c16;
     double A = colA[0][c16], B = colB[0][c16];
     for (int w = 1; w < NW; ++w) {
       A += colA[w][c16];
       B += colB[w][c16];
     }
-    double v = (icol < T && qp < f.nresp) ? A * cpar[icol].J[0][qp] + B * cpar[icol].J[1][qp] : 0.0;
+    double v = (icol < T && qp < f.nresp) ? A * J0 + B * J1 : 0.0;
     v = sum16(v);
     if (c16 == 0) out[qp] = v;
   }
   if (!MV) {  // rate partials sum_i F^_si u_i over the tile's 16 columns
-    for (int t = threadIdx.x; t < 256; t += NTH) {
-      const int s = t & 15, c = t >> 4;
+    static_assert(NTH >= 256, "one thread per (column, species)");
+    if (threadIdx.x < 256) {
+      const int s = threadIdx.x & 15, c = threadIdx.x >> 4;
       const int i = ct * kColTile + c;
       double u = colU[0][c];
       for (int w = 1; w < NW; ++w) u += colU[w][c];
-      rsum[c][s] = (i < T && s < S) ? F64[(size_t)i * kSP + s] * u : 0.0;
+      rsum[c][s] = (i < T && s < S) ? Fs * u : 0.0;
     }
     __syncthreads();
     if (threadIdx.x < kSP) {
