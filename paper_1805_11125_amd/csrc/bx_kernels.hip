@@ -1660,17 +1660,10 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
 // single histogram's w~ with pile-up as k_cells_bwd left it in H~) and
 // evaluates the step.  Writes bwdfix[ct] (zeros where nothing is left).
 template <class R, int KIND, bool MV>
-__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
-                                                                   int use_flags) {
+__device__ __forceinline__ void bwd_fix_tile(const FitDev& f, int ct, int pre) {
   constexpr int NW = kFixWaves, NTH = NW * 64;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  const int2 fb2 = fit_block();
-  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
-  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  const int ct = fb2.x;
-  // block-uniform; nothing left in this true tile: its partials are not read
-  if (ct >= f.n_ct || f.mv != (int)MV || (use_flags && ((GI*)f.fixflag)[f.n_rt + ct] == 0)) return;
   __shared__ int list[NTH], wcount[NW];
   __shared__ double colA[NW][16], colB[NW][16], colU[NW][16];
   __shared__ double rsum[16][kSP];
@@ -1792,18 +1785,35 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* 
   }
 }
 
+template <class R, int KIND, bool MV>
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
+                                                                   int use_flags) {
+  const int2 fb2 = fit_block();
+  const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
+  const int ct = fb2.x;
+  // block-uniform; nothing left in this true tile: its partials are not read
+  if (ct >= f.n_ct || f.mv != (int)MV || (use_flags && f.fixflag[f.n_rt + ct] == 0)) return;
+  bwd_fix_tile<R, KIND, MV>(f, ct, pre);
+}
+
 // ---------------------------------------------------------------------------
-// Fixed-order sums of the per-block partials into out[].  The partials are
-// split into kFinBlocks logical blocks of kFinThreads threads, each summing a
-// fixed share of every kind of partial into a row (wave sums in lane order,
-// the block's waves in order); the rows are then added in block order.  A
-// launch of few fits runs one workgroup per logical block (spread over many
+// Fixed-order sums of the per-block partials into out[].  The partials other
+// than the backward fix-up sweep's are split into kFinBlocks logical blocks
+// of kFinThreads threads, each summing a fixed share of every kind of partial
+// into a row (wave sums in lane order, the block's waves in order).  The
+// finish adds the rows in block order and then the fix-up sweep's partials
+// of the true tiles with steps left (per column: runs of tiles in tile order,
+// then the runs in order; tile t + 256 m at thread t), and writes the
+// results.  A single
+// fit runs its logical blocks as workgroups of their own (spread over many
 // CUs, the partials stream in at the rate of many CUs, where one workgroup
-// would wait on its own few outstanding loads), and the workgroup that
-// finishes last (a device-scope counter) adds the rows from fpart; a launch
-// of many fits runs one 1024-thread workgroup per fit, four logical blocks
-// at a time, with the rows in LDS.  The arithmetic, and so every bit, is the
-// same either way, and the same for the eval-only launch.
+// would wait on its own few outstanding loads): with the gradient inside the
+// backward fix-up sweep's launch, beside its true tiles, else in k_final;
+// the workgroup counted last on a device-scope counter finishes.  A launch of
+// many fits runs one 1024-thread workgroup per fit, four logical blocks at a
+// time, with the rows in LDS.  The arithmetic, and so every bit, is the same
+// in each of these forms.
 __device__ __forceinline__ double sum64(double x) {
   for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
@@ -1813,85 +1823,67 @@ __device__ __forceinline__ int or64(int x) {
   return x;
 }
 
-template <int PT>  // threads per workgroup: kFinThreads (kFinBlocks workgroups per fit) or 1024 (one)
-__global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* active, int with_grad) {
-  constexpr int NT = kFinThreads, NB = kFinBlocks, G = NT * NB;
-  constexpr int PW = PT / 64, LPB = PT / NT, NPASS = PT == NT ? 1 : NB / LPB;
-  static_assert(PT == NT || (PT % NT == 0 && NB % (PT / NT) == 0), "logical blocks per workgroup");
+constexpr int kFinA = 7;  // sums per row before the flags: NLL, 4 response-parameter
+                          // gradients, pile-up-fraction gradient, table-coordinate gradient
+constexpr int kFinFixParts = 12;  // runs of tiles of the fix-up partials' sums (x kBwdPart threads)
+constexpr int kFinFixRun = (kFinThreads + kFinFixParts - 1) / kFinFixParts;
+static_assert(kFinFixParts * kBwdPart <= kFinThreads, "one thread per (run, column)");
+
+// LDS of the final sums in a workgroup of PT threads.
+template <int PT>
+struct FinLds {
+  double wred[PT / 64][kFinA + kSP];
+  int wflag[PT / 64];
+  double rowl[kFinBlocks][kFinRow];  // the rows (one workgroup per fit)
+  double fx[kFinThreads][kBwdPart + 1];  // the fix-up partials by tile (odd stride: no bank conflicts)
+  double fpsum[kFinFixParts][kBwdPart];  // their sums over kFinFixParts runs of tiles
+  int last;
+};
+
+// The rows of logical blocks lb = lb0 + p (PT / kFinThreads) + t / kFinThreads,
+// p < npass, to fpart (each writing wave fences its row) or to L.rowl.
+template <int PT>
+__device__ __forceinline__ void fin_rows(const FitDev& f, int with_grad, int lb0, int npass, bool global,
+                                         FinLds<PT>& L) {
+  constexpr int NT = kFinThreads, G = NT * kFinBlocks, NA = kFinA, LPB = PT / NT;
+  static_assert(PT % NT == 0, "whole logical blocks per workgroup");
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
-  typedef __attribute__((address_space(1))) double GDw;
-  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
-  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
-  // acc: NLL, 4 response-parameter gradients, pile-up-fraction gradient,
-  // table-coordinate gradient
-  constexpr int NA = 7;
-  __shared__ double wred[PW][NA + kSP];
-  __shared__ int wflag[PW];
-  __shared__ double rowl[PT == NT ? 1 : NB][kFinRow];
-  __shared__ int slast;
   // every field used is read into registers before the first store (a store
   // through a generic pointer could alias f and force reloads after it)
-  const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N, S = f.S, P = f.P;
-  const int nresp = f.nresp, pu_float = f.pu_float, vsum = f.vsum, has_fix = f.has_fix, n_ct = f.n_ct;
-  const int n_rt = f.n_rt;
+  const int n_rowblk = f.n_rowblk, n_cpblk = f.n_cpblk, n_bwdblk = f.n_bwdblk, N = f.N;
+  const int pu_float = f.pu_float, vsum = f.vsum;
   const bool tab = f.kind == kTable && f.nresp > 0;
   const bool jt = f.mv && f.joint;
-  const bool rad = f.mv && f.n_rad > 0 && !f.joint;
   GD* const nllpart = (GD*)f.nllpart;
   GI* const flagpart = (GI*)f.flagpart;
   GD* const ppart = (GD*)f.ppart;
   GD* const tpart = (GD*)f.tpart;
   GI* const cpflag = (GI*)f.cpflag;
   GD* const bwdpart = (GD*)f.bwdpart;
-  GD* const bwdfix = (GD*)f.bwdfix;
-  GI* const fixflag = (GI*)f.fixflag;
   GD* const gpart = (GD*)f.gpart;
   GD* const jnll = (GD*)f.jnll;
   GI* const jflag = (GI*)f.jflag;
   GD* const jpp = (GD*)f.jpp;
   GD* const jtp = (GD*)f.jtp;
   GD* const jg = (GD*)f.jg;
-  GD* const rad_out = (GD*)f.rad_out;
-  GDw* const out = (GDw*)f.out;
   double* const fpart = f.fpart;
-  int* const fcount = f.fcount;
-  double* const out_host = f.out_host;
-  const double* const theta = f.theta;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  // the radial term's parts (one block wrote them) and the caller's sequence
-  // number, for the block that adds the rows, in flight with the first round
-  double rad_g = 0.0, rad_nll = 0.0, rad_fl = 0.0, rad_p = 0.0, rad_t = 0.0, seq = 0.0;
-  if (rad) {
-    if (t < S) rad_g = rad_out[2 + 16 + t];
-    if (t == 0) {
-      rad_nll = rad_out[0];
-      rad_fl = rad_out[1];
-      rad_p = rad_out[2 + 32];
-      rad_t = rad_out[2 + 33];
-    }
-  }
-  if (out_host && t == 0) seq = theta[P];
-  // The partials, in rounds: every load of a round is issued before any of
-  // its values is added, so a round costs one memory round trip (the 3000 x
-  // 900 fit needs one).  Thread gt of the G threads takes, per round, the
-  // row, cell-parameter and true-tile partials b = gt + G r, UQ backward
-  // blocks' response parts and, for species s = gt % 16, UR blocks' rate
-  // parts (or the row blocks' species sums) and UX true tiles' fix-up rate
-  // parts.  Sums within a round are pairwise in a fixed order, rounds are
-  // added in order.
-  constexpr int ST = G / 16, UQ = 2, UR = 4, UX = 2;
+  // In rounds: every load of a round is issued before any of its values is
+  // added, so a round costs one memory round trip (the 3000 x 900 fit needs
+  // one).  Thread gt of the G threads takes, per round, the row and
+  // cell-parameter partials b = gt + G r, UQ backward blocks' response parts
+  // and, for species s = gt % 16, UR blocks' rate parts (or the row blocks'
+  // species sums).  Sums within a round are pairwise in a fixed order, rounds
+  // are added in order.
+  constexpr int ST = G / 16, UQ = 2, UR = 4;
   const bool wg = with_grad != 0;
-  const bool fixg = has_fix && wg;
-  const int nA = max(max(n_rowblk, n_cpblk), max(jt ? N : 0, fixg ? n_ct : 0));
+  const int nA = max(max(n_rowblk, n_cpblk), jt ? N : 0);
   const int nQ = wg ? n_bwdblk : 0;
   const int nR = vsum ? (wg ? n_bwdblk : 0) : n_rowblk;
-  const int nX = vsum && fixg ? n_ct : 0;
-  const int rounds = max(max((nA + G - 1) / G, (nQ + UQ * G - 1) / (UQ * G)),
-                         max((nR + UR * ST - 1) / (UR * ST), (nX + UX * ST - 1) / (UX * ST)));
-  for (int pass = 0; pass < NPASS; ++pass) {
-    // logical block lb, its thread gt
-    const int lb = PT == NT ? (int)blockIdx.x : pass * LPB + t / NT;
+  const int rounds = max(max((nA + G - 1) / G, (nQ + UQ * G - 1) / (UQ * G)), (nR + UR * ST - 1) / (UR * ST));
+  for (int pass = 0; pass < npass; ++pass) {
+    const int lb = lb0 + pass * LPB + t / NT;  // logical block, its thread gt
     const int gt = lb * NT + (t & (NT - 1));
     const int sp = gt & 15, tb = gt >> 4;
     double acc[NA] = {0, 0, 0, 0, 0, 0, 0};
@@ -1899,21 +1891,17 @@ __global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* act
     double gr = 0.0;
     for (int r = 0; r < rounds; ++r) {
       const int b = gt + G * r;
-      const bool inR = b < n_rowblk, inF = fixg && b < n_ct, inJ = jt && b < N;
+      const bool inR = b < n_rowblk, inJ = jt && b < N;
       const double x0 = inR ? nllpart[b] : 0.0;
       const int xf = inR ? flagpart[b] : 0;
       const double x5 = inR && pu_float && wg ? ppart[b] : 0.0;
       const double x6 = inR && tab && wg ? tpart[b] : 0.0;
       const int xc = b < n_cpblk ? cpflag[b] : 0;
-      const int ff = inF ? fixflag[n_rt + b] : 0;
-      double fq[4], qv[UQ][4], rv[UR], xv[UX];
-      int xff[UX];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) fq[q] = inF ? bwdfix[(size_t)b * kBwdPart + q] : 0.0;
       const double y0 = inJ ? jnll[b] : 0.0;
       const int yf = inJ ? jflag[b] : 0;
       const double y5 = inJ && pu_float && wg ? jpp[b] : 0.0;
       const double y6 = inJ && tab && wg ? jtp[b] : 0.0;
+      double qv[UQ][4], rv[UR];
 #pragma unroll
       for (int u = 0; u < UQ; ++u) {
         const int bb = gt + G * (UQ * r + u);
@@ -1925,13 +1913,6 @@ __global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* act
         const int bb = tb + ST * (UR * r + u);
         rv[u] = bb >= nR ? 0.0 : vsum ? bwdpart[(size_t)bb * kBwdPart + 4 + sp] : gpart[bb * kSP + sp];
       }
-#pragma unroll
-      for (int u = 0; u < UX; ++u) {
-        const int c = tb + ST * (UX * r + u);
-        xff[u] = c < nX ? fixflag[n_rt + c] : 0;
-        xv[u] = c < nX ? bwdfix[(size_t)c * kBwdPart + 4 + sp] : 0.0;
-      }
-      // the sums (true tiles without fix-up steps left hold stale partials: not added)
       acc[0] += x0 + y0;
       fl |= xf | xc | yf;
       acc[5] += x5 + y5;
@@ -1941,20 +1922,13 @@ __global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* act
         double v = qv[0][q];
 #pragma unroll
         for (int u = 1; u < UQ; ++u) v += qv[u][q];
-        acc[1 + q] += v + (ff ? fq[q] : 0.0);
+        acc[1 + q] += v;
       }
-#pragma unroll
-      for (int u = 0; u < UX; ++u)
-        if (!xff[u]) xv[u] = 0.0;
 #pragma unroll
       for (int h = 1; h < UR; h *= 2)
 #pragma unroll
         for (int u = 0; u + h < UR; u += 2 * h) rv[u] += rv[u + h];
-#pragma unroll
-      for (int h = 1; h < UX; h *= 2)
-#pragma unroll
-        for (int u = 0; u + h < UX; u += 2 * h) xv[u] += xv[u + h];
-      gr += rv[0] + xv[0];
+      gr += rv[0];
     }
     if (jt && wg)  // the joint term's species sums, one per reco row
       for (int b = tb; b < N; b += ST) gr += jg[b * kSP + sp];
@@ -1964,55 +1938,138 @@ __global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* act
     for (int q = 0; q < NA; ++q) acc[q] = sum64(acc[q]);
     fl = or64(fl);
     if (lane == 0) {
-      for (int q = 0; q < NA; ++q) wred[w][q] = acc[q];
-      wflag[w] = fl;
+      for (int q = 0; q < NA; ++q) L.wred[w][q] = acc[q];
+      L.wflag[w] = fl;
     }
-    if (lane < kSP) wred[w][NA + lane] = gr;
+    if (lane < kSP) L.wred[w][NA + lane] = gr;
     __syncthreads();
     // the first wave of each logical block forms its row (lane c: column c,
     // summed over the block's waves in order; column NA holds the flags)
     if ((w & (NT / 64 - 1)) == 0) {
-      const int w0 = w;
       double v = 0.0;
       if (lane < kFinRow && lane != NA) {
         const int col = lane < NA ? lane : lane - 1;
-        v = wred[w0][col];
-        for (int u = 1; u < NT / 64; ++u) v += wred[w0 + u][col];
+        v = L.wred[w][col];
+        for (int u = 1; u < NT / 64; ++u) v += L.wred[w + u][col];
       }
       int fw = 0;
-      for (int u = 0; u < NT / 64; ++u) fw |= wflag[w0 + u];
+      for (int u = 0; u < NT / 64; ++u) fw |= L.wflag[w + u];
       if (lane == NA) v = (double)fw;
-      if (PT == NT) {  // to fpart, device-wide before the count
-        if (lane < kFinRow) fpart[lb * kFinRow + lane] = v;
-        __threadfence();
-        if (lane == 0) slast = atomicAdd(fcount, 1) == NB - 1;
-      } else if (lane < kFinRow) {
-        rowl[lb][lane] = v;
+      if (lane < kFinRow) {
+        if (global) fpart[lb * kFinRow + lane] = v;
+        else L.rowl[lb][lane] = v;
       }
+      if (global) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the row, device-wide
     }
     __syncthreads();  // wred[] is rewritten by the next pass
   }
-  if (PT == NT && !slast) return;  // block-uniform
-  if (w != 0) return;
-  // the workgroup that adds the rows, in block order
-  if (PT == NT) __threadfence();
-  double v = 0.0;
-  int fv = 0;
-  if (lane < kFinRow) {
-    GD* const rows = (GD*)fpart;
-    double x[NB];
+}
+
+// Counts the workgroup done (every wave that stored what the finish reads
+// has fenced it device-wide, release); true in the workgroup counted last of
+// `target`, which then sees every counted workgroup's stores (acquire).
+template <int PT>
+__device__ __forceinline__ bool fin_count(int* fcount, int target, FinLds<PT>& L) {
+  __syncthreads();
+  if (threadIdx.x == 0)
+    L.last = __hip_atomic_fetch_add(fcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == target - 1;
+  __syncthreads();
+  const bool last = L.last != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+// The finish, by a whole workgroup of PT >= 256 threads (rows from fpart or
+// L.rowl).
+template <int PT>
+__device__ __forceinline__ void fin_finish(const FitDev& f, int with_grad, bool global, FinLds<PT>& L) {
+  constexpr int NB = kFinBlocks, NA = kFinA;
+  static_assert(PT >= kFinThreads, "the fix-up partials' tree needs 256 threads");
+  typedef __attribute__((address_space(1))) const double GD;
+  typedef __attribute__((address_space(1))) const int GI;
+  typedef __attribute__((address_space(1))) double GDw;
+  const int S = f.S, P = f.P, nresp = f.nresp, pu_float = f.pu_float, n_ct = f.n_ct, n_rt = f.n_rt;
+  const bool tab = f.kind == kTable && f.nresp > 0;
+  const bool rad = f.mv && f.n_rad > 0 && !f.joint;
+  const bool fixg = f.has_fix && with_grad;
+  GI* const fixflag = (GI*)f.fixflag;
+  GD* const bwdfix = (GD*)f.bwdfix;
+  GD* const rad_out = (GD*)f.rad_out;
+  GD* const rows = (GD*)f.fpart;
+  GDw* const out = (GDw*)f.out;
+  int* const fcount = f.fcount;
+  double* const out_host = f.out_host;
+  const double* const theta = f.theta;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // every load first: the rows (wave 0, lane c < kFinRow: column c of every
+  // row), the radial parts, the caller's sequence number and the fix-up
+  // partials (threads < 256: tiles t + 256 m)
+  double x[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) x[u] = PT == NT ? rows[u * kFinRow + lane] : rowl[u][lane];
-    if (lane == NA) {
-#pragma unroll
-      for (int u = 0; u < NB; ++u) fv |= (int)x[u];
-    } else {
-      v = x[0];
-#pragma unroll
-      for (int u = 1; u < NB; ++u) v += x[u];
+  for (int u = 0; u < NB; ++u)
+    x[u] = (w == 0 && lane < kFinRow) ? (global ? rows[u * kFinRow + lane] : L.rowl[u][lane]) : 0.0;
+  double rad_g = 0.0, rad_nll = 0.0, rad_fl = 0.0, rad_p = 0.0, rad_t = 0.0, seq = 0.0;
+  if (rad && w == 0) {
+    if (lane < S) rad_g = rad_out[2 + 16 + lane];
+    if (lane == 0) {
+      rad_nll = rad_out[0];
+      rad_fl = rad_out[1];
+      rad_p = rad_out[2 + 32];
+      rad_t = rad_out[2 + 33];
     }
   }
-  if (PT == NT && lane == 0) *fcount = 0;  // for the next launch (the stage timer repeats this kernel alone)
+  if (out_host && t == 0) seq = theta[P];
+  double fq[kBwdPart];
+  const bool f0 = fixg && t < kFinThreads && t < n_ct;
+  const int fl0 = f0 ? fixflag[n_rt + t] : 0;
+#pragma unroll
+  for (int c = 0; c < kBwdPart; ++c)  // whatever the flag (a tile without steps left holds stale values)
+    fq[c] = f0 ? bwdfix[(size_t)t * kBwdPart + c] : 0.0;
+  if (!fl0) {
+#pragma unroll
+    for (int c = 0; c < kBwdPart; ++c) fq[c] = 0.0;
+  }
+  if (fixg && t < kFinThreads)
+    for (int ct = t + kFinThreads; ct < n_ct; ct += kFinThreads)
+      if (fixflag[n_rt + ct]) {
+#pragma unroll
+        for (int c = 0; c < kBwdPart; ++c) fq[c] += bwdfix[(size_t)ct * kBwdPart + c];
+      }
+  if (fixg) {  // block-uniform: the fix-up partials through LDS, by column over runs of tiles
+    if (t < kFinThreads) {
+#pragma unroll
+      for (int c = 0; c < kBwdPart; ++c) L.fx[t][c] = fq[c];
+    }
+    __syncthreads();
+    if (t < kFinFixParts * kBwdPart) {
+      const int c = t / kFinFixParts, part = t % kFinFixParts;
+      const int k0 = part * kFinFixRun, k1 = min(k0 + kFinFixRun, kFinThreads);
+      double a = 0.0;
+      for (int k = k0; k < k1; ++k) a += L.fx[k][c];
+      L.fpsum[part][c] = a;
+    }
+    __syncthreads();
+  }
+  if (w != 0) return;
+  double v = 0.0;
+  int fv = 0;
+  if (lane == NA) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) fv |= (int)x[u];
+  } else if (lane < kFinRow) {
+    v = x[0];
+#pragma unroll
+    for (int u = 1; u < NB; ++u) v += x[u];
+    // row columns 1-4 (response parameters) and 8-23 (rates) take the fix-up
+    // partials' columns 0-3 and 4-19
+    const int fc = lane >= 1 && lane <= 4 ? lane - 1 : lane >= NA + 1 ? lane - NA - 1 + 4 : -1;
+    if (fixg && fc >= 0) {
+      double s = L.fpsum[0][fc];
+      for (int u = 1; u < kFinFixParts; ++u) s += L.fpsum[u][fc];
+      v += s;
+    }
+  }
+  if (global && lane == 0) *fcount = 0;  // for the next launch (the stage timer repeats a launch alone)
   double tot[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) tot[q] = __shfl(v, q, 64);
@@ -2059,11 +2116,26 @@ __global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* act
     }
   }
   if (out_host) {  // then the completion mark the caller spins on (all writers are in this wave)
-    __threadfence_system();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the results before the mark
     if (lane == 0) {
       out_host[2 + P] = seq;
-      __threadfence_system();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     }
+  }
+}
+
+template <int PT>  // threads per workgroup: kFinThreads (kFinBlocks workgroups per fit) or 1024 (one)
+__global__ void __launch_bounds__(PT) k_final(const FitDev* fits, const int* active, int with_grad) {
+  const FitDev& f = fits[active ? active[blockIdx.y] : blockIdx.y];
+  if (f.skip) return;  // block-uniform: a batched fit whose minimiser has finished
+  __shared__ FinLds<PT> L;
+  if (PT == kFinThreads) {  // one logical block per workgroup
+    fin_rows<PT>(f, with_grad, blockIdx.x, 1, true, L);
+    if (!fin_count<PT>(f.fcount, kFinBlocks, L)) return;
+    fin_finish<PT>(f, with_grad, true, L);
+  } else {
+    fin_rows<PT>(f, with_grad, 0, kFinBlocks / (PT / kFinThreads), false, L);
+    fin_finish<PT>(f, with_grad, false, L);
   }
 }
 
@@ -2074,6 +2146,36 @@ static void launch_final(const FitDev* d_fits, const int* d_active, int n, bool 
                        with_grad ? 1 : 0);
   else
     hipLaunchKernelGGL(k_final<1024>, dim3(1, n), dim3(1024), 0, st, d_fits, d_active, with_grad ? 1 : 0);
+}
+
+// One fit's backward fix-up sweep and final sums in one launch: workgroups
+// ct < n_ct as k_cells_bwd_fix, the kFinBlocks / 2 after them two logical
+// blocks of the final sums each; the workgroup counted last finishes.
+template <class R, int KIND, bool MV>
+__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix_final(const FitDev* fits, const int* active,
+                                                                         int pre) {
+  constexpr int NTH = kFixWaves * 64, LPB = NTH / kFinThreads;
+  static_assert(kFinBlocks % LPB == 0, "whole workgroups of logical blocks");
+  const FitDev& f = fits[active ? active[0] : 0];
+  if (f.skip) return;  // uniform: a device-minimised fit that has finished
+  __shared__ FinLds<NTH> L;
+  const int b = blockIdx.x, n_ct = f.n_ct;
+  if (b >= n_ct) {
+    fin_rows<NTH>(f, 1, (b - n_ct) * LPB, 1, true, L);
+  } else if (f.mv == (int)MV && f.fixflag[f.n_rt + b]) {
+    bwd_fix_tile<R, KIND, MV>(f, b, pre);
+    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // wave 0 wrote the partials
+  }
+  if (!fin_count<NTH>(f.fcount, n_ct + kFinBlocks / LPB, L)) return;
+  fin_finish<NTH>(f, 1, true, L);
+}
+
+template <class R, int KIND>
+static void launch_bwd_fix_final(bool mv, int n_ct, hipStream_t st, const FitDev* d_fits, const int* d_active,
+                                 int pre) {
+  const dim3 g(n_ct + kFinBlocks / (kFixWaves * 64 / kFinThreads)), b(kFixWaves * 64);
+  if (mv) hipLaunchKernelGGL((k_cells_bwd_fix_final<R, KIND, true>), g, b, 0, st, d_fits, d_active, pre);
+  else hipLaunchKernelGGL((k_cells_bwd_fix_final<R, KIND, false>), g, b, 0, st, d_fits, d_active, pre);
 }
 
 // Joint energy x radius x pulse-shape term (the alternative to the additive
@@ -2486,7 +2588,20 @@ void launch_stage(const FitDev* d_fits, const int* d_active, int n, const Launch
 
 void launch_eval(const FitDev* d_fits, const int* d_active, int n, const LaunchShape& L, bool with_grad,
                  hipStream_t st) {
-  for (int k = 0; k < kStages; ++k) launch_stage(d_fits, d_active, n, L, with_grad, k, st);
+  // one fit with the gradient: the final sums in the backward fix-up sweep's launch
+  const bool fused = n == 1 && with_grad && (L.kind == kGG || L.kind == kGauss);
+  for (int k = 0; k < kStages; ++k) {
+    if (fused && k == 6) {
+      launch_stage(d_fits, d_active, n, L, with_grad, kStageBwdMain, st);
+      const bool f32 = L.prec == kF32, mv = L.any_mv;
+      if (f32 && L.kind == kGauss) launch_bwd_fix_final<float, kGauss>(mv, L.max_ct, st, d_fits, d_active, 0);
+      if (f32 && L.kind == kGG) launch_bwd_fix_final<float, kGG>(mv, L.max_ct, st, d_fits, d_active, 0);
+      if (!f32 && L.kind == kGauss) launch_bwd_fix_final<double, kGauss>(mv, L.max_ct, st, d_fits, d_active, 0);
+      if (!f32 && L.kind == kGG) launch_bwd_fix_final<double, kGG>(mv, L.max_ct, st, d_fits, d_active, 0);
+    } else if (!(fused && k == 7)) {
+      launch_stage(d_fits, d_active, n, L, with_grad, k, st);
+    }
+  }
 }
 
 // Expected counts of every term over the full reco range (diagnostics):
