@@ -452,8 +452,11 @@ def main():
                 "flop_per_cell": FLOP_BWD_CELL}
 
     rl = roofline(st["cells_bwd"], st["cells_bwd_main"], 1)
-    rl["traffic"] = profiled("config2_hbm_counters.md", "traffic_bytes", "k_cells_bwd")
-    rl["traffic_unit"] = "HBM bytes per launch of k_cells_bwd (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+    t_main = profiled("config2_hbm_counters.md", "traffic_bytes", "k_cells_bwd")
+    t_fix = profiled("config2_hbm_counters.md", "traffic_bytes", "k_cells_bwd_fix")
+    rl["traffic"] = t_main + t_fix if t_main is not None and t_fix is not None else None
+    rl["traffic_unit"] = ("HBM bytes per launch of k_cells_bwd and k_cells_bwd_fix (rocprofv3 FETCH_SIZE + "
+                          "WRITE_SIZE, calibrated against a 256 MiB copy)")
     rl["valu_issue_frac"] = profiled("config2_valu_counters.md", "valu_issue", "k_cells_bwd")
     ceil_cps = m.cell_ceiling(th, reps=64)
     rl["measured_ceiling"] = {
@@ -484,6 +487,7 @@ def main():
         brl = roofline(bt["cells_bwd"], bt["cells_bwd_main"], a.batch)
         brl["forward_TFLOP_s"] = a.batch * cells * FLOP_FWD_CELL / (bt["cells_fwd"] * 1e-3) / 1e12
         brl["frac_of_ceiling"] = a.batch * cells / (bt["cells_bwd"] * 1e-3) / ceil_cps
+        brl["valu_issue_frac"] = profiled("config2_valu_counters.md", "valu_issue", "k_cells_bwd_batched")
         res["batched_eval"] = {
             "copies": a.batch, "evals_per_s": a.batch / (bt["total"] * 1e-3),
             "us_per_eval": bt["total"] * 1e3 / a.batch,
