@@ -1,45 +1,50 @@
 // HIP kernels of one likelihood evaluation (gfx950, wave64).
 //
 //   k_colparams   per true bin: response column parameters, support, chain
-//                 factors to the response parameters (Eq. 1's R_x(N_x, E; p)).
-//   k_cells_fwd   per (reco tile, listed true tiles): each wave evaluates the
-//                 CDF at 16 shared reco edges x 16 true bins, forms the cells
-//                 by differencing neighbour lanes and feeds them straight into
-//                 MFMA 16x16x4 as A with the species spectra as B:
-//                 M[j, s] += sum_i R[j, i] F^[i, s] (Eq. 1).  Tiles are added
-//                 in a fixed tree; cells never touch HBM.  When the gradient
-//                 is wanted it also evaluates dF/dc1, dF/dc2 at the edges and
-//                 stores each cell's differences (Dcell).
-//   k_reduce_M    FP64 sum of the forward partials (fixed order).
-//   k_rowterms    pile-up
-//                 M' = (1-p) M + p g^*M (Eq. 2) from LDS, expected counts of
-//                 every likelihood term per reco row (Eqs. 3-4), Poisson NLL
-//                 terms, the adjoint weights H and per-block partials.
+//                 factors to the response parameters (Eq. 1's R_x(N_x, E; p)),
+//                 and each wave step's column factor of the one-interval test.
+//   k_cells_fwd   per (reco tile, listed true tiles): each lane integrates the
+//                 response density of one column over its reco bin (Eq. 1's
+//                 cell, Gauss-Legendre in the column's variable) and the cells
+//                 are contracted with the spectra in FP64 -- one FMA per cell
+//                 for a single histogram, FP64 MFMA 16x16x4 with several species
+//                 histograms (M = R F^T).  Tiles are added in a fixed tree;
+//                 cells never touch HBM.  Wave steps whose bins are wide
+//                 against their columns, or start at x <= 0, are left to
+//   k_cells_fwd_fix  (composite quadrature, or a CDF difference).
+//   k_reduce_M    FP64 sum of the forward partials (several species histograms;
+//                 a single histogram's column is summed by k_rowterms).
+//   k_rowterms    pile-up M' = (1-p) M + p g^*M (Eq. 2) from LDS, expected
+//                 counts of every likelihood term per reco row (Eqs. 3-4),
+//                 Poisson NLL terms, the adjoint weights H, per-block partials.
 //   k_radial      radial term (Eq. 4) -- one block per fit.
 //   k_joint       joint energy x radius x pulse-shape term per reco row, over
 //                 the histogram's non-zero bins (closed-form sum of the
 //                 expected counts for the rest).
 //   k_adjoint     H~ = P^T H (the pile-up adjoint), from LDS; k_adjoint1 the
 //                 single-histogram w~ once per fit for batched launches.
-//   k_cells_bwd   per (true tile, 4 reco tiles): reads the cells' derivatives
-//                 in the two column parameters from Dcell; accumulates
+//   k_cells_bwd   per (true tile, RG reco tiles per wave): the cells again,
+//                 with their derivatives in the two column parameters;
 //                 alpha_i = sum_j W_ji dR_ji/dc1, beta_i = ... dc2 in FP64,
-//                 W_ji = sum_s H~_js r_s F^_si (FP64 MFMA per tile with
-//                 several species histograms), and contracts them with the
-//                 column chain factors into a per-block gradient partial.
+//                 contracted with the chain factors into a per-block partial
+//                 (W_ji = w~_j v_i, or an FP64 MFMA product with several
+//                 species histograms).  The steps left go to
+//   k_cells_bwd_fix  (one fit: k_cells_bwd_fix_final, with the final sums).
 //   k_final       fixed-order totals: NLL, rate gradient, response gradient;
 //                 also written to the caller's pinned host buffer when set.
 //   k_table_gemm  tabulated response, at build: M_g = R_g F^T (FP64 MFMA);
 //   k_table       per evaluation: M and dM/dlam interpolated between grid
-//                 points (replaces k_colparams .. k_reduce_M).
-//   k_mark        a server step's completion mark; k_cell_ceiling the cell
-//                 arithmetic alone, for the measured ceiling.
+//                 points (replaces the column and cell kernels).
+//   k_fit_start, k_fit_step  the device-minimised batch's quasi-Newton steps
+//                 (one wave per fit); k_mark a server step's completion mark;
+//                 k_cell_ceiling the cell arithmetic alone, for the measured
+//                 ceiling.
 //
-// No reduction uses atomics: every sum has a fixed order, so a fit's result
-// does not depend on what else runs in the same launch.  Cross-block sums are
-// separate launches rather than last-block elections: an agent-scope fence
-// per block writes back the XCD's L2 on gfx950 and costs far more than a
-// kernel boundary inside a graph.
+// Every sum has a fixed order, so a fit's result does not depend on what else
+// runs in its launch, nor on the form of the launch.  The one device-scope
+// counter (the final sums of a single fit) only elects the workgroup that adds
+// the rows, in their fixed order; an election in every block of a sweep would
+// cost an L2 write-back per block on gfx950 (agent-scope release).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

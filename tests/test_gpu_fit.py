@@ -56,11 +56,11 @@ def test_plain_fit_matches_oracle_minimum(bx, name, prec, tol):
         assert np.all(dev[: d.S] <= 1e-6), dev
         assert np.all(dsig[d.S:] <= 1e-6), dsig
     else:
-        # FP32 cells: their rounding (~1e-7 relative per cell over ~1e6 cells)
-        # biases the gradient, which moves the minimum by ~1e-4 sigma on the
-        # 3000 x 900 grid; every parameter must sit within 1e-3 sigma
+        # FP32 cells alone: their rounding (~1e-7 relative per cell) biases the
+        # gradient a little and EDM stops at 1e-8; the minimum moves by ~3e-6
+        # sigma on the 3000 x 900 grid; every parameter within 1e-4 sigma
         dall = np.abs(r.x - z["theta"]) / np.where(err > 0, err, np.inf)
-        assert np.all(dall <= 1e-3), dall
+        assert np.all(dall <= 1e-4), dall
     assert abs(r.nll - float(z["nll"])) <= 1e-9 * abs(float(z["nll"]))
 
 
