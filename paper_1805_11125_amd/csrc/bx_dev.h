@@ -190,6 +190,7 @@ void launch_fit_start(void* opts, FitSlot* slots, FitDev* fits, int n, hipStream
 void launch_fit_step(void* opts, FitSlot* slots, FitDev* fits, int n, int* d_count, int* d_running,
                      const int* d_ready, hipStream_t st);
 void launch_mark(double* d_mark, double v, hipStream_t st);
+void launch_mark_from(double* d_mark, const double* d_src, hipStream_t st);
 void launch_table_gemm(const double* d_R, const double* d_F64, double* d_Mg, int G, int N, int T, hipStream_t st);
 void launch_cell_ceiling(const FitDev* d_fit, int kind, int prec, int blocks, int reps, double* d_sink,
                          hipStream_t st);

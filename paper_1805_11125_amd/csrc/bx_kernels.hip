@@ -36,7 +36,8 @@
 //   k_table       per evaluation: M and dM/dlam interpolated between grid
 //                 points (replaces the column and cell kernels).
 //   k_fit_start, k_fit_step  the device-minimised batch's quasi-Newton steps
-//                 (one wave per fit); k_mark a server step's completion mark;
+//                 (one wave per fit); k_mark, k_mark_from a server step's
+//                 completion mark;
 //                 k_cell_ceiling the cell arithmetic alone, for the measured
 //                 ceiling.
 //
@@ -2448,6 +2449,19 @@ __global__ void k_mark(double* mark, double v) {
 
 void launch_mark(double* d_mark, double v, hipStream_t st) {
   hipLaunchKernelGGL(k_mark, dim3(1), dim3(1), 0, st, d_mark, v);
+}
+
+// The same with the value read from pinned host memory at run time (a
+// captured step then marks the step number the host wrote for this replay).
+__global__ void k_mark_from(double* mark, const double* src) {
+  const double v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+  *mark = v;
+  __threadfence_system();
+}
+
+void launch_mark_from(double* d_mark, const double* d_src, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_from, dim3(1), dim3(1), 0, st, d_mark, d_src);
 }
 
 // ---------------------------------------------------------------------------

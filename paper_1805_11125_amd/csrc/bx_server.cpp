@@ -96,6 +96,8 @@ static int64_t now_ns() {
 
 constexpr int kThetaStride = 40;  // theta[P] and the step number, 5 cache lines
 constexpr int kOutStride = 40;    // nll, grad[P], flags, completion mark
+constexpr int kSeqAt = 64;        // the step number in the mark's allocation (its own cache line)
+constexpr int kGraphFits = 16;    // steps of at most this many fits are replayed from a graph
 
 struct Req {
   uint64_t ticket = 0;
@@ -149,6 +151,12 @@ struct bx_server {
   double* dh_mark = nullptr;
   double seq = 0.0;               // steps so far (completion marks)
   int* h_active = nullptr;        // pinned
+  // A step over the same fits as the last two is replayed from a graph
+  // captured once (a few fits: their launches would otherwise cost the host
+  // more than the device's work); the step number comes from h_mark[kSeqAt].
+  hipGraphExec_t step_exec = nullptr;
+  std::vector<uint64_t> step_key;
+  int stable = 0;
   std::vector<int> free_slots;
   std::deque<std::shared_ptr<Req>> queue;
   std::vector<std::shared_ptr<Req>> active;
@@ -224,17 +232,10 @@ static void retire(bx_server* s, const std::shared_ptr<Req>& r) {
 // the step number), finish_step waits and hands the results to the
 // minimisers (false when the launch failed); the worker admits new fits in
 // between, while the step runs on the GPU.
-static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
-  const double seq = (s->seq += 1.0);
-  // stage every active fit's next point (with the step number after it)
-  s->pool->run((int)act.size(), [&](int k) {
-    auto& r = act[k];
-    double* th = s->h_theta + (size_t)r->slot * kThetaStride;
-    r->opt->next(th);
-    th[r->h.P] = seq;
-    flush_lines(th, r->h.P + 1);
-  });
-  // one batched launch per group of (kind, precision, forward tiles per wave)
+// One batched launch per group of (kind, precision, forward tiles per wave),
+// then the step's mark; with lists = false the groups' device lists are
+// taken as in place.
+static void enqueue_step(bx_server* s, const std::vector<std::shared_ptr<Req>>& act, bool lists) {
   for (int grp = 0; grp < kGroups; ++grp) {
     int n = 0;
     LaunchShape L{};
@@ -249,10 +250,54 @@ static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) 
     // a multiple of 8 fits (the slot past the last never runs): the kernels
     // then keep each fit's blocks on one XCD
     while (n >= 64 && (n & 7)) act_list[n++] = s->max_slots;
-    (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
+    if (lists) (void)hipMemcpyAsync(d_list, act_list, sizeof(int) * n, hipMemcpyHostToDevice, s->stream);
     launch_eval(s->d_fits, d_list, n, L, true, s->stream);
   }
-  launch_mark(s->dh_mark, seq, s->stream);
+  launch_mark_from(s->dh_mark, s->dh_mark + kSeqAt, s->stream);
+}
+
+// Captures a step's launches (without the list copies) as a graph in
+// s->step_exec; on failure it stays null and the step is launched directly.
+static void capture_step(bx_server* s, const std::vector<std::shared_ptr<Req>>& act) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
+  enqueue_step(s, act, false);
+  if (hipStreamEndCapture(s->stream, &g) != hipSuccess || !g) return;
+  if (hipGraphInstantiate(&s->step_exec, g, nullptr, nullptr, 0) != hipSuccess) s->step_exec = nullptr;
+  (void)hipGraphDestroy(g);
+}
+
+static double launch_step(bx_server* s, std::vector<std::shared_ptr<Req>>& act) {
+  const double seq = (s->seq += 1.0);
+  // stage every active fit's next point (with the step number after it)
+  s->pool->run((int)act.size(), [&](int k) {
+    auto& r = act[k];
+    double* th = s->h_theta + (size_t)r->slot * kThetaStride;
+    r->opt->next(th);
+    th[r->h.P] = seq;
+    flush_lines(th, r->h.P + 1);
+  });
+  s->h_mark[kSeqAt] = seq;
+  flush_lines(s->h_mark + kSeqAt, 1);
+  // the same fits (and placements) as the last step?
+  std::vector<uint64_t> key;
+  key.reserve(act.size());
+  for (auto& r : act) key.push_back(2 * r->ticket + (r->polished ? 1 : 0));
+  if (key == s->step_key) {
+    ++s->stable;
+  } else {
+    s->step_key.swap(key);
+    s->stable = 0;
+    if (s->step_exec) (void)hipGraphExecDestroy(s->step_exec);
+    s->step_exec = nullptr;
+  }
+  // their device lists are in place since the last step: replay (capturing
+  // the launches once)
+  if (s->stable >= 2 && (int)act.size() <= kGraphFits) {
+    if (!s->step_exec) capture_step(s, act);
+    if (s->step_exec && hipGraphLaunch(s->step_exec, s->stream) == hipSuccess) return seq;
+  }
+  enqueue_step(s, act, true);
   return seq;
 }
 
@@ -416,6 +461,7 @@ bx_status bx_server_destroy(bx_server* s) {
     s->worker.join();
   }
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->step_exec) (void)hipGraphExecDestroy(s->step_exec);
   if (s->d_fits) (void)hipFree(s->d_fits);
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_theta) (void)hipFree(s->d_theta);
