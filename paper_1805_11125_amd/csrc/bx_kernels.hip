@@ -1541,7 +1541,9 @@ __global__ void __launch_bounds__(kBwdWaves * 64) k_cells_bwd(const FitDev* fits
 // they are about 0.4 % of the wave steps: the reco bin from x <= 0 (its cell
 // the CDF at x_1) and wide low-energy bins against narrow columns.
 
-constexpr int kFixWaves = 8;  // waves per fix-up block
+constexpr int kFixWaves = 8;     // waves per forward fix-up block
+constexpr int kBwdFixWaves = 4;  // waves per backward fix-up block (a true tile has few entries:
+                                 // idle waves would only hold a CU's registers)
 
 // Compacts the entries with want = true of one chunk of NW * 64 candidates
 // (candidate c at thread c) into list[], in candidate order; returns their
@@ -1667,7 +1669,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
 // evaluates the step.  Writes bwdfix[ct] (zeros where nothing is left).
 template <class R, int KIND, bool MV>
 __device__ __forceinline__ void bwd_fix_tile(const FitDev& f, int ct, int pre) {
-  constexpr int NW = kFixWaves, NTH = NW * 64;
+  constexpr int NW = kBwdFixWaves, NTH = NW * 64;
   typedef __attribute__((address_space(1))) const double GD;
   typedef __attribute__((address_space(1))) const int GI;
   __shared__ int list[NTH], wcount[NW];
@@ -1792,7 +1794,7 @@ __device__ __forceinline__ void bwd_fix_tile(const FitDev& f, int ct, int pre) {
 }
 
 template <class R, int KIND, bool MV>
-__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
+__global__ void __launch_bounds__(kBwdFixWaves * 64) k_cells_bwd_fix(const FitDev* fits, const int* active, int pre,
                                                                    int use_flags) {
   const int2 fb2 = fit_block();
   const FitDev& f = fits[active ? active[fb2.y] : fb2.y];
@@ -2155,12 +2157,12 @@ static void launch_final(const FitDev* d_fits, const int* d_active, int n, bool 
 }
 
 // One fit's backward fix-up sweep and final sums in one launch: workgroups
-// ct < n_ct as k_cells_bwd_fix, the kFinBlocks / 2 after them two logical
-// blocks of the final sums each; the workgroup counted last finishes.
+// ct < n_ct as k_cells_bwd_fix, the kFinBlocks after them one logical block
+// of the final sums each; the workgroup counted last finishes.
 template <class R, int KIND, bool MV>
-__global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix_final(const FitDev* fits, const int* active,
+__global__ void __launch_bounds__(kBwdFixWaves * 64) k_cells_bwd_fix_final(const FitDev* fits, const int* active,
                                                                          int pre) {
-  constexpr int NTH = kFixWaves * 64, LPB = NTH / kFinThreads;
+  constexpr int NTH = kBwdFixWaves * 64, LPB = NTH / kFinThreads;
   static_assert(kFinBlocks % LPB == 0, "whole workgroups of logical blocks");
   const FitDev& f = fits[active ? active[0] : 0];
   if (f.skip) return;  // uniform: a device-minimised fit that has finished
@@ -2179,7 +2181,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_bwd_fix_final(const Fi
 template <class R, int KIND>
 static void launch_bwd_fix_final(bool mv, int n_ct, hipStream_t st, const FitDev* d_fits, const int* d_active,
                                  int pre) {
-  const dim3 g(n_ct + kFinBlocks / (kFixWaves * 64 / kFinThreads)), b(kFixWaves * 64);
+  const dim3 g(n_ct + kFinBlocks / (kBwdFixWaves * 64 / kFinThreads)), b(kBwdFixWaves * 64);
   if (mv) hipLaunchKernelGGL((k_cells_bwd_fix_final<R, KIND, true>), g, b, 0, st, d_fits, d_active, pre);
   else hipLaunchKernelGGL((k_cells_bwd_fix_final<R, KIND, false>), g, b, 0, st, d_fits, d_active, pre);
 }
@@ -2483,7 +2485,7 @@ static void launch_fwd(int cg, bool mv, dim3 grid, dim3 blk, hipStream_t st, con
 template <class R, int KIND>
 static void launch_fix(bool fwd, bool mv, dim3 grid, hipStream_t st, const FitDev* d_fits, const int* d_active,
                        int pre, int use_flags, int nsplit) {
-  const dim3 b(kFixWaves * 64);
+  const dim3 b((fwd ? kFixWaves : kBwdFixWaves) * 64);
   if (fwd && mv)
     hipLaunchKernelGGL((k_cells_fwd_fix<R, KIND, true>), grid, b, 0, st, d_fits, d_active, use_flags, nsplit);
   if (fwd && !mv)
