@@ -14,7 +14,8 @@ CG changes no result bit (the forward partials are summed in a fixed tree),
 so the two modes take their own best CG.  RG groups the backward partials, so
 both modes share one RG (a fit gives the same bits alone and in a batch): the
 one whose best times, alone and batched, are together the least above the
-best of each mode.  The block sizes (waves per forward and backward
+best of each mode, the time alone counted `ws` times (3 for the shape class of
+the 3000 x 900 single fit, whose latency the plain path serves; 1 otherwise).  The block sizes (waves per forward and backward
 workgroup, fits per workgroup = 1) are compile-time constants of the kernels,
 chosen by the measurements recorded with them.
 
@@ -43,17 +44,18 @@ def _time(bx, desc, data, prec, theta, cg, rg, copies):
 
 
 def tune(classes, copies=128, log=print):
-    """classes: list of (kind, prec, Tmin, Tmax, Nmin, Nmax, desc, data, theta).
+    """classes: list of (kind, prec, Tmin, Tmax, Nmin, Nmax, desc, data, theta, ws).
     Returns the table lines."""
     import paper_1805_11125_amd as bx
     lines = []
-    for kind, prec, tmin, tmax, nmin, nmax, desc, data, theta in classes:
+    for kind, prec, tmin, tmax, nmin, nmax, desc, data, theta, ws in classes:
         res = {(cg, rg): _time(bx, desc, data, prec, theta, cg, rg, copies)
                for rg in RG_CANDIDATES for cg in CANDIDATES}
         best_mode = [min(v[mode] for v in res.values()) for mode in (0, 1)]
 
         def cost(rg):  # relative excess over each mode's best, at the best CG for this RG
-            return sum(min(res[(cg, rg)][mode] for cg in CANDIDATES) / best_mode[mode] for mode in (0, 1))
+            return sum((ws if mode == 0 else 1) * min(res[(cg, rg)][mode] for cg in CANDIDATES) / best_mode[mode]
+                       for mode in (0, 1))
 
         rg = min(RG_CANDIDATES, key=cost)
         for batched in (0, 1):
@@ -73,14 +75,14 @@ def standard_classes():
     import synth
     out = []
     d1, x1 = synth.load("c1")
-    out.append((0, 1, 1, 2000, 1, 2000, d1, x1, d1.theta_true))
+    out.append((0, 1, 1, 2000, 1, 2000, d1, x1, d1.theta_true, 1))
     d2, x2 = synth.load("c2")
     th2 = d2.theta_true * (1 + 0.01 * np.random.default_rng(3).standard_normal(d2.P))
     base, per_species, theta = synth.catalogue()
     t = synth.toy(9, per_species, theta)   # a short reco window (303 bins)
-    out.append((1, 0, 1, 100000, 1, 600, synth.toy_desc(base, t), synth.Data(energy=t.counts), t.theta0))
-    out.append((1, 0, 1, 100000, 601, 100000, d2, x2, th2))
-    out.append((1, 1, 1, 100000, 1, 100000, d2, x2, th2))
+    out.append((1, 0, 1, 100000, 1, 600, synth.toy_desc(base, t), synth.Data(energy=t.counts), t.theta0, 1))
+    out.append((1, 0, 1, 100000, 601, 100000, d2, x2, th2, 3))
+    out.append((1, 1, 1, 100000, 1, 100000, d2, x2, th2, 1))
     return out
 
 
