@@ -54,6 +54,8 @@ struct ColPar {
   int jlo, jhi;     // cells that may be non-zero (support)
   int bad;          // domain flags
   int pad;
+  double e1[3];     // GG: the cell of the reco bin from x <= 0 (row0), the CDF at its upper edge,
+                    // and its two derivatives as the fix-up sweeps form them; 0 beyond the support
 };
 
 struct FitDev {
@@ -63,6 +65,7 @@ struct FitDev {
   int n_rt, n_ct, CG, n_cg, n_fb, RG, n_rg, n_rowblk;  // n_cg: forward chunks, n_fb: forward blocks per reco tile
   int n_cpblk, n_bwdblk;  // column-parameter blocks, backward blocks
   int uniform;            // reco bins of equal width
+  int row0;               // GG: the reco bin from x <= 0 into x > 0 (its cell is F(x_row0+1)), or -1
   int vsum;               // one energy histogram with analytic cells: the sweeps contract the cells
                           // with v_i = sum_s r_s F^_si (mu0 = R v) and the rate gradient is
                           // F^T (R^T w~); otherwise per-species M = R F^T (FP64 MFMA)

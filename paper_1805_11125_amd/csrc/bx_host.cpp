@@ -595,6 +595,7 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   f.gg = h.gg;
   if (shared) {  // inputs (and what is derived from them) already in place
     f.uniform = shared->uniform;
+    f.row0 = shared->row0;
     f.x0 = shared->x0;
     f.inv_w = shared->inv_w;
     return BX_OK;
@@ -604,6 +605,9 @@ bx_status place_fit(const HostModel& h, void* base, DeviceFit* df, hipStream_t s
   bool uni = true;
   for (int j = 1; j < h.N && uni; ++j) uni = std::fabs((h.xraw[j + 1] - h.xraw[j]) - w0) <= 1e-12 * std::fabs(w0);
   f.uniform = uni ? 1 : 0;
+  f.row0 = -1;
+  for (int j = 0; j < h.N && h.kind == kGG && f.row0 < 0; ++j)
+    if (h.xraw[j] <= 0.0 && h.xraw[j + 1] > 0.0) f.row0 = j;
   f.x0 = h.xraw[0];
   f.inv_w = 1.0 / w0;
   BX_HIP(up(f.xraw, h.xraw, st), "upload");

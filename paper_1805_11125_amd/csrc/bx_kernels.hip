@@ -439,6 +439,31 @@ __global__ void __launch_bounds__(kCpBlock) k_colparams(const FitDev* fits, cons
     }
     if (bad & (kBadSigma | kBadGG | kBadTheta)) { jlo = 1 << 30; jhi = -1; }
     c.jlo = jlo; c.jhi = jhi; c.bad = bad; c.pad = 0;
+    // GG: the cell of the reco bin from x <= 0, F(x) at its upper edge (the
+    // value in FP64, the derivatives in the cell precision, as the fix-up
+    // sweeps form a CDF-difference cell), for a support that reaches it
+    c.e1[0] = c.e1[1] = c.e1[2] = 0.0;
+    if (f.kind == kGG && f.row0 >= 0 && jlo <= f.row0 && f.row0 <= jhi) {
+      const double lnx1 = f.xe[f.row0 + 1];
+      GGCol<double> g;
+      g.ct = c.c0;
+      g.k = c.f64[0]; g.ik = c.f64[1]; g.skh = c.f64[2]; g.cR = c.f64[3]; g.ce = c.f64[4];
+      g.dlngs = c.f64[5]; g.lnk_psi = c.f64[6]; g.p = c.f64[7];
+      c.e1[0] = cell_from(0.0, gg_edge<double, false>(lnx1, g).v);
+      if (f.prec == kF32) {
+        GGCol<float> h;
+        h.ct = c.c0;
+        h.k = c.f32[0]; h.ik = c.f32[1]; h.skh = c.f32[2]; h.cR = c.f32[3]; h.ce = c.f32[4];
+        h.dlngs = c.f32[5]; h.lnk_psi = c.f32[6]; h.p = c.f32[7];
+        const EdgeVal<float> e = gg_edge<float, true>(lnx1, h);
+        c.e1[1] = e.d1;
+        c.e1[2] = e.d2;
+      } else {
+        const EdgeVal<double> e = gg_edge<double, true>(lnx1, g);
+        c.e1[1] = e.d1;
+        c.e1[2] = e.d2;
+      }
+    }
     cpo[i] = c;
     // the column's factor of the sweeps' one-interval test, as the cells
     // form it (step_lean)
@@ -602,14 +627,17 @@ __device__ __forceinline__ CellVal<R> cell_lean(const ColPre<R>& c, const RowQ<R
 }
 
 template <class R, int KIND, bool D>
-__device__ __forceinline__ CellVal<R> cell_general(const ColPre<R>& c, const RowQ<R>& rq, double xe, bool ok) {
+__device__ __forceinline__ CellVal<R> cell_general(const ColPre<R>& c, const RowQ<R>& rq, double xe, bool ok,
+                                                   bool zrow) {
   CellVal<R> o;
   o.v = 0.0;
   o.d1 = o.d2 = (R)0;
   // inverse width of the column in the quadrature variable: GG sqrt(k) in
   // t = ln(y/k); Gaussian 1/sigma (none for a zero width)
   const double iw = KIND == kGG ? 1.4142135623730950488 * (double)c.s[2] : (c.c1 > 0.0 ? c.c1 : NAN);
-  const int ns = ok ? quad_intervals(rq.b, iw) : 1;  // lanes without a cell side with quadrature
+  // lanes without a cell side with quadrature; the GG bin from x <= 0 (zrow)
+  // takes the cell k_colparams formed, and needs no edge from its neighbour
+  const int ns = ok && !zrow ? quad_intervals(rq.b, iw) : 1;
   const unsigned long long eb = __ballot(ns == 0);
   const int lane = threadIdx.x & 63;
   const bool row_edge = ((eb >> (lane & 48)) & 0xffffull) != 0;  // row-uniform
@@ -618,7 +646,7 @@ __device__ __forceinline__ CellVal<R> cell_general(const ColPre<R>& c, const Row
   // a series or continued fraction of up to ~100 terms, so the other lanes
   // leave it alone
   const bool need = ((eb >> lane) & 1) || ((lane & 15) > 0 && ((eb >> (lane - 1)) & 1));
-  if (ns > 0) {
+  if (ns > 0 && !zrow) {
     if constexpr (KIND == kGG)
       o = gg_cell_quad<R, RowQ<R>::NQ, D>(rq.a, rq.b, c.c0, rq.g, c.s[0], c.c1, c.s[6], c.s[7] * c.s[0], ns);
     else
@@ -637,6 +665,14 @@ __device__ __forceinline__ CellVal<R> cell_general(const ColPre<R>& c, const Row
         o.d1 = (R)(d1h - e.d1);
         o.d2 = (R)(d2h - e.d2);
       }
+    }
+  }
+  if (zrow) {
+    GColPar* cp = c.cp;
+    o.v = cp->e1[0];
+    if (D) {
+      o.d1 = (R)cp->e1[1];
+      o.d2 = (R)cp->e1[2];
     }
   }
   if (!ok) {
@@ -1611,6 +1647,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
   const bool row_ok = (jr < kRowStep) && (j0 + jr < N);
   const double xe = ((GD*)f.xe)[min(j0 + jr, N)];
   const RowQ<R> rq = load_rowq<R, KIND>(f, min(j0 + jr, N - 1));
+  const bool zrow = KIND == kGG && row_ok && j0 + jr == f.row0;  // the bin from x <= 0
   // logical share ls takes the entries e = ls NW + wv (mod kFixSplit NW),
   // whatever the number of blocks that run the shares (same sums either way)
   for (int ls = sh; ls < kFixSplit; ls += nsplit) {
@@ -1628,7 +1665,7 @@ __global__ void __launch_bounds__(kFixWaves * 64) k_cells_fwd_fix(const FitDev* 
         const int ent = list[e];
         const int i = (ent >> 2) * kColTile + 4 * (ent & 3) + g;
         const ColPre<R> c = fix_col<R, KIND>(f, i, MV && i < T ? F64[i * kSP + jr] : 0.0, MV);
-        const CellVal<R> ev = cell_general<R, KIND, false>(c, rq, xe, row_ok && i < T);
+        const CellVal<R> ev = cell_general<R, KIND, false>(c, rq, xe, row_ok && i < T, zrow);
         if constexpr (MV) acc = mfma16(ev.v, c.v, acc);
         else acc = fma(ev.v, c.v, acc);
       }
@@ -1741,7 +1778,7 @@ __device__ __forceinline__ void bwd_fix_tile(const FitDev& f, int ct, int pre) {
         if (row_ok) w1 = wsrc[(size_t)j * kSP];
         Wq = w1 * c.v;
       }
-      const CellVal<R> ev = cell_general<R, KIND, true>(c, rq, xe, row_ok && i < T);
+      const CellVal<R> ev = cell_general<R, KIND, true>(c, rq, xe, row_ok && i < T, KIND == kGG && j == f.row0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q != qe) continue;  // wave-uniform
