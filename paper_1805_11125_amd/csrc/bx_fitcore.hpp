@@ -11,9 +11,12 @@
 // parameter per evaluation, and is refined by BFGS updates.  Each step solves
 // B_FF d_F = -g_F on the free set F (parameters not held at a bound by the
 // gradient) by Cholesky with a diagonal shift when B_FF is not positive
-// definite, truncates the step at the box, and backtracks (Armijo, quadratic
-// interpolation).  EDM = g_F^T B_FF^-1 g_F / 2; the fit has converged when it
-// falls below the tolerance.
+// definite; parameters whose Newton component would cross their bound are
+// held on it and the rest solve again with that coupling.  The step is
+// truncated at the box and backtracks (Armijo, quadratic interpolation).
+// EDM, the decrease the quadratic model predicts for the step
+// (g_F^T B_FF^-1 g_F / 2 when nothing crosses), ends the fit when it falls
+// below the tolerance.
 //
 // The minimiser is compiled for the host (plain path, fit server) and for the
 // device (the batched fits' minimiser steps, k_fit_step): one code, with
@@ -241,6 +244,7 @@ class Bfgs {
  private:
   enum { kInit, kHess, kSearch, kDone, kReeval };
   static constexpr double kProbe = 1e-4;  // Hessian probe step (scaled units)
+  static constexpr int kHoldPasses = 4;  // newton_dir: rounds of holding crossing parameters
 
   BX_FHD double lo_u(int a) const { return pb_.lo[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
   BX_FHD double hi_u(int a) const { return pb_.hi[pb_.idx[a]] / pb_.scale[pb_.idx[a]]; }
@@ -256,23 +260,10 @@ class Bfgs {
     xt_[q] = v * pb_.scale[q];
   }
 
-  // Newton direction on the free set at point x with gradient g:
-  // B_FF d_F = -g_F (Cholesky, shifted if needed); returns EDM = -g.d/2 and
-  // writes d (scaled units, zero on held parameters) when d != nullptr.
-  BX_FHD double newton_dir(const double* g, const double* x, double* d) const {
+  // Cholesky solve of B_FF z = r on the free set fr[0..m) (a diagonal shift
+  // when B_FF is not positive definite); z may alias nothing else.
+  BX_FHD void solve_free(const int* fr, int m, const double* r, double* z) const {
     const int n = pb_.nf;
-    int* const fr = wi_;  // work arrays are members: on the device they live with the state in LDS
-    double* const gu = wa_;
-    int m = 0;
-    for (int a = 0; a < n; ++a) {
-      const int q = pb_.idx[a];
-      gu[a] = g[q] * pb_.scale[q];
-      const double v = x[q] / pb_.scale[q];
-      const bool held = (v <= lo_u(a) && gu[a] > 0) || (v >= hi_u(a) && gu[a] < 0);
-      if (d) d[a] = 0.0;
-      if (!held) fr[m++] = a;
-    }
-    if (m == 0) return 0.0;
     double dmax = 0.0;
     for (int i = 0; i < m; ++i) dmax = std::max(dmax, std::fabs(B_[fr[i] * n + fr[i]]));
     if (!(dmax > 0)) dmax = 1.0;
@@ -298,23 +289,99 @@ class Bfgs {
       shift = shift > 0 ? 4.0 * shift : 1e-10 * dmax;
     }
     double* const y = wb_;
-    double* const dd = wc_;
-    for (int i = 0; i < m; ++i) {  // L y = -g
-      double t = -gu[fr[i]];
+    for (int i = 0; i < m; ++i) {  // L y = r
+      double t = r[i];
       for (int k = 0; k < i; ++k) t -= L[i * m + k] * y[k];
       y[i] = t / L[i * m + i];
     }
-    for (int i = m - 1; i >= 0; --i) {  // L^T d = y
+    for (int i = m - 1; i >= 0; --i) {  // L^T z = y
       double t = y[i];
-      for (int k = i + 1; k < m; ++k) t -= L[k * m + i] * dd[k];
-      dd[i] = t / L[i * m + i];
+      for (int k = i + 1; k < m; ++k) t -= L[k * m + i] * z[k];
+      z[i] = t / L[i * m + i];
     }
+  }
+
+  // Step at point x with gradient g.  The free set F holds the parameters
+  // that the gradient does not push out of the box from a bound they sit on;
+  // the Newton step solves B_FF d_F = -g_F.  A free parameter whose Newton
+  // component would cross its bound is then held on that bound (it moves
+  // there), and the others solve again with that move's coupling,
+  // B_F'F' d_F' = -(g_F' + B_F'H m_H), up to kHoldPasses times.  Clipping
+  // the first step at the box instead ignores the coupling, and the clipped
+  // step of a correlated fit can fail to descend, so that a parameter a hair
+  // above its bound stalls the fit.  When no component crosses, or the held
+  // step predicts no decrease, the step is the plain Newton step on F.
+  // Returns EDM, the decrease the quadratic model predicts for the step
+  // (g_F^T B_FF^-1 g_F / 2 for the plain step), and writes d (scaled units)
+  // when d != nullptr.
+  BX_FHD double newton_dir(const double* g, const double* x, double* d) const {
+    const int n = pb_.nf;
+    int* const fr = wi_;  // work arrays are members: on the device they live with the state in LDS
+    double* const gu = wa_;
+    double* const dd = wc_;
+    double* const r = wd_;
+    double* const dh = we_;  // the held step: moves of the held parameters, then d_F'
+    int m = 0;
+    for (int a = 0; a < n; ++a) {
+      const int q = pb_.idx[a];
+      gu[a] = g[q] * pb_.scale[q];
+      const double v = x[q] / pb_.scale[q];
+      const bool held = (v <= lo_u(a) && gu[a] > 0) || (v >= hi_u(a) && gu[a] < 0);
+      if (d) d[a] = 0.0;
+      dh[a] = 0.0;
+      if (!held) fr[m++] = a;
+    }
+    if (m == 0) return 0.0;
+    for (int i = 0; i < m; ++i) r[i] = -gu[fr[i]];
+    solve_free(fr, m, r, dd);
     double gd = 0.0;
     for (int i = 0; i < m; ++i) {
       gd += gu[fr[i]] * dd[i];
       if (d) d[fr[i]] = dd[i];
     }
-    return -0.5 * gd;
+    const double edm0 = -0.5 * gd;
+    // free parameters whose Newton component crosses their bound
+    bool crossed = false;
+    for (int pass = 0; pass < kHoldPasses; ++pass) {
+      int k = 0;
+      bool more = false;
+      for (int i = 0; i < m; ++i) {
+        const int a = fr[i];
+        const double v = x[pb_.idx[a]] / pb_.scale[pb_.idx[a]];
+        if (v + dd[i] < lo_u(a)) {
+          dh[a] = lo_u(a) - v;
+          more = true;
+        } else if (v + dd[i] > hi_u(a)) {
+          dh[a] = hi_u(a) - v;
+          more = true;
+        } else {
+          fr[k++] = a;
+        }
+      }
+      if (!more) break;
+      crossed = true;
+      m = k;
+      if (m == 0) break;
+      for (int i = 0; i < m; ++i) {
+        double t = -gu[fr[i]];
+        for (int b = 0; b < n; ++b) t -= B_[fr[i] * n + b] * dh[b];
+        r[i] = t;
+      }
+      solve_free(fr, m, r, dd);
+    }
+    if (!crossed) return edm0;
+    for (int i = 0; i < m; ++i) dh[fr[i]] = dd[i];
+    // predicted decrease of the held step: -(g.d + d^T B d / 2)
+    double q = 0.0;
+    for (int a = 0; a < n; ++a) {
+      double bd = 0.0;
+      for (int b = 0; b < n; ++b) bd += B_[a * n + b] * dh[b];
+      q += dh[a] * (gu[a] + 0.5 * bd);
+    }
+    if (!(-q > 0)) return edm0;  // no decrease predicted: the plain step
+    if (d)
+      for (int a = 0; a < n; ++a) d[a] = dh[a];
+    return -q;
   }
 
   BX_FHD void start_iteration() {
@@ -404,7 +471,7 @@ class Bfgs {
   double hsign_ = 1.0;
   double x_[32], xt_[32], g_[32], d_[32], B_[32 * 32], Hs_[32 * 32];
   mutable double L_[32 * 32];  // Cholesky factor of the free block of B
-  mutable double wa_[32], wb_[32], wc_[32];  // work vectors of newton_dir and accept
+  mutable double wa_[32], wb_[32], wc_[32], wd_[32], we_[32];  // work vectors of newton_dir and accept
   mutable int wi_[32];
   double f_ = INFINITY, alpha_ = 1.0, slope_ = 0.0, edm_ = INFINITY;
 };
