@@ -237,6 +237,36 @@ def test_device_minimised_batch_equals_plain(bx):
         print("device-minimised:", [(b.status, b.n_eval, f"{b.edm:.1e}") for b in bat])
 
 
+def test_toy_fits_converge_at_the_bounds(bx):
+    # 256 toy fits (FP32 cells, then FP64): the minimiser holds a rate whose
+    # Newton step would cross zero on its bound and solves again for the
+    # rest, so fits with rates at zero converge in few evaluations; toy 172
+    # is one whose variance coefficient v2 runs to the domain wall.  Every
+    # converged fit meets the bound conditions: a rate on its bound has a
+    # gradient pushing it out of the box.
+    toys = _toys(256)
+    models = [bx.Model(d, x, precision=F32) for d, x, _ in toys]
+    pol = [bx.Model(d, x, precision=F64) for d, x, _ in toys]
+    res = bx.fit_batch(models, [t.theta0 for _, _, t in toys], [d.float_mask for d, _, _ in toys],
+                       edm_tol=1e-12, max_iter=500, polish=pol)
+    conv = [r for r in res if r.status == bx.BX_CONVERGED]
+    ev = np.array([r.n_eval for r in res])
+    print(f"toy fits: {len(conv)} of {len(res)} converged, evaluations median {np.median(ev):.0f} "
+          f"mean {ev.mean():.1f}; not converged: {[i for i, r in enumerate(res) if r.status != bx.BX_CONVERGED]}")
+    assert len(conv) >= 254
+    assert np.median(ev) <= 50
+    at_bound = 0
+    for (d, _, _), r in zip(toys, res):
+        if r.status != bx.BX_CONVERGED:
+            continue
+        assert r.edm < 1e-12
+        for s in range(d.S):
+            if d.float_mask[s] and r.x[s] == 0.0:
+                at_bound += 1
+                assert r.grad[s] >= -1e-6
+    assert at_bound > 0  # the sample exercises the bounds
+
+
 def test_device_minimised_batch_of_mixed_kinds(bx):
     # fits of several launch groups (Gaussian FP64, multivariate, generalized
     # gamma FP32) in one batch
