@@ -43,6 +43,20 @@
 #pragma clang fp contract(off)
 #endif
 
+// Loops over independent elements.  On the device the fit's whole wave runs
+// the minimiser (every lane the same serial code on the state in LDS, so the
+// control flow stays uniform), each lane takes every 64th element of such a
+// loop, and the wave (the whole workgroup) then waits at a barrier; the host
+// runs the elements in order.  An element's arithmetic is the same either
+// way, and ordered sums stay serial, so host and device give the same bits.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BX_PFOR(i, n) for (int i = (int)threadIdx.x; i < (n); i += 64)
+#define BX_PSYNC() __syncthreads()
+#else
+#define BX_PFOR(i, n) for (int i = 0; i < (n); ++i)
+#define BX_PSYNC() ((void)0)
+#endif
+
 namespace bx {
 
 void set_error(const std::string& msg);
@@ -174,17 +188,21 @@ class Bfgs {
         return;
       }
       const double h = hsign_ * kProbe;
-      for (int b = 0; b < n; ++b) {
+      BX_PFOR(b, n) {
         const int qb = pb_.idx[b];
         Hs_[b * n + hq_] = std::isfinite(f) ? (g[qb] - g_[qb]) * pb_.scale[qb] / h : 0.0;
       }
+      BX_PSYNC();
       if (++hq_ < n) {
         hsign_ = 1.0;
         set_probe();
         return;
       }
-      for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) B_[a * n + b] = 0.5 * (Hs_[a * n + b] + Hs_[b * n + a]);
+      BX_PFOR(e, n * n) {
+        const int a = e / n, b = e - a * n;
+        B_[e] = 0.5 * (Hs_[a * n + b] + Hs_[b * n + a]);
+      }
+      BX_PSYNC();
       refresh_iter_ = iter_;
       edm_refresh_ = INFINITY;
       start_iteration();
@@ -279,11 +297,13 @@ class Bfgs {
           break;
         }
         L[j * m + j] = std::sqrt(s);
-        for (int i = j + 1; i < m; ++i) {
+        BX_PFOR(ii, m - j - 1) {  // the rows below: column j of the factor
+          const int i = j + 1 + ii;
           double t = B_[fr[i] * n + fr[j]];
           for (int k = 0; k < j; ++k) t -= L[i * m + k] * L[j * m + k];
           L[i * m + j] = t / L[j * m + j];
         }
+        BX_PSYNC();
       }
       if (ok) break;
       shift = shift > 0 ? 4.0 * shift : 1e-10 * dmax;
@@ -362,22 +382,27 @@ class Bfgs {
       crossed = true;
       m = k;
       if (m == 0) break;
-      for (int i = 0; i < m; ++i) {
+      BX_PFOR(i, m) {
         double t = -gu[fr[i]];
         for (int b = 0; b < n; ++b) t -= B_[fr[i] * n + b] * dh[b];
         r[i] = t;
       }
+      BX_PSYNC();
       solve_free(fr, m, r, dd);
     }
     if (!crossed) return edm0;
     for (int i = 0; i < m; ++i) dh[fr[i]] = dd[i];
-    // predicted decrease of the held step: -(g.d + d^T B d / 2)
-    double q = 0.0;
-    for (int a = 0; a < n; ++a) {
+    // predicted decrease of the held step: -(g.d + d^T B d / 2), the terms
+    // per parameter, then summed in order
+    double* const qt = wb_;
+    BX_PFOR(a, n) {
       double bd = 0.0;
       for (int b = 0; b < n; ++b) bd += B_[a * n + b] * dh[b];
-      q += dh[a] * (gu[a] + 0.5 * bd);
+      qt[a] = dh[a] * (gu[a] + 0.5 * bd);
     }
+    BX_PSYNC();
+    double q = 0.0;
+    for (int a = 0; a < n; ++a) q += qt[a];
     if (!(-q > 0)) return edm0;  // no decrease predicted: the plain step
     if (d)
       for (int a = 0; a < n; ++a) d[a] = dh[a];
@@ -441,11 +466,13 @@ class Bfgs {
       y[a] = (g[q] - g_[q]) * pb_.scale[q];
       sy += s[a] * y[a];
     }
-    for (int a = 0; a < n; ++a) {
-      Bs[a] = 0.0;
-      for (int b = 0; b < n; ++b) Bs[a] += B_[a * n + b] * s[b];
-      sBs += s[a] * Bs[a];
+    BX_PFOR(a, n) {
+      double t = 0.0;
+      for (int b = 0; b < n; ++b) t += B_[a * n + b] * s[b];
+      Bs[a] = t;
     }
+    BX_PSYNC();
+    for (int a = 0; a < n; ++a) sBs += s[a] * Bs[a];
     fcopy(x_, xt_, 32);
     fcopy(g_, g, pb_.P);
     f_ = f;
@@ -453,8 +480,11 @@ class Bfgs {
     restarted_ = false;
     // BFGS update of the Hessian, skipped when the curvature condition fails
     if (sy > 1e-12 * std::sqrt(sBs > 0 ? sBs : 0.0) * 0 + 1e-300 && sBs > 1e-300) {
-      for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) B_[a * n + b] += y[a] * y[b] / sy - Bs[a] * Bs[b] / sBs;
+      BX_PFOR(e, n * n) {
+        const int a = e / n, b = e - a * n;
+        B_[e] += y[a] * y[b] / sy - Bs[a] * Bs[b] / sBs;
+      }
+      BX_PSYNC();
     }
     start_iteration();
   }

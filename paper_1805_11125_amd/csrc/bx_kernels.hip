@@ -2728,9 +2728,10 @@ __global__ void k_zero_count(int* c) { *c = 0; }
 // running[i]: 0 finished, 1 on its first model, 2 waiting for its polishing
 // placement to join the graph, 3 on the polishing model.  ready[i]: the
 // polishing placement is in the graph now.  One block (one wave) per fit:
-// the minimiser state is staged in LDS by the whole wave, one lane runs the
-// step on it (its Cholesky and BFGS updates then read LDS, not scattered
-// global memory), and the wave writes it back.
+// the wave stages the minimiser state in LDS, runs the step on it with every
+// lane (the loops over independent elements shared out, the rest computed
+// alike by all lanes, so the control flow is uniform) and writes it back;
+// lane 0 alone does the bookkeeping in global memory.
 __global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, FitDev* fits, int n, int* count,
                                                  int* running, const int* ready) {
   const int i = blockIdx.x;
@@ -2739,11 +2740,12 @@ __global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, Fit
   static_assert(sizeof(Bfgs) % sizeof(double) == 0, "minimiser state in whole words");
   __shared__ int go;
   __shared__ __align__(16) double sw[kWords];  // the fit's minimiser (raw words: no constructor runs)
-  Bfgs& sb = *reinterpret_cast<Bfgs*>(sw);
-  if (threadIdx.x == 0) {
-    const Bfgs& o = opts[i];
-    const FitSlot& sl = slots[i];
-    go = !o.done() || (sl.fit_p >= 0 && sl.phase == 0 && o.can_polish());
+  Bfgs& o = *reinterpret_cast<Bfgs*>(sw);
+  const bool lead = threadIdx.x == 0;
+  FitSlot& sl = slots[i];
+  if (lead) {
+    const Bfgs& og = opts[i];
+    go = !og.done() || (sl.fit_p >= 0 && sl.phase == 0 && og.can_polish());
     if (!go) running[i] = 0;
   }
   __syncthreads();
@@ -2751,40 +2753,42 @@ __global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, Fit
   double* const gw = reinterpret_cast<double*>(opts + i);
   for (int w = threadIdx.x; w < kWords; w += 64) sw[w] = gw[w];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    Bfgs& o = sb;
-    FitSlot& sl = slots[i];
-    running[i] = 0;
-    const bool waiting = o.done();  // only a fit about to move to its polishing model gets here done
-    if (!waiting) {  // the results of the last evaluation
-      const FitDev& f = fits[sl.phase ? sl.fit_p : sl.fit];
-      const double* out = f.out;
-      const int fl = (int)out[1 + sl.P];
-      const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
-      o.feed(bad ? INFINITY : out[0], out + 1);
-    }
-    bool held = false;
-    if (o.done() && sl.fit_p >= 0 && sl.phase == 0 && o.can_polish()) {
-      fits[sl.fit].skip = 1;
-      if (!ready[i]) {  // wait (no evaluation) until the host adds the FP64 placement
+  // the slot's fields, read once by every lane (lane 0 may rewrite phase)
+  const int fit = sl.fit, fit_p = sl.fit_p, P = sl.P;
+  int phase = sl.phase;
+  if (lead) running[i] = 0;
+  if (!o.done()) {  // the results of the last evaluation (only a fit about to move to its polishing model is done)
+    const double* out = fits[phase ? fit_p : fit].out;
+    const int fl = (int)out[1 + P];
+    const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
+    o.feed(bad ? INFINITY : out[0], out + 1);
+  }
+  bool held = false;
+  if (o.done() && fit_p >= 0 && phase == 0 && o.can_polish()) {
+    if (lead) fits[fit].skip = 1;
+    if (!ready[i]) {  // wait (no evaluation) until the host adds the FP64 placement
+      if (lead) {
         running[i] = 2;
         atomicAdd(count, 1);
-        held = true;
-      } else {
-        o.polish(sl.final_tol, sl.noise_p);  // on to the polishing placement (same theta and result rows)
+      }
+      held = true;
+    } else {
+      o.polish(sl.final_tol, sl.noise_p);  // on to the polishing placement (same theta and result rows)
+      phase = 1;
+      if (lead) {
         sl.phase = 1;
-        fits[sl.fit_p].skip = 0;
+        fits[fit_p].skip = 0;
       }
     }
-    if (!held) {
-      FitDev& g = fits[sl.phase ? sl.fit_p : sl.fit];
-      if (o.done()) {
-        g.skip = 1;
-      } else {
-        o.next(const_cast<double*>(g.theta));
-        running[i] = 1 + 2 * sl.phase;
-        atomicAdd(count, 1);
-      }
+  }
+  if (!held && lead) {
+    FitDev& g = fits[phase ? fit_p : fit];
+    if (o.done()) {
+      g.skip = 1;
+    } else {
+      o.next(const_cast<double*>(g.theta));
+      running[i] = 1 + 2 * phase;
+      atomicAdd(count, 1);
     }
   }
   __syncthreads();
