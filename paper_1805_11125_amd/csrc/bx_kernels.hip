@@ -2750,18 +2750,38 @@ __global__ void __launch_bounds__(64) k_fit_step(Bfgs* opts, FitSlot* slots, Fit
   }
   __syncthreads();
   if (!go) return;  // block-uniform: a finished fit
+  // the state in (all of a lane's loads issued before its first store: one
+  // memory latency, not one per word), and the last evaluation's result row
+  // (NLL, gradient, flags), which the step reads in serial loops
   double* const gw = reinterpret_cast<double*>(opts + i);
-  for (int w = threadIdx.x; w < kWords; w += 64) sw[w] = gw[w];
-  __syncthreads();
+  constexpr int kPer = (kWords + 63) / 64;
+  {
+    double v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int w = threadIdx.x + 64 * k;
+      v[k] = w < kWords ? gw[w] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int w = threadIdx.x + 64 * k;
+      if (w < kWords) sw[w] = v[k];
+    }
+  }
   // the slot's fields, read once by every lane (lane 0 may rewrite phase)
   const int fit = sl.fit, fit_p = sl.fit_p, P = sl.P;
   int phase = sl.phase;
+  __shared__ double res[kMaxP + 2];
+  {
+    const double* out = fits[phase ? fit_p : fit].out;
+    if ((int)threadIdx.x < P + 2) res[threadIdx.x] = out[threadIdx.x];
+  }
+  __syncthreads();
   if (lead) running[i] = 0;
   if (!o.done()) {  // the results of the last evaluation (only a fit about to move to its polishing model is done)
-    const double* out = fits[phase ? fit_p : fit].out;
-    const int fl = (int)out[1 + P];
+    const int fl = (int)res[1 + P];
     const bool bad = (fl & (kBadSigma | kBadGG | kBadMu | kBadTheta | kZeroWidth)) != 0;
-    o.feed(bad ? INFINITY : out[0], out + 1);
+    o.feed(bad ? INFINITY : res[0], res + 1);
   }
   bool held = false;
   if (o.done() && fit_p >= 0 && phase == 0 && o.can_polish()) {
