@@ -296,7 +296,7 @@ bx_status bx_fit(bx_model* m, const bx_fit_opts* o, bx_fit_result* r);
  * i < n, with the fits' minimisers on the device.  Each fit is placed once
  * (inputs shared with its model, its own workspace); one iteration of all of
  * them -- the evaluation launches of every launch group, then a kernel that
- * runs each fit's minimiser step (one thread per fit) -- is captured as a HIP
+ * runs each fit's minimiser step (one wave per fit) -- is captured as a HIP
  * graph and replayed until no fit is running, the host reading the count of
  * running fits every check_every replays (<= 0: 4).  results[i] equal
  * bx_fit's bit for bit (the minimiser is the same code, compiled for the

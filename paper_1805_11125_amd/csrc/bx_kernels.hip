@@ -2711,7 +2711,7 @@ void launch_expected(const FitDev* d_fit, double* d_out, int N, int n_rad, int n
 
 // ---------------------------------------------------------------------------
 // Device-minimised batched fits (Sec. 4, steps 5-6 for many fits at once):
-// the minimiser of every fit runs on the device, one thread per fit, between
+// the minimiser of every fit runs on the device, one wave per fit, between
 // the evaluation launches of a captured graph, so that an iteration of all
 // the fits needs no host round trip.  The minimiser is the host's own code
 // (bx_fitcore.hpp, contraction off), so a fit takes the same steps as on the
